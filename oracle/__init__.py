@@ -1,0 +1,12 @@
+"""CPU oracle for the l2 Tikhonov-regularized Toeplitz least-squares solve.
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, __graft_entry__.smoke() and the
+cpu_baseline leg of bench.py, never by the product package.  See
+oracle/tikh_oracle.c for what it computes (dense Householder QR of the stacked
+system [T; lambda I], the plain definition of eq. (tiksol) with L = lambda I).
+"""
+from .oracle import (build, solve, solve_normal, gradients, T_apply, TH_apply,
+                     dense_T, normal_residual)
+
+__all__ = ["build", "solve", "solve_normal", "gradients", "T_apply", "TH_apply",
+           "dense_T", "normal_residual"]

@@ -1,0 +1,130 @@
+"""ctypes binding of oracle/tikh_oracle.c (test infrastructure only).
+
+Every function takes numpy arrays and works in complex FP64; real inputs are
+promoted.  Toeplitz convention (paper Sec. 1, T = [a_{i-j}]): col[i] = a_i
+(i < m), row[j] = a_{-j} (0 < j < n); row[0] is ignored.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "tikh_oracle.c")
+_LIB = os.path.join(_HERE, "libtikh_oracle.so")
+_lib = None
+
+
+def build(force=False):
+    """Compile the C oracle with gcc (plain -O2, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        I64 = ctypes.c_int64
+        lib.tikh_oracle_qr_solve.argtypes = [I64, I64, P, P, P, P, ctypes.c_double, P, ctypes.c_int]
+        lib.tikh_oracle_qr_solve.restype = ctypes.c_int
+        lib.tikh_oracle_T_apply.argtypes = [I64, I64, P, P, P, P]
+        lib.tikh_oracle_TH_apply.argtypes = [I64, I64, P, P, P, P]
+        lib.tikh_oracle_gradients.argtypes = [I64, I64, P, P, P, ctypes.c_double, P, P, P, P, P,
+                                              ctypes.POINTER(ctypes.c_double), ctypes.c_int]
+        lib.tikh_oracle_gradients.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _c(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.complex128))
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _threads(nthreads):
+    return int(nthreads) if nthreads else 1
+
+
+def solve(col, row, b, lam, nthreads=1):
+    """x = argmin ||Tx - b||^2 + lam^2 ||x||^2 by dense Householder QR of [T; lam I]."""
+    col, row, b = _c(col), _c(row), _c(b)
+    m, n = len(col), len(row)
+    assert len(b) == m
+    x = np.zeros(n, np.complex128)
+    st = _load().tikh_oracle_qr_solve(m, n, _p(col), _p(row), _p(b), None, float(lam), _p(x), _threads(nthreads))
+    if st != 0:
+        raise RuntimeError("oracle QR failed with status %d" % st)
+    return x
+
+
+def solve_normal(col, row, y, lam, nthreads=1):
+    """x = (T^H T + lam^2 I)^{-1} y, as least squares of [T; lam I] x ~ [0; y/lam]."""
+    col, row, y = _c(col), _c(row), _c(y)
+    m, n = len(col), len(row)
+    assert len(y) == n
+    d = _c(y / float(lam))
+    x = np.zeros(n, np.complex128)
+    st = _load().tikh_oracle_qr_solve(m, n, _p(col), _p(row), None, _p(d), float(lam), _p(x), _threads(nthreads))
+    if st != 0:
+        raise RuntimeError("oracle QR failed with status %d" % st)
+    return x
+
+
+def T_apply(col, row, v):
+    col, row, v = _c(col), _c(row), _c(v)
+    m, n = len(col), len(row)
+    y = np.zeros(m, np.complex128)
+    _load().tikh_oracle_T_apply(m, n, _p(col), _p(row), _p(v), _p(y))
+    return y
+
+
+def TH_apply(col, row, v):
+    col, row, v = _c(col), _c(row), _c(v)
+    m, n = len(col), len(row)
+    y = np.zeros(n, np.complex128)
+    _load().tikh_oracle_TH_apply(m, n, _p(col), _p(row), _p(v), _p(y))
+    return y
+
+
+def gradients(col, row, b, lam, gx, nthreads=1):
+    """Returns dict(x, g_b, g_col, g_row, g_lam) for loss gradient gx = dL/dRe x + i dL/dIm x."""
+    col, row, b, gx = _c(col), _c(row), _c(b), _c(gx)
+    m, n = len(col), len(row)
+    x = np.zeros(n, np.complex128)
+    gb = np.zeros(m, np.complex128)
+    gcol = np.zeros(m, np.complex128)
+    grow = np.zeros(n, np.complex128)
+    glam = ctypes.c_double(0.0)
+    st = _load().tikh_oracle_gradients(m, n, _p(col), _p(row), _p(b), float(lam), _p(gx), _p(x), _p(gb),
+                                       _p(gcol), _p(grow), ctypes.byref(glam), _threads(nthreads))
+    if st != 0:
+        raise RuntimeError("oracle gradient failed with status %d" % st)
+    return dict(x=x, g_b=gb, g_col=gcol, g_row=grow, g_lam=glam.value)
+
+
+def dense_T(col, row):
+    """The m x n Toeplitz matrix T = [a_{i-j}] written out (small sizes only)."""
+    col, row = _c(col), _c(row)
+    m, n = len(col), len(row)
+    T = np.empty((m, n), np.complex128)
+    for i in range(m):
+        for j in range(n):
+            T[i, j] = col[i - j] if i >= j else row[j - i]
+    return T
+
+
+def normal_residual(col, row, b, lam, x):
+    """Relative residual of the optimality condition T^H (b - T x) = lam^2 x."""
+    r = TH_apply(col, row, _c(b) - T_apply(col, row, x)) - float(lam) ** 2 * _c(x)
+    scale = np.linalg.norm(TH_apply(col, row, b)) + float(lam) ** 2 * np.linalg.norm(x)
+    return float(np.linalg.norm(r) / scale)

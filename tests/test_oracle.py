@@ -1,0 +1,182 @@
+"""Pins for the CPU oracle (dense Householder QR of [T; lambda I]).
+
+Each test checks the oracle against something the paper or the mathematics
+fixes independently of the oracle's own code: exact rational arithmetic on tiny
+inputs, 50-digit normal equations, the circulant closed form (Fourier domain),
+special cases, the scaling law, the large-lambda limit, an independent library
+least-squares routine and the optimality condition of eq. (tik)/(tiksol).
+"""
+from fractions import Fraction
+
+import mpmath
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+
+def test_T_matches_definition():
+    # Sec. 1: T = [a_{i-j}]; col holds a_0..a_{m-1}, row holds a_0, a_{-1}, ...
+    col = np.array([10, 11, 12, 13]); row = np.array([10, 21, 22])
+    T = oracle.dense_T(col, row).real
+    expect = np.array([[10, 21, 22], [11, 10, 21], [12, 11, 10], [13, 12, 11]])
+    assert np.array_equal(T, expect)
+
+
+def _exact_solution(T_int, b_int, lam2):
+    """Exact rational solve of (T^T T + lam2 I) x = T^T b by Gaussian elimination."""
+    m, n = len(T_int), len(T_int[0])
+    A = [[sum(Fraction(T_int[k][i]) * T_int[k][j] for k in range(m)) + (lam2 if i == j else 0)
+          for j in range(n)] for i in range(n)]
+    y = [sum(Fraction(T_int[k][i]) * b_int[k] for k in range(m)) for i in range(n)]
+    for c in range(n):
+        p = next(r for r in range(c, n) if A[r][c] != 0)
+        A[c], A[p] = A[p], A[c]; y[c], y[p] = y[p], y[c]
+        for r in range(n):
+            if r != c and A[r][c] != 0:
+                f = A[r][c] / A[c][c]
+                A[r] = [A[r][k] - f * A[c][k] for k in range(n)]
+                y[r] -= f * y[c]
+    return [y[i] / A[i][i] for i in range(n)]
+
+
+@pytest.mark.parametrize("m,n", [(3, 2), (2, 3), (5, 5), (6, 4), (4, 7), (1, 1), (1, 3), (3, 1)])
+def test_exact_rational_bruteforce(m, n):
+    rng = np.random.default_rng(100 * m + n)
+    col = rng.integers(-5, 6, size=m); row = rng.integers(-5, 6, size=n); row[0] = col[0]
+    b = rng.integers(-5, 6, size=m)
+    lam2 = Fraction(3, 4)
+    T = [[int(col[i - j]) if i >= j else int(row[j - i]) for j in range(n)] for i in range(m)]
+    xe = np.array([float(v) for v in _exact_solution(T, [int(v) for v in b], lam2)])
+    x = oracle.solve(col, row, b, float(lam2) ** 0.5)
+    assert np.abs(x.imag).max() == 0.0
+    np.testing.assert_allclose(x.real, xe, rtol=1e-12, atol=1e-13)
+
+
+@pytest.mark.parametrize("m,n", [(5, 3), (3, 5), (6, 6), (8, 2)])
+def test_mpmath_complex_bruteforce(m, n):
+    rng = np.random.default_rng(7 * m + n)
+    col = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+    row = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    b = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+    lam = 0.3
+    mpmath.mp.dps = 50
+    T = mpmath.matrix(m, n)
+    for i in range(m):
+        for j in range(n):
+            v = col[i - j] if i >= j else row[j - i]
+            T[i, j] = mpmath.mpc(v.real, v.imag)
+    TH = T.transpose_conj()
+    A = TH * T + lam ** 2 * mpmath.eye(n)
+    bb = mpmath.matrix([mpmath.mpc(v.real, v.imag) for v in b])
+    xe = mpmath.lu_solve(A, TH * bb)
+    xe = np.array([complex(xe[i]) for i in range(n)])
+    x = oracle.solve(col, row, b, lam)
+    np.testing.assert_allclose(x, xe, rtol=1e-12, atol=1e-13)
+    # mutation check: the transposed or conjugated operand must be rejected by this pin
+    x_bad = oracle.solve(np.conj(col), np.conj(row), b, lam)
+    assert np.abs(x_bad - xe).max() > 1e-6
+
+
+@pytest.mark.parametrize("n", [16, 64, 257])
+@pytest.mark.parametrize("cplx", [False, True])
+def test_circulant_closed_form(n, cplx):
+    """Circulant T (m = n, a_{-j} = a_{n-j}): the Fourier-domain closed form
+    x = IDFT(conj(a^) b^ / (|a^|^2 + lambda^2))."""
+    rng = np.random.default_rng(n + 1000 * cplx)
+    c = rng.standard_normal(n) + (1j * rng.standard_normal(n) if cplx else 0)
+    col = c.copy(); row = np.array([c[(n - j) % n] for j in range(n)])
+    b = rng.standard_normal(n) + (1j * rng.standard_normal(n) if cplx else 0)
+    lam = 0.4
+    ah = np.fft.fft(c); bh = np.fft.fft(b)
+    xe = np.fft.ifft(np.conj(ah) * bh / (np.abs(ah) ** 2 + lam ** 2))
+    x = oracle.solve(col, row, b, lam)
+    np.testing.assert_allclose(x, xe, rtol=1e-11, atol=1e-12)
+
+
+def test_scaled_identity_and_zero():
+    n = 9
+    rng = np.random.default_rng(3)
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    c = 1.5 - 0.5j; lam = 0.8
+    col = np.zeros(n, complex); col[0] = c; row = np.zeros(n, complex); row[0] = c
+    np.testing.assert_allclose(oracle.solve(col, row, b, lam), np.conj(c) * b / (abs(c) ** 2 + lam ** 2), rtol=1e-13)
+    z = np.zeros(n)
+    assert np.abs(oracle.solve(np.zeros(12), z, rng.standard_normal(12), lam)).max() < 1e-14
+
+
+def test_scaling_law_and_large_lambda():
+    rng = np.random.default_rng(5)
+    col, row, b = W.random_problem(rng, 20, 13, cplx=True)
+    lam, alpha = 0.6, 3.7
+    x1 = oracle.solve(col, row, b, lam)
+    x2 = oracle.solve(alpha * col, alpha * row, b, alpha * lam)
+    np.testing.assert_allclose(x2, x1 / alpha, rtol=1e-12)
+    big = 1e5
+    xl = oracle.solve(col, row, b, big)
+    np.testing.assert_allclose(big ** 2 * xl, oracle.TH_apply(col, row, b), rtol=1e-6)
+
+
+@pytest.mark.parametrize("m,n,cplx", [(40, 30, False), (30, 40, True), (64, 64, True)])
+def test_lstsq_and_optimality(m, n, cplx):
+    rng = np.random.default_rng(m * n)
+    col, row, b = W.random_problem(rng, m, n, cplx=cplx)
+    lam = 0.25
+    x = oracle.solve(col, row, b, lam)
+    T = oracle.dense_T(col, row)
+    A = np.vstack([T, lam * np.eye(n)])
+    xe = np.linalg.lstsq(A, np.concatenate([b, np.zeros(n)]), rcond=None)[0]
+    np.testing.assert_allclose(x, xe, rtol=1e-10, atol=1e-12)
+    assert oracle.normal_residual(col, row, b, lam, x) < 1e-13
+    # T_apply / TH_apply against the dense matrix
+    v = rng.standard_normal(n); w = rng.standard_normal(m)
+    np.testing.assert_allclose(oracle.T_apply(col, row, v), T @ v, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(oracle.TH_apply(col, row, w), T.conj().T @ w, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_normal_form_entry(cplx):
+    rng = np.random.default_rng(11)
+    col, row, _ = W.random_problem(rng, 25, 17, cplx=cplx)
+    y = rng.standard_normal(17) + (1j * rng.standard_normal(17) if cplx else 0)
+    lam = 0.9
+    x = oracle.solve_normal(col, row, y, lam)
+    T = oracle.dense_T(col, row)
+    np.testing.assert_allclose((T.conj().T @ T + lam ** 2 * np.eye(17)) @ x, y, rtol=1e-11, atol=1e-12)
+
+
+def _loss(col, row, b, lam, xt):
+    x = oracle.solve(col, row, b, lam)
+    return 0.5 * np.sum(np.abs(x - xt) ** 2)
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_gradients_central_differences(cplx):
+    """Hand-derived adjoint (w = A^{-1} g, g_b = T w, g_lam = -2 lam Re<w,x>,
+    G_T = (b - T x) w^H - (T w) x^H) against central differences of the oracle."""
+    rng = np.random.default_rng(21 + cplx)
+    m, n = 14, 9
+    col, row, b = W.random_problem(rng, m, n, cplx=cplx)
+    lam = 0.7
+    xt = rng.standard_normal(n) + (1j * rng.standard_normal(n) if cplx else 0)
+    x = oracle.solve(col, row, b, lam)
+    g = oracle.gradients(col, row, b, lam, x - xt)
+    np.testing.assert_allclose(g["x"], x, rtol=1e-13)
+    h = 1e-6
+    dirs = rng.standard_normal((6, 2 * m + 2 * n + 1))
+    for d in dirs:
+        d /= np.linalg.norm(d)
+        dcol = d[:m] + (1j * d[m:2 * m] if cplx else 0)
+        drow = np.concatenate([[0], d[2 * m:2 * m + n - 1]]) + (1j * np.concatenate([[0], d[2 * m + n - 1:2 * m + 2 * n - 2]]) if cplx else 0)
+        db = d[-1 - m:-1] if not cplx else d[-1 - m:-1] * (1 + 1j)
+        dl = d[-1]
+        fp = _loss(col + h * dcol, row + h * drow, b + h * db, lam + h * dl, xt)
+        fm = _loss(col - h * dcol, row - h * drow, b - h * db, lam - h * dl, xt)
+        fd = (fp - fm) / (2 * h)
+        an = (np.sum((np.conj(g["g_col"]) * dcol).real) + np.sum((np.conj(g["g_row"]) * drow).real)
+              + np.sum((np.conj(g["g_b"]) * db).real) + g["g_lam"] * dl)
+        assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (fd, an)
+    # dx/dlambda = -2 lambda A^{-1} x
+    dxdl = (oracle.solve(col, row, b, lam + h) - oracle.solve(col, row, b, lam - h)) / (2 * h)
+    np.testing.assert_allclose(dxdl, -2 * lam * oracle.solve_normal(col, row, x, lam), rtol=1e-6, atol=1e-8)
