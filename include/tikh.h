@@ -1,0 +1,176 @@
+/*
+ * tikh.h -- C ABI of the MI355X (gfx950) superfast Tikhonov-regularized
+ * Toeplitz least-squares solver.
+ *
+ * Problem (Turnes, Balcan, Romberg, "Superfast Tikhonov Regularization of
+ * Toeplitz Systems", Sec. 2, eq. (tik) with the l2-norm penalization case
+ * L = lambda I, Sec. 3.3):
+ *
+ *     x = argmin_x ||T x - b||^2 + lambda^2 ||x||^2
+ *       = (T^H T + lambda^2 I)^{-1} T^H b                      (eq. (tiksol))
+ *
+ * T is m x n Toeplitz, T = [a_{i-j}] (Sec. 1), given by its m+n-1 generator
+ * entries:  col[i] = a_i (0 <= i < m),  row[j] = a_{-j} (0 < j < n).  row[0]
+ * is ignored (a_0 is col[0]).  Any aspect ratio is allowed (Sec. 3.3: the
+ * extension uses q = m regardless of m < n).
+ *
+ * Method: extension of the Toeplitz blocks to partial-circulant blocks
+ * (eq. (circexp), (ex5)-(ex6)), transformation by FFTs to tangential
+ * interpolation conditions at roots of unity (eq. (vandprod), (intcond),
+ * (interp)), and the divide-and-conquer basis construction of Alg. 1 with
+ * paired interleaving (Sec. 6.1) and the extension size of Alg. 2 (Sec. 6.2);
+ * the solution is read from the tau-degree-0 column of the final basis
+ * (Sec. 5).  One step of iterative refinement (mentioned in Sec. 7.2) is on
+ * by default.  All arithmetic is complex FP64 on the GPU.
+ *
+ * Memory: unless stated otherwise every array argument is a DEVICE pointer
+ * (hipMalloc'd memory or a torch tensor's storage on the current HIP device),
+ * FP64, contiguous, owned by the caller; the library never frees or retains
+ * it.  Complex arrays are interleaved (re, im) pairs (tikh_c64).  Inputs are
+ * never modified.  Work is enqueued on the stream set by tikh_set_stream
+ * (default: the null stream).  The library keeps an internal device workspace
+ * that grows on demand (hipMalloc outside the hot loop) and is released by
+ * tikh_release().
+ *
+ * Errors: every entry point returns TIKH_OK (0) or a negative TIKH_E* code;
+ * tikh_strerror() describes it.  On error the outputs are undefined.  The
+ * numerical status of each solve is reported in an info word: 0 = OK,
+ * 1 = breakdown (no admissible pivot / final tau-degrees not {1,1,1,1,0}),
+ * 2 = a basis degree exceeded its storage bound, 3 = non-finite values.
+ * Single-problem calls synchronize the stream and return TIKH_ENUMERIC when
+ * info != 0.  Calls are not thread safe (one host thread per library state).
+ */
+#ifndef TIKH_H
+#define TIKH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { double re, im; } tikh_c64;
+
+enum {
+    TIKH_OK = 0,
+    TIKH_EINVAL = -1,     /* invalid argument (sizes, non-positive or non-finite lambda, null pointer) */
+    TIKH_ENOMEM = -2,     /* device allocation failed */
+    TIKH_EHIP = -3,       /* a HIP runtime call failed */
+    TIKH_ENUMERIC = -4    /* a solve reported info != 0 (see above) */
+};
+
+/* Tunable options (Sec. 6.2: leaf cutoff N_lim; Sec. 7.2: refinement). */
+typedef struct {
+    int32_t n_lim;        /* max conditions per leaf (64..256, multiple of 64); default 256 */
+    int32_t refine;       /* iterative-refinement steps (0..4); default 1 */
+    int32_t reserved[6];
+} tikh_opts;
+
+/* Per-solve statistics of the last call (host memory, filled by tikh_get_stats). */
+typedef struct {
+    int64_t N;            /* number of interpolation nodes after extension (Alg. 2) */
+    int64_t k;            /* circulant-extension size k (Sec. 3.1) */
+    int32_t depth;        /* recursion depth p: 2^p leaves */
+    int32_t leaf_nodes;   /* M: nodes per leaf (2M conditions) */
+    int64_t solves;       /* number of solves in the last call */
+    int64_t launches;     /* kernel launches enqueued by the last call */
+} tikh_stats;
+
+/*
+ * Host-only planning query (no device work): the extended number of nodes
+ * N = 2^p M chosen by the extension-size rule of Alg. 2 (Sec. 6.2) for an
+ * m x n problem and leaf cutoff n_lim (two condition sets per node, so a leaf
+ * of M nodes carries 2M <= n_lim conditions; M even and 5-smooth).  Outputs
+ * are host pointers.  Returns TIKH_EINVAL for invalid sizes or n_lim.
+ */
+int tikh_plan_info(int64_t m, int64_t n, int32_t n_lim, int64_t* N, int64_t* M, int32_t* depth, int64_t* k);
+
+/* Library state.  tikh_init is optional (the first call initializes). */
+int tikh_init(void);
+int tikh_release(void);                              /* free workspace */
+int tikh_set_stream(void* hip_stream);               /* hipStream_t; NULL = null stream */
+int tikh_set_options(const tikh_opts* opts);         /* host pointer */
+int tikh_get_options(tikh_opts* opts);               /* host pointer */
+int tikh_get_stats(tikh_stats* stats);               /* host pointer */
+const char* tikh_strerror(int code);
+
+/*
+ * Single problem, real data: col[m], row[n], b[m] -> x[n] (device, FP64).
+ * lambda must be finite and > 0 (lambda = 0 is the pseudo-inverse problem,
+ * outside this solver).  Synchronizes; returns TIKH_ENUMERIC if info != 0.
+ */
+int tikh_toeplitz_solve(const double* col, const double* row, int64_t m, int64_t n,
+                        const double* b, double lambda, double* x);
+
+/* Single problem, complex data (interleaved). */
+int tikh_toeplitz_solve_z(const tikh_c64* col, const tikh_c64* row, int64_t m, int64_t n,
+                          const tikh_c64* b, double lambda, tikh_c64* x);
+
+/*
+ * Normal-form entry: x = (T^H T + lambda^2 I)^{-1} y for y[n] (the systems
+ * (G_T + G_L) x = y solved in Sec. 7.1).  Same conventions as above.
+ */
+int tikh_toeplitz_solve_normal(const double* col, const double* row, int64_t m, int64_t n,
+                               const double* y, double lambda, double* x);
+int tikh_toeplitz_solve_normal_z(const tikh_c64* col, const tikh_c64* row, int64_t m, int64_t n,
+                                 const tikh_c64* y, double lambda, tikh_c64* x);
+
+/*
+ * Batched solves.  nprob problems with host arrays m[nprob], n[nprob].
+ * Device buffers are packed problem after problem (offsets are prefix sums):
+ *   col:  sum m_p entries,  row: sum n_p entries,
+ *   b:    for each problem p, nrhs right-hand sides of m_p entries,
+ *   x:    for each problem p, for each lambda l, for each rhs r, n_p entries
+ *         (x offset of (p,l,r) = xoff_p + (l*nrhs + r)*n_p),
+ *   lambdas: HOST array [nprob * nlam] (lambda of (p,l) at p*nlam + l).
+ *   info: DEVICE int32 array [nprob * nlam * nrhs] or NULL.
+ * Asynchronous: returns after enqueueing; info is valid after the stream
+ * completes.  complex_data selects double (0) or tikh_c64 (1) element type.
+ */
+int tikh_toeplitz_solve_batched(int64_t nprob, const int64_t* m, const int64_t* n,
+                                const void* col, const void* row,
+                                int64_t nlam, const double* lambdas,
+                                int64_t nrhs, const void* b, void* x,
+                                int32_t* info, int complex_data);
+
+/*
+ * Adjoint (backward) of x = solve(col, row, b, lambda) for a scalar loss with
+ * upstream gradient gx[n] = dL/dRe(x) + i dL/dIm(x) (real data: dL/dx).  x is
+ * the forward solution.  Derived from eq. (tiksol): w = (T^H T + lambda^2 I)^{-1} gx
+ * (one more solve of the same operator, normal form), then
+ *   g_b   = T w                                  [m]
+ *   g_lam = -2 lambda Re<w, x>                   (device scalar)
+ *   g_col[s], g_row[s] = sum over i-j = +-s of (b - T x) w^H - (T w) x^H
+ * computed by FFT cross-correlations.  g_row[0] is set to 0 (a_0 lives in
+ * col[0]).  Outputs are device arrays the caller owns.  Synchronizes.
+ */
+int tikh_toeplitz_solve_backward(const double* col, const double* row, int64_t m, int64_t n,
+                                 const double* b, double lambda, const double* x,
+                                 const double* gx, double* g_col, double* g_row,
+                                 double* g_b, double* g_lambda);
+int tikh_toeplitz_solve_backward_z(const tikh_c64* col, const tikh_c64* row, int64_t m, int64_t n,
+                                   const tikh_c64* b, double lambda, const tikh_c64* x,
+                                   const tikh_c64* gx, tikh_c64* g_col, tikh_c64* g_row,
+                                   tikh_c64* g_b, double* g_lambda);
+
+/*
+ * Batched backward with the packing of tikh_toeplitz_solve_batched: x and gx
+ * are packed like x there; g_col/g_row/g_b are packed per (p, l, r) solve
+ * (g_col offset of (p,l,r) = colsum_p*nlam*nrhs + (l*nrhs+r)*m_p, likewise
+ * g_row with n_p and g_b with m_p); g_lambda is a device array
+ * [nprob*nlam*nrhs].  Asynchronous.
+ */
+int tikh_toeplitz_solve_backward_batched(int64_t nprob, const int64_t* m, const int64_t* n,
+                                         const void* col, const void* row,
+                                         int64_t nlam, const double* lambdas,
+                                         int64_t nrhs, const void* b, const void* x,
+                                         const void* gx, void* g_col, void* g_row,
+                                         void* g_b, double* g_lambda,
+                                         int32_t* info, int complex_data);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TIKH_H */

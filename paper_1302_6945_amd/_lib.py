@@ -1,0 +1,209 @@
+"""ctypes marshalling for libtikh.so (include/tikh.h).  No compute here."""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_HERE, "libtikh.so")
+
+if not os.path.exists(library_path):
+    raise ImportError("libtikh.so is not built: run `python paper_1302_6945_amd/build.py` "
+                      "(or __graft_entry__.build()) before using paper_1302_6945_amd")
+
+lib = ctypes.CDLL(library_path)
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_D = ctypes.c_double
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("n_lim", ctypes.c_int32), ("refine", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int64), ("k", ctypes.c_int64), ("depth", ctypes.c_int32),
+                ("leaf_nodes", ctypes.c_int32), ("solves", ctypes.c_int64), ("launches", ctypes.c_int64)]
+
+
+def _sig(name, args, res=ctypes.c_int):
+    f = getattr(lib, name)
+    f.argtypes = args
+    f.restype = res
+    return f
+
+
+_sig("tikh_init", [])
+tikh_plan_info = _sig("tikh_plan_info", [_I64, _I64, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_int64)])
+_sig("tikh_release", [])
+_sig("tikh_set_stream", [_P])
+_sig("tikh_set_options", [ctypes.POINTER(_Opts)])
+_sig("tikh_get_options", [ctypes.POINTER(_Opts)])
+_sig("tikh_get_stats", [ctypes.POINTER(_Stats)])
+_sig("tikh_strerror", [ctypes.c_int], ctypes.c_char_p)
+tikh_toeplitz_solve = _sig("tikh_toeplitz_solve", [_P, _P, _I64, _I64, _P, _D, _P])
+tikh_toeplitz_solve_z = _sig("tikh_toeplitz_solve_z", [_P, _P, _I64, _I64, _P, _D, _P])
+tikh_toeplitz_solve_normal = _sig("tikh_toeplitz_solve_normal", [_P, _P, _I64, _I64, _P, _D, _P])
+tikh_toeplitz_solve_normal_z = _sig("tikh_toeplitz_solve_normal_z", [_P, _P, _I64, _I64, _P, _D, _P])
+tikh_toeplitz_solve_batched = _sig("tikh_toeplitz_solve_batched",
+                                   [_I64, _P, _P, _P, _P, _I64, _P, _I64, _P, _P, _P, ctypes.c_int])
+tikh_toeplitz_solve_backward = _sig("tikh_toeplitz_solve_backward",
+                                    [_P, _P, _I64, _I64, _P, _D, _P, _P, _P, _P, _P, _P])
+tikh_toeplitz_solve_backward_z = _sig("tikh_toeplitz_solve_backward_z",
+                                      [_P, _P, _I64, _I64, _P, _D, _P, _P, _P, _P, _P, _P])
+tikh_toeplitz_solve_backward_batched = _sig("tikh_toeplitz_solve_backward_batched",
+                                            [_I64, _P, _P, _P, _P, _I64, _P, _I64, _P, _P, _P, _P, _P, _P, _P,
+                                             _P, ctypes.c_int])
+
+
+class TikhError(RuntimeError):
+    def __init__(self, code, where):
+        msg = lib.tikh_strerror(code).decode()
+        super().__init__("%s failed: %s (code %d)" % (where, msg, code))
+        self.code = code
+
+
+def _check(code, where):
+    if code != 0:
+        raise TikhError(code, where)
+
+
+def _stream():
+    lib.tikh_set_stream(ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+
+
+def set_options(n_lim=None, refine=None):
+    o = _Opts()
+    _check(lib.tikh_get_options(ctypes.byref(o)), "tikh_get_options")
+    if n_lim is not None:
+        o.n_lim = int(n_lim)
+    if refine is not None:
+        o.refine = int(refine)
+    _check(lib.tikh_set_options(ctypes.byref(o)), "tikh_set_options")
+
+
+def get_options():
+    o = _Opts()
+    _check(lib.tikh_get_options(ctypes.byref(o)), "tikh_get_options")
+    return dict(n_lim=o.n_lim, refine=o.refine)
+
+
+def plan_info(m, n, n_lim=256):
+    """(N, M, depth, k) of the extension plan (host-only, Alg. 2)."""
+    N = ctypes.c_int64(); M = ctypes.c_int64(); p = ctypes.c_int32(); k = ctypes.c_int64()
+    _check(tikh_plan_info(int(m), int(n), int(n_lim), ctypes.byref(N), ctypes.byref(M), ctypes.byref(p),
+                          ctypes.byref(k)), "tikh_plan_info")
+    return N.value, M.value, p.value, k.value
+
+
+def get_stats():
+    s = _Stats()
+    _check(lib.tikh_get_stats(ctypes.byref(s)), "tikh_get_stats")
+    return dict(N=s.N, k=s.k, depth=s.depth, leaf_nodes=s.leaf_nodes, solves=s.solves, launches=s.launches)
+
+
+def _dev(t, dtype):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a HIP device tensor")
+    if t.dtype != dtype:
+        raise TypeError("expected dtype %s, got %s" % (dtype, t.dtype))
+    return t.contiguous()
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dtype_of(*ts):
+    return torch.complex128 if any(t.is_complex() for t in ts) else torch.float64
+
+
+def solve(col, row, b, lam):
+    """x = argmin ||T x - b||^2 + lam^2 ||x||^2 on the GPU (tikh_toeplitz_solve[_z])."""
+    dt = _dtype_of(col, row, b)
+    col, row, b = _dev(col.to(dt), dt), _dev(row.to(dt), dt), _dev(b.to(dt), dt)
+    m, n = col.numel(), row.numel()
+    x = torch.empty(n, dtype=dt, device=col.device)
+    _stream()
+    f = tikh_toeplitz_solve_z if dt == torch.complex128 else tikh_toeplitz_solve
+    _check(f(_ptr(col), _ptr(row), m, n, _ptr(b), float(lam), _ptr(x)), f.__name__)
+    return x
+
+
+def solve_normal(col, row, y, lam):
+    """x = (T^H T + lam^2 I)^{-1} y on the GPU (tikh_toeplitz_solve_normal[_z])."""
+    dt = _dtype_of(col, row, y)
+    col, row, y = _dev(col.to(dt), dt), _dev(row.to(dt), dt), _dev(y.to(dt), dt)
+    m, n = col.numel(), row.numel()
+    x = torch.empty(n, dtype=dt, device=col.device)
+    _stream()
+    f = tikh_toeplitz_solve_normal_z if dt == torch.complex128 else tikh_toeplitz_solve_normal
+    _check(f(_ptr(col), _ptr(row), m, n, _ptr(y), float(lam), _ptr(x)), f.__name__)
+    return x
+
+
+def _i64(vals):
+    arr = (ctypes.c_int64 * len(vals))(*[int(v) for v in vals])
+    return arr
+
+
+def solve_batched(ms, ns, col, row, lambdas, nrhs, b, complex_data=False, info=None, x=None):
+    """Packed batched solve (tikh_toeplitz_solve_batched).  col/row/b are packed
+    device tensors; lambdas is a host sequence of nprob*nlam values.  Returns
+    (x, info) tensors; asynchronous on the current stream."""
+    dt = torch.complex128 if complex_data else torch.float64
+    nprob = len(ms)
+    nlam = len(lambdas) // max(nprob, 1)
+    assert nlam * nprob == len(lambdas)
+    col, row, b = _dev(col, dt), _dev(row, dt), _dev(b, dt)
+    xn = sum(nlam * nrhs * int(n) for n in ns)
+    if x is None:
+        x = torch.empty(xn, dtype=dt, device=col.device)
+    if info is None:
+        info = torch.zeros(nprob * nlam * nrhs, dtype=torch.int32, device=col.device)
+    lam_arr = (ctypes.c_double * len(lambdas))(*[float(v) for v in lambdas])
+    _stream()
+    _check(tikh_toeplitz_solve_batched(nprob, _i64(ms), _i64(ns), _ptr(col), _ptr(row), nlam, lam_arr, int(nrhs),
+                                       _ptr(b), _ptr(x), _ptr(info), 1 if complex_data else 0),
+           "tikh_toeplitz_solve_batched")
+    return x, info
+
+
+def backward(col, row, b, lam, x, gx):
+    """Adjoint of solve: returns (g_col, g_row, g_b, g_lam) (tikh_toeplitz_solve_backward[_z])."""
+    dt = _dtype_of(col, row, b, x, gx)
+    col, row, b, x, gx = [_dev(t.to(dt), dt) for t in (col, row, b, x, gx)]
+    m, n = col.numel(), row.numel()
+    g_col = torch.empty(m, dtype=dt, device=col.device)
+    g_row = torch.empty(n, dtype=dt, device=col.device)
+    g_b = torch.empty(m, dtype=dt, device=col.device)
+    g_lam = torch.empty(1, dtype=torch.float64, device=col.device)
+    _stream()
+    f = tikh_toeplitz_solve_backward_z if dt == torch.complex128 else tikh_toeplitz_solve_backward
+    _check(f(_ptr(col), _ptr(row), m, n, _ptr(b), float(lam), _ptr(x), _ptr(gx), _ptr(g_col), _ptr(g_row),
+             _ptr(g_b), _ptr(g_lam)), f.__name__)
+    return g_col, g_row, g_b, g_lam[0]
+
+
+def backward_batched(ms, ns, col, row, lambdas, nrhs, b, x, gx, complex_data=False):
+    """Packed batched backward (tikh_toeplitz_solve_backward_batched); asynchronous."""
+    dt = torch.complex128 if complex_data else torch.float64
+    nprob = len(ms)
+    nlam = len(lambdas) // max(nprob, 1)
+    col, row, b, x, gx = [_dev(t, dt) for t in (col, row, b, x, gx)]
+    nsol = nprob * nlam * nrhs
+    g_col = torch.empty(sum(nlam * nrhs * int(m) for m in ms), dtype=dt, device=col.device)
+    g_row = torch.empty(sum(nlam * nrhs * int(n) for n in ns), dtype=dt, device=col.device)
+    g_b = torch.empty(sum(nlam * nrhs * int(m) for m in ms), dtype=dt, device=col.device)
+    g_lam = torch.empty(nsol, dtype=torch.float64, device=col.device)
+    info = torch.zeros(nsol, dtype=torch.int32, device=col.device)
+    lam_arr = (ctypes.c_double * len(lambdas))(*[float(v) for v in lambdas])
+    _stream()
+    _check(tikh_toeplitz_solve_backward_batched(nprob, _i64(ms), _i64(ns), _ptr(col), _ptr(row), nlam, lam_arr,
+                                                int(nrhs), _ptr(b), _ptr(x), _ptr(gx), _ptr(g_col), _ptr(g_row),
+                                                _ptr(g_b), _ptr(g_lam), _ptr(info), 1 if complex_data else 0),
+           "tikh_toeplitz_solve_backward_batched")
+    return g_col, g_row, g_b, g_lam, info

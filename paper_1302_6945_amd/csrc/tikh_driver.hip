@@ -1,0 +1,689 @@
+// Host driver and C ABI of the superfast Tikhonov-Toeplitz solver (gfx950).
+//
+// Paper: Turnes, Balcan, Romberg, "Superfast Tikhonov Regularization of
+// Toeplitz Systems".  The driver plans the extension (Alg. 2), builds the
+// interpolation data (Sec. 3-4) and walks the recursion tree of Alg. 1 in
+// order, launching one kernel per task for all solves of a bucket at once
+// (solves that share the extended size N share the tree).
+#include "../../include/tikh.h"
+#include "tikh_kernels.hip"
+
+#include <hip/hip_runtime.h>
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <vector>
+
+namespace tikh {
+
+#define HIPCHK(x)                                   \
+    do {                                            \
+        hipError_t e_ = (x);                        \
+        if (e_ != hipSuccess) {                     \
+            last_hip_error = e_;                    \
+            return TIKH_EHIP;                       \
+        }                                           \
+    } while (0)
+
+static hipError_t last_hip_error = hipSuccess;
+
+struct Ctx {
+    bool init = false;
+    hipStream_t stream = nullptr;
+    tikh_opts opts{};
+    tikh_stats stats{};
+    char* ws = nullptr;
+    size_t ws_size = 0;
+    std::map<int64_t, double2*> tw;      // twiddle tables by size Q
+    int64_t launches = 0;
+};
+static Ctx g;
+
+static void ensure_init() {
+    if (g.init) return;
+    g.opts.n_lim = 256;
+    g.opts.refine = 1;
+    g.init = true;
+}
+
+// ---------------------------------------------------------------- planning (Alg. 2)
+static bool smooth5(int64_t v) {
+    if (v <= 0) return false;
+    for (int f : {2, 3, 5}) while (v % f == 0) v /= f;
+    return v == 1;
+}
+
+// OptExtend adapted to the paired split of the l2 problem: two condition sets
+// per node, so a leaf of M nodes holds 2M conditions and must satisfy
+// 2M <= n_lim; M is forced even (the leaf is two cosets of M/2 nodes) and
+// rounded up to a 5-smooth value so that every FFT length is a product of
+// radices 2, 3, 4, 5.  Returns false if n_lim is unusable.
+static bool opt_extend(int64_t Nt, int nlim, int64_t* N, int64_t* M, int* p) {
+    int64_t m = Nt;
+    int pp = 0;
+    while (2 * m > nlim) { ++pp; m = (m + 1) / 2; }
+    if (m % 2) ++m;
+    while (!smooth5(m)) m += 2;
+    if (2 * m > nlim) return false;
+    *M = m; *p = pp; *N = ((int64_t)1 << pp) * m;
+    return true;
+}
+
+static int64_t smallest_divisor_geq(int64_t Q, int64_t need) {
+    int64_t best = Q;
+    for (int64_t a = 1; a * a <= Q; ++a) {
+        if (Q % a) continue;
+        int64_t b = Q / a;
+        if (a >= need && a < best) best = a;
+        if (b >= need && b < best) best = b;
+    }
+    return best;
+}
+
+static bool make_plan(int64_t N, int64_t M, int p, Plan* pl) {
+    memset(pl, 0, sizeof(*pl));
+    pl->N = N; pl->M = M; pl->p = p; pl->K = (int)(2 * M);
+    pl->Q = 8 * N;
+    // Degree capacity of a basis built from the cnt conditions of a depth-d
+    // subtree: every condition raises the largest degree by at most one, so
+    // deg <= cnt; cnt itself is reached only if one column takes every pivot,
+    // which the degree bookkeeping reports as info = 2.  cap = cnt - 1 makes the
+    // product length of the parent exactly cnt_parent (a divisor of Q).
+    for (int d = 0; d <= p; ++d) {
+        int64_t cnt = (2 * N) >> d;
+        pl->cap[d] = (p == 0) ? cnt : cnt - 1;
+    }
+    for (int d = 0; d < p; ++d) {
+        int64_t need = 2 * pl->cap[d + 1] + 1;
+        pl->P[d] = smallest_divisor_geq(pl->Q, need);
+        if (!smooth5(pl->P[d])) return false;
+    }
+    return true;
+}
+
+static bool fft_plan(int64_t L, FftPlanDev* f) {
+    if (L < 1 || L > FFT_LDS_MAX) return false;
+    f->L = (int)L; f->nst = 0;
+    int64_t v = L;
+    while (v % 4 == 0) { f->radix[f->nst++] = 4; v /= 4; }
+    while (v % 2 == 0) { f->radix[f->nst++] = 2; v /= 2; }
+    while (v % 3 == 0) { f->radix[f->nst++] = 3; v /= 3; }
+    while (v % 5 == 0) { f->radix[f->nst++] = 5; v /= 5; }
+    return v == 1;
+}
+
+static double2* twiddles(int64_t Q) {
+    auto it = g.tw.find(Q);
+    if (it != g.tw.end()) return it->second;
+    std::vector<double2> h(Q);
+    const long double pi2 = 6.283185307179586476925286766559005768L;
+    for (int64_t q = 0; q < Q; ++q) {
+        long double a = pi2 * (long double)q / (long double)Q;
+        h[q] = make_double2((double)cosl(a), (double)sinl(a));
+    }
+    double2* d = nullptr;
+    if (hipMalloc(&d, sizeof(double2) * Q) != hipSuccess) return nullptr;
+    if (hipMemcpy(d, h.data(), sizeof(double2) * Q, hipMemcpyHostToDevice) != hipSuccess) { hipFree(d); return nullptr; }
+    g.tw[Q] = d;
+    return d;
+}
+
+// ---------------------------------------------------------------- workspace layout
+struct Layout {
+    int64_t nmax;                    // max n over the chunk
+    int64_t mmax;
+    // per-solve strides in double2 units
+    int64_t sN, sn, sphi, srec, sV, sF, sscr;
+    int64_t sslot[40];
+    int64_t Lmax, Pmax, nF;
+    size_t per_solve_bytes;
+};
+
+static void make_layout(const Plan& pl, int64_t mmax, int64_t nmax, Layout* L) {
+    L->nmax = nmax; L->mmax = mmax;
+    L->sN = pl.N;
+    L->sn = std::max(mmax, nmax);
+    L->sphi = 10 * pl.N;
+    L->srec = (int64_t)pl.K * (int64_t)(sizeof(LeafRec) / sizeof(double2));
+    L->Lmax = pl.p >= 1 ? pl.N / 4 : 1;
+    L->sV = 40 * L->Lmax;
+    int64_t fmax = 1;
+    for (int d = 0; d < pl.p; ++d) fmax = std::max(fmax, (d == 0 ? 5 : 20) * pl.P[d]);
+    L->sF = fmax;
+    L->sscr = std::max(std::max(L->sV, L->sF), pl.N);
+    size_t tot = 0;
+    tot += 4 * L->sN + 4 * L->sn + L->sphi + L->srec + L->sV + 2 * L->sF + L->sscr;
+    for (int d = 0; d <= pl.p; ++d) {
+        L->sslot[d] = 20 * (pl.cap[d] + 1);
+        tot += 2 * L->sslot[d];
+    }
+    L->per_solve_bytes = tot * sizeof(double2) + 2 * (pl.p + 1) * sizeof(SlotMeta) + sizeof(SolveState) +
+                         sizeof(SolveDesc) + sizeof(double) + 64;
+}
+
+struct Bufs {
+    SolveDesc* sd;
+    SolveState* st;
+    double* rms;
+    double2 *chat, *bA, *bB, *bC;
+    double2 *yv, *xacc, *t1, *t2;
+    double2* phi;
+    LeafRec* rec;
+    double2* V;
+    double2 *FL, *FR, *FO, *scr;
+    double2* slotS[40];
+    double2* slotT[40];
+    SlotMeta* metaS[40];
+    SlotMeta* metaT[40];
+    int* elist;                      // device entry lists
+};
+
+static int ensure_ws(size_t bytes) {
+    if (bytes <= g.ws_size) return TIKH_OK;
+    if (g.ws) { hipStreamSynchronize(g.stream); hipFree(g.ws); g.ws = nullptr; g.ws_size = 0; }
+    if (hipMalloc(&g.ws, bytes) != hipSuccess) { g.ws = nullptr; return TIKH_ENOMEM; }
+    g.ws_size = bytes;
+    return TIKH_OK;
+}
+
+static char* carve(char*& p, size_t bytes) {
+    char* r = p;
+    p += (bytes + 255) & ~(size_t)255;
+    return r;
+}
+
+// entry lists (fixed): all 20 entries; left row 0 = {0..4}; right column 5 = {4, 9, 14, 19}; x entry = {4}
+static const int h_elist[20 + 5 + 4 + 1] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19,
+                                           0, 1, 2, 3, 4, 4, 9, 14, 19, 4};
+enum { EL_ALL = 0, EL_ROW0 = 20, EL_COL5 = 25, EL_X = 29 };
+
+static int carve_bufs(const Plan& pl, const Layout& L, int64_t S, Bufs* b) {
+    size_t need = 0;
+    need += (size_t)S * L.per_solve_bytes + 64 * 1024 + 256 * 64;
+    int rc = ensure_ws(need);
+    if (rc) return rc;
+    char* p = g.ws;
+    b->sd = (SolveDesc*)carve(p, sizeof(SolveDesc) * S);
+    b->st = (SolveState*)carve(p, sizeof(SolveState) * S);
+    b->rms = (double*)carve(p, sizeof(double) * S);
+    b->elist = (int*)carve(p, sizeof(h_elist));
+    auto cv = [&](int64_t per) { return (double2*)carve(p, sizeof(double2) * per * S); };
+    b->chat = cv(L.sN); b->bA = cv(L.sN); b->bB = cv(L.sN); b->bC = cv(L.sN);
+    b->yv = cv(L.sn); b->xacc = cv(L.sn); b->t1 = cv(L.sn); b->t2 = cv(L.sn);
+    b->phi = cv(L.sphi);
+    b->rec = (LeafRec*)cv(L.srec);
+    b->V = cv(L.sV);
+    b->FL = cv(L.sF); b->FR = cv(L.sF); b->FO = nullptr; b->scr = cv(L.sscr);
+    for (int d = 0; d <= pl.p; ++d) {
+        b->slotS[d] = cv(L.sslot[d]);
+        b->slotT[d] = cv(L.sslot[d]);
+        b->metaS[d] = (SlotMeta*)carve(p, sizeof(SlotMeta) * S);
+        b->metaT[d] = (SlotMeta*)carve(p, sizeof(SlotMeta) * S);
+    }
+    if ((size_t)(p - g.ws) > g.ws_size) return TIKH_ENOMEM;
+    return TIKH_OK;
+}
+
+// ---------------------------------------------------------------- launch helpers
+static inline dim3 grid1(int64_t work, int64_t S, int bs = 256) {
+    int64_t gx = (work + bs - 1) / bs;
+    gx = std::max<int64_t>(1, std::min<int64_t>(gx, 4096));
+    return dim3((unsigned)gx, (unsigned)S, 1);
+}
+
+// In-place FFT of `nlines` contiguous lines of length Lf per solve
+// (line stride Lf, solve stride sstride), direction `sign`, scratch for the
+// four-step reordering.
+static int fft_lines(double2* data, int64_t S, int64_t sstride, int64_t nlines, int64_t Lf, int sign,
+                     const double2* tw, int64_t Q, double2* scratch, int64_t scr_stride) {
+    if (Lf == 1) return TIKH_OK;
+    FftArgs a{};
+    a.data = data; a.solve_stride = sstride; a.sign = sign; a.scale = 1.0; a.tw = tw; a.Q = Q;
+    if (Lf <= FFT_LDS_MAX) {
+        if (!fft_plan(Lf, &a.pl)) return TIKH_EINVAL;
+        a.line_stride = Lf; a.elem_stride = 1; a.nlines = nlines; a.post_L = 0;
+        a.lines_inner = nlines; a.outer_stride = 0;
+        a.lpw = (int)std::max<int64_t>(1, std::min<int64_t>(FFT_LDS_MAX / Lf, 64));
+        dim3 gr((unsigned)((nlines + a.lpw - 1) / a.lpw), (unsigned)S);
+        hipLaunchKernelGGL(k_fft, gr, dim3(FFT_THREADS), 0, g.stream, a);
+        g.launches++;
+        return TIKH_OK;
+    }
+    // four-step: Lf = L1 * L2
+    int64_t L1 = 0;
+    for (int64_t c = 1; c <= FFT_LDS_MAX; ++c)
+        if (Lf % c == 0 && Lf / c <= FFT_LDS_MAX && smooth5(c)) {
+            if (L1 == 0 || std::llabs((long long)(c * c - Lf)) < std::llabs((long long)(L1 * L1 - Lf))) L1 = c;
+        }
+    if (L1 == 0) return TIKH_EINVAL;
+    int64_t L2 = Lf / L1;
+    // pass 1: for each line and each k2 < L2, transform over k1 (stride L2), twiddle w_Lf^{j1 k2}
+    FftArgs p1 = a;
+    if (!fft_plan(L1, &p1.pl)) return TIKH_EINVAL;
+    p1.lines_inner = L2; p1.line_stride = 1; p1.outer_stride = Lf; p1.elem_stride = L2;
+    p1.nlines = nlines * L2; p1.post_L = Lf;
+    p1.lpw = (int)std::max<int64_t>(1, std::min<int64_t>(FFT_LDS_MAX / L1, 16));
+    hipLaunchKernelGGL(k_fft, dim3((unsigned)((p1.nlines + p1.lpw - 1) / p1.lpw), (unsigned)S), dim3(FFT_THREADS), 0,
+                       g.stream, p1);
+    // pass 2: for each line and each j1 < L1, transform the contiguous row of length L2
+    FftArgs p2 = a;
+    if (!fft_plan(L2, &p2.pl)) return TIKH_EINVAL;
+    p2.lines_inner = L1; p2.line_stride = L2; p2.outer_stride = Lf; p2.elem_stride = 1;
+    p2.nlines = nlines * L1; p2.post_L = 0;
+    p2.lpw = (int)std::max<int64_t>(1, std::min<int64_t>(FFT_LDS_MAX / L2, 64));
+    hipLaunchKernelGGL(k_fft, dim3((unsigned)((p2.nlines + p2.lpw - 1) / p2.lpw), (unsigned)S), dim3(FFT_THREADS), 0,
+                       g.stream, p2);
+    hipLaunchKernelGGL(k_fourstep_unscramble, grid1(nlines * Lf, S), dim3(256), 0, g.stream, data, scratch, sstride,
+                       scr_stride, Lf, nlines, L1, L2);
+    hipLaunchKernelGGL(k_copy, grid1(nlines * Lf, S), dim3(256), 0, g.stream, scratch, data, scr_stride, sstride,
+                       nlines * Lf);
+    g.launches += 4;
+    return TIKH_OK;
+}
+
+// ---------------------------------------------------------------- recursion (Alg. 1)
+static int run_leaf(const Plan& pl, const Layout& L, const Bufs& b, int64_t S, int t, double2* dst, SlotMeta* dmeta,
+                    int64_t dcap, const double2* tw) {
+    LeafArgs la{};
+    la.sd = b.sd; la.st = b.st; la.phi = b.phi; la.phi_stride = L.sphi; la.rec = b.rec;
+    la.rec_stride = pl.K; la.N = pl.N; la.M = pl.M; la.p = pl.p; la.K = pl.K; la.leaf = t; la.tw = tw; la.Q = pl.Q;
+    if (pl.K <= 64) hipLaunchKernelGGL(k_leaf_loop<1>, dim3((unsigned)S), dim3(64), 0, g.stream, la);
+    else if (pl.K <= 128) hipLaunchKernelGGL(k_leaf_loop<2>, dim3((unsigned)S), dim3(64), 0, g.stream, la);
+    else if (pl.K <= 192) hipLaunchKernelGGL(k_leaf_loop<3>, dim3((unsigned)S), dim3(64), 0, g.stream, la);
+    else hipLaunchKernelGGL(k_leaf_loop<4>, dim3((unsigned)S), dim3(64), 0, g.stream, la);
+    BuildArgs ba{};
+    ba.st = b.st; ba.rec = b.rec; ba.rec_stride = pl.K; ba.out = dst; ba.out_stride = 20 * (dcap + 1);
+    ba.cap = dcap; ba.meta = dmeta; ba.K = pl.K;
+    int slots = (int)((std::min<int64_t>(dcap, pl.K) + 1 + 63) / 64);
+    if (slots <= 1) hipLaunchKernelGGL(k_leaf_build<1>, dim3((unsigned)S), dim3(256), 0, g.stream, ba);
+    else if (slots <= 2) hipLaunchKernelGGL(k_leaf_build<2>, dim3((unsigned)S), dim3(256), 0, g.stream, ba);
+    else if (slots <= 3) hipLaunchKernelGGL(k_leaf_build<3>, dim3((unsigned)S), dim3(256), 0, g.stream, ba);
+    else if (slots <= 4) hipLaunchKernelGGL(k_leaf_build<4>, dim3((unsigned)S), dim3(256), 0, g.stream, ba);
+    else hipLaunchKernelGGL(k_leaf_build<5>, dim3((unsigned)S), dim3(256), 0, g.stream, ba);
+    g.launches += 2;
+    return TIKH_OK;
+}
+
+// Evaluate the completed left child (depth d, index idx) at the nodes of its
+// right sibling and update the sibling subtree's residual data.
+static int run_eval(const Plan& pl, const Layout& L, const Bufs& b, int64_t S, int d, int64_t idx, const double2* tw) {
+    const int64_t ridx = idx + 1;
+    const int64_t oR = 2 * (int64_t)(d == 0 ? 0 : (int)(__builtin_bitreverse32((uint32_t)ridx) >> (32 - d)));
+    const int64_t Lc = pl.N >> (d + 1);
+    const int64_t cp1 = pl.cap[d] + 1;
+    hipLaunchKernelGGL(k_twist_fold, dim3((unsigned)std::min<int64_t>((Lc + 255) / 256, 1024), 40, (unsigned)S),
+                       dim3(256), 0, g.stream, b.slotS[d], L.sslot[d], cp1, b.metaS[d], b.V, L.sV, Lc, oR, pl.N, tw,
+                       pl.Q);
+    g.launches++;
+    int rc = fft_lines(b.V, S, L.sV, 40, Lc, +1, tw, pl.Q, b.scr, L.sscr);
+    if (rc) return rc;
+    const int64_t nleaves = (int64_t)1 << (pl.p - d);
+    const int64_t t0 = ridx << (pl.p - d);
+    hipLaunchKernelGGL(k_eval_apply, grid1(nleaves * pl.K, S), dim3(256), 0, g.stream, b.phi, L.sphi, b.V, L.sV, Lc,
+                       oR, d, t0, nleaves, pl.N, pl.M, pl.p, pl.K);
+    g.launches++;
+    return TIKH_OK;
+}
+
+// B_parent = B_L B_R for the parent at depth dp (children at depth dp+1).
+static int run_product(const Plan& pl, const Layout& L, const Bufs& b, int64_t S, int dp, double2* dst,
+                       SlotMeta* dmeta, int64_t dcap, const double2* tw) {
+    const int dc = dp + 1;
+    const int64_t P = pl.P[dp];
+    const int64_t cp1 = pl.cap[dc] + 1;
+    const bool root = (dp == 0);
+    const int nL = root ? 5 : 20, nR = root ? 4 : 20, nO = root ? 1 : 20;
+    const int* eL = b.elist + (root ? EL_ROW0 : EL_ALL);
+    const int* eR = b.elist + (root ? EL_COL5 : EL_ALL);
+    const int* eO = b.elist + (root ? EL_X : EL_ALL);
+    hipLaunchKernelGGL(k_prod_meta, dim3((unsigned)((S + 63) / 64)), dim3(64), 0, g.stream, b.metaS[dc], b.metaT[dc],
+                       dmeta, b.st, dcap, (int)S);
+    unsigned gx = (unsigned)std::min<int64_t>((P + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_prod_load, dim3(gx, nL, (unsigned)S), dim3(256), 0, g.stream, b.slotS[dc], L.sslot[dc], cp1,
+                       b.metaS[dc], eL, b.FL, L.sF, P);
+    hipLaunchKernelGGL(k_prod_load, dim3(gx, nR, (unsigned)S), dim3(256), 0, g.stream, b.slotT[dc], L.sslot[dc], cp1,
+                       b.metaT[dc], eR, b.FR, L.sF, P);
+    g.launches += 3;
+    int rc = fft_lines(b.FL, S, L.sF, nL, P, -1, tw, pl.Q, b.scr, L.sscr);
+    if (rc) return rc;
+    rc = fft_lines(b.FR, S, L.sF, nR, P, -1, tw, pl.Q, b.scr, L.sscr);
+    if (rc) return rc;
+    // the pointwise product reads every input of a frequency before writing, so it runs in place over FL
+    hipLaunchKernelGGL(k_prod_mul, grid1(P, S), dim3(256), 0, g.stream, b.FL, b.FR, b.FL, L.sF, P, root ? 1 : 0);
+    g.launches++;
+    rc = fft_lines(b.FL, S, L.sF, nO, P, +1, tw, pl.Q, b.scr, L.sscr);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_prod_store, dim3(gx, nO, (unsigned)S), dim3(256), 0, g.stream, b.FL, L.sF, P, dst,
+                       20 * (dcap + 1), dcap + 1, dmeta, nO, eO);
+    g.launches++;
+    return TIKH_OK;
+}
+
+static int run_recursion(const Plan& pl, const Layout& L, const Bufs& b, int64_t S, const double2* tw) {
+    const int p = pl.p;
+    const int64_t nleaf = (int64_t)1 << p;
+    for (int64_t t = 0; t < nleaf; ++t) {
+        double2* dst;
+        SlotMeta* dm;
+        if (p == 0) { dst = b.slotT[0]; dm = b.metaT[0]; }
+        else if (t & 1) { dst = b.slotT[p]; dm = b.metaT[p]; }
+        else { dst = b.slotS[p]; dm = b.metaS[p]; }
+        int rc = run_leaf(pl, L, b, S, (int)t, dst, dm, pl.cap[p], tw);
+        if (rc) return rc;
+        int d = p;
+        int64_t idx = t;
+        while (d > 0) {
+            if ((idx & 1) == 0) {
+                rc = run_eval(pl, L, b, S, d, idx, tw);
+                if (rc) return rc;
+                break;
+            }
+            const int dp = d - 1;
+            const int64_t pidx = idx >> 1;
+            double2* pdst;
+            SlotMeta* pm;
+            if (dp == 0 || (pidx & 1)) { pdst = b.slotT[dp]; pm = b.metaT[dp]; }
+            else { pdst = b.slotS[dp]; pm = b.metaS[dp]; }
+            rc = run_product(pl, L, b, S, dp, pdst, pm, pl.cap[dp], tw);
+            if (rc) return rc;
+            d = dp;
+            idx = pidx;
+        }
+    }
+    return TIKH_OK;
+}
+
+// circulant products on length-N buffers
+static void circ_apply(const Plan& pl, const Layout& L, const Bufs& b, int64_t S, double2* buf, int mode,
+                       const double2* tw) {
+    fft_lines(buf, S, L.sN, 1, pl.N, +1, tw, pl.Q, b.scr, L.sscr);
+    hipLaunchKernelGGL(k_mul_symbol, grid1(pl.N, S), dim3(256), 0, g.stream, b.sd, b.chat, buf, pl.N, L.sN, mode, tw,
+                       pl.Q);
+    fft_lines(buf, S, L.sN, 1, pl.N, -1, tw, pl.Q, b.scr, L.sscr);
+    g.launches++;
+}
+
+// One chunk of solves sharing the plan.
+static int run_chunk(const Plan& pl, const std::vector<SolveDesc>& sds, int32_t* info) {
+    const int64_t S = (int64_t)sds.size();
+    int64_t mmax = 1, nmax = 1;
+    for (auto& d : sds) { mmax = std::max(mmax, d.m); nmax = std::max(nmax, d.n); }
+    Layout L;
+    make_layout(pl, mmax, nmax, &L);
+    Bufs b;
+    int rc = carve_bufs(pl, L, S, &b);
+    if (rc) return rc;
+    const double2* tw = twiddles(pl.Q);
+    if (!tw) return TIKH_ENOMEM;
+    HIPCHK(hipMemcpyAsync(b.sd, sds.data(), sizeof(SolveDesc) * S, hipMemcpyHostToDevice, g.stream));
+    HIPCHK(hipMemcpyAsync(b.elist, h_elist, sizeof(h_elist), hipMemcpyHostToDevice, g.stream));
+    const int64_t N = pl.N;
+    const double invN = 1.0 / (double)N;
+    hipLaunchKernelGGL(k_init_state, dim3((unsigned)((S + 63) / 64)), dim3(64), 0, g.stream, b.sd, b.st, (int)S, 0);
+    // extension (eq. (circexp)) and its symbol c^ = F c_T (eq. (circdiag))
+    hipLaunchKernelGGL(k_gen_rms, dim3((unsigned)S), dim3(256), 0, g.stream, b.sd, b.rms);
+    hipLaunchKernelGGL(k_build_ct, grid1(N, S), dim3(256), 0, g.stream, b.sd, b.rms, b.chat, N, L.sN);
+    g.launches += 3;
+    rc = fft_lines(b.chat, S, L.sN, 1, N, +1, tw, pl.Q, b.scr, L.sscr);
+    if (rc) return rc;
+    // right-hand side y = T^H b as the bottom n entries of C_k(T^H) [b; 0]
+    const bool normal = sds[0].mode == 1;
+    if (!normal) {
+        hipLaunchKernelGGL(k_load_pad, grid1(N, S), dim3(256), 0, g.stream, b.sd, 0, (const double2*)nullptr, 0, 0,
+                           0, 1.0, b.bB, N, L.sN);
+        circ_apply(pl, L, b, S, b.bB, 1, tw);
+        hipLaunchKernelGGL(k_take_tail, grid1(nmax, S), dim3(256), 0, g.stream, b.sd, b.bB, N, L.sN, 1, invN, b.yv,
+                           L.sn);
+    } else {
+        hipLaunchKernelGGL(k_load_pad, grid1(nmax, S), dim3(256), 0, g.stream, b.sd, 0, (const double2*)nullptr, 0, 1,
+                           0, 1.0, b.yv, nmax, L.sn);
+    }
+    g.launches += 2;
+    const int steps = 1 + std::max(0, std::min(4, (int)g.opts.refine));
+    for (int it = 0; it < steps; ++it) {
+        const double2* rhs = b.yv;
+        if (it > 0) {
+            // residual of the normal equations, r = y - (T^H T + lam^2) x (Sec. 7.2: iterative refinement)
+            hipLaunchKernelGGL(k_load_pad, grid1(N, S), dim3(256), 0, g.stream, b.sd, 0, b.xacc, L.sn, 1, 0, 1.0,
+                               b.bB, N, L.sN);
+            circ_apply(pl, L, b, S, b.bB, 0, tw);
+            hipLaunchKernelGGL(k_take_tail, grid1(mmax, S), dim3(256), 0, g.stream, b.sd, b.bB, N, L.sN, 0, invN,
+                               b.t1, L.sn);
+            hipLaunchKernelGGL(k_load_pad, grid1(N, S), dim3(256), 0, g.stream, b.sd, 0, b.t1, L.sn, 0, 0, 1.0, b.bB,
+                               N, L.sN);
+            circ_apply(pl, L, b, S, b.bB, 1, tw);
+            hipLaunchKernelGGL(k_take_tail, grid1(nmax, S), dim3(256), 0, g.stream, b.sd, b.bB, N, L.sN, 1, invN,
+                               b.t2, L.sn);
+            hipLaunchKernelGGL(k_normal_residual, grid1(nmax, S), dim3(256), 0, g.stream, b.sd, b.yv, b.t2, b.xacc,
+                               b.t1, L.sn);
+            hipLaunchKernelGGL(k_init_state, dim3((unsigned)((S + 63) / 64)), dim3(64), 0, g.stream, b.sd, b.st,
+                               (int)S, 1);
+            g.launches += 6;
+            rhs = b.t1;
+        }
+        hipLaunchKernelGGL(k_load_pad, grid1(N, S), dim3(256), 0, g.stream, b.sd, 0, rhs, L.sn, 1, 0, 1.0, b.bA, N,
+                           L.sN);
+        g.launches++;
+        rc = fft_lines(b.bA, S, L.sN, 1, N, +1, tw, pl.Q, b.scr, L.sscr);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_assemble, grid1(2 * N, S), dim3(256), 0, g.stream, b.sd, b.chat, b.bA, L.sN, b.phi,
+                           L.sphi, N, pl.M, pl.p, pl.K, tw, pl.Q);
+        g.launches++;
+        rc = run_recursion(pl, L, b, S, tw);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_extract, grid1(nmax, S), dim3(256), 0, g.stream, b.sd, b.st, b.slotT[0], L.sslot[0],
+                           pl.cap[0] + 1, b.metaT[0], b.xacc, L.sn, it > 0 ? 1 : 0);
+        g.launches++;
+    }
+    hipLaunchKernelGGL(k_store_x, grid1(nmax, S), dim3(256), 0, g.stream, b.sd, b.xacc, L.sn, b.st, info);
+    g.launches++;
+    HIPCHK(hipGetLastError());
+    return TIKH_OK;
+}
+
+// Group solves by plan and run them in chunks that fit the workspace budget.
+static int run_solves(std::vector<SolveDesc>& sds, int32_t* info) {
+    ensure_init();
+    g.launches = 0;
+    if (sds.empty()) return TIKH_OK;
+    std::map<int64_t, std::vector<int64_t>> buckets;     // N -> solve indices
+    std::map<int64_t, std::pair<int64_t, int>> shapes;   // N -> (M, p)
+    for (size_t i = 0; i < sds.size(); ++i) {
+        int64_t N, M;
+        int p;
+        if (!opt_extend(sds[i].m + sds[i].n - 1, g.opts.n_lim, &N, &M, &p)) return TIKH_EINVAL;
+        sds[i].k = N - (sds[i].m + sds[i].n - 1);
+        buckets[N].push_back((int64_t)i);
+        shapes[N] = {M, p};
+    }
+    size_t freeb = 0, totb = 0;
+    hipMemGetInfo(&freeb, &totb);
+    size_t budget = std::max<size_t>((size_t)1 << 30, (size_t)((double)(freeb + g.ws_size) * 0.6));
+    for (auto& kv : buckets) {
+        Plan pl;
+        if (!make_plan(kv.first, shapes[kv.first].first, shapes[kv.first].second, &pl)) return TIKH_EINVAL;
+        std::vector<int64_t>& idx = kv.second;
+        int64_t mmax = 1, nmax = 1;
+        for (int64_t i : idx) { mmax = std::max(mmax, sds[i].m); nmax = std::max(nmax, sds[i].n); }
+        Layout L;
+        make_layout(pl, mmax, nmax, &L);
+        int64_t chunk = std::max<int64_t>(1, (int64_t)(budget / L.per_solve_bytes));
+        chunk = std::min<int64_t>(chunk, 65535);
+        for (size_t c0 = 0; c0 < idx.size(); c0 += (size_t)chunk) {
+            size_t c1 = std::min(idx.size(), c0 + (size_t)chunk);
+            std::vector<SolveDesc> part;
+            for (size_t u = c0; u < c1; ++u) part.push_back(sds[idx[u]]);
+            // info is per original solve: run the chunk with a temporary device array when not contiguous
+            int32_t* dinfo = nullptr;
+            bool contiguous = true;
+            for (size_t u = c0; u < c1; ++u) if (idx[u] != idx[c0] + (int64_t)(u - c0)) contiguous = false;
+            if (info && contiguous) dinfo = info + idx[c0];
+            int rc;
+            if (info && !contiguous) {
+                int32_t* tmp = nullptr;
+                HIPCHK(hipMallocAsync((void**)&tmp, sizeof(int32_t) * part.size(), g.stream));
+                rc = run_chunk(pl, part, tmp);
+                if (rc) { hipFreeAsync(tmp, g.stream); return rc; }
+                std::vector<int32_t> h(part.size());
+                HIPCHK(hipMemcpyAsync(h.data(), tmp, sizeof(int32_t) * part.size(), hipMemcpyDeviceToHost, g.stream));
+                HIPCHK(hipStreamSynchronize(g.stream));
+                for (size_t u = c0; u < c1; ++u)
+                    HIPCHK(hipMemcpyAsync(info + idx[u], &h[u - c0], sizeof(int32_t), hipMemcpyHostToDevice, g.stream));
+                HIPCHK(hipStreamSynchronize(g.stream));
+                hipFreeAsync(tmp, g.stream);
+            } else {
+                rc = run_chunk(pl, part, dinfo);
+                if (rc) return rc;
+            }
+            g.stats.N = pl.N;
+            g.stats.k = part[0].k;
+            g.stats.depth = pl.p;
+            g.stats.leaf_nodes = (int32_t)pl.M;
+        }
+    }
+    g.stats.solves = (int64_t)sds.size();
+    g.stats.launches = g.launches;
+    return TIKH_OK;
+}
+
+static bool bad_lambda(double lam) { return !(lam > 0.0) || !std::isfinite(lam); }
+
+static int solve_single(const void* col, const void* row, int64_t m, int64_t n, const void* rhs, double lambda,
+                        void* x, int cplx, int mode) {
+    ensure_init();
+    if (!col || !row || !rhs || !x || m < 1 || n < 1 || bad_lambda(lambda)) return TIKH_EINVAL;
+    if (m + n > ((int64_t)1 << 30)) return TIKH_EINVAL;
+    std::vector<SolveDesc> sds(1);
+    SolveDesc& d = sds[0];
+    d.col = col; d.row = row; d.rhs = rhs; d.x = x; d.m = m; d.n = n; d.lam = lambda; d.cplx = cplx; d.mode = mode;
+    int32_t* dinfo = nullptr;
+    HIPCHK(hipMallocAsync((void**)&dinfo, sizeof(int32_t), g.stream));
+    int rc = run_solves(sds, dinfo);
+    int32_t hinfo = 0;
+    if (rc == TIKH_OK) {
+        HIPCHK(hipMemcpyAsync(&hinfo, dinfo, sizeof(int32_t), hipMemcpyDeviceToHost, g.stream));
+    }
+    HIPCHK(hipStreamSynchronize(g.stream));
+    hipFreeAsync(dinfo, g.stream);
+    HIPCHK(hipStreamSynchronize(g.stream));
+    if (rc) return rc;
+    return hinfo ? TIKH_ENUMERIC : TIKH_OK;
+}
+
+}  // namespace tikh
+
+using namespace tikh;
+
+extern "C" {
+
+int tikh_init(void) { ensure_init(); return TIKH_OK; }
+
+int tikh_plan_info(int64_t m, int64_t n, int32_t n_lim, int64_t* N, int64_t* M, int32_t* depth, int64_t* k) {
+    if (m < 1 || n < 1 || n_lim < 4 || !N || !M || !depth || !k) return TIKH_EINVAL;
+    int64_t NN, MM;
+    int pp;
+    if (!opt_extend(m + n - 1, n_lim, &NN, &MM, &pp)) return TIKH_EINVAL;
+    *N = NN; *M = MM; *depth = pp; *k = NN - (m + n - 1);
+    return TIKH_OK;
+}
+
+int tikh_release(void) {
+    if (g.ws) { hipStreamSynchronize(g.stream); hipFree(g.ws); g.ws = nullptr; g.ws_size = 0; }
+    for (auto& kv : g.tw) hipFree(kv.second);
+    g.tw.clear();
+    return TIKH_OK;
+}
+
+int tikh_set_stream(void* s) { ensure_init(); g.stream = (hipStream_t)s; return TIKH_OK; }
+
+int tikh_set_options(const tikh_opts* o) {
+    ensure_init();
+    if (!o) return TIKH_EINVAL;
+    if (o->n_lim < 64 || o->n_lim > LEAF_MAX || o->refine < 0 || o->refine > 4) return TIKH_EINVAL;
+    g.opts = *o;
+    return TIKH_OK;
+}
+
+int tikh_get_options(tikh_opts* o) { ensure_init(); if (!o) return TIKH_EINVAL; *o = g.opts; return TIKH_OK; }
+
+int tikh_get_stats(tikh_stats* s) { ensure_init(); if (!s) return TIKH_EINVAL; *s = g.stats; return TIKH_OK; }
+
+const char* tikh_strerror(int code) {
+    switch (code) {
+        case TIKH_OK: return "ok";
+        case TIKH_EINVAL: return "invalid argument";
+        case TIKH_ENOMEM: return "device allocation failed";
+        case TIKH_EHIP: return hipGetErrorString(last_hip_error);
+        case TIKH_ENUMERIC: return "numerical breakdown reported by a solve (info != 0)";
+        default: return "unknown error";
+    }
+}
+
+int tikh_toeplitz_solve(const double* col, const double* row, int64_t m, int64_t n, const double* b, double lambda,
+                        double* x) {
+    return solve_single(col, row, m, n, b, lambda, x, 0, 0);
+}
+
+int tikh_toeplitz_solve_z(const tikh_c64* col, const tikh_c64* row, int64_t m, int64_t n, const tikh_c64* b,
+                          double lambda, tikh_c64* x) {
+    return solve_single(col, row, m, n, b, lambda, x, 1, 0);
+}
+
+int tikh_toeplitz_solve_normal(const double* col, const double* row, int64_t m, int64_t n, const double* y,
+                               double lambda, double* x) {
+    return solve_single(col, row, m, n, y, lambda, x, 0, 1);
+}
+
+int tikh_toeplitz_solve_normal_z(const tikh_c64* col, const tikh_c64* row, int64_t m, int64_t n, const tikh_c64* y,
+                                 double lambda, tikh_c64* x) {
+    return solve_single(col, row, m, n, y, lambda, x, 1, 1);
+}
+
+int tikh_toeplitz_solve_batched(int64_t nprob, const int64_t* m, const int64_t* n, const void* col, const void* row,
+                                int64_t nlam, const double* lambdas, int64_t nrhs, const void* b, void* x,
+                                int32_t* info, int complex_data) {
+    ensure_init();
+    if (nprob < 0 || nlam < 1 || nrhs < 1 || !m || !n || !lambdas) return TIKH_EINVAL;
+    if (nprob == 0) return TIKH_OK;
+    if (!col || !row || !b || !x) return TIKH_EINVAL;
+    const size_t es = complex_data ? sizeof(double2) : sizeof(double);
+    std::vector<SolveDesc> sds;
+    sds.reserve((size_t)(nprob * nlam * nrhs));
+    int64_t co = 0, ro = 0, bo = 0, xo = 0;
+    for (int64_t p = 0; p < nprob; ++p) {
+        if (m[p] < 1 || n[p] < 1) return TIKH_EINVAL;
+        for (int64_t l = 0; l < nlam; ++l) {
+            double lam = lambdas[p * nlam + l];
+            if (bad_lambda(lam)) return TIKH_EINVAL;
+            for (int64_t r = 0; r < nrhs; ++r) {
+                SolveDesc d{};
+                d.col = (const char*)col + es * co;
+                d.row = (const char*)row + es * ro;
+                d.rhs = (const char*)b + es * (bo + r * m[p]);
+                d.x = (char*)x + es * (xo + (l * nrhs + r) * n[p]);
+                d.m = m[p]; d.n = n[p]; d.lam = lam; d.cplx = complex_data ? 1 : 0; d.mode = 0;
+                sds.push_back(d);
+            }
+        }
+        co += m[p]; ro += n[p]; bo += nrhs * m[p]; xo += nlam * nrhs * n[p];
+    }
+    return run_solves(sds, info);
+}
+
+int tikh_toeplitz_solve_backward(const double*, const double*, int64_t, int64_t, const double*, double,
+                                 const double*, const double*, double*, double*, double*, double*) {
+    return TIKH_EINVAL;
+}
+int tikh_toeplitz_solve_backward_z(const tikh_c64*, const tikh_c64*, int64_t, int64_t, const tikh_c64*, double,
+                                   const tikh_c64*, const tikh_c64*, tikh_c64*, tikh_c64*, tikh_c64*, double*) {
+    return TIKH_EINVAL;
+}
+int tikh_toeplitz_solve_backward_batched(int64_t, const int64_t*, const int64_t*, const void*, const void*, int64_t,
+                                         const double*, int64_t, const void*, const void*, const void*, void*, void*,
+                                         void*, double*, int32_t*, int) {
+    return TIKH_EINVAL;
+}
+
+}  // extern "C"

@@ -1,0 +1,61 @@
+// Internal declarations shared by the device kernels and the host driver of
+// the superfast Tikhonov-Toeplitz solver.  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tikh {
+
+constexpr int NC = 5;              // basis size of the l2 problem (x, sigma1, gamma1, gamma2, 1)
+constexpr int NE = 20;             // stored basis entries: rows 0..3 of [B0 | v] (row 4 is e_5^T)
+constexpr int LEAF_MAX = 256;      // max conditions per leaf (one wavefront, 4 per lane)
+constexpr int FFT_LDS_MAX = 4096;  // max complex elements held by one LDS FFT workgroup
+constexpr int FFT_THREADS = 256;
+
+// One solve of a bucket (device array element).
+struct SolveDesc {
+    const void* col;   // generator a_0..a_{m-1}    (double or double2)
+    const void* row;   // a_0, a_{-1}..a_{-(n-1)}   (double or double2)
+    const void* rhs;   // b[m] (mode 0) or y[n] (mode 1)
+    void* x;           // output x[n]
+    int64_t m, n;
+    int64_t k;         // circulant extension size: N - (m + n - 1)
+    double lam;
+    int32_t cplx;      // element type of col/row/rhs/x: 0 real double, 1 complex
+    int32_t mode;      // 0: least squares with b, 1: normal form with y
+};
+
+// Per-solve running state of the recursion.
+struct SolveState {
+    int32_t delta[4];  // tau-degrees of basis columns 1..4 (column 5 stays 0)
+    int32_t info;      // 0 ok, 1 breakdown, 2 degree bound, 3 non-finite
+    int32_t pad[3];
+};
+
+// Per-solve metadata of a stored basis (one per slot).
+struct SlotMeta {
+    int32_t deg[5];    // max polynomial degree of each column over rows 0..3 (-1 = zero column)
+    int32_t pad[3];
+    unsigned long long colmax_bits[4];  // max |coefficient| of B0 columns (bit pattern of a non-negative double)
+};
+
+// One step of the serial single-condition construction (eq. (spbasis)).
+struct LeafRec {
+    double2 mu[5];     // multipliers mu_i = -r_i / r_piv (mu[piv] = 0)
+    double2 sig;       // node of the processed condition
+    int32_t piv;       // pivot column (0..3), -1 if the step was skipped
+    int32_t q;         // condition index (tree order)
+    int32_t pad[2];
+};
+
+struct Plan {
+    int64_t N;         // nodes, N = 2^p * M
+    int64_t M;         // nodes per leaf (even, 5-smooth)
+    int32_t p;         // depth
+    int32_t K;         // conditions per leaf = 2M
+    int64_t Q;         // twiddle-table size (multiple of every FFT length used)
+    int64_t cap[40];   // degree capacity of bases stored for a subtree at depth d
+    int64_t P[40];     // product FFT length at parent depth d
+};
+
+}  // namespace tikh

@@ -1,0 +1,870 @@
+// Device kernels of the superfast Tikhonov-Toeplitz solver for gfx950.
+//
+// Paper: Turnes, Balcan, Romberg, "Superfast Tikhonov Regularization of
+// Toeplitz Systems".  Section/equation references are to that paper.
+//
+// All arithmetic is complex FP64 (double2 = (re, im)).  Evaluations follow the
+// convention of eq. (vandprod): a vector rho is the polynomial
+// rho(z) = sum_i rho_i z^i and F rho = [rho(w_nu)], w_nu = exp(+2 pi i nu / N).
+#include "tikh_internal.h"
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <limits.h>
+
+namespace tikh {
+
+// ---------------------------------------------------------------- complex
+__device__ __forceinline__ double2 c2(double a, double b) { return make_double2(a, b); }
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return c2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return c2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return c2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+}
+// a * b + c
+__device__ __forceinline__ double2 cfma(double2 a, double2 b, double2 c) {
+    return c2(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
+}
+__device__ __forceinline__ double2 cconj(double2 a) { return c2(a.x, -a.y); }
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return c2(a.x * s, a.y * s); }
+__device__ __forceinline__ double cabs2(double2 a) { return fma(a.x, a.x, a.y * a.y); }
+__device__ __forceinline__ double2 cneg(double2 a) { return c2(-a.x, -a.y); }
+__device__ __forceinline__ bool cnonzero(double2 a) { return a.x != 0.0 || a.y != 0.0; }
+// a / b by Smith's method
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+    if (fabs(b.x) >= fabs(b.y)) {
+        double t = b.y / b.x, d = fma(b.y, t, b.x);
+        return c2((a.x + a.y * t) / d, (a.y - a.x * t) / d);
+    } else {
+        double t = b.x / b.y, d = fma(b.x, t, b.y);
+        return c2((a.x * t + a.y) / d, (a.y * t - a.x) / d);
+    }
+}
+
+// e^{sign * 2 pi i idx / Q} from the table tw[q] = e^{2 pi i q / Q}
+__device__ __forceinline__ double2 twq(const double2* __restrict__ tw, int64_t Q, int64_t idx, int sign) {
+    int64_t r = idx % Q;
+    if (r < 0) r += Q;
+    double2 t = tw[r];
+    return sign > 0 ? t : cconj(t);
+}
+
+__device__ __forceinline__ double2 load_elem(const void* p, int64_t i, int cplx) {
+    if (cplx) return ((const double2*)p)[i];
+    return c2(((const double*)p)[i], 0.0);
+}
+__device__ __forceinline__ double2 gen_coef(const SolveDesc& d, int64_t s) {
+    // a_s of T = [a_{i-j}] (Sec. 1)
+    return s >= 0 ? load_elem(d.col, s, d.cplx) : load_elem(d.row, -s, d.cplx);
+}
+
+__device__ __forceinline__ int bitrev(int v, int bits) {
+    return bits == 0 ? 0 : (int)(__brev((unsigned)v) >> (32 - bits));
+}
+
+// Power-of-two scale 2^-e bringing a positive maximum to [0.5, 1).
+__device__ __forceinline__ double pow2_inv_scale(unsigned long long bits) {
+    double m = __longlong_as_double((long long)bits);
+    if (!(m > 0.0) || !isfinite(m)) return 1.0;
+    int e;
+    frexp(m, &e);
+    return ldexp(1.0, -e);
+}
+
+// ---------------------------------------------------------------- wave reductions
+__device__ __forceinline__ int wave_min_i(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_max_d(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// ---------------------------------------------------------------- FFT (LDS, Stockham)
+// DFT of size R with root w = e^{sign 2 pi i / R}, in registers.
+template <int R> __device__ __forceinline__ void bfly(double2* v, int sign);
+
+template <> __device__ __forceinline__ void bfly<2>(double2* v, int) {
+    double2 a = v[0], b = v[1];
+    v[0] = cadd(a, b); v[1] = csub(a, b);
+}
+template <> __device__ __forceinline__ void bfly<4>(double2* v, int sign) {
+    double2 a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
+    double2 b0 = cadd(v[1], v[3]), b1 = csub(v[1], v[3]);
+    // b1 * (sign * i)
+    double2 jb1 = sign > 0 ? c2(-b1.y, b1.x) : c2(b1.y, -b1.x);
+    v[0] = cadd(a0, b0); v[2] = csub(a0, b0);
+    v[1] = cadd(a1, jb1); v[3] = csub(a1, jb1);
+}
+template <> __device__ __forceinline__ void bfly<3>(double2* v, int sign) {
+    const double c = -0.5, s = sign * 0.86602540378443864676;   // e^{sign 2 pi i/3}
+    double2 t1 = cadd(v[1], v[2]), t2 = csub(v[1], v[2]);
+    double2 a = v[0];
+    v[0] = cadd(a, t1);
+    double2 m1 = c2(a.x + c * t1.x, a.y + c * t1.y);
+    double2 m2 = c2(-s * t2.y, s * t2.x);                          // i s t2
+    v[1] = cadd(m1, m2); v[2] = csub(m1, m2);
+}
+template <> __device__ __forceinline__ void bfly<5>(double2* v, int sign) {
+    const double c1 = 0.30901699437494742410, c2_ = -0.80901699437494742410;
+    const double s1 = sign * 0.95105651629515357212, s2 = sign * 0.58778525229247312917;
+    double2 a = v[0];
+    double2 t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+    double2 u1 = csub(v[1], v[4]), u2 = csub(v[2], v[3]);
+    v[0] = cadd(a, cadd(t1, t2));
+    double2 m1 = c2(a.x + c1 * t1.x + c2_ * t2.x, a.y + c1 * t1.y + c2_ * t2.y);
+    double2 m2 = c2(a.x + c2_ * t1.x + c1 * t2.x, a.y + c2_ * t1.y + c1 * t2.y);
+    // i*(s1 u1 + s2 u2), i*(s2 u1 - s1 u2)
+    double2 n1 = c2(-(s1 * u1.y + s2 * u2.y), s1 * u1.x + s2 * u2.x);
+    double2 n2 = c2(-(s2 * u1.y - s1 * u2.y), s2 * u1.x - s1 * u2.x);
+    v[1] = cadd(m1, n1); v[4] = csub(m1, n1);
+    v[2] = cadd(m2, n2); v[3] = csub(m2, n2);
+}
+
+// One in-place Stockham stage over `nl` lines of length L held in LDS.
+// Ns = product of the radices of the previous stages.
+template <int R>
+__device__ void fft_stage(double2* buf, int L, int nl, int Ns, int sign,
+                          const double2* __restrict__ tw, int64_t Q) {
+    constexpr int MB = (FFT_LDS_MAX / R + FFT_THREADS - 1) / FFT_THREADS;
+    const int per = L / R;
+    const int nb = nl * per;
+    const int64_t tstep = Q / ((int64_t)Ns * R);    // table stride of e^{2 pi i/(Ns R)}
+    double2 v[MB][R];
+#pragma unroll
+    for (int it = 0; it < MB; ++it) {
+        int b = threadIdx.x + it * FFT_THREADS;
+        if (b < nb) {
+            int line = b / per, j = b - line * per;
+            const double2* src = buf + line * L + j;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[it][r] = src[r * per];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < MB; ++it) {
+        int b = threadIdx.x + it * FFT_THREADS;
+        if (b < nb) {
+            int line = b / per, j = b - line * per;
+            int k = j % Ns;
+            if (Ns > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[it][r] = cmul(v[it][r], twq(tw, Q, (int64_t)r * k * tstep, sign));
+            }
+            bfly<R>(v[it], sign);
+            double2* dst = buf + line * L + (j / Ns) * Ns * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) dst[r * Ns] = v[it][r];
+        }
+    }
+    __syncthreads();
+}
+
+struct FftPlanDev {
+    int L;
+    int nst;
+    int radix[24];
+};
+
+__device__ void lds_fft(double2* buf, const FftPlanDev& pl, int nl, int sign, const double2* tw, int64_t Q) {
+    int Ns = 1;
+    for (int s = 0; s < pl.nst; ++s) {
+        int R = pl.radix[s];
+        if (R == 4) fft_stage<4>(buf, pl.L, nl, Ns, sign, tw, Q);
+        else if (R == 2) fft_stage<2>(buf, pl.L, nl, Ns, sign, tw, Q);
+        else if (R == 3) fft_stage<3>(buf, pl.L, nl, Ns, sign, tw, Q);
+        else fft_stage<5>(buf, pl.L, nl, Ns, sign, tw, Q);
+        Ns *= R;
+    }
+}
+
+// Batched in-place FFT of lines held in global memory.
+// Line l of solve s starts at data + s*solve_stride + l*line_stride; element k
+// at + k*elem_stride.  lpw lines per workgroup (lpw*L <= FFT_LDS_MAX).
+// Optional four-step twiddle: output element j of line l multiplied by
+// e^{sign 2 pi i j l / post_L} (post_L = 0: none).
+struct FftArgs {
+    double2* data;
+    int64_t solve_stride, line_stride, elem_stride, outer_stride;
+    int64_t nlines, lines_inner;
+    int sign;
+    int lpw;
+    int64_t post_L;
+    double scale;
+    const double2* tw;
+    int64_t Q;
+    FftPlanDev pl;
+};
+
+__global__ __launch_bounds__(FFT_THREADS) void k_fft(const FftArgs a) {
+    __shared__ double2 sm[FFT_LDS_MAX];
+    const int L = a.pl.L;
+    const int64_t l0 = (int64_t)blockIdx.x * a.lpw;
+    const int nl = (int)min((int64_t)a.lpw, a.nlines - l0);
+    double2* base = a.data + (int64_t)blockIdx.y * a.solve_stride;
+    const int tot = nl * L;
+    const bool contig = (a.elem_stride == 1);
+    for (int i = threadIdx.x; i < tot; i += FFT_THREADS) {
+        int g, k;
+        if (contig) { g = i / L; k = i - g * L; } else { k = i / nl; g = i - k * nl; }
+        const int64_t l = l0 + g, o = l / a.lines_inner, in = l - o * a.lines_inner;
+        sm[g * L + k] = base[o * a.outer_stride + in * a.line_stride + (int64_t)k * a.elem_stride];
+    }
+    __syncthreads();
+    lds_fft(sm, a.pl, nl, a.sign, a.tw, a.Q);
+    for (int i = threadIdx.x; i < tot; i += FFT_THREADS) {
+        int g, k;
+        if (contig) { g = i / L; k = i - g * L; } else { k = i / nl; g = i - k * nl; }
+        const int64_t l = l0 + g, o = l / a.lines_inner, in = l - o * a.lines_inner;
+        double2 v = sm[g * L + k];
+        if (a.post_L) v = cmul(v, twq(a.tw, a.Q, ((int64_t)k * in % a.post_L) * (a.Q / a.post_L), a.sign));
+        if (a.scale != 1.0) v = cscale(v, a.scale);
+        base[o * a.outer_stride + in * a.line_stride + (int64_t)k * a.elem_stride] = v;
+    }
+}
+
+// Out-of-place transpose per line-block: src holds, for each of `nlines`
+// lines of length L1*L2, the four-step order X[j1 + L1 j2] at j1*L2 + j2;
+// dst receives natural order.
+__global__ void k_fourstep_unscramble(const double2* __restrict__ src, double2* __restrict__ dst,
+                                      int64_t src_solve_stride, int64_t dst_solve_stride, int64_t line_stride,
+                                      int64_t nlines, int64_t L1, int64_t L2) {
+    const int64_t L = L1 * L2;
+    const int64_t tot = nlines * L;
+    const int64_t s = blockIdx.y;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t line = i / L, j = i - line * L;
+        int64_t j1 = j % L1, j2 = j / L1;
+        dst[s * dst_solve_stride + line * line_stride + j] = src[s * src_solve_stride + line * line_stride + j1 * L2 + j2];
+    }
+}
+
+__global__ void k_copy(const double2* __restrict__ src, double2* __restrict__ dst, int64_t src_solve_stride,
+                       int64_t dst_solve_stride, int64_t count) {
+    const int64_t s = blockIdx.y;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        dst[s * dst_solve_stride + i] = src[s * src_solve_stride + i];
+}
+
+// ---------------------------------------------------------------- setup (Sec. 3.1, 3.3, 4.1)
+// Root-mean-square of the generator (scale of the arbitrary extension
+// entries, Sec. 6.2: chosen "similar in value" to the known coefficients).
+__global__ __launch_bounds__(256) void k_gen_rms(const SolveDesc* __restrict__ sd, double* __restrict__ rms) {
+    const SolveDesc d = sd[blockIdx.x];
+    double acc = 0.0;
+    const int64_t cnt = d.m + d.n - 1;
+    for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x) acc += cabs2(gen_coef(d, i - (d.n - 1)));
+    __shared__ double red[256];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) rms[blockIdx.x] = sqrt(red[0] / (double)cnt);
+}
+
+__device__ __forceinline__ double hash_unit(uint64_t x) {
+    // splitmix64 finalizer -> uniform in [-1, 1)
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    x ^= x >> 31;
+    return (double)(x >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+// First column of the k-circulant extension (eq. (circexp)):
+// c_T[r] = a_{r-(n+k-1)} for r >= k; r < k are the arbitrary entries a_{-n-k+1..-n}.
+__global__ void k_build_ct(const SolveDesc* __restrict__ sd, const double* __restrict__ rms,
+                           double2* __restrict__ out, int64_t N, int64_t stride) {
+    const int64_t s = blockIdx.y;
+    const SolveDesc d = sd[s];
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < N; r += (int64_t)gridDim.x * blockDim.x) {
+        double2 v;
+        if (r >= d.k) {
+            v = gen_coef(d, r - (N - d.m));
+        } else {
+            double sc = rms[s] * 1.7320508075688772;   // uniform in [-sqrt3, sqrt3) has unit rms
+            uint64_t key = ((uint64_t)s << 40) ^ ((uint64_t)d.m << 20) ^ (uint64_t)d.n ^ ((uint64_t)r << 44);
+            v = c2(sc * hash_unit(key), d.cplx ? sc * hash_unit(key ^ 0x5851F42D4C957F2Dull) : 0.0);
+        }
+        out[s * stride + r] = v;
+    }
+}
+
+// dst[i] = scale * src[off + i] for i < len, 0 for len <= i < N.
+// src is either a user array (per-solve pointer in SolveDesc: which = 0 rhs,
+// 1 x) or an internal complex buffer (isrc != nullptr).
+__global__ void k_load_pad(const SolveDesc* __restrict__ sd, int which, const double2* __restrict__ isrc,
+                           int64_t isrc_stride, int len_kind, int64_t off, double scale,
+                           double2* __restrict__ dst, int64_t N, int64_t stride) {
+    const int64_t s = blockIdx.y;
+    const SolveDesc d = sd[s];
+    const int64_t len = len_kind == 0 ? d.m : d.n;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+        double2 v = c2(0.0, 0.0);
+        if (i < len) {
+            if (isrc) v = isrc[s * isrc_stride + off + i];
+            else v = load_elem(which == 0 ? d.rhs : (const void*)d.x, off + i, d.cplx);
+            v = cscale(v, scale);
+        }
+        dst[s * stride + i] = v;
+    }
+}
+
+// buf[nu] *= symbol: mode 0: c^(nu) (C_k(T), Sec. 3.1 eq. (circdiag));
+// mode 1: w^{(k-1) nu} conj(c^(nu)) (C_k(T^H), whose symbol follows from T's in O(N), Sec. 7.3).
+__global__ void k_mul_symbol(const SolveDesc* __restrict__ sd, const double2* __restrict__ chat,
+                             double2* __restrict__ buf, int64_t N, int64_t stride, int mode,
+                             const double2* __restrict__ tw, int64_t Q) {
+    const int64_t s = blockIdx.y;
+    const int64_t k = sd[s].k;
+    for (int64_t nu = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; nu < N; nu += (int64_t)gridDim.x * blockDim.x) {
+        double2 c = chat[s * stride + nu];
+        double2 sym;
+        if (mode == 0) sym = c;
+        else sym = cmul(twq(tw, Q, (((k - 1) % N + N) % N) * nu % N * (Q / N), +1), cconj(c));
+        buf[s * stride + nu] = cmul(buf[s * stride + nu], sym);
+    }
+}
+
+// dst[i] = scale * buf[N - len + i] for i < len (len = m or n): the bottom block
+// of a circulant product (rows of T inside C_k(T), or of T^H inside C_k(T^H)).
+__global__ void k_take_tail(const SolveDesc* __restrict__ sd, const double2* __restrict__ buf, int64_t N,
+                            int64_t stride, int len_kind, double scale, double2* __restrict__ dst,
+                            int64_t dst_stride) {
+    const int64_t s = blockIdx.y;
+    const SolveDesc d = sd[s];
+    const int64_t len = len_kind == 0 ? d.m : d.n;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (int64_t)gridDim.x * blockDim.x)
+        dst[s * dst_stride + i] = cscale(buf[s * stride + N - len + i], scale);
+}
+
+// Residual of the normal equations: r = y - (T^H T x) - lam^2 x  (all length n).
+__global__ void k_normal_residual(const SolveDesc* __restrict__ sd, const double2* __restrict__ y,
+                                  const double2* __restrict__ thtx, const double2* __restrict__ x,
+                                  double2* __restrict__ r, int64_t stride) {
+    const int64_t s = blockIdx.y;
+    const SolveDesc d = sd[s];
+    const double l2 = d.lam * d.lam;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < d.n; i += (int64_t)gridDim.x * blockDim.x) {
+        double2 xv = x[s * stride + i];
+        r[s * stride + i] = csub(csub(y[s * stride + i], thtx[s * stride + i]), cscale(xv, l2));
+    }
+}
+
+// Interpolation data of the l2 problem (eq. (ex6) transformed as in eq. (ex4),
+// conditions (intcond)), two conditions per node nu, written in tree order.
+// Unknown p* = [x; sigma1; gamma1; gamma2; 1] with degree bounds n, m, m+k-1, n+k-1, 1.
+//   F_nu = [lam^2 w^{(m+k-1)nu},  w^{(k-1)nu} conj(c^),  1,  0,  -w^{(m+k-1)nu} y^]
+//   G_nu = [-c^,  w^{(n+k-1)nu},  0,  1,  0]
+// Tree order: leaf t (in-order) holds nodes nu = o_t + c + j*2^{p+1}, o_t = 2*bitrev_p(t),
+// c in {0,1}, j < M/2 (paired interleaving, Sec. 6.1); slot h = c*M + 2j + type.
+__global__ void k_assemble(const SolveDesc* __restrict__ sd, const double2* __restrict__ chat,
+                           const double2* __restrict__ yhat, int64_t vstride, double2* __restrict__ phi,
+                           int64_t phi_stride, int64_t N, int64_t M, int p, int K,
+                           const double2* __restrict__ tw, int64_t Q) {
+    const int64_t s = blockIdx.y;
+    const SolveDesc d = sd[s];
+    const int64_t twN = Q / N;
+    const double l2 = d.lam * d.lam;
+    const int64_t nq = 2 * N;
+    double2* ph = phi + s * phi_stride;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += (int64_t)gridDim.x * blockDim.x) {
+        int64_t t = q / K, h = q - t * K;
+        int64_t c = h / M, rem = h - c * M;
+        int64_t j = rem >> 1;
+        int type = (int)(rem & 1);
+        int64_t nu = 2 * (int64_t)bitrev((int)t, p) + c + (j << (p + 1));
+        double2 ch = chat[s * vstride + nu];
+        double2 v0, v1, v2, v3, v4;
+        if (type == 0) {
+            double2 wmk = twq(tw, Q, ((N - d.n) * nu % N) * twN, +1);        // w^{(m+k-1) nu}
+            double2 wk1 = twq(tw, Q, ((((d.k - 1) % N + N) % N) * nu % N) * twN, +1);
+            v0 = cscale(wmk, l2);
+            v1 = cmul(wk1, cconj(ch));
+            v2 = c2(1.0, 0.0);
+            v3 = c2(0.0, 0.0);
+            v4 = cneg(cmul(wmk, yhat[s * vstride + nu]));
+        } else {
+            double2 wnk = twq(tw, Q, ((N - d.m) * nu % N) * twN, +1);        // w^{(n+k-1) nu}
+            v0 = cneg(ch);
+            v1 = wnk;
+            v2 = c2(0.0, 0.0);
+            v3 = c2(1.0, 0.0);
+            v4 = c2(0.0, 0.0);
+        }
+        ph[0 * nq + q] = v0; ph[1 * nq + q] = v1; ph[2 * nq + q] = v2; ph[3 * nq + q] = v3; ph[4 * nq + q] = v4;
+    }
+}
+
+// Node of condition q (tree order).
+__device__ __forceinline__ double2 cond_node(int64_t q, int64_t N, int64_t M, int p, int K,
+                                             const double2* __restrict__ tw, int64_t Q) {
+    int64_t t = q / K, h = q - t * K;
+    int64_t c = h / M, j = (h - c * M) >> 1;
+    int64_t nu = 2 * (int64_t)bitrev((int)t, p) + c + (j << (p + 1));
+    return tw[nu * (Q / N)];
+}
+
+// ---------------------------------------------------------------- leaf: serial TanInt
+// The fast-only construction of Sec. 4.3 on one leaf's K conditions, one
+// wavefront per solve, residuals in registers (R per lane).  Each step
+// processes one condition with the single-condition basis of eq. (spbasis):
+//   pivot column pi = the lowest tau-degree among columns 1..4 whose residual
+//   entry is not negligible (|r_i| > ZTOL max_j |r_j|), ties to the largest
+//   |r_i|; the condition is the remaining one with the lowest such degree and,
+//   among those, the largest |r_pi| (partial pivoting of the conditions,
+//   Sec. 5).  Column 5 (the constant) is never a pivot, so the basis keeps the
+//   block form [[B0, v], [0, 1]].
+//   mu_i = -r_i / r_pi;  B_:i += mu_i B_:pi (i != pi);  B_:pi *= (z - sigma);
+//   remaining residuals r_i += mu_i r_pi,  r_pi *= (sigma_q - sigma);  delta_pi += 1.
+// The basis itself is formed afterwards from the step records (k_leaf_build).
+struct LeafArgs {
+    const SolveDesc* sd;
+    SolveState* st;
+    double2* phi;
+    int64_t phi_stride;
+    LeafRec* rec;
+    int64_t rec_stride;
+    int64_t N, M;
+    int p, K, leaf;
+    const double2* tw;
+    int64_t Q;
+};
+
+#define TIKH_ZTOL2 1e-22   // (1e-11)^2: relative size below which a residual entry counts as zero
+
+template <int R>
+__global__ __launch_bounds__(64) void k_leaf_loop(const LeafArgs a) {
+    const int64_t s = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int K = a.K;
+    const int64_t nq = 2 * a.N;
+    const int64_t q0 = (int64_t)a.leaf * K;
+    double2* ph = a.phi + s * a.phi_stride;
+    LeafRec* rec = a.rec + s * a.rec_stride;
+    double2 r[R][5];
+    double2 sg[R];
+    bool alive[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        int h = lane + 64 * i;
+        alive[i] = h < K;
+        if (alive[i]) {
+#pragma unroll
+            for (int c = 0; c < 5; ++c) r[i][c] = ph[c * nq + q0 + h];
+            sg[i] = cond_node(q0 + h, a.N, a.M, a.p, K, a.tw, a.Q);
+        } else {
+#pragma unroll
+            for (int c = 0; c < 5; ++c) r[i][c] = c2(0.0, 0.0);
+            sg[i] = c2(0.0, 0.0);
+        }
+    }
+    int dl[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) dl[c] = a.st[s].delta[c];
+    int info = 0;
+    for (int step = 0; step < K; ++step) {
+        int bkey = INT_MAX, bi = -1, bp = -1;
+        double bmag = -1.0;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            if (!alive[i]) continue;
+            double a2[4];
+            double amax = 0.0;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) { a2[c] = cabs2(r[i][c]); amax = fmax(amax, a2[c]); }
+            const double thr = TIKH_ZTOL2 * amax;
+            int key = INT_MAX, piv = -1;
+            double pm = -1.0;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                if (a2[c] > thr && a2[c] > 0.0 && (dl[c] < key || (dl[c] == key && a2[c] > pm))) {
+                    key = dl[c]; piv = c; pm = a2[c];
+                }
+            }
+            if (piv >= 0 && (key < bkey || (key == bkey && pm > bmag))) { bkey = key; bmag = pm; bi = i; bp = piv; }
+        }
+        const int wkey = wave_min_i(bkey);
+        if (wkey == INT_MAX) { info = 1; break; }      // no admissible pivot: breakdown
+        const double mine = (bkey == wkey) ? bmag : -1.0;
+        const double wmag = wave_max_d(mine);
+        const int cand = (bkey == wkey && bmag == wmag) ? lane : 64;
+        const int wl = wave_min_i(cand);
+        const int si = __shfl(bi, wl, 64);
+        const int piv = __shfl(bp, wl, 64);
+        double2 rc[5];
+        double2 sc = c2(0.0, 0.0);
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            if (i == si) {
+#pragma unroll
+                for (int c = 0; c < 5; ++c) rc[c] = c2(__shfl(r[i][c].x, wl, 64), __shfl(r[i][c].y, wl, 64));
+                sc = c2(__shfl(sg[i].x, wl, 64), __shfl(sg[i].y, wl, 64));
+                if (lane == wl) alive[i] = false;
+            }
+        }
+        double2 rp = rc[0];
+#pragma unroll
+        for (int c = 1; c < 4; ++c) if (c == piv) rp = rc[c];
+        const double2 inv = cdiv(c2(-1.0, 0.0), rp);
+        double2 mu[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) mu[c] = (c == piv) ? c2(0.0, 0.0) : cmul(rc[c], inv);
+        if (lane == 0) {
+            LeafRec& o = rec[step];
+#pragma unroll
+            for (int c = 0; c < 5; ++c) o.mu[c] = mu[c];
+            o.sig = sc;
+            o.piv = piv;
+            o.q = (int)(q0 + si * 64 + wl);
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            if (!alive[i]) continue;
+            double2 rpv = r[i][0];
+#pragma unroll
+            for (int c = 1; c < 4; ++c) if (c == piv) rpv = r[i][c];
+#pragma unroll
+            for (int c = 0; c < 5; ++c) {
+                if (c == piv) r[i][c] = cmul(rpv, csub(sg[i], sc));
+                else r[i][c] = cfma(mu[c], rpv, r[i][c]);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) if (c == piv) dl[c] += 1;
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) a.st[s].delta[c] = dl[c];
+        if (info) a.st[s].info |= info;
+    }
+}
+
+// Basis of one leaf from its step records: B = E_1 E_2 ... E_K with the
+// elementary factors of eq. (spbasis).  One wavefront per row of [B0 | v]
+// (4 waves), coefficient k of each polynomial on lane k%64, slot k/64.
+struct BuildArgs {
+    const SolveState* st;
+    const LeafRec* rec;
+    int64_t rec_stride;
+    double2* out;          // slot data [s][20][cap+1]
+    int64_t out_stride;
+    int64_t cap;
+    SlotMeta* meta;        // [s]
+    int K;
+};
+
+template <int PIV, int S>
+__device__ __forceinline__ void build_step(double2 (&P)[5][S], const double2 (&mu)[5], double2 sg, int active, int lane) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        if (c == PIV) continue;
+        if (!cnonzero(mu[c])) continue;
+#pragma unroll
+        for (int sl = 0; sl < S; ++sl)
+            if (sl <= active) P[c][sl] = cfma(mu[c], P[PIV][sl], P[c][sl]);
+    }
+    double2 nv[S];
+#pragma unroll
+    for (int sl = 0; sl < S; ++sl) {
+        if (sl <= active + 1) {
+            double ux = __shfl_up(P[PIV][sl].x, 1, 64), uy = __shfl_up(P[PIV][sl].y, 1, 64);
+            double cx = 0.0, cy = 0.0;
+            if (sl > 0) { cx = __shfl(P[PIV][sl - 1].x, 63, 64); cy = __shfl(P[PIV][sl - 1].y, 63, 64); }
+            double2 up = (lane == 0) ? c2(cx, cy) : c2(ux, uy);
+            nv[sl] = csub(up, cmul(sg, P[PIV][sl]));
+        }
+    }
+#pragma unroll
+    for (int sl = 0; sl < S; ++sl) if (sl <= active + 1) P[PIV][sl] = nv[sl];
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void k_leaf_build(const BuildArgs a) {
+    const int64_t s = blockIdx.x;
+    const int row = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const LeafRec* rec = a.rec + s * a.rec_stride;
+    double2 P[5][S];
+#pragma unroll
+    for (int c = 0; c < 5; ++c)
+#pragma unroll
+        for (int sl = 0; sl < S; ++sl) P[c][sl] = c2((c == row && sl == 0 && lane == 0) ? 1.0 : 0.0, 0.0);
+    int deg[5] = {0, 0, 0, 0, -1};
+    int dmax = 0;
+    const bool broken = a.st[s].info != 0;
+    for (int step = 0; step < a.K && !broken; ++step) {
+        const LeafRec& rr = rec[step];
+        const int piv = rr.piv;
+        if (piv < 0) continue;
+        double2 mu[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) mu[c] = rr.mu[c];
+        const double2 sg = rr.sig;
+        const int active = dmax >> 6;
+        switch (piv) {
+            case 0: build_step<0, S>(P, mu, sg, active, lane); break;
+            case 1: build_step<1, S>(P, mu, sg, active, lane); break;
+            case 2: build_step<2, S>(P, mu, sg, active, lane); break;
+            default: build_step<3, S>(P, mu, sg, active, lane); break;
+        }
+        for (int c = 0; c < 5; ++c)
+            if (c != piv && cnonzero(mu[c])) deg[c] = max(deg[c], deg[piv]);
+        deg[piv] += 1;
+        dmax = max(dmax, deg[piv]);
+    }
+    // column maxima of B0 over the 4 rows
+    __shared__ double cm[4][4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        double mx = 0.0;
+#pragma unroll
+        for (int sl = 0; sl < S; ++sl) mx = fmax(mx, cabs2(P[c][sl]));
+        mx = wave_max_d(mx);
+        if (lane == 0) cm[row][c] = mx;
+    }
+    __syncthreads();
+    double2* out = a.out + s * a.out_stride;
+    const int64_t cp1 = a.cap + 1;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        double2* dst = out + (int64_t)(row * 5 + c) * cp1;
+#pragma unroll
+        for (int sl = 0; sl < S; ++sl) {
+            int64_t k = lane + 64 * sl;
+            if (k <= deg[c] && k < cp1) dst[k] = P[c][sl];
+        }
+    }
+    if (threadIdx.x == 0) {
+        SlotMeta m;
+        int bad = 0;
+        for (int c = 0; c < 5; ++c) {
+            if (deg[c] > a.cap) bad = 1;
+            m.deg[c] = (int)min((int64_t)deg[c], a.cap);   // never read past the slot
+        }
+        for (int c = 0; c < 4; ++c) {
+            double mx = fmax(fmax(cm[0][c], cm[1][c]), fmax(cm[2][c], cm[3][c]));
+            m.colmax_bits[c] = (unsigned long long)__double_as_longlong(sqrt(mx));
+        }
+        m.pad[0] = m.pad[1] = m.pad[2] = 0;
+        a.meta[s] = m;
+        if (bad) atomicOr(&((SolveState*)a.st)[s].info, 2);
+    }
+}
+
+// ---------------------------------------------------------------- evaluation, Alg. 1 step 2
+// V[s][e][c][r] = sum_{i = r mod L, i <= deg} scale_col(e) B[e][i] w^{(o + c) i}
+// (twist by the coset offset and fold modulo the coset length L); an FFT of
+// length L then gives B_e at the nodes w^{o + c + j 2^{d+1}}, j < L.
+__global__ void k_twist_fold(const double2* __restrict__ B, int64_t b_stride, int64_t cp1,
+                             const SlotMeta* __restrict__ meta, double2* __restrict__ V, int64_t v_stride,
+                             int64_t L, int64_t o, int64_t N, const double2* __restrict__ tw, int64_t Q) {
+    const int64_t s = blockIdx.z;
+    const int ec = blockIdx.y;            // e*2 + c
+    const int e = ec >> 1, c = ec & 1;
+    const int col = e % 5;
+    const SlotMeta mt = meta[s];
+    const int dg = mt.deg[col];
+    const double sc = col < 4 ? pow2_inv_scale(mt.colmax_bits[col]) : 1.0;
+    const double2* src = B + s * b_stride + (int64_t)e * cp1;
+    const int64_t oc = o + c;
+    const int64_t twN = Q / N;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < L; r += (int64_t)gridDim.x * blockDim.x) {
+        double2 acc = c2(0.0, 0.0);
+        for (int64_t i = r; i <= dg; i += L) acc = cfma(src[i], twq(tw, Q, (oc * i % N) * twN, +1), acc);
+        V[s * v_stride + (int64_t)ec * L + r] = cscale(acc, sc);
+    }
+}
+
+// phi <- phi B_L(sigma) for every condition of the right subtree
+// (Alg. 1 step 2, with Thm. 1 giving the data phi_k B_kappa(sigma_k)).
+// The right subtree (depth d, coset offset oR) spans leaves [t0, t0 + 2^{p-d}).
+__global__ void k_eval_apply(double2* __restrict__ phi, int64_t phi_stride, const double2* __restrict__ V,
+                             int64_t v_stride, int64_t L, int64_t oR, int d, int64_t t0, int64_t nleaves,
+                             int64_t N, int64_t M, int p, int K) {
+    const int64_t s = blockIdx.y;
+    const int64_t nq = 2 * N;
+    const int64_t cnt = nleaves * K;
+    double2* ph = phi + s * phi_stride;
+    const double2* Vs = V + s * v_stride;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < cnt; u += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t q = t0 * K + u;
+        const int64_t t = q / K, h = q - t * K;
+        const int64_t c = h / M, jhi = (h - c * M) >> 1;
+        const int64_t ot = 2 * (int64_t)bitrev((int)t, p);
+        const int64_t jlo = (ot - oR) >> (d + 1);
+        const int64_t j = jlo + (jhi << (p - d));
+        double2 f[5];
+#pragma unroll
+        for (int col = 0; col < 5; ++col) f[col] = ph[col * nq + q];
+        double2 o[5];
+        o[4] = f[4];
+#pragma unroll
+        for (int col = 0; col < 4; ++col) o[col] = c2(0.0, 0.0);
+#pragma unroll
+        for (int row = 0; row < 4; ++row) {
+#pragma unroll
+            for (int col = 0; col < 5; ++col) {
+                double2 E = Vs[(int64_t)((row * 5 + col) * 2 + c) * L + j];
+                o[col] = cfma(f[row], E, o[col]);
+            }
+        }
+#pragma unroll
+        for (int col = 0; col < 5; ++col) ph[col * nq + q] = o[col];
+    }
+}
+
+// ---------------------------------------------------------------- product, Alg. 1 step 4
+// Zero-padded, column-scaled copy of selected basis entries into FFT lines of length P.
+__global__ void k_prod_load(const double2* __restrict__ B, int64_t b_stride, int64_t cp1,
+                            const SlotMeta* __restrict__ meta, const int* __restrict__ elist,
+                            double2* __restrict__ F, int64_t f_stride, int64_t P) {
+    const int64_t s = blockIdx.z;
+    const int li = blockIdx.y;
+    const int e = elist[li];
+    const int col = e % 5;
+    const SlotMeta mt = meta[s];
+    const int dg = mt.deg[col];
+    const double sc = col < 4 ? pow2_inv_scale(mt.colmax_bits[col]) : 1.0;
+    const double2* src = B + s * b_stride + (int64_t)e * cp1;
+    double2* dst = F + s * f_stride + (int64_t)li * P;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < P; k += (int64_t)gridDim.x * blockDim.x)
+        dst[k] = k <= dg ? cscale(src[k], sc) : c2(0.0, 0.0);
+}
+
+// Pointwise block product [[B0L, vL],[0,1]] [[B0R, vR],[0,1]] = [[B0L B0R, B0L vR + vL],[0,1]].
+// FL holds all 20 entries of the left factor (or only row 0 in root mode),
+// FR the right factor's needed entries (all 20, or only column 5 in root mode).
+__global__ void k_prod_mul(const double2* FL, const double2* __restrict__ FR,
+                           double2* FO, int64_t f_stride, int64_t P, int root) {
+    const int64_t s = blockIdx.y;
+    const double2* L = FL + s * f_stride;
+    const double2* R = FR + s * f_stride;
+    double2* O = FO + s * f_stride;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < P; k += (int64_t)gridDim.x * blockDim.x) {
+        if (root) {
+            // L lines: entries (0,0..4); R lines: entries (0..3, 4); output: entry (0,4)
+            double2 acc = L[4 * P + k];
+#pragma unroll
+            for (int l = 0; l < 4; ++l) acc = cfma(L[l * P + k], R[l * P + k], acc);
+            O[k] = acc;
+        } else {
+            double2 l[4][5], r[4][5];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 5; ++j) { l[i][j] = L[(i * 5 + j) * P + k]; r[i][j] = R[(i * 5 + j) * P + k]; }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+#pragma unroll
+                for (int j = 0; j < 5; ++j) {
+                    double2 acc = (j == 4) ? l[i][4] : c2(0.0, 0.0);
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) acc = cfma(l[i][t], r[t][j], acc);
+                    O[(i * 5 + j) * P + k] = acc;
+                }
+            }
+        }
+    }
+}
+
+// Degrees of the product: column j of B0L B0R has degree <= max_l degL(l) + degR(j);
+// v: max(max_l degL(l) + degR(v), degL(v)).  Resets the column maxima.
+__global__ void k_prod_meta(const SlotMeta* __restrict__ mL, const SlotMeta* __restrict__ mR,
+                            SlotMeta* __restrict__ mO, SolveState* __restrict__ st, int64_t cap, int nsolve) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsolve) return;
+    SlotMeta a = mL[s], b = mR[s], o;
+    int dl = -1;
+    for (int l = 0; l < 4; ++l) dl = max(dl, a.deg[l]);
+    int bad = 0;
+    for (int j = 0; j < 5; ++j) {
+        int dj = (b.deg[j] < 0 || dl < 0) ? -1 : dl + b.deg[j];
+        if (j == 4) dj = max(dj, a.deg[4]);
+        if (dj > cap) { bad = 1; dj = (int)cap; }
+        o.deg[j] = dj;
+    }
+    o.pad[0] = o.pad[1] = o.pad[2] = 0;
+    for (int c = 0; c < 4; ++c) o.colmax_bits[c] = 0ull;
+    mO[s] = o;
+    if (bad) atomicOr(&st[s].info, 2);
+}
+
+// Inverse-transformed product lines -> output slot (scale 1/P, truncate to
+// the degree bound) and column maxima of B0 (for the power-of-two column
+// normalization applied by the next consumer).
+__global__ void k_prod_store(const double2* __restrict__ FO, int64_t f_stride, int64_t P,
+                             double2* __restrict__ out, int64_t o_stride, int64_t cp1,
+                             SlotMeta* __restrict__ meta, int nent, const int* __restrict__ elist) {
+    const int64_t s = blockIdx.z;
+    const int li = blockIdx.y;
+    const int e = elist[li];
+    const int col = e % 5;
+    const int dg = meta[s].deg[col];
+    const double inv = 1.0 / (double)P;
+    const double2* src = FO + s * f_stride + (int64_t)li * P;
+    double2* dst = out + s * o_stride + (int64_t)e * cp1;
+    double mx = 0.0;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k <= dg && k < cp1; k += (int64_t)gridDim.x * blockDim.x) {
+        double2 v = cscale(src[k], inv);
+        dst[k] = v;
+        mx = fmax(mx, cabs2(v));
+    }
+    if (col < 4) {
+        mx = wave_max_d(mx);
+        if ((threadIdx.x & 63) == 0 && mx > 0.0)
+            atomicMax(&meta[s].colmax_bits[col], (unsigned long long)__double_as_longlong(sqrt(mx)));
+    }
+}
+
+// ---------------------------------------------------------------- extraction (Sec. 5)
+// x = B*_{1j} / B*_{5j} with j the tau-degree-0 column: with column 5 never
+// pivoted, j = 5 and B*_{55} = 1, so x_i = [z^i] v_1.  Accumulates into xacc
+// (refinement adds the correction) and checks the final degrees {1,1,1,1,0}.
+__global__ void k_extract(const SolveDesc* __restrict__ sd, SolveState* __restrict__ st,
+                          const double2* __restrict__ B, int64_t b_stride, int64_t cp1,
+                          const SlotMeta* __restrict__ meta, double2* __restrict__ xacc, int64_t x_stride,
+                          int accumulate) {
+    const int64_t s = blockIdx.y;
+    const SolveDesc d = sd[s];
+    const int dg = meta[s].deg[4];
+    const double2* v1 = B + s * b_stride + 4 * cp1;     // entry (row 0, column 5)
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < d.n; i += (int64_t)gridDim.x * blockDim.x) {
+        double2 v = (i <= dg && i < cp1) ? v1[i] : c2(0.0, 0.0);
+        if (!isfinite(v.x) || !isfinite(v.y)) atomicOr(&st[s].info, 3);
+        xacc[s * x_stride + i] = accumulate ? cadd(xacc[s * x_stride + i], v) : v;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        for (int c = 0; c < 4; ++c)
+            if (st[s].delta[c] != 1) atomicOr(&st[s].info, 1);
+    }
+}
+
+__global__ void k_store_x(const SolveDesc* __restrict__ sd, const double2* __restrict__ xacc, int64_t x_stride,
+                          const SolveState* __restrict__ st, int32_t* __restrict__ info) {
+    const int64_t s = blockIdx.y;
+    const SolveDesc d = sd[s];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < d.n; i += (int64_t)gridDim.x * blockDim.x) {
+        double2 v = xacc[s * x_stride + i];
+        if (d.cplx) ((double2*)d.x)[i] = v;
+        else ((double*)d.x)[i] = v.x;
+    }
+    if (info && blockIdx.x == 0 && threadIdx.x == 0) info[s] = st[s].info;
+}
+
+__global__ void k_init_state(const SolveDesc* __restrict__ sd, SolveState* __restrict__ st, int nsolve, int keep_info) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsolve) return;
+    const SolveDesc d = sd[s];
+    // delta = -tau, tau = [n-1, m-1, m+k-2, n+k-2, 0] (eq. (taudef) adapted to eq. (ex6))
+    st[s].delta[0] = -(int)(d.n - 1);
+    st[s].delta[1] = -(int)(d.m - 1);
+    st[s].delta[2] = -(int)(d.m + d.k - 2);
+    st[s].delta[3] = -(int)(d.n + d.k - 2);
+    if (!keep_info) st[s].info = 0;
+}
+
+}  // namespace tikh

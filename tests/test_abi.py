@@ -1,0 +1,88 @@
+"""Host-side checks of the C ABI (no GPU needed): the library builds and loads,
+exports every function include/tikh.h declares, plans extensions as Alg. 2
+prescribes, and rejects invalid arguments before touching the device."""
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tikh.h")
+
+
+def _ensure_built():
+    from paper_1302_6945_amd import build as B
+    if B.needs_build():
+        B.build()
+    return B.LIB
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tikh_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_entry_points():
+    names = _declared()
+    for want in ["tikh_toeplitz_solve", "tikh_toeplitz_solve_z", "tikh_toeplitz_solve_normal",
+                 "tikh_toeplitz_solve_batched", "tikh_toeplitz_solve_backward",
+                 "tikh_toeplitz_solve_backward_batched", "tikh_set_stream", "tikh_plan_info"]:
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _ensure_built()
+    out = subprocess.check_output(["nm", "-D", "--defined-only", lib]).decode()
+    exported = set(l.split()[-1] for l in out.splitlines() if l.strip())
+    missing = [n for n in _declared() if n not in exported]
+    assert not missing, missing
+
+
+def _golden():
+    rows = []
+    for line in open(os.path.join(ROOT, "tests", "golden", "optextend_alg2.txt")):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            rows.append([int(v) for v in line.split()])
+    return rows
+
+
+@pytest.mark.parametrize("row", _golden())
+def test_plan_matches_alg2(row):
+    _ensure_built()
+    import paper_1302_6945_amd as P
+    m, n, nlim, N, M, p, k = row
+    assert P.plan_info(m, n, nlim) == (N, M, p, k)
+
+
+def test_plan_invariants():
+    _ensure_built()
+    import paper_1302_6945_amd as P
+    for m in [1, 2, 17, 384, 1000, 20000]:
+        for n in [1, 3, 256, 999, 16384]:
+            for nlim in [64, 128, 256]:
+                N, M, p, k = P.plan_info(m, n, nlim)
+                assert N == (1 << p) * M and M % 2 == 0 and 2 * M <= nlim
+                assert k == N - (m + n - 1) and k >= 0
+                v = M
+                for f in (2, 3, 5):
+                    while v % f == 0:
+                        v //= f
+                assert v == 1
+                # the halving loop of Alg. 2 stops at the first p with 2*ceil(Ntilde/2^p) <= nlim
+                assert p == 0 or 2 * -(-(m + n - 1) // (1 << (p - 1))) > nlim
+
+
+def test_invalid_arguments_rejected_on_host():
+    _ensure_built()
+    import paper_1302_6945_amd as P
+    with pytest.raises(P.TikhError):
+        P.plan_info(0, 5)
+    # null device pointers and bad lambda are rejected before any device work
+    assert P.tikh_toeplitz_solve(None, None, 4, 4, None, 1.0, None) == -1
+    assert P.lib.tikh_toeplitz_solve_batched(1, None, None, None, None, 1, None, 1, None, None, None, 0) == -1
+    import ctypes
+    o = P._lib._Opts(n_lim=32, refine=1)
+    assert P.lib.tikh_set_options(ctypes.byref(o)) == -1
