@@ -477,8 +477,51 @@ static int run_chunk(const Plan& pl, const std::vector<SolveDesc>& sds, int32_t*
                            pl.cap[0] + 1, b.metaT[0], b.xacc, L.sn, it > 0 ? 1 : 0);
         g.launches++;
     }
-    hipLaunchKernelGGL(k_store_x, grid1(nmax, S), dim3(256), 0, g.stream, b.sd, b.xacc, L.sn, b.st, info);
-    g.launches++;
+    if (!sds[0].backward) {
+        hipLaunchKernelGGL(k_store_x, grid1(nmax, S), dim3(256), 0, g.stream, b.sd, b.xacc, L.sn, b.st, info);
+        g.launches++;
+    } else {
+        // adjoint: xacc holds w = (T^H T + lam^2 I)^{-1} gx
+        const int64_t lmax = std::max(mmax, nmax);
+        // X = F[x; 0]; T x = tail_m(F^-1(c^ X)) / N; r = b - T x  (t1)
+        hipLaunchKernelGGL(k_load_pad, grid1(N, S), dim3(256), 0, g.stream, b.sd, 2, (const double2*)nullptr, 0, 1, 0,
+                           1.0, b.bA, N, L.sN);
+        rc = fft_lines(b.bA, S, L.sN, 1, N, +1, tw, pl.Q, b.scr, L.sscr);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_copy, grid1(N, S), dim3(256), 0, g.stream, b.bA, b.bB, L.sN, L.sN, N);
+        hipLaunchKernelGGL(k_mul_symbol, grid1(N, S), dim3(256), 0, g.stream, b.sd, b.chat, b.bB, N, L.sN, 0, tw, pl.Q);
+        rc = fft_lines(b.bB, S, L.sN, 1, N, -1, tw, pl.Q, b.scr, L.sscr);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_take_tail, grid1(mmax, S), dim3(256), 0, g.stream, b.sd, b.bB, N, L.sN, 0, invN, b.t2, L.sn);
+        hipLaunchKernelGGL(k_sub_from_b, grid1(mmax, S), dim3(256), 0, g.stream, b.sd, b.t2, b.t1, L.sn);
+        // W = F[w; 0]; T w = tail_m(F^-1(c^ W)) / N  (t2)
+        hipLaunchKernelGGL(k_load_pad, grid1(N, S), dim3(256), 0, g.stream, b.sd, 0, b.xacc, L.sn, 1, 0, 1.0, b.bC, N,
+                           L.sN);
+        rc = fft_lines(b.bC, S, L.sN, 1, N, +1, tw, pl.Q, b.scr, L.sscr);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_copy, grid1(N, S), dim3(256), 0, g.stream, b.bC, b.bB, L.sN, L.sN, N);
+        hipLaunchKernelGGL(k_mul_symbol, grid1(N, S), dim3(256), 0, g.stream, b.sd, b.chat, b.bB, N, L.sN, 0, tw, pl.Q);
+        rc = fft_lines(b.bB, S, L.sN, 1, N, -1, tw, pl.Q, b.scr, L.sscr);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_take_tail, grid1(mmax, S), dim3(256), 0, g.stream, b.sd, b.bB, N, L.sN, 0, invN, b.t2, L.sn);
+        // G^ = F[r;0] conj(W) - F[Tw;0] conj(X); lag sums = F^-1(G^) / N
+        hipLaunchKernelGGL(k_load_pad, grid1(N, S), dim3(256), 0, g.stream, b.sd, 0, b.t1, L.sn, 0, 0, 1.0, b.bB, N,
+                           L.sN);
+        rc = fft_lines(b.bB, S, L.sN, 1, N, +1, tw, pl.Q, b.scr, L.sscr);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_xcorr_spec, grid1(N, S), dim3(256), 0, g.stream, b.bB, b.bC, b.bB, N, L.sN, 0);
+        hipLaunchKernelGGL(k_load_pad, grid1(N, S), dim3(256), 0, g.stream, b.sd, 0, b.t2, L.sn, 0, 0, 1.0, b.bC, N,
+                           L.sN);
+        rc = fft_lines(b.bC, S, L.sN, 1, N, +1, tw, pl.Q, b.scr, L.sscr);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_xcorr_spec, grid1(N, S), dim3(256), 0, g.stream, b.bC, b.bA, b.bB, N, L.sN, 1);
+        rc = fft_lines(b.bB, S, L.sN, 1, N, -1, tw, pl.Q, b.scr, L.sscr);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_store_grads, grid1(2 * lmax + nmax, S), dim3(256), 0, g.stream, b.sd, b.bB, N, L.sN, invN,
+                           b.t2, L.sn);
+        hipLaunchKernelGGL(k_grad_lambda, dim3((unsigned)S), dim3(256), 0, g.stream, b.sd, b.xacc, L.sn, b.st, info);
+        g.launches += 14;
+    }
     HIPCHK(hipGetLastError());
     return TIKH_OK;
 }
@@ -672,18 +715,77 @@ int tikh_toeplitz_solve_batched(int64_t nprob, const int64_t* m, const int64_t* 
     return run_solves(sds, info);
 }
 
-int tikh_toeplitz_solve_backward(const double*, const double*, int64_t, int64_t, const double*, double,
-                                 const double*, const double*, double*, double*, double*, double*) {
-    return TIKH_EINVAL;
+static int backward_single(const void* col, const void* row, int64_t m, int64_t n, const void* b, double lambda,
+                           const void* x, const void* gx, void* gcol, void* grow, void* gb, double* glam, int cplx) {
+    ensure_init();
+    if (!col || !row || !b || !x || !gx || !gcol || !grow || !gb || !glam || m < 1 || n < 1 || bad_lambda(lambda))
+        return TIKH_EINVAL;
+    std::vector<SolveDesc> sds(1);
+    SolveDesc& d = sds[0];
+    d.col = col; d.row = row; d.rhs = gx; d.x = nullptr; d.m = m; d.n = n; d.lam = lambda; d.cplx = cplx; d.mode = 1;
+    d.bin = b; d.xin = x; d.gcol = gcol; d.grow = grow; d.gb = gb; d.glam = glam; d.backward = 1;
+    int32_t* dinfo = nullptr;
+    HIPCHK(hipMallocAsync((void**)&dinfo, sizeof(int32_t), g.stream));
+    int rc = run_solves(sds, dinfo);
+    int32_t hinfo = 0;
+    if (rc == TIKH_OK) HIPCHK(hipMemcpyAsync(&hinfo, dinfo, sizeof(int32_t), hipMemcpyDeviceToHost, g.stream));
+    HIPCHK(hipStreamSynchronize(g.stream));
+    (void)hipFreeAsync(dinfo, g.stream);
+    HIPCHK(hipStreamSynchronize(g.stream));
+    if (rc) return rc;
+    return hinfo ? TIKH_ENUMERIC : TIKH_OK;
 }
-int tikh_toeplitz_solve_backward_z(const tikh_c64*, const tikh_c64*, int64_t, int64_t, const tikh_c64*, double,
-                                   const tikh_c64*, const tikh_c64*, tikh_c64*, tikh_c64*, tikh_c64*, double*) {
-    return TIKH_EINVAL;
+
+int tikh_toeplitz_solve_backward(const double* col, const double* row, int64_t m, int64_t n, const double* b,
+                                 double lambda, const double* x, const double* gx, double* g_col, double* g_row,
+                                 double* g_b, double* g_lambda) {
+    return backward_single(col, row, m, n, b, lambda, x, gx, g_col, g_row, g_b, g_lambda, 0);
 }
-int tikh_toeplitz_solve_backward_batched(int64_t, const int64_t*, const int64_t*, const void*, const void*, int64_t,
-                                         const double*, int64_t, const void*, const void*, const void*, void*, void*,
-                                         void*, double*, int32_t*, int) {
-    return TIKH_EINVAL;
+
+int tikh_toeplitz_solve_backward_z(const tikh_c64* col, const tikh_c64* row, int64_t m, int64_t n, const tikh_c64* b,
+                                   double lambda, const tikh_c64* x, const tikh_c64* gx, tikh_c64* g_col,
+                                   tikh_c64* g_row, tikh_c64* g_b, double* g_lambda) {
+    return backward_single(col, row, m, n, b, lambda, x, gx, g_col, g_row, g_b, g_lambda, 1);
+}
+
+int tikh_toeplitz_solve_backward_batched(int64_t nprob, const int64_t* m, const int64_t* n, const void* col,
+                                         const void* row, int64_t nlam, const double* lambdas, int64_t nrhs,
+                                         const void* b, const void* x, const void* gx, void* g_col, void* g_row,
+                                         void* g_b, double* g_lambda, int32_t* info, int complex_data) {
+    ensure_init();
+    if (nprob < 0 || nlam < 1 || nrhs < 1 || !m || !n || !lambdas) return TIKH_EINVAL;
+    if (nprob == 0) return TIKH_OK;
+    if (!col || !row || !b || !x || !gx || !g_col || !g_row || !g_b || !g_lambda) return TIKH_EINVAL;
+    const size_t es = complex_data ? sizeof(double2) : sizeof(double);
+    std::vector<SolveDesc> sds;
+    sds.reserve((size_t)(nprob * nlam * nrhs));
+    int64_t co = 0, ro = 0, bo = 0, xo = 0, gco = 0, gro = 0, gbo = 0, si = 0;
+    for (int64_t p = 0; p < nprob; ++p) {
+        if (m[p] < 1 || n[p] < 1) return TIKH_EINVAL;
+        for (int64_t l = 0; l < nlam; ++l) {
+            double lam = lambdas[p * nlam + l];
+            if (bad_lambda(lam)) return TIKH_EINVAL;
+            for (int64_t r = 0; r < nrhs; ++r) {
+                SolveDesc d{};
+                const int64_t u = l * nrhs + r;
+                d.col = (const char*)col + es * co;
+                d.row = (const char*)row + es * ro;
+                d.bin = (const char*)b + es * (bo + r * m[p]);
+                d.xin = (const char*)x + es * (xo + u * n[p]);
+                d.rhs = (const char*)gx + es * (xo + u * n[p]);
+                d.gcol = (char*)g_col + es * (gco + u * m[p]);
+                d.grow = (char*)g_row + es * (gro + u * n[p]);
+                d.gb = (char*)g_b + es * (gbo + u * m[p]);
+                d.glam = g_lambda + si;
+                d.m = m[p]; d.n = n[p]; d.lam = lam; d.cplx = complex_data ? 1 : 0; d.mode = 1; d.backward = 1;
+                sds.push_back(d);
+                ++si;
+            }
+        }
+        co += m[p]; ro += n[p]; bo += nrhs * m[p]; xo += nlam * nrhs * n[p];
+        gco += nlam * nrhs * m[p]; gro += nlam * nrhs * n[p]; gbo += nlam * nrhs * m[p];
+    }
+    return run_solves(sds, info);
 }
 
 }  // extern "C"

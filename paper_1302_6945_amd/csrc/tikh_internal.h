@@ -23,6 +23,15 @@ struct SolveDesc {
     double lam;
     int32_t cplx;      // element type of col/row/rhs/x: 0 real double, 1 complex
     int32_t mode;      // 0: least squares with b, 1: normal form with y
+    // backward (adjoint) solves only: rhs = upstream gradient gx (mode 1)
+    const void* bin;   // forward right-hand side b[m]
+    const void* xin;   // forward solution x[n]
+    void* gcol;        // dL/d col [m]
+    void* grow;        // dL/d row [n]
+    void* gb;          // dL/d b [m]
+    double* glam;      // dL/d lambda (scalar)
+    int32_t backward;
+    int32_t pad;
 };
 
 // Per-solve running state of the recursion.

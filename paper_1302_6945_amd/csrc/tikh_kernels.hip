@@ -295,7 +295,8 @@ __global__ void k_build_ct(const SolveDesc* __restrict__ sd, const double* __res
 
 // dst[i] = scale * src[off + i] for i < len, 0 for len <= i < N.
 // src is either a user array (per-solve pointer in SolveDesc: which = 0 rhs,
-// 1 x) or an internal complex buffer (isrc != nullptr).
+// 1 x, 2 the forward solution xin of an adjoint solve) or an internal complex
+// buffer (isrc != nullptr).
 __global__ void k_load_pad(const SolveDesc* __restrict__ sd, int which, const double2* __restrict__ isrc,
                            int64_t isrc_stride, int len_kind, int64_t off, double scale,
                            double2* __restrict__ dst, int64_t N, int64_t stride) {
@@ -306,7 +307,7 @@ __global__ void k_load_pad(const SolveDesc* __restrict__ sd, int which, const do
         double2 v = c2(0.0, 0.0);
         if (i < len) {
             if (isrc) v = isrc[s * isrc_stride + off + i];
-            else v = load_elem(which == 0 ? d.rhs : (const void*)d.x, off + i, d.cplx);
+            else v = load_elem(which == 0 ? d.rhs : (which == 1 ? (const void*)d.x : d.xin), off + i, d.cplx);
             v = cscale(v, scale);
         }
         dst[s * stride + i] = v;
@@ -853,6 +854,74 @@ __global__ void k_store_x(const SolveDesc* __restrict__ sd, const double2* __res
         else ((double*)d.x)[i] = v.x;
     }
     if (info && blockIdx.x == 0 && threadIdx.x == 0) info[s] = st[s].info;
+}
+
+// ---------------------------------------------------------------- adjoint (backward)
+// Gradients of a loss through x = (T^H T + lam^2 I)^{-1} T^H b (eq. (tiksol)), given
+// w = (T^H T + lam^2 I)^{-1} gx:  g_b = T w,  g_lam = -2 lam Re<w, x>,
+// g_{a_s} = sum_{i-j=s} [(b - T x) w^H - (T w) x^H]_{ij}, a lag-s cross-correlation.
+
+// out[i] = user_b[i] - v[i] for i < m  (r = b - T x)
+__global__ void k_sub_from_b(const SolveDesc* __restrict__ sd, const double2* __restrict__ v, double2* __restrict__ out,
+                             int64_t stride) {
+    const int64_t s = blockIdx.y;
+    const SolveDesc d = sd[s];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < d.m; i += (int64_t)gridDim.x * blockDim.x)
+        out[s * stride + i] = csub(load_elem(d.bin, i, d.cplx), v[s * stride + i]);
+}
+
+// dst = A * conj(B) (accumulate = 0) or dst -= A * conj(B) (accumulate = 1), length N
+__global__ void k_xcorr_spec(const double2* __restrict__ A, const double2* __restrict__ B, double2* dst,
+                             int64_t N, int64_t stride, int accumulate) {
+    const int64_t s = blockIdx.y;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+        double2 v = cmul(A[s * stride + i], cconj(B[s * stride + i]));
+        dst[s * stride + i] = accumulate ? csub(dst[s * stride + i], v) : v;
+    }
+}
+
+// Lag sums (already inverse transformed, scale 1/N): g_col[s] = G[s] (s < m),
+// g_row[s] = G[N - s] (0 < s < n), g_row[0] = 0; g_b = T w.
+__global__ void k_store_grads(const SolveDesc* __restrict__ sd, const double2* __restrict__ G, int64_t N,
+                              int64_t gstride, double invN, const double2* __restrict__ Tw, int64_t vstride) {
+    const int64_t s = blockIdx.y;
+    const SolveDesc d = sd[s];
+    const int64_t tot = d.m + d.n + d.m;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < tot; u += (int64_t)gridDim.x * blockDim.x) {
+        double2 v;
+        void* out;
+        int64_t i;
+        if (u < d.m) { i = u; v = cscale(G[s * gstride + i], invN); out = d.gcol; }
+        else if (u < d.m + d.n) { i = u - d.m; v = i == 0 ? c2(0.0, 0.0) : cscale(G[s * gstride + N - i], invN); out = d.grow; }
+        else { i = u - d.m - d.n; v = Tw[s * vstride + i]; out = d.gb; }
+        if (d.cplx) ((double2*)out)[i] = v;
+        else ((double*)out)[i] = v.x;
+    }
+}
+
+// g_lam = -2 lam Re sum_j conj(w_j) x_j
+__global__ __launch_bounds__(256) void k_grad_lambda(const SolveDesc* __restrict__ sd, const double2* __restrict__ w,
+                                                     int64_t stride, SolveState* __restrict__ st,
+                                                     int32_t* __restrict__ info) {
+    const int64_t s = blockIdx.x;
+    const SolveDesc d = sd[s];
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < d.n; i += blockDim.x) {
+        double2 wv = w[s * stride + i];
+        double2 xv = load_elem(d.xin, i, d.cplx);
+        acc += wv.x * xv.x + wv.y * xv.y;
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        *d.glam = -2.0 * d.lam * red[0];
+        if (info) info[s] = st[s].info;
+    }
 }
 
 __global__ void k_init_state(const SolveDesc* __restrict__ sd, SolveState* __restrict__ st, int nsolve, int keep_info) {

@@ -1,0 +1,128 @@
+"""GPU adjoint (backward) through the C ABI, against the CPU oracle's
+hand-derived gradients (dense FP64), against central finite differences of the
+GPU forward solve, and through torch.autograd."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle
+import workloads as W
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1302_6945_amd as P
+    P.set_options(n_lim=256, refine=1)
+    return P
+
+
+def dev(a):
+    return torch.tensor(np.asarray(a), device="cuda:0")
+
+
+def rel(a, b):
+    return np.linalg.norm(np.asarray(a) - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.mark.parametrize("m,n,cplx", [(20, 13, False), (13, 20, True), (150, 97, False), (120, 160, True),
+                                      (576, 512, True)])
+def test_backward_vs_oracle(P, m, n, cplx):
+    rng = np.random.default_rng(m * 31 + n + cplx)
+    col, row, b = W.random_problem(rng, m, n, cplx=cplx, L=16.0)
+    lam = 0.3
+    xt = rng.standard_normal(n) + (1j * rng.standard_normal(n) if cplx else 0)
+    x = P.solve(dev(col), dev(row), dev(b), lam)
+    gx = x - dev(xt)                       # L = 0.5 ||x - x_true||^2
+    g_col, g_row, g_b, g_lam = P.backward(dev(col), dev(row), dev(b), lam, x, gx)
+    ref = oracle.gradients(col, row, b, lam, x.cpu().numpy() - xt)
+    ref_row = ref["g_row"].copy(); ref_row[0] = 0
+    for got, want in ((g_col, ref["g_col"]), (g_row, ref_row), (g_b, ref["g_b"])):
+        got = got.cpu().numpy()
+        want = want if cplx else want.real
+        assert rel(got, want) <= 1e-9
+    assert abs(float(g_lam) - ref["g_lam"]) <= 1e-9 * max(1.0, abs(ref["g_lam"]))
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_backward_central_differences(P, cplx):
+    """Central differences of the GPU forward solve, h = 1e-6, 16 random unit directions."""
+    rng = np.random.default_rng(77 + cplx)
+    m, n = 90, 64
+    col, row, b = W.random_problem(rng, m, n, cplx=cplx, L=12.0)
+    lam = 0.4
+    xt = rng.standard_normal(n) + (1j * rng.standard_normal(n) if cplx else 0)
+
+    def loss(c, r, bb, l):
+        x = P.solve(dev(c), dev(r), dev(bb), l).cpu().numpy()
+        return 0.5 * np.sum(np.abs(x - xt) ** 2)
+
+    x = P.solve(dev(col), dev(row), dev(b), lam)
+    g_col, g_row, g_b, g_lam = [t.cpu().numpy() if hasattr(t, "cpu") else t
+                                for t in P.backward(dev(col), dev(row), dev(b), lam, x, x - dev(xt))]
+    g_lam = float(g_lam)
+    h = 1e-6
+    for _ in range(16):
+        dc = rng.standard_normal(m) + (1j * rng.standard_normal(m) if cplx else 0)
+        dr = rng.standard_normal(n) + (1j * rng.standard_normal(n) if cplx else 0); dr[0] = 0
+        db = rng.standard_normal(m) + (1j * rng.standard_normal(m) if cplx else 0)
+        dl = rng.standard_normal()
+        nrm = np.sqrt(np.sum(np.abs(dc) ** 2) + np.sum(np.abs(dr) ** 2) + np.sum(np.abs(db) ** 2) + dl ** 2)
+        dc, dr, db, dl = dc / nrm, dr / nrm, db / nrm, dl / nrm
+        fd = (loss(col + h * dc, row + h * dr, b + h * db, lam + h * dl)
+              - loss(col - h * dc, row - h * dr, b - h * db, lam - h * dl)) / (2 * h)
+        an = (np.sum((np.conj(g_col) * dc).real) + np.sum((np.conj(g_row) * dr).real)
+              + np.sum((np.conj(g_b) * db).real) + g_lam * dl)
+        assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (fd, an)
+
+
+def test_autograd_function(P):
+    rng = np.random.default_rng(9)
+    col, row, b = W.random_problem(rng, 70, 50, L=10.0)
+    xt = dev(rng.standard_normal(50))
+    c, r, bb = dev(col).requires_grad_(), dev(row).requires_grad_(), dev(b).requires_grad_()
+    lam = torch.tensor(0.25, dtype=torch.float64, device="cuda:0", requires_grad=True)
+    x = P.tikhonov_solve(c, r, bb, lam)
+    L = 0.5 * ((x - xt) ** 2).sum()
+    L.backward()
+    ref = oracle.gradients(col, row, b, 0.25, x.detach().cpu().numpy() - xt.cpu().numpy())
+    assert rel(c.grad.cpu().numpy(), ref["g_col"].real) <= 1e-9
+    assert rel(bb.grad.cpu().numpy(), ref["g_b"].real) <= 1e-9
+    assert abs(float(lam.grad) - ref["g_lam"]) <= 1e-9 * max(1, abs(ref["g_lam"]))
+
+
+def test_backward_batched_matches_single(P):
+    rng = np.random.default_rng(123)
+    shapes = [(60, 40), (35, 70)]
+    nlam, nrhs = 2, 2
+    cols, rows, bs, lams, xs, gxs = [], [], [], [], [], []
+    for (m, n) in shapes:
+        col, row, _ = W.random_problem(rng, m, n, L=9.0)
+        cols.append(col); rows.append(row)
+        B = [rng.standard_normal(m) for _ in range(nrhs)]
+        bs.extend(B)
+        L = [0.2, 0.7]
+        lams.extend(L)
+    ms = [s[0] for s in shapes]; ns = [s[1] for s in shapes]
+    x, info = P.solve_batched(ms, ns, dev(np.concatenate(cols)), dev(np.concatenate(rows)), lams, nrhs,
+                              dev(np.concatenate(bs)))
+    gx = dev(rng.standard_normal(x.numel()))
+    g_col, g_row, g_b, g_lam, info = P.backward_batched(ms, ns, dev(np.concatenate(cols)), dev(np.concatenate(rows)),
+                                                        lams, nrhs, dev(np.concatenate(bs)), x, gx)
+    torch.cuda.synchronize()
+    assert (info.cpu().numpy() == 0).all()
+    xo = co = ro = 0; k = 0
+    for pi, (m, n) in enumerate(shapes):
+        for li in range(nlam):
+            for ri in range(nrhs):
+                xs_ = x[xo:xo + n]; gx_ = gx[xo:xo + n]
+                gc, gr, gb, gl = P.backward(dev(cols[pi]), dev(rows[pi]), dev(bs[pi * nrhs + ri]), lams[pi * nlam + li],
+                                            xs_, gx_)
+                assert rel(g_col[co:co + m].cpu().numpy(), gc.cpu().numpy()) <= 1e-12
+                assert rel(g_row[ro:ro + n].cpu().numpy(), gr.cpu().numpy()) <= 1e-12
+                assert rel(g_b[co:co + m].cpu().numpy(), gb.cpu().numpy()) <= 1e-12
+                assert abs(float(g_lam[k]) - float(gl)) <= 1e-12 * max(1, abs(float(gl)))
+                xo += n; co += m; ro += n; k += 1
