@@ -86,6 +86,16 @@ typedef struct {
  */
 int tikh_plan_info(int64_t m, int64_t n, int32_t n_lim, int64_t* N, int64_t* M, int32_t* depth, int64_t* k);
 
+/*
+ * Launch timing of one kernel kind (for benchmarks): after
+ * tikh_profile_kernel("leaf_loop" | "leaf_build" | "fft"), each launch of that
+ * kernel is bracketed by HIP events on the library stream; tikh_profile_read
+ * synchronizes the stream and returns the summed duration (ms) and the launch
+ * count since the last tikh_profile_kernel call.  NULL or "" disables.
+ */
+int tikh_profile_kernel(const char* name);
+int tikh_profile_read(double* total_ms, int64_t* count);
+
 /* Library state.  tikh_init is optional (the first call initializes). */
 int tikh_init(void);
 int tikh_release(void);                              /* free workspace */

@@ -39,6 +39,8 @@ tikh_plan_info = _sig("tikh_plan_info", [_I64, _I64, ctypes.c_int32, ctypes.POIN
                                          ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
                                          ctypes.POINTER(ctypes.c_int64)])
 _sig("tikh_release", [])
+_sig("tikh_profile_kernel", [ctypes.c_char_p])
+_sig("tikh_profile_read", [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)])
 _sig("tikh_set_stream", [_P])
 _sig("tikh_set_options", [ctypes.POINTER(_Opts)])
 _sig("tikh_get_options", [ctypes.POINTER(_Opts)])
@@ -97,6 +99,18 @@ def plan_info(m, n, n_lim=256):
     _check(tikh_plan_info(int(m), int(n), int(n_lim), ctypes.byref(N), ctypes.byref(M), ctypes.byref(p),
                           ctypes.byref(k)), "tikh_plan_info")
     return N.value, M.value, p.value, k.value
+
+
+def profile_kernel(name):
+    """Time every launch of one kernel kind with HIP events (None disables)."""
+    _check(lib.tikh_profile_kernel(name.encode() if name else None), "tikh_profile_kernel")
+
+
+def profile_read():
+    """(total_ms, launches) of the profiled kernel since profile_kernel()."""
+    t = ctypes.c_double(); c = ctypes.c_int64()
+    _check(lib.tikh_profile_read(ctypes.byref(t), ctypes.byref(c)), "tikh_profile_read")
+    return t.value, c.value
 
 
 def get_stats():

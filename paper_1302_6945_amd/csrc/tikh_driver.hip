@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <string>
 #include <vector>
 
 namespace tikh {
@@ -40,6 +41,47 @@ struct Ctx {
     int64_t launches = 0;
 };
 static Ctx g;
+
+// Optional timing of one kernel kind: HIP event pairs recorded on the library
+// stream around each launch whose name matches (used by the benchmark to
+// measure the dominant kernel's average launch duration live).
+struct KProf {
+    std::string name;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    double total_ms = 0.0;
+    int64_t count = 0;
+};
+static KProf kprof;
+
+static bool prof_on(const char* name) { return !kprof.name.empty() && kprof.name == name; }
+static void prof_begin(const char* name) {
+    if (!prof_on(name)) return;
+    if (kprof.used + 2 > kprof.pool.size()) {
+        for (int i = 0; i < 256; ++i) { hipEvent_t e; if (hipEventCreate(&e) == hipSuccess) kprof.pool.push_back(e); }
+    }
+    if (kprof.used + 2 <= kprof.pool.size()) (void)hipEventRecord(kprof.pool[kprof.used], g.stream);
+}
+static void prof_end(const char* name) {
+    if (!prof_on(name)) return;
+    if (kprof.used + 2 <= kprof.pool.size()) { (void)hipEventRecord(kprof.pool[kprof.used + 1], g.stream); kprof.used += 2; }
+}
+static void prof_collect() {
+    if (kprof.used == 0) return;
+    (void)hipStreamSynchronize(g.stream);
+    for (size_t i = 0; i + 1 < kprof.used; i += 2) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, kprof.pool[i], kprof.pool[i + 1]) == hipSuccess) { kprof.total_ms += ms; kprof.count++; }
+    }
+    kprof.used = 0;
+}
+#define LAUNCH(kname, kern, grid, block, ...)                                              \
+    do {                                                                                 \
+        prof_begin(kname);                                                               \
+        hipLaunchKernelGGL(kern, grid, block, 0, g.stream, __VA_ARGS__);                 \
+        prof_end(kname);                                                                 \
+        g.launches++;                                                                    \
+    } while (0)
 
 static void ensure_init() {
     if (g.init) return;
@@ -247,8 +289,7 @@ static int fft_lines(double2* data, int64_t S, int64_t sstride, int64_t nlines, 
         a.lines_inner = nlines; a.outer_stride = 0;
         a.lpw = (int)std::max<int64_t>(1, std::min<int64_t>(FFT_LDS_MAX / Lf, 64));
         dim3 gr((unsigned)((nlines + a.lpw - 1) / a.lpw), (unsigned)S);
-        hipLaunchKernelGGL(k_fft, gr, dim3(FFT_THREADS), 0, g.stream, a);
-        g.launches++;
+        LAUNCH("fft", k_fft, gr, dim3(FFT_THREADS), a);
         return TIKH_OK;
     }
     // four-step: Lf = L1 * L2
@@ -289,20 +330,19 @@ static int run_leaf(const Plan& pl, const Layout& L, const Bufs& b, int64_t S, i
     LeafArgs la{};
     la.sd = b.sd; la.st = b.st; la.phi = b.phi; la.phi_stride = L.sphi; la.rec = b.rec;
     la.rec_stride = pl.K; la.N = pl.N; la.M = pl.M; la.p = pl.p; la.K = pl.K; la.leaf = t; la.tw = tw; la.Q = pl.Q;
-    if (pl.K <= 64) hipLaunchKernelGGL(k_leaf_loop<1>, dim3((unsigned)S), dim3(64), 0, g.stream, la);
-    else if (pl.K <= 128) hipLaunchKernelGGL(k_leaf_loop<2>, dim3((unsigned)S), dim3(64), 0, g.stream, la);
-    else if (pl.K <= 192) hipLaunchKernelGGL(k_leaf_loop<3>, dim3((unsigned)S), dim3(64), 0, g.stream, la);
-    else hipLaunchKernelGGL(k_leaf_loop<4>, dim3((unsigned)S), dim3(64), 0, g.stream, la);
+    if (pl.K <= 64) LAUNCH("leaf_loop", k_leaf_loop<1>, dim3((unsigned)S), dim3(64), la);
+    else if (pl.K <= 128) LAUNCH("leaf_loop", k_leaf_loop<2>, dim3((unsigned)S), dim3(64), la);
+    else if (pl.K <= 192) LAUNCH("leaf_loop", k_leaf_loop<3>, dim3((unsigned)S), dim3(64), la);
+    else LAUNCH("leaf_loop", k_leaf_loop<4>, dim3((unsigned)S), dim3(64), la);
     BuildArgs ba{};
     ba.st = b.st; ba.rec = b.rec; ba.rec_stride = pl.K; ba.out = dst; ba.out_stride = 20 * (dcap + 1);
     ba.cap = dcap; ba.meta = dmeta; ba.K = pl.K;
     int slots = (int)((std::min<int64_t>(dcap, pl.K) + 1 + 63) / 64);
-    if (slots <= 1) hipLaunchKernelGGL(k_leaf_build<1>, dim3((unsigned)S), dim3(256), 0, g.stream, ba);
-    else if (slots <= 2) hipLaunchKernelGGL(k_leaf_build<2>, dim3((unsigned)S), dim3(256), 0, g.stream, ba);
-    else if (slots <= 3) hipLaunchKernelGGL(k_leaf_build<3>, dim3((unsigned)S), dim3(256), 0, g.stream, ba);
-    else if (slots <= 4) hipLaunchKernelGGL(k_leaf_build<4>, dim3((unsigned)S), dim3(256), 0, g.stream, ba);
-    else hipLaunchKernelGGL(k_leaf_build<5>, dim3((unsigned)S), dim3(256), 0, g.stream, ba);
-    g.launches += 2;
+    if (slots <= 1) LAUNCH("leaf_build", k_leaf_build<1>, dim3((unsigned)S), dim3(256), ba);
+    else if (slots <= 2) LAUNCH("leaf_build", k_leaf_build<2>, dim3((unsigned)S), dim3(256), ba);
+    else if (slots <= 3) LAUNCH("leaf_build", k_leaf_build<3>, dim3((unsigned)S), dim3(256), ba);
+    else if (slots <= 4) LAUNCH("leaf_build", k_leaf_build<4>, dim3((unsigned)S), dim3(256), ba);
+    else LAUNCH("leaf_build", k_leaf_build<5>, dim3((unsigned)S), dim3(256), ba);
     return TIKH_OK;
 }
 
@@ -622,6 +662,23 @@ using namespace tikh;
 extern "C" {
 
 int tikh_init(void) { ensure_init(); return TIKH_OK; }
+
+int tikh_profile_kernel(const char* name) {
+    ensure_init();
+    prof_collect();
+    kprof.name = name ? std::string(name) : std::string();
+    kprof.total_ms = 0.0;
+    kprof.count = 0;
+    return TIKH_OK;
+}
+
+int tikh_profile_read(double* total_ms, int64_t* count) {
+    if (!total_ms || !count) return TIKH_EINVAL;
+    prof_collect();
+    *total_ms = kprof.total_ms;
+    *count = kprof.count;
+    return TIKH_OK;
+}
 
 int tikh_plan_info(int64_t m, int64_t n, int32_t n_lim, int64_t* N, int64_t* M, int32_t* depth, int64_t* k) {
     if (m < 1 || n < 1 || n_lim < 4 || !N || !M || !depth || !k) return TIKH_EINVAL;

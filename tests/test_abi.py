@@ -12,7 +12,10 @@ HEADER = os.path.join(ROOT, "include", "tikh.h")
 
 
 def _ensure_built():
-    from paper_1302_6945_amd import build as B
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("_tikh_build", os.path.join(ROOT, "paper_1302_6945_amd", "build.py"))
+    B = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(B)
     if B.needs_build():
         B.build()
     return B.LIB
