@@ -108,7 +108,8 @@ const char* tikh_strerror(int code);
 /*
  * Single problem, real data: col[m], row[n], b[m] -> x[n] (device, FP64).
  * lambda must be finite and > 0 (lambda = 0 is the pseudo-inverse problem,
- * outside this solver).  Synchronizes; returns TIKH_ENUMERIC if info != 0.
+ * outside this solver); the extended size N (about m + n) must not exceed
+ * 2^19.  Synchronizes; returns TIKH_ENUMERIC if info != 0.
  */
 int tikh_toeplitz_solve(const double* col, const double* row, int64_t m, int64_t n,
                         const double* b, double lambda, double* x);

@@ -39,6 +39,8 @@ struct Ctx {
     size_t ws_size = 0;
     std::map<int64_t, double2*> tw;      // twiddle tables by size Q
     int64_t launches = 0;
+    int* dneed = nullptr;                // device / pinned host word for degree readback
+    int* hneed = nullptr;
 };
 static Ctx g;
 
@@ -87,6 +89,8 @@ static void ensure_init() {
     if (g.init) return;
     g.opts.n_lim = 256;
     g.opts.refine = 1;
+    if (hipMalloc((void**)&g.dneed, sizeof(int)) != hipSuccess) g.dneed = nullptr;
+    if (hipHostMalloc((void**)&g.hneed, sizeof(int), hipHostMallocDefault) != hipSuccess) g.hneed = nullptr;
     g.init = true;
 }
 
@@ -172,59 +176,109 @@ static double2* twiddles(int64_t Q) {
     return d;
 }
 
+// subtrees with at most this many conditions are merged by the direct kernels
+static const int64_t DIRECT_MAX_COND = 256;
+
 // ---------------------------------------------------------------- workspace layout
+// A bucket holds G groups of nr solves (nr right-hand sides of one operator).
+// Group data: symbol, interpolation data, step records, basis slots.
+// Solve data: per right-hand side FFT lines and vectors.
 struct Layout {
-    int64_t nmax;                    // max n over the chunk
-    int64_t mmax;
-    // per-solve strides in double2 units
+    int nr, C;
+    int64_t nmax, mmax;
+    // strides in double2 units
     int64_t sN, sn, sphi, srec, sV, sF, sscr;
     int64_t sslot[40];
-    int64_t Lmax, Pmax, nF;
-    size_t per_solve_bytes;
+    int64_t sT;                      // stride of the shared right-child slot
+    int64_t tOff;                    // offset of odd-depth results inside it
+    int64_t Lmax;
+    size_t group_bytes;              // per group, held for the whole solve
+    size_t solve_bytes;              // per right-hand side
+    size_t temp_bytes;               // per group of a merge chunk (evaluation and product scratch)
 };
 
-static void make_layout(const Plan& pl, int64_t mmax, int64_t nmax, Layout* L) {
+static void make_layout(const Plan& pl, int nr, int64_t mmax, int64_t nmax, Layout* L) {
+    L->nr = nr; L->C = 4 + nr;
+    const int64_t E = 4 * L->C;      // stored basis entries
     L->nmax = nmax; L->mmax = mmax;
     L->sN = pl.N;
     L->sn = std::max(mmax, nmax);
-    L->sphi = 10 * pl.N;
+    L->sphi = (int64_t)L->C * 2 * pl.N;
     L->srec = (int64_t)pl.K * (int64_t)(sizeof(LeafRec) / sizeof(double2));
     L->Lmax = pl.p >= 1 ? pl.N / 4 : 1;
-    L->sV = 40 * L->Lmax;
+    L->sV = 2 * E * L->Lmax;
     int64_t fmax = 1;
-    for (int d = 0; d < pl.p; ++d) fmax = std::max(fmax, (d == 0 ? 5 : 20) * pl.P[d]);
+    for (int d = 0; d < pl.p; ++d) fmax = std::max(fmax, (d == 0 ? std::max<int64_t>(L->C, 4 * nr) : E) * pl.P[d]);
     L->sF = fmax;
-    L->sscr = std::max(std::max(L->sV, L->sF), pl.N);
+    L->sscr = std::max(L->sV, L->sF);
     size_t tot = 0;
-    tot += 4 * L->sN + 4 * L->sn + L->sphi + L->srec + L->sV + 2 * L->sF + L->sscr;
+    tot += L->sN + L->sphi + L->srec;
+    // pending left children: one slot per depth; right-child results: one
+    // shared slot (a right child's basis is consumed by the next product,
+    // which reads it completely before it writes its own result).  Results
+    // at odd depths sit at offset tOff, so a fused direct product (which reads
+    // its right factor while it writes the parent) never overwrites its input.
+    L->sT = 0;
+    L->tOff = 0;
     for (int d = 0; d <= pl.p; ++d) {
-        L->sslot[d] = 20 * (pl.cap[d] + 1);
-        tot += 2 * L->sslot[d];
+        L->sslot[d] = E * (pl.cap[d] + 1);
+        if (d >= 1) tot += L->sslot[d];
+        if (((2 * pl.N) >> d) <= 2 * DIRECT_MAX_COND || d >= pl.p - 1) L->tOff = std::max(L->tOff, L->sslot[d]);
     }
-    L->per_solve_bytes = tot * sizeof(double2) + 2 * (pl.p + 1) * sizeof(SlotMeta) + sizeof(SolveState) +
-                         sizeof(SolveDesc) + sizeof(double) + 64;
+    for (int d = 0; d <= pl.p; ++d) {
+        int64_t sz = (d == 0 && pl.p > 0) ? (int64_t)(4 + nr) * (pl.cap[0] + 1) : L->sslot[d];
+        L->sT = std::max(L->sT, ((d & 1) ? L->tOff : 0) + sz);
+    }
+    tot += L->sT;
+    L->group_bytes = tot * sizeof(double2) + 2 * (pl.p + 1) * sizeof(SlotMeta) + sizeof(SolveState) + sizeof(double) + 256;
+    L->solve_bytes = (size_t)(4 * L->sN + 4 * L->sn) * sizeof(double2) + sizeof(SolveDesc) + 64;
+    L->temp_bytes = (size_t)(L->sV + 2 * L->sF + L->sscr) * sizeof(double2);
 }
 
 struct Bufs {
-    SolveDesc* sd;
-    SolveState* st;
-    double* rms;
-    double2 *chat, *bA, *bB, *bC;
-    double2 *yv, *xacc, *t1, *t2;
-    double2* phi;
-    LeafRec* rec;
-    double2* V;
-    double2 *FL, *FR, *FO, *scr;
+    int nr;
+    SolveDesc* sd;                   // [G*nr]
+    SolveState* st;                  // [G]
+    double* rms;                     // [G]
+    double2* chat;                   // [G][N]
+    double2 *bA, *bB, *bC, *bS;      // [G*nr][N]
+    double2 *yv, *xacc, *t1, *t2;    // [G*nr][sn]
+    double2* phi;                    // [G][C][2N]
+    LeafRec* rec;                    // [G][K]
     double2* slotS[40];
     double2* slotT[40];
     SlotMeta* metaS[40];
     SlotMeta* metaT[40];
+    // merge scratch shared by the groups of one merge chunk
+    double2* V;
+    double2 *FL, *FR, *scr;
+    int64_t chunk;                   // groups per merge chunk
     int* elist;                      // device entry lists
 };
 
+// Group pointers advanced by c0 groups, solve pointers by c0*nr solves
+// (merge scratch and entry lists stay).
+static Bufs shift_bufs(const Bufs& b, const Layout& L, const Plan& pl, int64_t c0) {
+    Bufs o = b;
+    const int64_t s0 = c0 * b.nr;
+    o.sd += s0; o.st += c0; o.rms += c0;
+    o.chat += c0 * L.sN;
+    o.bA += s0 * L.sN; o.bB += s0 * L.sN; o.bC += s0 * L.sN; o.bS += s0 * L.sN;
+    o.yv += s0 * L.sn; o.xacc += s0 * L.sn; o.t1 += s0 * L.sn; o.t2 += s0 * L.sn;
+    o.phi += c0 * L.sphi;
+    o.rec += c0 * pl.K;
+    for (int d = 0; d <= pl.p; ++d) {
+        if (b.slotS[d]) o.slotS[d] = b.slotS[d] + c0 * L.sslot[d];
+        o.slotT[d] = b.slotT[d] + c0 * L.sT;
+        o.metaS[d] = b.metaS[d] + c0;
+        o.metaT[d] = b.metaT[d] + c0;
+    }
+    return o;
+}
+
 static int ensure_ws(size_t bytes) {
     if (bytes <= g.ws_size) return TIKH_OK;
-    if (g.ws) { hipStreamSynchronize(g.stream); hipFree(g.ws); g.ws = nullptr; g.ws_size = 0; }
+    if (g.ws) { (void)hipStreamSynchronize(g.stream); (void)hipFree(g.ws); g.ws = nullptr; g.ws_size = 0; }
     if (hipMalloc(&g.ws, bytes) != hipSuccess) { g.ws = nullptr; return TIKH_ENOMEM; }
     g.ws_size = bytes;
     return TIKH_OK;
@@ -236,34 +290,54 @@ static char* carve(char*& p, size_t bytes) {
     return r;
 }
 
-// entry lists (fixed): all 20 entries; left row 0 = {0..4}; right column 5 = {4, 9, 14, 19}; x entry = {4}
-static const int h_elist[20 + 5 + 4 + 1] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19,
-                                           0, 1, 2, 3, 4, 4, 9, 14, 19, 4};
-enum { EL_ALL = 0, EL_ROW0 = 20, EL_COL5 = 25, EL_X = 29 };
+// Entry lists of the product (entry e = row * C + column):
+//   all 4C entries; root: left row 0 (C entries), right columns 4..C-1 of rows 0..3, output row 0 columns 4..C-1.
+struct EList {
+    int all[4 * MAXC];
+    int row0[MAXC];
+    int vcols[4 * MAXNR];
+    int xout[MAXNR];
+};
+static EList make_elist(int nr) {
+    EList e{};
+    const int C = 4 + nr;
+    for (int i = 0; i < 4 * C; ++i) e.all[i] = i;
+    for (int j = 0; j < C; ++j) e.row0[j] = j;
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < nr; ++j) e.vcols[i * nr + j] = i * C + 4 + j;
+    for (int j = 0; j < nr; ++j) e.xout[j] = 4 + j;
+    return e;
+}
 
-static int carve_bufs(const Plan& pl, const Layout& L, int64_t S, Bufs* b) {
-    size_t need = 0;
-    need += (size_t)S * L.per_solve_bytes + 64 * 1024 + 256 * 64;
+static int carve_bufs(const Plan& pl, const Layout& L, int64_t G, int64_t CH, Bufs* b) {
+    const int nr = L.nr;
+    const int64_t S = G * nr;
+    size_t need = (size_t)G * L.group_bytes + (size_t)S * L.solve_bytes + (size_t)CH * L.temp_bytes + 64 * 1024 +
+                  256 * 128;
     int rc = ensure_ws(need);
     if (rc) return rc;
     char* p = g.ws;
+    b->nr = nr;
+    b->chunk = CH;
     b->sd = (SolveDesc*)carve(p, sizeof(SolveDesc) * S);
-    b->st = (SolveState*)carve(p, sizeof(SolveState) * S);
-    b->rms = (double*)carve(p, sizeof(double) * S);
-    b->elist = (int*)carve(p, sizeof(h_elist));
-    auto cv = [&](int64_t per) { return (double2*)carve(p, sizeof(double2) * per * S); };
-    b->chat = cv(L.sN); b->bA = cv(L.sN); b->bB = cv(L.sN); b->bC = cv(L.sN);
-    b->yv = cv(L.sn); b->xacc = cv(L.sn); b->t1 = cv(L.sn); b->t2 = cv(L.sn);
-    b->phi = cv(L.sphi);
-    b->rec = (LeafRec*)cv(L.srec);
-    b->V = cv(L.sV);
-    b->FL = cv(L.sF); b->FR = cv(L.sF); b->FO = nullptr; b->scr = cv(L.sscr);
+    b->st = (SolveState*)carve(p, sizeof(SolveState) * G);
+    b->rms = (double*)carve(p, sizeof(double) * G);
+    b->elist = (int*)carve(p, sizeof(EList));
+    auto cv = [&](int64_t per, int64_t cnt) { return (double2*)carve(p, sizeof(double2) * per * cnt); };
+    b->chat = cv(L.sN, G);
+    b->bA = cv(L.sN, S); b->bB = cv(L.sN, S); b->bC = cv(L.sN, S); b->bS = cv(L.sN, S);
+    b->yv = cv(L.sn, S); b->xacc = cv(L.sn, S); b->t1 = cv(L.sn, S); b->t2 = cv(L.sn, S);
+    b->phi = cv(L.sphi, G);
+    b->rec = (LeafRec*)cv(L.srec, G);
+    double2* tslot = cv(L.sT, G);
     for (int d = 0; d <= pl.p; ++d) {
-        b->slotS[d] = cv(L.sslot[d]);
-        b->slotT[d] = cv(L.sslot[d]);
-        b->metaS[d] = (SlotMeta*)carve(p, sizeof(SlotMeta) * S);
-        b->metaT[d] = (SlotMeta*)carve(p, sizeof(SlotMeta) * S);
+        b->slotS[d] = d >= 1 ? cv(L.sslot[d], G) : nullptr;
+        b->slotT[d] = tslot + ((d & 1) ? L.tOff : 0);
+        b->metaS[d] = (SlotMeta*)carve(p, sizeof(SlotMeta) * G);
+        b->metaT[d] = (SlotMeta*)carve(p, sizeof(SlotMeta) * G);
     }
+    b->V = cv(L.sV, CH);
+    b->FL = cv(L.sF, CH); b->FR = cv(L.sF, CH); b->scr = cv(L.sscr, CH);
     if ((size_t)(p - g.ws) > g.ws_size) return TIKH_ENOMEM;
     return TIKH_OK;
 }
@@ -275,158 +349,248 @@ static inline dim3 grid1(int64_t work, int64_t S, int bs = 256) {
     return dim3((unsigned)gx, (unsigned)S, 1);
 }
 
-// In-place FFT of `nlines` contiguous lines of length Lf per solve
-// (line stride Lf, solve stride sstride), direction `sign`, scratch for the
-// four-step reordering.
-static int fft_lines(double2* data, int64_t S, int64_t sstride, int64_t nlines, int64_t Lf, int sign,
-                     const double2* tw, int64_t Q, double2* scratch, int64_t scr_stride) {
-    if (Lf == 1) return TIKH_OK;
-    FftArgs a{};
-    a.data = data; a.solve_stride = sstride; a.sign = sign; a.scale = 1.0; a.tw = tw; a.Q = Q;
-    if (Lf <= FFT_LDS_MAX) {
-        if (!fft_plan(Lf, &a.pl)) return TIKH_EINVAL;
-        a.line_stride = Lf; a.elem_stride = 1; a.nlines = nlines; a.post_L = 0;
-        a.lines_inner = nlines; a.outer_stride = 0;
-        a.lpw = (int)std::max<int64_t>(1, std::min<int64_t>(FFT_LDS_MAX / Lf, 64));
-        dim3 gr((unsigned)((nlines + a.lpw - 1) / a.lpw), (unsigned)S);
-        LAUNCH("fft", k_fft, gr, dim3(FFT_THREADS), a);
-        return TIKH_OK;
-    }
-    // four-step: Lf = L1 * L2
+// Split of a long FFT into L1 x L2 (both <= FFT_LDS_MAX, balanced); the
+// same split is used for every transform of a given length, so a spectrum
+// left in four-step order by a forward transform is read back correctly by
+// the inverse.  Returns L1 (L1 = Lf for a single-pass length).
+static int64_t fft_split(int64_t Lf) {
+    if (Lf <= FFT_LDS_MAX) return Lf;
     int64_t L1 = 0;
     for (int64_t c = 1; c <= FFT_LDS_MAX; ++c)
         if (Lf % c == 0 && Lf / c <= FFT_LDS_MAX && smooth5(c)) {
             if (L1 == 0 || std::llabs((long long)(c * c - Lf)) < std::llabs((long long)(L1 * L1 - Lf))) L1 = c;
         }
+    return L1;
+}
+
+enum FftOrder {
+    FFT_NATURAL = 0,   // natural order in and out (four-step followed by a reordering pass)
+    FFT_FWD_T = 1,     // natural in, four-step order out: X[j1 + L1 j2] at j1*L2 + j2
+    FFT_INV_T = 2      // four-step order in, natural out
+};
+
+static void fft_pass(double2* data, int64_t S, int64_t sstride, int64_t nlines, int64_t lines_inner,
+                     int64_t line_stride, int64_t outer_stride, int64_t elem_stride, int64_t L, int sign,
+                     int64_t post_L, const double2* tw, int64_t Q, int lpw_cap) {
+    FftArgs a{};
+    a.data = data; a.solve_stride = sstride; a.sign = sign; a.scale = 1.0; a.tw = tw; a.Q = Q;
+    fft_plan(L, &a.pl);
+    a.nlines = nlines; a.lines_inner = lines_inner; a.line_stride = line_stride; a.outer_stride = outer_stride;
+    a.elem_stride = elem_stride; a.post_L = post_L;
+    a.lpw = (int)std::max<int64_t>(1, std::min<int64_t>(FFT_LDS_MAX / L, lpw_cap));
+    dim3 gr((unsigned)((nlines + a.lpw - 1) / a.lpw), (unsigned)S);
+    LAUNCH("fft", k_fft, gr, dim3(FFT_THREADS), a);
+}
+
+// In-place FFT of `nlines` contiguous lines of length Lf per item (line
+// stride Lf, item stride sstride), direction `sign`.
+static int fft_lines(double2* data, int64_t S, int64_t sstride, int64_t nlines, int64_t Lf, int sign,
+                     const double2* tw, int64_t Q, double2* scratch, int64_t scr_stride, int order = FFT_NATURAL) {
+    if (Lf == 1) return TIKH_OK;
+    FftPlanDev chk;
+    if (Lf <= FFT_LDS_MAX) {
+        if (!fft_plan(Lf, &chk)) return TIKH_EINVAL;
+        fft_pass(data, S, sstride, nlines, nlines, Lf, 0, 1, Lf, sign, 0, tw, Q, 64);
+        return TIKH_OK;
+    }
+    const int64_t L1 = fft_split(Lf);
     if (L1 == 0) return TIKH_EINVAL;
-    int64_t L2 = Lf / L1;
-    // pass 1: for each line and each k2 < L2, transform over k1 (stride L2), twiddle w_Lf^{j1 k2}
-    FftArgs p1 = a;
-    if (!fft_plan(L1, &p1.pl)) return TIKH_EINVAL;
-    p1.lines_inner = L2; p1.line_stride = 1; p1.outer_stride = Lf; p1.elem_stride = L2;
-    p1.nlines = nlines * L2; p1.post_L = Lf;
-    p1.lpw = (int)std::max<int64_t>(1, std::min<int64_t>(FFT_LDS_MAX / L1, 16));
-    hipLaunchKernelGGL(k_fft, dim3((unsigned)((p1.nlines + p1.lpw - 1) / p1.lpw), (unsigned)S), dim3(FFT_THREADS), 0,
-                       g.stream, p1);
-    // pass 2: for each line and each j1 < L1, transform the contiguous row of length L2
-    FftArgs p2 = a;
-    if (!fft_plan(L2, &p2.pl)) return TIKH_EINVAL;
-    p2.lines_inner = L1; p2.line_stride = L2; p2.outer_stride = Lf; p2.elem_stride = 1;
-    p2.nlines = nlines * L1; p2.post_L = 0;
-    p2.lpw = (int)std::max<int64_t>(1, std::min<int64_t>(FFT_LDS_MAX / L2, 64));
-    hipLaunchKernelGGL(k_fft, dim3((unsigned)((p2.nlines + p2.lpw - 1) / p2.lpw), (unsigned)S), dim3(FFT_THREADS), 0,
-                       g.stream, p2);
-    hipLaunchKernelGGL(k_fourstep_unscramble, grid1(nlines * Lf, S), dim3(256), 0, g.stream, data, scratch, sstride,
-                       scr_stride, Lf, nlines, L1, L2);
-    hipLaunchKernelGGL(k_copy, grid1(nlines * Lf, S), dim3(256), 0, g.stream, scratch, data, scr_stride, sstride,
-                       nlines * Lf);
-    g.launches += 4;
+    const int64_t L2 = Lf / L1;
+    if (!fft_plan(L1, &chk) || !fft_plan(L2, &chk)) return TIKH_EINVAL;
+    if (order == FFT_INV_T) {
+        // rows j1 (contiguous, length L2) with twiddle w^{j1 k2}, then columns k2 (stride L2, length L1)
+        fft_pass(data, S, sstride, nlines * L1, L1, L2, Lf, 1, L2, sign, Lf, tw, Q, 64);
+        fft_pass(data, S, sstride, nlines * L2, L2, 1, Lf, L2, L1, sign, 0, tw, Q, 16);
+        return TIKH_OK;
+    }
+    // columns k2 (stride L2, length L1) with twiddle w^{j1 k2}, then rows j1 (contiguous, length L2)
+    fft_pass(data, S, sstride, nlines * L2, L2, 1, Lf, L2, L1, sign, Lf, tw, Q, 16);
+    fft_pass(data, S, sstride, nlines * L1, L1, L2, Lf, 1, L2, sign, 0, tw, Q, 64);
+    if (order == FFT_NATURAL) {
+        hipLaunchKernelGGL(k_fourstep_unscramble, grid1(nlines * Lf, S), dim3(256), 0, g.stream, data, scratch,
+                           sstride, scr_stride, Lf, nlines, L1, L2);
+        hipLaunchKernelGGL(k_copy, grid1(nlines * Lf, S), dim3(256), 0, g.stream, scratch, data, scr_stride, sstride,
+                           nlines * Lf);
+        g.launches += 2;
+    }
     return TIKH_OK;
 }
 
 // ---------------------------------------------------------------- recursion (Alg. 1)
-static int run_leaf(const Plan& pl, const Layout& L, const Bufs& b, int64_t S, int t, double2* dst, SlotMeta* dmeta,
-                    int64_t dcap, const double2* tw) {
+template <int NR>
+static void launch_leaf(const Plan& pl, const LeafArgs& la, const BuildArgs& ba, int64_t G, int slots) {
+    if (pl.K <= 64) LAUNCH("leaf_loop", (k_leaf_loop<1, NR>), dim3((unsigned)G), dim3(64), la);
+    else if (pl.K <= 128) LAUNCH("leaf_loop", (k_leaf_loop<2, NR>), dim3((unsigned)G), dim3(64), la);
+    else if (pl.K <= 192) LAUNCH("leaf_loop", (k_leaf_loop<3, NR>), dim3((unsigned)G), dim3(64), la);
+    else LAUNCH("leaf_loop", (k_leaf_loop<4, NR>), dim3((unsigned)G), dim3(64), la);
+    if (slots <= 1) LAUNCH("leaf_build", (k_leaf_build<1, NR>), dim3((unsigned)G), dim3(256), ba);
+    else if (slots <= 2) LAUNCH("leaf_build", (k_leaf_build<2, NR>), dim3((unsigned)G), dim3(256), ba);
+    else if (slots <= 3) LAUNCH("leaf_build", (k_leaf_build<3, NR>), dim3((unsigned)G), dim3(256), ba);
+    else if (slots <= 4) LAUNCH("leaf_build", (k_leaf_build<4, NR>), dim3((unsigned)G), dim3(256), ba);
+    else LAUNCH("leaf_build", (k_leaf_build<5, NR>), dim3((unsigned)G), dim3(256), ba);
+}
+
+static int run_leaf(const Plan& pl, const Layout& L, const Bufs& b, int64_t G, int t, double2* dst, int64_t dstride,
+                    SlotMeta* dmeta, int64_t dcap, const double2* tw) {
     LeafArgs la{};
     la.sd = b.sd; la.st = b.st; la.phi = b.phi; la.phi_stride = L.sphi; la.rec = b.rec;
     la.rec_stride = pl.K; la.N = pl.N; la.M = pl.M; la.p = pl.p; la.K = pl.K; la.leaf = t; la.tw = tw; la.Q = pl.Q;
-    if (pl.K <= 64) LAUNCH("leaf_loop", k_leaf_loop<1>, dim3((unsigned)S), dim3(64), la);
-    else if (pl.K <= 128) LAUNCH("leaf_loop", k_leaf_loop<2>, dim3((unsigned)S), dim3(64), la);
-    else if (pl.K <= 192) LAUNCH("leaf_loop", k_leaf_loop<3>, dim3((unsigned)S), dim3(64), la);
-    else LAUNCH("leaf_loop", k_leaf_loop<4>, dim3((unsigned)S), dim3(64), la);
     BuildArgs ba{};
-    ba.st = b.st; ba.rec = b.rec; ba.rec_stride = pl.K; ba.out = dst; ba.out_stride = 20 * (dcap + 1);
+    ba.st = b.st; ba.rec = b.rec; ba.rec_stride = pl.K; ba.out = dst; ba.out_stride = dstride;
     ba.cap = dcap; ba.meta = dmeta; ba.K = pl.K;
-    int slots = (int)((std::min<int64_t>(dcap, pl.K) + 1 + 63) / 64);
-    if (slots <= 1) LAUNCH("leaf_build", k_leaf_build<1>, dim3((unsigned)S), dim3(256), ba);
-    else if (slots <= 2) LAUNCH("leaf_build", k_leaf_build<2>, dim3((unsigned)S), dim3(256), ba);
-    else if (slots <= 3) LAUNCH("leaf_build", k_leaf_build<3>, dim3((unsigned)S), dim3(256), ba);
-    else if (slots <= 4) LAUNCH("leaf_build", k_leaf_build<4>, dim3((unsigned)S), dim3(256), ba);
-    else LAUNCH("leaf_build", k_leaf_build<5>, dim3((unsigned)S), dim3(256), ba);
+    const int slots = (int)((std::min<int64_t>(dcap, pl.K) + 1 + 63) / 64);
+    if (L.nr == 1) launch_leaf<1>(pl, la, ba, G, slots);
+    else if (L.nr == 2) launch_leaf<2>(pl, la, ba, G, slots);
+    else launch_leaf<4>(pl, la, ba, G, slots);
     return TIKH_OK;
 }
 
 // Evaluate the completed left child (depth d, index idx) at the nodes of its
 // right sibling and update the sibling subtree's residual data.
-static int run_eval(const Plan& pl, const Layout& L, const Bufs& b, int64_t S, int d, int64_t idx, const double2* tw) {
+static int run_eval_chunk(const Plan& pl, const Layout& L, const Bufs& b, int64_t G, int d, int64_t idx,
+                          const double2* tw) {
     const int64_t ridx = idx + 1;
     const int64_t oR = 2 * (int64_t)(d == 0 ? 0 : (int)(__builtin_bitreverse32((uint32_t)ridx) >> (32 - d)));
     const int64_t Lc = pl.N >> (d + 1);
     const int64_t cp1 = pl.cap[d] + 1;
-    hipLaunchKernelGGL(k_twist_fold, dim3((unsigned)std::min<int64_t>((Lc + 255) / 256, 1024), 40, (unsigned)S),
-                       dim3(256), 0, g.stream, b.slotS[d], L.sslot[d], cp1, b.metaS[d], b.V, L.sV, Lc, oR, pl.N, tw,
-                       pl.Q);
+    const int E = 4 * L.C;
+    hipLaunchKernelGGL(k_twist_fold, dim3((unsigned)std::min<int64_t>((Lc + 255) / 256, 1024), 2 * E, (unsigned)G),
+                       dim3(256), 0, g.stream, b.slotS[d], L.sslot[d], cp1, L.C, b.metaS[d], b.V, L.sV, Lc, oR, pl.N,
+                       tw, pl.Q);
     g.launches++;
-    int rc = fft_lines(b.V, S, L.sV, 40, Lc, +1, tw, pl.Q, b.scr, L.sscr);
+    int rc = fft_lines(b.V, G, L.sV, 2 * E, Lc, +1, tw, pl.Q, b.scr, L.sscr, FFT_FWD_T);
     if (rc) return rc;
+    const int64_t L1 = fft_split(Lc);
     const int64_t nleaves = (int64_t)1 << (pl.p - d);
     const int64_t t0 = ridx << (pl.p - d);
-    hipLaunchKernelGGL(k_eval_apply, grid1(nleaves * pl.K, S), dim3(256), 0, g.stream, b.phi, L.sphi, b.V, L.sV, Lc,
-                       oR, d, t0, nleaves, pl.N, pl.M, pl.p, pl.K);
-    g.launches++;
+    if (L.nr == 1)
+        LAUNCH("eval_apply", k_eval_apply<1>, grid1(nleaves * pl.K, G), dim3(256), b.phi, L.sphi, b.V, L.sV, Lc, L1, oR,
+               d, t0, nleaves, pl.N, pl.M, pl.p, pl.K);
+    else if (L.nr == 2)
+        LAUNCH("eval_apply", k_eval_apply<2>, grid1(nleaves * pl.K, G), dim3(256), b.phi, L.sphi, b.V, L.sV, Lc, L1, oR,
+               d, t0, nleaves, pl.N, pl.M, pl.p, pl.K);
+    else
+        LAUNCH("eval_apply", k_eval_apply<4>, grid1(nleaves * pl.K, G), dim3(256), b.phi, L.sphi, b.V, L.sV, Lc, L1, oR,
+               d, t0, nleaves, pl.N, pl.M, pl.p, pl.K);
     return TIKH_OK;
 }
 
-// B_parent = B_L B_R for the parent at depth dp (children at depth dp+1).
-static int run_product(const Plan& pl, const Layout& L, const Bufs& b, int64_t S, int dp, double2* dst,
-                       SlotMeta* dmeta, int64_t dcap, const double2* tw) {
+// B_parent = B_L B_R for the parent at depth dp (children at depth dp+1), one merge chunk.
+static int run_product_chunk(const Plan& pl, const Layout& L, const Bufs& b, int64_t G, int dp, double2* dst,
+                             int64_t dstride, SlotMeta* dmeta, int64_t dcap, const double2* tw) {
     const int dc = dp + 1;
-    const int64_t P = pl.P[dp];
+    const int C = L.C, nr = L.nr;
+    int64_t P = pl.P[dp];
+    {
+        // size the transforms by the actual degrees of this chunk (host readback)
+        hipLaunchKernelGGL(k_deg_need, dim3(1), dim3(256), 0, g.stream, b.metaS[dc], b.metaT[dc], (int)G, C, g.dneed);
+        HIPCHK(hipMemcpyAsync(g.hneed, g.dneed, sizeof(int), hipMemcpyDeviceToHost, g.stream));
+        HIPCHK(hipStreamSynchronize(g.stream));
+        g.launches += 1;
+        const int64_t need = std::max<int64_t>(1, (int64_t)*g.hneed);
+        if (need <= P) P = smallest_divisor_geq(pl.Q, need);
+        if (P > pl.P[dp]) P = pl.P[dp];
+    }
     const int64_t cp1 = pl.cap[dc] + 1;
     const bool root = (dp == 0);
-    const int nL = root ? 5 : 20, nR = root ? 4 : 20, nO = root ? 1 : 20;
-    const int* eL = b.elist + (root ? EL_ROW0 : EL_ALL);
-    const int* eR = b.elist + (root ? EL_COL5 : EL_ALL);
-    const int* eO = b.elist + (root ? EL_X : EL_ALL);
-    hipLaunchKernelGGL(k_prod_meta, dim3((unsigned)((S + 63) / 64)), dim3(64), 0, g.stream, b.metaS[dc], b.metaT[dc],
-                       dmeta, b.st, dcap, (int)S);
+    const int nL = root ? C : 4 * C, nR = root ? 4 * nr : 4 * C, nO = root ? nr : 4 * C;
+    const int* eL = b.elist + (root ? offsetof(EList, row0) : offsetof(EList, all)) / sizeof(int);
+    const int* eR = b.elist + (root ? offsetof(EList, vcols) : offsetof(EList, all)) / sizeof(int);
+    const int* eO = b.elist + (root ? offsetof(EList, xout) : offsetof(EList, all)) / sizeof(int);
+    hipLaunchKernelGGL(k_prod_meta, dim3((unsigned)((G + 63) / 64)), dim3(64), 0, g.stream, b.metaS[dc], b.metaT[dc],
+                       dmeta, b.st, dcap, (int)G, C);
     unsigned gx = (unsigned)std::min<int64_t>((P + 255) / 256, 1024);
-    hipLaunchKernelGGL(k_prod_load, dim3(gx, nL, (unsigned)S), dim3(256), 0, g.stream, b.slotS[dc], L.sslot[dc], cp1,
+    hipLaunchKernelGGL(k_prod_load, dim3(gx, nL, (unsigned)G), dim3(256), 0, g.stream, b.slotS[dc], L.sslot[dc], cp1, C,
                        b.metaS[dc], eL, b.FL, L.sF, P);
-    hipLaunchKernelGGL(k_prod_load, dim3(gx, nR, (unsigned)S), dim3(256), 0, g.stream, b.slotT[dc], L.sslot[dc], cp1,
+    hipLaunchKernelGGL(k_prod_load, dim3(gx, nR, (unsigned)G), dim3(256), 0, g.stream, b.slotT[dc], L.sT, cp1, C,
                        b.metaT[dc], eR, b.FR, L.sF, P);
     g.launches += 3;
-    int rc = fft_lines(b.FL, S, L.sF, nL, P, -1, tw, pl.Q, b.scr, L.sscr);
+    int rc = fft_lines(b.FL, G, L.sF, nL, P, -1, tw, pl.Q, b.scr, L.sscr, FFT_FWD_T);
     if (rc) return rc;
-    rc = fft_lines(b.FR, S, L.sF, nR, P, -1, tw, pl.Q, b.scr, L.sscr);
+    rc = fft_lines(b.FR, G, L.sF, nR, P, -1, tw, pl.Q, b.scr, L.sscr, FFT_FWD_T);
     if (rc) return rc;
     // the pointwise product reads every input of a frequency before writing, so it runs in place over FL
-    hipLaunchKernelGGL(k_prod_mul, grid1(P, S), dim3(256), 0, g.stream, b.FL, b.FR, b.FL, L.sF, P, root ? 1 : 0);
-    g.launches++;
-    rc = fft_lines(b.FL, S, L.sF, nO, P, +1, tw, pl.Q, b.scr, L.sscr);
+    if (nr == 1) LAUNCH("prod_mul", k_prod_mul<1>, grid1(P, G), dim3(256), b.FL, b.FR, b.FL, L.sF, P, root ? 1 : 0);
+    else if (nr == 2) LAUNCH("prod_mul", k_prod_mul<2>, grid1(P, G), dim3(256), b.FL, b.FR, b.FL, L.sF, P, root ? 1 : 0);
+    else LAUNCH("prod_mul", k_prod_mul<4>, grid1(P, G), dim3(256), b.FL, b.FR, b.FL, L.sF, P, root ? 1 : 0);
+    rc = fft_lines(b.FL, G, L.sF, nO, P, +1, tw, pl.Q, b.scr, L.sscr, FFT_INV_T);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_prod_store, dim3(gx, nO, (unsigned)S), dim3(256), 0, g.stream, b.FL, L.sF, P, dst,
-                       20 * (dcap + 1), dcap + 1, dmeta, nO, eO);
+    hipLaunchKernelGGL(k_prod_store, dim3(gx, nO, (unsigned)G), dim3(256), 0, g.stream, b.FL, L.sF, P, dst, dstride,
+                       dcap + 1, C, dmeta, eO);
     g.launches++;
     return TIKH_OK;
 }
 
-static int run_recursion(const Plan& pl, const Layout& L, const Bufs& b, int64_t S, const double2* tw) {
+static int run_eval(const Plan& pl, const Layout& L, const Bufs& b, int64_t G, int d, int64_t idx, const double2* tw) {
+    if (d == pl.p || ((2 * pl.N) >> d) <= DIRECT_MAX_COND) {
+        const int64_t ridx = idx + 1;
+        const int64_t nleaves = (int64_t)1 << (pl.p - d);
+        const int64_t t0 = ridx << (pl.p - d);
+        if (L.nr == 1)
+            LAUNCH("eval_direct", k_eval_direct<1>, dim3((unsigned)G), dim3(256), b.phi, L.sphi, b.slotS[d], L.sslot[d],
+                   pl.cap[d] + 1, b.metaS[d], t0, nleaves, pl.N, pl.M, pl.p, pl.K, tw, pl.Q);
+        else if (L.nr == 2)
+            LAUNCH("eval_direct", k_eval_direct<2>, dim3((unsigned)G), dim3(256), b.phi, L.sphi, b.slotS[d], L.sslot[d],
+                   pl.cap[d] + 1, b.metaS[d], t0, nleaves, pl.N, pl.M, pl.p, pl.K, tw, pl.Q);
+        else
+            LAUNCH("eval_direct", k_eval_direct<4>, dim3((unsigned)G), dim3(256), b.phi, L.sphi, b.slotS[d], L.sslot[d],
+                   pl.cap[d] + 1, b.metaS[d], t0, nleaves, pl.N, pl.M, pl.p, pl.K, tw, pl.Q);
+        return TIKH_OK;
+    }
+    for (int64_t c0 = 0; c0 < G; c0 += b.chunk) {
+        Bufs bc = shift_bufs(b, L, pl, c0);
+        int rc = run_eval_chunk(pl, L, bc, std::min(b.chunk, G - c0), d, idx, tw);
+        if (rc) return rc;
+    }
+    return TIKH_OK;
+}
+
+// dst / dmeta are given for group 0 with per-group stride dstride
+static int run_product(const Plan& pl, const Layout& L, const Bufs& b, int64_t G, int dp, double2* dst,
+                       int64_t dstride, SlotMeta* dmeta, int64_t dcap, const double2* tw) {
+    const int dc = dp + 1;
+    if (dp > 0 && dc == pl.p) {
+        LAUNCH("prod_direct", k_prod_direct, dim3((unsigned)G), dim3(256), b.slotS[dc], L.sslot[dc], pl.cap[dc] + 1,
+               b.metaS[dc], b.slotT[dc], L.sT, pl.cap[dc] + 1, b.metaT[dc], dst, dstride, dcap + 1, dmeta, b.st, L.C);
+        return TIKH_OK;
+    }
+    for (int64_t c0 = 0; c0 < G; c0 += b.chunk) {
+        Bufs bc = shift_bufs(b, L, pl, c0);
+        int rc = run_product_chunk(pl, L, bc, std::min(b.chunk, G - c0), dp, dst + c0 * dstride, dstride, dmeta + c0,
+                                   dcap, tw);
+        if (rc) return rc;
+    }
+    return TIKH_OK;
+}
+
+static int run_recursion(const Plan& pl, const Layout& L, const Bufs& b, int64_t G, const double2* tw) {
     const int p = pl.p;
     const int64_t nleaf = (int64_t)1 << p;
     for (int64_t t = 0; t < nleaf; ++t) {
         double2* dst;
+        int64_t dstr;
         SlotMeta* dm;
-        if (p == 0) { dst = b.slotT[0]; dm = b.metaT[0]; }
-        else if (t & 1) { dst = b.slotT[p]; dm = b.metaT[p]; }
-        else { dst = b.slotS[p]; dm = b.metaS[p]; }
-        int rc = run_leaf(pl, L, b, S, (int)t, dst, dm, pl.cap[p], tw);
+        if (p == 0) { dst = b.slotT[0]; dm = b.metaT[0]; dstr = L.sT; }
+        else if (t & 1) { dst = b.slotT[p]; dm = b.metaT[p]; dstr = L.sT; }
+        else { dst = b.slotS[p]; dm = b.metaS[p]; dstr = L.sslot[p]; }
+        int rc = run_leaf(pl, L, b, G, (int)t, dst, dstr, dm, pl.cap[p], tw);
         if (rc) return rc;
         int d = p;
         int64_t idx = t;
         while (d > 0) {
             if ((idx & 1) == 0) {
-                rc = run_eval(pl, L, b, S, d, idx, tw);
+                rc = run_eval(pl, L, b, G, d, idx, tw);
                 if (rc) return rc;
                 break;
             }
             const int dp = d - 1;
             const int64_t pidx = idx >> 1;
             double2* pdst;
+            int64_t pstr;
             SlotMeta* pm;
-            if (dp == 0 || (pidx & 1)) { pdst = b.slotT[dp]; pm = b.metaT[dp]; }
-            else { pdst = b.slotS[dp]; pm = b.metaS[dp]; }
-            rc = run_product(pl, L, b, S, dp, pdst, pm, pl.cap[dp], tw);
+            if (dp == 0 || (pidx & 1)) { pdst = b.slotT[dp]; pm = b.metaT[dp]; pstr = L.sT; }
+            else { pdst = b.slotS[dp]; pm = b.metaS[dp]; pstr = L.sslot[dp]; }
+            rc = run_product(pl, L, b, G, dp, pdst, pstr, pm, pl.cap[dp], tw);
             if (rc) return rc;
             d = dp;
             idx = pidx;
@@ -435,40 +599,42 @@ static int run_recursion(const Plan& pl, const Layout& L, const Bufs& b, int64_t
     return TIKH_OK;
 }
 
-// circulant products on length-N buffers
+// circulant products on length-N per-solve buffers (symbol from the group)
 static void circ_apply(const Plan& pl, const Layout& L, const Bufs& b, int64_t S, double2* buf, int mode,
                        const double2* tw) {
-    fft_lines(buf, S, L.sN, 1, pl.N, +1, tw, pl.Q, b.scr, L.sscr);
-    hipLaunchKernelGGL(k_mul_symbol, grid1(pl.N, S), dim3(256), 0, g.stream, b.sd, b.chat, buf, pl.N, L.sN, mode, tw,
-                       pl.Q);
-    fft_lines(buf, S, L.sN, 1, pl.N, -1, tw, pl.Q, b.scr, L.sscr);
+    fft_lines(buf, S, L.sN, 1, pl.N, +1, tw, pl.Q, b.bS, L.sN);
+    hipLaunchKernelGGL(k_mul_symbol, grid1(pl.N, S), dim3(256), 0, g.stream, b.sd, L.nr, b.chat, buf, pl.N, L.sN, mode,
+                       tw, pl.Q);
+    fft_lines(buf, S, L.sN, 1, pl.N, -1, tw, pl.Q, b.bS, L.sN);
     g.launches++;
 }
 
-// One chunk of solves sharing the plan.
-static int run_chunk(const Plan& pl, const std::vector<SolveDesc>& sds, int32_t* info) {
+// One chunk of groups sharing the plan (sds holds G*nr solves, group-major).
+static int run_chunk(const Plan& pl, int nr, const std::vector<SolveDesc>& sds, int32_t* info, int64_t merge_chunk) {
     const int64_t S = (int64_t)sds.size();
+    const int64_t G = S / nr;
     int64_t mmax = 1, nmax = 1;
     for (auto& d : sds) { mmax = std::max(mmax, d.m); nmax = std::max(nmax, d.n); }
     Layout L;
-    make_layout(pl, mmax, nmax, &L);
+    make_layout(pl, nr, mmax, nmax, &L);
     Bufs b;
-    int rc = carve_bufs(pl, L, S, &b);
+    int rc = carve_bufs(pl, L, G, std::min<int64_t>(G, merge_chunk), &b);
     if (rc) return rc;
     const double2* tw = twiddles(pl.Q);
     if (!tw) return TIKH_ENOMEM;
+    const EList el = make_elist(nr);
     HIPCHK(hipMemcpyAsync(b.sd, sds.data(), sizeof(SolveDesc) * S, hipMemcpyHostToDevice, g.stream));
-    HIPCHK(hipMemcpyAsync(b.elist, h_elist, sizeof(h_elist), hipMemcpyHostToDevice, g.stream));
+    HIPCHK(hipMemcpyAsync(b.elist, &el, sizeof(EList), hipMemcpyHostToDevice, g.stream));
     const int64_t N = pl.N;
     const double invN = 1.0 / (double)N;
-    hipLaunchKernelGGL(k_init_state, dim3((unsigned)((S + 63) / 64)), dim3(64), 0, g.stream, b.sd, b.st, (int)S, 0);
-    // extension (eq. (circexp)) and its symbol c^ = F c_T (eq. (circdiag))
-    hipLaunchKernelGGL(k_gen_rms, dim3((unsigned)S), dim3(256), 0, g.stream, b.sd, b.rms);
-    hipLaunchKernelGGL(k_build_ct, grid1(N, S), dim3(256), 0, g.stream, b.sd, b.rms, b.chat, N, L.sN);
+    hipLaunchKernelGGL(k_init_state, dim3((unsigned)((G + 63) / 64)), dim3(64), 0, g.stream, b.sd, nr, b.st, (int)G, 0);
+    // extension (eq. (circexp)) and its symbol c^ = F c_T (eq. (circdiag)), per group
+    hipLaunchKernelGGL(k_gen_rms, dim3((unsigned)G), dim3(256), 0, g.stream, b.sd, nr, b.rms);
+    hipLaunchKernelGGL(k_build_ct, grid1(N, G), dim3(256), 0, g.stream, b.sd, nr, b.rms, b.chat, N, L.sN);
     g.launches += 3;
-    rc = fft_lines(b.chat, S, L.sN, 1, N, +1, tw, pl.Q, b.scr, L.sscr);
+    rc = fft_lines(b.chat, G, L.sN, 1, N, +1, tw, pl.Q, b.bS, L.sN);
     if (rc) return rc;
-    // right-hand side y = T^H b as the bottom n entries of C_k(T^H) [b; 0]
+    // right-hand side y = T^H b as the bottom n entries of C_k(T^H) [b; 0], per solve
     const bool normal = sds[0].mode == 1;
     if (!normal) {
         hipLaunchKernelGGL(k_load_pad, grid1(N, S), dim3(256), 0, g.stream, b.sd, 0, (const double2*)nullptr, 0, 0,
@@ -498,27 +664,28 @@ static int run_chunk(const Plan& pl, const std::vector<SolveDesc>& sds, int32_t*
                                b.t2, L.sn);
             hipLaunchKernelGGL(k_normal_residual, grid1(nmax, S), dim3(256), 0, g.stream, b.sd, b.yv, b.t2, b.xacc,
                                b.t1, L.sn);
-            hipLaunchKernelGGL(k_init_state, dim3((unsigned)((S + 63) / 64)), dim3(64), 0, g.stream, b.sd, b.st,
-                               (int)S, 1);
+            hipLaunchKernelGGL(k_init_state, dim3((unsigned)((G + 63) / 64)), dim3(64), 0, g.stream, b.sd, nr, b.st,
+                               (int)G, 1);
             g.launches += 6;
             rhs = b.t1;
         }
         hipLaunchKernelGGL(k_load_pad, grid1(N, S), dim3(256), 0, g.stream, b.sd, 0, rhs, L.sn, 1, 0, 1.0, b.bA, N,
                            L.sN);
         g.launches++;
-        rc = fft_lines(b.bA, S, L.sN, 1, N, +1, tw, pl.Q, b.scr, L.sscr);
+        rc = fft_lines(b.bA, S, L.sN, 1, N, +1, tw, pl.Q, b.bS, L.sN);
         if (rc) return rc;
-        hipLaunchKernelGGL(k_assemble, grid1(2 * N, S), dim3(256), 0, g.stream, b.sd, b.chat, b.bA, L.sN, b.phi,
+        hipLaunchKernelGGL(k_assemble, grid1(2 * N, G), dim3(256), 0, g.stream, b.sd, nr, b.chat, b.bA, L.sN, b.phi,
                            L.sphi, N, pl.M, pl.p, pl.K, tw, pl.Q);
         g.launches++;
-        rc = run_recursion(pl, L, b, S, tw);
+        rc = run_recursion(pl, L, b, G, tw);
         if (rc) return rc;
-        hipLaunchKernelGGL(k_extract, grid1(nmax, S), dim3(256), 0, g.stream, b.sd, b.st, b.slotT[0], L.sslot[0],
-                           pl.cap[0] + 1, b.metaT[0], b.xacc, L.sn, it > 0 ? 1 : 0);
+        const int64_t xcp1 = pl.cap[0] + 1;
+        hipLaunchKernelGGL(k_extract, grid1(nmax, S), dim3(256), 0, g.stream, b.sd, nr, b.st, b.slotT[0], L.sT,
+                           pl.p == 0 ? xcp1 : xcp1, b.metaT[0], b.xacc, L.sn, it > 0 ? 1 : 0);
         g.launches++;
     }
     if (!sds[0].backward) {
-        hipLaunchKernelGGL(k_store_x, grid1(nmax, S), dim3(256), 0, g.stream, b.sd, b.xacc, L.sn, b.st, info);
+        hipLaunchKernelGGL(k_store_x, grid1(nmax, S), dim3(256), 0, g.stream, b.sd, nr, b.xacc, L.sn, b.st, info);
         g.launches++;
     } else {
         // adjoint: xacc holds w = (T^H T + lam^2 I)^{-1} gx
@@ -526,40 +693,42 @@ static int run_chunk(const Plan& pl, const std::vector<SolveDesc>& sds, int32_t*
         // X = F[x; 0]; T x = tail_m(F^-1(c^ X)) / N; r = b - T x  (t1)
         hipLaunchKernelGGL(k_load_pad, grid1(N, S), dim3(256), 0, g.stream, b.sd, 2, (const double2*)nullptr, 0, 1, 0,
                            1.0, b.bA, N, L.sN);
-        rc = fft_lines(b.bA, S, L.sN, 1, N, +1, tw, pl.Q, b.scr, L.sscr);
+        rc = fft_lines(b.bA, S, L.sN, 1, N, +1, tw, pl.Q, b.bS, L.sN);
         if (rc) return rc;
         hipLaunchKernelGGL(k_copy, grid1(N, S), dim3(256), 0, g.stream, b.bA, b.bB, L.sN, L.sN, N);
-        hipLaunchKernelGGL(k_mul_symbol, grid1(N, S), dim3(256), 0, g.stream, b.sd, b.chat, b.bB, N, L.sN, 0, tw, pl.Q);
-        rc = fft_lines(b.bB, S, L.sN, 1, N, -1, tw, pl.Q, b.scr, L.sscr);
+        hipLaunchKernelGGL(k_mul_symbol, grid1(N, S), dim3(256), 0, g.stream, b.sd, nr, b.chat, b.bB, N, L.sN, 0, tw,
+                           pl.Q);
+        rc = fft_lines(b.bB, S, L.sN, 1, N, -1, tw, pl.Q, b.bS, L.sN);
         if (rc) return rc;
         hipLaunchKernelGGL(k_take_tail, grid1(mmax, S), dim3(256), 0, g.stream, b.sd, b.bB, N, L.sN, 0, invN, b.t2, L.sn);
         hipLaunchKernelGGL(k_sub_from_b, grid1(mmax, S), dim3(256), 0, g.stream, b.sd, b.t2, b.t1, L.sn);
         // W = F[w; 0]; T w = tail_m(F^-1(c^ W)) / N  (t2)
         hipLaunchKernelGGL(k_load_pad, grid1(N, S), dim3(256), 0, g.stream, b.sd, 0, b.xacc, L.sn, 1, 0, 1.0, b.bC, N,
                            L.sN);
-        rc = fft_lines(b.bC, S, L.sN, 1, N, +1, tw, pl.Q, b.scr, L.sscr);
+        rc = fft_lines(b.bC, S, L.sN, 1, N, +1, tw, pl.Q, b.bS, L.sN);
         if (rc) return rc;
         hipLaunchKernelGGL(k_copy, grid1(N, S), dim3(256), 0, g.stream, b.bC, b.bB, L.sN, L.sN, N);
-        hipLaunchKernelGGL(k_mul_symbol, grid1(N, S), dim3(256), 0, g.stream, b.sd, b.chat, b.bB, N, L.sN, 0, tw, pl.Q);
-        rc = fft_lines(b.bB, S, L.sN, 1, N, -1, tw, pl.Q, b.scr, L.sscr);
+        hipLaunchKernelGGL(k_mul_symbol, grid1(N, S), dim3(256), 0, g.stream, b.sd, nr, b.chat, b.bB, N, L.sN, 0, tw,
+                           pl.Q);
+        rc = fft_lines(b.bB, S, L.sN, 1, N, -1, tw, pl.Q, b.bS, L.sN);
         if (rc) return rc;
         hipLaunchKernelGGL(k_take_tail, grid1(mmax, S), dim3(256), 0, g.stream, b.sd, b.bB, N, L.sN, 0, invN, b.t2, L.sn);
         // G^ = F[r;0] conj(W) - F[Tw;0] conj(X); lag sums = F^-1(G^) / N
         hipLaunchKernelGGL(k_load_pad, grid1(N, S), dim3(256), 0, g.stream, b.sd, 0, b.t1, L.sn, 0, 0, 1.0, b.bB, N,
                            L.sN);
-        rc = fft_lines(b.bB, S, L.sN, 1, N, +1, tw, pl.Q, b.scr, L.sscr);
+        rc = fft_lines(b.bB, S, L.sN, 1, N, +1, tw, pl.Q, b.bS, L.sN);
         if (rc) return rc;
         hipLaunchKernelGGL(k_xcorr_spec, grid1(N, S), dim3(256), 0, g.stream, b.bB, b.bC, b.bB, N, L.sN, 0);
         hipLaunchKernelGGL(k_load_pad, grid1(N, S), dim3(256), 0, g.stream, b.sd, 0, b.t2, L.sn, 0, 0, 1.0, b.bC, N,
                            L.sN);
-        rc = fft_lines(b.bC, S, L.sN, 1, N, +1, tw, pl.Q, b.scr, L.sscr);
+        rc = fft_lines(b.bC, S, L.sN, 1, N, +1, tw, pl.Q, b.bS, L.sN);
         if (rc) return rc;
         hipLaunchKernelGGL(k_xcorr_spec, grid1(N, S), dim3(256), 0, g.stream, b.bC, b.bA, b.bB, N, L.sN, 1);
-        rc = fft_lines(b.bB, S, L.sN, 1, N, -1, tw, pl.Q, b.scr, L.sscr);
+        rc = fft_lines(b.bB, S, L.sN, 1, N, -1, tw, pl.Q, b.bS, L.sN);
         if (rc) return rc;
         hipLaunchKernelGGL(k_store_grads, grid1(2 * lmax + nmax, S), dim3(256), 0, g.stream, b.sd, b.bB, N, L.sN, invN,
                            b.t2, L.sn);
-        hipLaunchKernelGGL(k_grad_lambda, dim3((unsigned)S), dim3(256), 0, g.stream, b.sd, b.xacc, L.sn, b.st, info);
+        hipLaunchKernelGGL(k_grad_lambda, dim3((unsigned)S), dim3(256), 0, g.stream, b.sd, nr, b.xacc, L.sn, b.st, info);
         g.launches += 14;
     }
     HIPCHK(hipGetLastError());
@@ -567,59 +736,49 @@ static int run_chunk(const Plan& pl, const std::vector<SolveDesc>& sds, int32_t*
 }
 
 // Group solves by plan and run them in chunks that fit the workspace budget.
-static int run_solves(std::vector<SolveDesc>& sds, int32_t* info) {
+// sds is group-major: solves g*nr .. g*nr + nr - 1 share the operator.
+static int run_solves(std::vector<SolveDesc>& sds, int nr, int32_t* info) {
     ensure_init();
     g.launches = 0;
     if (sds.empty()) return TIKH_OK;
-    std::map<int64_t, std::vector<int64_t>> buckets;     // N -> solve indices
+    if (nr != 1 && nr != 2 && nr != 4) return TIKH_EINVAL;
+    const int64_t G = (int64_t)sds.size() / nr;
+    std::map<int64_t, std::vector<int64_t>> buckets;     // N -> group indices
     std::map<int64_t, std::pair<int64_t, int>> shapes;   // N -> (M, p)
-    for (size_t i = 0; i < sds.size(); ++i) {
+    for (int64_t gi = 0; gi < G; ++gi) {
+        SolveDesc& d0 = sds[gi * nr];
         int64_t N, M;
         int p;
-        if (!opt_extend(sds[i].m + sds[i].n - 1, g.opts.n_lim, &N, &M, &p)) return TIKH_EINVAL;
-        sds[i].k = N - (sds[i].m + sds[i].n - 1);
-        buckets[N].push_back((int64_t)i);
+        if (!opt_extend(d0.m + d0.n - 1, g.opts.n_lim, &N, &M, &p)) return TIKH_EINVAL;
+        if (N > ((int64_t)1 << 19)) return TIKH_EINVAL;   // tau-degrees must fit the 20-bit pivot key
+        for (int r = 0; r < nr; ++r) sds[gi * nr + r].k = N - (d0.m + d0.n - 1);
+        buckets[N].push_back(gi);
         shapes[N] = {M, p};
     }
     size_t freeb = 0, totb = 0;
-    hipMemGetInfo(&freeb, &totb);
+    (void)hipMemGetInfo(&freeb, &totb);
     size_t budget = std::max<size_t>((size_t)1 << 30, (size_t)((double)(freeb + g.ws_size) * 0.6));
     for (auto& kv : buckets) {
         Plan pl;
         if (!make_plan(kv.first, shapes[kv.first].first, shapes[kv.first].second, &pl)) return TIKH_EINVAL;
         std::vector<int64_t>& idx = kv.second;
         int64_t mmax = 1, nmax = 1;
-        for (int64_t i : idx) { mmax = std::max(mmax, sds[i].m); nmax = std::max(nmax, sds[i].n); }
+        for (int64_t gi : idx) { mmax = std::max(mmax, sds[gi * nr].m); nmax = std::max(nmax, sds[gi * nr].n); }
         Layout L;
-        make_layout(pl, mmax, nmax, &L);
-        int64_t chunk = std::max<int64_t>(1, (int64_t)(budget / L.per_solve_bytes));
+        make_layout(pl, nr, mmax, nmax, &L);
+        // merge scratch for up to 256 groups (at most a quarter of the budget), the rest held per group
+        int64_t mchunk = std::max<int64_t>(1, std::min<int64_t>(256, (int64_t)(budget / 4 / L.temp_bytes)));
+        const size_t per_group = L.group_bytes + (size_t)nr * L.solve_bytes;
+        int64_t chunk = std::max<int64_t>(1, (int64_t)((budget - (size_t)mchunk * L.temp_bytes) / per_group));
         chunk = std::min<int64_t>(chunk, 65535);
         for (size_t c0 = 0; c0 < idx.size(); c0 += (size_t)chunk) {
             size_t c1 = std::min(idx.size(), c0 + (size_t)chunk);
             std::vector<SolveDesc> part;
-            for (size_t u = c0; u < c1; ++u) part.push_back(sds[idx[u]]);
-            // info is per original solve: run the chunk with a temporary device array when not contiguous
-            int32_t* dinfo = nullptr;
-            bool contiguous = true;
-            for (size_t u = c0; u < c1; ++u) if (idx[u] != idx[c0] + (int64_t)(u - c0)) contiguous = false;
-            if (info && contiguous) dinfo = info + idx[c0];
-            int rc;
-            if (info && !contiguous) {
-                int32_t* tmp = nullptr;
-                HIPCHK(hipMallocAsync((void**)&tmp, sizeof(int32_t) * part.size(), g.stream));
-                rc = run_chunk(pl, part, tmp);
-                if (rc) { hipFreeAsync(tmp, g.stream); return rc; }
-                std::vector<int32_t> h(part.size());
-                HIPCHK(hipMemcpyAsync(h.data(), tmp, sizeof(int32_t) * part.size(), hipMemcpyDeviceToHost, g.stream));
-                HIPCHK(hipStreamSynchronize(g.stream));
-                for (size_t u = c0; u < c1; ++u)
-                    HIPCHK(hipMemcpyAsync(info + idx[u], &h[u - c0], sizeof(int32_t), hipMemcpyHostToDevice, g.stream));
-                HIPCHK(hipStreamSynchronize(g.stream));
-                hipFreeAsync(tmp, g.stream);
-            } else {
-                rc = run_chunk(pl, part, dinfo);
-                if (rc) return rc;
-            }
+            part.reserve((c1 - c0) * nr);
+            for (size_t u = c0; u < c1; ++u)
+                for (int r = 0; r < nr; ++r) part.push_back(sds[idx[u] * nr + r]);
+            int rc = run_chunk(pl, nr, part, info, mchunk);
+            if (rc) return rc;
             g.stats.N = pl.N;
             g.stats.k = part[0].k;
             g.stats.depth = pl.p;
@@ -633,6 +792,16 @@ static int run_solves(std::vector<SolveDesc>& sds, int32_t* info) {
 
 static bool bad_lambda(double lam) { return !(lam > 0.0) || !std::isfinite(lam); }
 
+static int sync_info(int rc, int32_t* dinfo) {
+    int32_t hinfo = 0;
+    if (rc == TIKH_OK) HIPCHK(hipMemcpyAsync(&hinfo, dinfo, sizeof(int32_t), hipMemcpyDeviceToHost, g.stream));
+    HIPCHK(hipStreamSynchronize(g.stream));
+    (void)hipFreeAsync(dinfo, g.stream);
+    HIPCHK(hipStreamSynchronize(g.stream));
+    if (rc) return rc;
+    return hinfo ? TIKH_ENUMERIC : TIKH_OK;
+}
+
 static int solve_single(const void* col, const void* row, int64_t m, int64_t n, const void* rhs, double lambda,
                         void* x, int cplx, int mode) {
     ensure_init();
@@ -641,19 +810,15 @@ static int solve_single(const void* col, const void* row, int64_t m, int64_t n, 
     std::vector<SolveDesc> sds(1);
     SolveDesc& d = sds[0];
     d.col = col; d.row = row; d.rhs = rhs; d.x = x; d.m = m; d.n = n; d.lam = lambda; d.cplx = cplx; d.mode = mode;
+    d.orig = 0;
     int32_t* dinfo = nullptr;
     HIPCHK(hipMallocAsync((void**)&dinfo, sizeof(int32_t), g.stream));
-    int rc = run_solves(sds, dinfo);
-    int32_t hinfo = 0;
-    if (rc == TIKH_OK) {
-        HIPCHK(hipMemcpyAsync(&hinfo, dinfo, sizeof(int32_t), hipMemcpyDeviceToHost, g.stream));
-    }
-    HIPCHK(hipStreamSynchronize(g.stream));
-    hipFreeAsync(dinfo, g.stream);
-    HIPCHK(hipStreamSynchronize(g.stream));
-    if (rc) return rc;
-    return hinfo ? TIKH_ENUMERIC : TIKH_OK;
+    HIPCHK(hipMemsetAsync(dinfo, 0, sizeof(int32_t), g.stream));
+    return sync_info(run_solves(sds, 1, dinfo), dinfo);
 }
+
+// right-hand sides per group for a batched call
+static int group_size(int64_t nrhs) { return nrhs >= 4 ? 4 : (nrhs >= 2 ? 2 : 1); }
 
 }  // namespace tikh
 
@@ -749,27 +914,35 @@ int tikh_toeplitz_solve_batched(int64_t nprob, const int64_t* m, const int64_t* 
     if (nprob == 0) return TIKH_OK;
     if (!col || !row || !b || !x) return TIKH_EINVAL;
     const size_t es = complex_data ? sizeof(double2) : sizeof(double);
+    const int nr = group_size(nrhs);
     std::vector<SolveDesc> sds;
-    sds.reserve((size_t)(nprob * nlam * nrhs));
-    int64_t co = 0, ro = 0, bo = 0, xo = 0;
+    int64_t co = 0, ro = 0, bo = 0, xo = 0, si = 0;
     for (int64_t p = 0; p < nprob; ++p) {
         if (m[p] < 1 || n[p] < 1) return TIKH_EINVAL;
         for (int64_t l = 0; l < nlam; ++l) {
             double lam = lambdas[p * nlam + l];
             if (bad_lambda(lam)) return TIKH_EINVAL;
-            for (int64_t r = 0; r < nrhs; ++r) {
-                SolveDesc d{};
-                d.col = (const char*)col + es * co;
-                d.row = (const char*)row + es * ro;
-                d.rhs = (const char*)b + es * (bo + r * m[p]);
-                d.x = (char*)x + es * (xo + (l * nrhs + r) * n[p]);
-                d.m = m[p]; d.n = n[p]; d.lam = lam; d.cplx = complex_data ? 1 : 0; d.mode = 0;
-                sds.push_back(d);
+            // the rhs of (p, l) in groups of nr; the last group is padded with empty solves
+            for (int64_t r0 = 0; r0 < nrhs; r0 += nr) {
+                for (int64_t r = r0; r < r0 + nr; ++r) {
+                    SolveDesc d{};
+                    d.col = (const char*)col + es * co;
+                    d.row = (const char*)row + es * ro;
+                    d.m = m[p]; d.n = n[p]; d.lam = lam; d.cplx = complex_data ? 1 : 0; d.mode = 0;
+                    if (r < nrhs) {
+                        d.rhs = (const char*)b + es * (bo + r * m[p]);
+                        d.x = (char*)x + es * (xo + (l * nrhs + r) * n[p]);
+                        d.orig = (int32_t)(si + l * nrhs + r);
+                    } else {
+                        d.orig = -1;
+                    }
+                    sds.push_back(d);
+                }
             }
         }
-        co += m[p]; ro += n[p]; bo += nrhs * m[p]; xo += nlam * nrhs * n[p];
+        co += m[p]; ro += n[p]; bo += nrhs * m[p]; xo += nlam * nrhs * n[p]; si += nlam * nrhs;
     }
-    return run_solves(sds, info);
+    return run_solves(sds, nr, info);
 }
 
 static int backward_single(const void* col, const void* row, int64_t m, int64_t n, const void* b, double lambda,
@@ -780,17 +953,11 @@ static int backward_single(const void* col, const void* row, int64_t m, int64_t 
     std::vector<SolveDesc> sds(1);
     SolveDesc& d = sds[0];
     d.col = col; d.row = row; d.rhs = gx; d.x = nullptr; d.m = m; d.n = n; d.lam = lambda; d.cplx = cplx; d.mode = 1;
-    d.bin = b; d.xin = x; d.gcol = gcol; d.grow = grow; d.gb = gb; d.glam = glam; d.backward = 1;
+    d.bin = b; d.xin = x; d.gcol = gcol; d.grow = grow; d.gb = gb; d.glam = glam; d.backward = 1; d.orig = 0;
     int32_t* dinfo = nullptr;
     HIPCHK(hipMallocAsync((void**)&dinfo, sizeof(int32_t), g.stream));
-    int rc = run_solves(sds, dinfo);
-    int32_t hinfo = 0;
-    if (rc == TIKH_OK) HIPCHK(hipMemcpyAsync(&hinfo, dinfo, sizeof(int32_t), hipMemcpyDeviceToHost, g.stream));
-    HIPCHK(hipStreamSynchronize(g.stream));
-    (void)hipFreeAsync(dinfo, g.stream);
-    HIPCHK(hipStreamSynchronize(g.stream));
-    if (rc) return rc;
-    return hinfo ? TIKH_ENUMERIC : TIKH_OK;
+    HIPCHK(hipMemsetAsync(dinfo, 0, sizeof(int32_t), g.stream));
+    return sync_info(run_solves(sds, 1, dinfo), dinfo);
 }
 
 int tikh_toeplitz_solve_backward(const double* col, const double* row, int64_t m, int64_t n, const double* b,
@@ -814,35 +981,41 @@ int tikh_toeplitz_solve_backward_batched(int64_t nprob, const int64_t* m, const 
     if (nprob == 0) return TIKH_OK;
     if (!col || !row || !b || !x || !gx || !g_col || !g_row || !g_b || !g_lambda) return TIKH_EINVAL;
     const size_t es = complex_data ? sizeof(double2) : sizeof(double);
+    const int nr = group_size(nrhs);
     std::vector<SolveDesc> sds;
-    sds.reserve((size_t)(nprob * nlam * nrhs));
     int64_t co = 0, ro = 0, bo = 0, xo = 0, gco = 0, gro = 0, gbo = 0, si = 0;
     for (int64_t p = 0; p < nprob; ++p) {
         if (m[p] < 1 || n[p] < 1) return TIKH_EINVAL;
         for (int64_t l = 0; l < nlam; ++l) {
             double lam = lambdas[p * nlam + l];
             if (bad_lambda(lam)) return TIKH_EINVAL;
-            for (int64_t r = 0; r < nrhs; ++r) {
-                SolveDesc d{};
-                const int64_t u = l * nrhs + r;
-                d.col = (const char*)col + es * co;
-                d.row = (const char*)row + es * ro;
-                d.bin = (const char*)b + es * (bo + r * m[p]);
-                d.xin = (const char*)x + es * (xo + u * n[p]);
-                d.rhs = (const char*)gx + es * (xo + u * n[p]);
-                d.gcol = (char*)g_col + es * (gco + u * m[p]);
-                d.grow = (char*)g_row + es * (gro + u * n[p]);
-                d.gb = (char*)g_b + es * (gbo + u * m[p]);
-                d.glam = g_lambda + si;
-                d.m = m[p]; d.n = n[p]; d.lam = lam; d.cplx = complex_data ? 1 : 0; d.mode = 1; d.backward = 1;
-                sds.push_back(d);
-                ++si;
+            for (int64_t r0 = 0; r0 < nrhs; r0 += nr) {
+                for (int64_t r = r0; r < r0 + nr; ++r) {
+                    SolveDesc d{};
+                    d.col = (const char*)col + es * co;
+                    d.row = (const char*)row + es * ro;
+                    d.m = m[p]; d.n = n[p]; d.lam = lam; d.cplx = complex_data ? 1 : 0; d.mode = 1; d.backward = 1;
+                    if (r < nrhs) {
+                        const int64_t u = l * nrhs + r;
+                        d.bin = (const char*)b + es * (bo + r * m[p]);
+                        d.xin = (const char*)x + es * (xo + u * n[p]);
+                        d.rhs = (const char*)gx + es * (xo + u * n[p]);
+                        d.gcol = (char*)g_col + es * (gco + u * m[p]);
+                        d.grow = (char*)g_row + es * (gro + u * n[p]);
+                        d.gb = (char*)g_b + es * (gbo + u * m[p]);
+                        d.glam = g_lambda + si + u;
+                        d.orig = (int32_t)(si + u);
+                    } else {
+                        d.orig = -1;
+                    }
+                    sds.push_back(d);
+                }
             }
         }
         co += m[p]; ro += n[p]; bo += nrhs * m[p]; xo += nlam * nrhs * n[p];
-        gco += nlam * nrhs * m[p]; gro += nlam * nrhs * n[p]; gbo += nlam * nrhs * m[p];
+        gco += nlam * nrhs * m[p]; gro += nlam * nrhs * n[p]; gbo += nlam * nrhs * m[p]; si += nlam * nrhs;
     }
-    return run_solves(sds, info);
+    return run_solves(sds, nr, info);
 }
 
 }  // extern "C"

@@ -6,13 +6,20 @@
 
 namespace tikh {
 
-constexpr int NC = 5;              // basis size of the l2 problem (x, sigma1, gamma1, gamma2, 1)
-constexpr int NE = 20;             // stored basis entries: rows 0..3 of [B0 | v] (row 4 is e_5^T)
+// The l2 basis for one right-hand side is 5 x 5 (x, sigma1, gamma1, gamma2, 1).
+// Right-hand sides of the same operator (same T and lambda) share the pivot
+// sequence, because the constant column is never a pivot: a group of NR
+// right-hand sides carries the basis [[B0, v_1 .. v_NR], [0, I]] with
+// C = 4 + NR columns, of which rows 0..3 are stored (4 C polynomials).
+constexpr int MAXNR = 4;           // right-hand sides per group
+constexpr int MAXC = 4 + MAXNR;    // basis columns
 constexpr int LEAF_MAX = 256;      // max conditions per leaf (one wavefront, 4 per lane)
 constexpr int FFT_LDS_MAX = 4096;  // max complex elements held by one LDS FFT workgroup
 constexpr int FFT_THREADS = 256;
 
-// One solve of a bucket (device array element).
+// One solve (one right-hand side) of a bucket (device array element).  The
+// solves of a group are consecutive; col/row/m/n/k/lam/cplx are equal within a
+// group.  A padding solve (group not full) has rhs == nullptr: zero data, no output.
 struct SolveDesc {
     const void* col;   // generator a_0..a_{m-1}    (double or double2)
     const void* row;   // a_0, a_{-1}..a_{-(n-1)}   (double or double2)
@@ -31,26 +38,25 @@ struct SolveDesc {
     void* gb;          // dL/d b [m]
     double* glam;      // dL/d lambda (scalar)
     int32_t backward;
-    int32_t pad;
+    int32_t orig;      // index of this solve in the caller's info array (-1: padding solve)
 };
 
-// Per-solve running state of the recursion.
+// Per-group running state of the recursion.
 struct SolveState {
     int32_t delta[4];  // tau-degrees of basis columns 1..4 (column 5 stays 0)
     int32_t info;      // 0 ok, 1 breakdown, 2 degree bound, 3 non-finite
     int32_t pad[3];
 };
 
-// Per-solve metadata of a stored basis (one per slot).
+// Per-group metadata of a stored basis (one per slot).
 struct SlotMeta {
-    int32_t deg[5];    // max polynomial degree of each column over rows 0..3 (-1 = zero column)
-    int32_t pad[3];
+    int32_t deg[MAXC]; // max polynomial degree of each column over rows 0..3 (-1 = zero column)
     unsigned long long colmax_bits[4];  // max |coefficient| of B0 columns (bit pattern of a non-negative double)
 };
 
 // One step of the serial single-condition construction (eq. (spbasis)).
 struct LeafRec {
-    double2 mu[5];     // multipliers mu_i = -r_i / r_piv (mu[piv] = 0)
+    double2 mu[MAXC];  // multipliers mu_i = -r_i / r_piv (mu[piv] = 0)
     double2 sig;       // node of the processed condition
     int32_t piv;       // pivot column (0..3), -1 if the step was skipped
     int32_t q;         // condition index (tree order)

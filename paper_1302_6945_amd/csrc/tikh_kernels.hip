@@ -248,10 +248,13 @@ __global__ void k_copy(const double2* __restrict__ src, double2* __restrict__ ds
 }
 
 // ---------------------------------------------------------------- setup (Sec. 3.1, 3.3, 4.1)
+// Indexing: a bucket holds G groups of nr solves; solve s = g * nr + r.
+// Group-level kernels use sd[g * nr] for the operator (col, row, m, n, k, lambda).
+
 // Root-mean-square of the generator (scale of the arbitrary extension
 // entries, Sec. 6.2: chosen "similar in value" to the known coefficients).
-__global__ __launch_bounds__(256) void k_gen_rms(const SolveDesc* __restrict__ sd, double* __restrict__ rms) {
-    const SolveDesc d = sd[blockIdx.x];
+__global__ __launch_bounds__(256) void k_gen_rms(const SolveDesc* __restrict__ sd, int nr, double* __restrict__ rms) {
+    const SolveDesc d = sd[(int64_t)blockIdx.x * nr];
     double acc = 0.0;
     const int64_t cnt = d.m + d.n - 1;
     for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x) acc += cabs2(gen_coef(d, i - (d.n - 1)));
@@ -274,40 +277,41 @@ __device__ __forceinline__ double hash_unit(uint64_t x) {
     return (double)(x >> 11) * (2.0 / 9007199254740992.0) - 1.0;
 }
 
-// First column of the k-circulant extension (eq. (circexp)):
+// First column of the k-circulant extension (eq. (circexp)) per group:
 // c_T[r] = a_{r-(n+k-1)} for r >= k; r < k are the arbitrary entries a_{-n-k+1..-n}.
-__global__ void k_build_ct(const SolveDesc* __restrict__ sd, const double* __restrict__ rms,
+__global__ void k_build_ct(const SolveDesc* __restrict__ sd, int nr, const double* __restrict__ rms,
                            double2* __restrict__ out, int64_t N, int64_t stride) {
-    const int64_t s = blockIdx.y;
-    const SolveDesc d = sd[s];
+    const int64_t g = blockIdx.y;
+    const SolveDesc d = sd[g * nr];
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < N; r += (int64_t)gridDim.x * blockDim.x) {
         double2 v;
         if (r >= d.k) {
             v = gen_coef(d, r - (N - d.m));
         } else {
-            double sc = rms[s] * 1.7320508075688772;   // uniform in [-sqrt3, sqrt3) has unit rms
-            uint64_t key = ((uint64_t)s << 40) ^ ((uint64_t)d.m << 20) ^ (uint64_t)d.n ^ ((uint64_t)r << 44);
+            double sc = rms[g] * 1.7320508075688772;   // uniform in [-sqrt3, sqrt3) has unit rms
+            uint64_t key = ((uint64_t)d.m << 20) ^ (uint64_t)d.n ^ ((uint64_t)r << 44);
             v = c2(sc * hash_unit(key), d.cplx ? sc * hash_unit(key ^ 0x5851F42D4C957F2Dull) : 0.0);
         }
-        out[s * stride + r] = v;
+        out[g * stride + r] = v;
     }
 }
 
-// dst[i] = scale * src[off + i] for i < len, 0 for len <= i < N.
+// dst[i] = scale * src[off + i] for i < len, 0 for len <= i < N, per solve.
 // src is either a user array (per-solve pointer in SolveDesc: which = 0 rhs,
-// 1 x, 2 the forward solution xin of an adjoint solve) or an internal complex
-// buffer (isrc != nullptr).
+// 1 x, 2 the forward solution xin of an adjoint solve; padding solves read 0)
+// or an internal complex buffer (isrc != nullptr).
 __global__ void k_load_pad(const SolveDesc* __restrict__ sd, int which, const double2* __restrict__ isrc,
                            int64_t isrc_stride, int len_kind, int64_t off, double scale,
                            double2* __restrict__ dst, int64_t N, int64_t stride) {
     const int64_t s = blockIdx.y;
     const SolveDesc d = sd[s];
     const int64_t len = len_kind == 0 ? d.m : d.n;
+    const void* src = which == 0 ? d.rhs : (which == 1 ? (const void*)d.x : d.xin);
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
         double2 v = c2(0.0, 0.0);
         if (i < len) {
             if (isrc) v = isrc[s * isrc_stride + off + i];
-            else v = load_elem(which == 0 ? d.rhs : (which == 1 ? (const void*)d.x : d.xin), off + i, d.cplx);
+            else if (d.rhs) v = load_elem(src, off + i, d.cplx);
             v = cscale(v, scale);
         }
         dst[s * stride + i] = v;
@@ -316,13 +320,15 @@ __global__ void k_load_pad(const SolveDesc* __restrict__ sd, int which, const do
 
 // buf[nu] *= symbol: mode 0: c^(nu) (C_k(T), Sec. 3.1 eq. (circdiag));
 // mode 1: w^{(k-1) nu} conj(c^(nu)) (C_k(T^H), whose symbol follows from T's in O(N), Sec. 7.3).
-__global__ void k_mul_symbol(const SolveDesc* __restrict__ sd, const double2* __restrict__ chat,
+// chat is per group (solve s uses group s / nr).
+__global__ void k_mul_symbol(const SolveDesc* __restrict__ sd, int nr, const double2* __restrict__ chat,
                              double2* __restrict__ buf, int64_t N, int64_t stride, int mode,
                              const double2* __restrict__ tw, int64_t Q) {
     const int64_t s = blockIdx.y;
+    const int64_t g = s / nr;
     const int64_t k = sd[s].k;
     for (int64_t nu = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; nu < N; nu += (int64_t)gridDim.x * blockDim.x) {
-        double2 c = chat[s * stride + nu];
+        double2 c = chat[g * stride + nu];
         double2 sym;
         if (mode == 0) sym = c;
         else sym = cmul(twq(tw, Q, (((k - 1) % N + N) % N) * nu % N * (Q / N), +1), cconj(c));
@@ -360,43 +366,43 @@ __global__ void k_normal_residual(const SolveDesc* __restrict__ sd, const double
 // Unknown p* = [x; sigma1; gamma1; gamma2; 1] with degree bounds n, m, m+k-1, n+k-1, 1.
 //   F_nu = [lam^2 w^{(m+k-1)nu},  w^{(k-1)nu} conj(c^),  1,  0,  -w^{(m+k-1)nu} y^]
 //   G_nu = [-c^,  w^{(n+k-1)nu},  0,  1,  0]
+// The nr right-hand sides of a group give columns 4 .. 3+nr (one y^ each).
 // Tree order: leaf t (in-order) holds nodes nu = o_t + c + j*2^{p+1}, o_t = 2*bitrev_p(t),
 // c in {0,1}, j < M/2 (paired interleaving, Sec. 6.1); slot h = c*M + 2j + type.
-__global__ void k_assemble(const SolveDesc* __restrict__ sd, const double2* __restrict__ chat,
+__global__ void k_assemble(const SolveDesc* __restrict__ sd, int nr, const double2* __restrict__ chat,
                            const double2* __restrict__ yhat, int64_t vstride, double2* __restrict__ phi,
                            int64_t phi_stride, int64_t N, int64_t M, int p, int K,
                            const double2* __restrict__ tw, int64_t Q) {
-    const int64_t s = blockIdx.y;
-    const SolveDesc d = sd[s];
+    const int64_t g = blockIdx.y;
+    const SolveDesc d = sd[g * nr];
     const int64_t twN = Q / N;
     const double l2 = d.lam * d.lam;
     const int64_t nq = 2 * N;
-    double2* ph = phi + s * phi_stride;
+    double2* ph = phi + g * phi_stride;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += (int64_t)gridDim.x * blockDim.x) {
         int64_t t = q / K, h = q - t * K;
         int64_t c = h / M, rem = h - c * M;
         int64_t j = rem >> 1;
         int type = (int)(rem & 1);
         int64_t nu = 2 * (int64_t)bitrev((int)t, p) + c + (j << (p + 1));
-        double2 ch = chat[s * vstride + nu];
-        double2 v0, v1, v2, v3, v4;
+        double2 ch = chat[g * vstride + nu];
         if (type == 0) {
             double2 wmk = twq(tw, Q, ((N - d.n) * nu % N) * twN, +1);        // w^{(m+k-1) nu}
             double2 wk1 = twq(tw, Q, ((((d.k - 1) % N + N) % N) * nu % N) * twN, +1);
-            v0 = cscale(wmk, l2);
-            v1 = cmul(wk1, cconj(ch));
-            v2 = c2(1.0, 0.0);
-            v3 = c2(0.0, 0.0);
-            v4 = cneg(cmul(wmk, yhat[s * vstride + nu]));
+            ph[0 * nq + q] = cscale(wmk, l2);
+            ph[1 * nq + q] = cmul(wk1, cconj(ch));
+            ph[2 * nq + q] = c2(1.0, 0.0);
+            ph[3 * nq + q] = c2(0.0, 0.0);
+            for (int r = 0; r < nr; ++r)
+                ph[(4 + r) * nq + q] = cneg(cmul(wmk, yhat[(g * nr + r) * vstride + nu]));
         } else {
             double2 wnk = twq(tw, Q, ((N - d.m) * nu % N) * twN, +1);        // w^{(n+k-1) nu}
-            v0 = cneg(ch);
-            v1 = wnk;
-            v2 = c2(0.0, 0.0);
-            v3 = c2(1.0, 0.0);
-            v4 = c2(0.0, 0.0);
+            ph[0 * nq + q] = cneg(ch);
+            ph[1 * nq + q] = wnk;
+            ph[2 * nq + q] = c2(0.0, 0.0);
+            ph[3 * nq + q] = c2(1.0, 0.0);
+            for (int r = 0; r < nr; ++r) ph[(4 + r) * nq + q] = c2(0.0, 0.0);
         }
-        ph[0 * nq + q] = v0; ph[1 * nq + q] = v1; ph[2 * nq + q] = v2; ph[3 * nq + q] = v3; ph[4 * nq + q] = v4;
     }
 }
 
@@ -411,14 +417,15 @@ __device__ __forceinline__ double2 cond_node(int64_t q, int64_t N, int64_t M, in
 
 // ---------------------------------------------------------------- leaf: serial TanInt
 // The fast-only construction of Sec. 4.3 on one leaf's K conditions, one
-// wavefront per solve, residuals in registers (R per lane).  Each step
+// wavefront per group, residuals in registers (R per lane).  Each step
 // processes one condition with the single-condition basis of eq. (spbasis):
 //   pivot column pi = the lowest tau-degree among columns 1..4 whose residual
 //   entry is not negligible (|r_i| > ZTOL max_j |r_j|), ties to the largest
 //   |r_i|; the condition is the remaining one with the lowest such degree and,
 //   among those, the largest |r_pi| (partial pivoting of the conditions,
-//   Sec. 5).  Column 5 (the constant) is never a pivot, so the basis keeps the
-//   block form [[B0, v], [0, 1]].
+//   Sec. 5).  The constant columns are never pivots, so the basis keeps the
+//   block form [[B0, V], [0, I]] and every right-hand side of the group shares
+//   the pivot sequence.
 //   mu_i = -r_i / r_pi;  B_:i += mu_i B_:pi (i != pi);  B_:pi *= (z - sigma);
 //   remaining residuals r_i += mu_i r_pi,  r_pi *= (sigma_q - sigma);  delta_pi += 1.
 // The basis itself is formed afterwards from the step records (k_leaf_build).
@@ -437,16 +444,59 @@ struct LeafArgs {
 
 #define TIKH_ZTOL2 1e-22   // (1e-11)^2: relative size below which a residual entry counts as zero
 
-template <int R>
+// ---- cross-lane helpers (DPP, wave64)
+template <int CTRL, int RM = 0xF>
+__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long old, unsigned long long v) {
+    int lo = __builtin_amdgcn_update_dpp((int)(unsigned)old, (int)(unsigned)v, CTRL, RM, 0xF, false);
+    int hi = __builtin_amdgcn_update_dpp((int)(unsigned)(old >> 32), (int)(unsigned)(v >> 32), CTRL, RM, 0xF, false);
+    return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+// maximum over the 64 lanes, returned uniformly
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+    unsigned long long t;
+    t = dpp_u64<0xB1>(v, v); v = v > t ? v : t;          // quad_perm [1,0,3,2]
+    t = dpp_u64<0x4E>(v, v); v = v > t ? v : t;          // quad_perm [2,3,0,1]
+    t = dpp_u64<0x141>(v, v); v = v > t ? v : t;         // row_half_mirror
+    t = dpp_u64<0x140>(v, v); v = v > t ? v : t;         // row_mirror: every lane holds its row maximum
+    t = dpp_u64<0x142, 0xA>(v, v); v = v > t ? v : t;    // row_bcast:15 into rows 1, 3
+    t = dpp_u64<0x143, 0xC>(v, v); v = v > t ? v : t;    // row_bcast:31 into rows 2, 3: lane 63 holds the maximum
+    unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, 63);
+    unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), 63);
+    return ((unsigned long long)hi << 32) | lo;
+}
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+    int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+// lane i receives lane i-1 (lane 0 receives 0)
+__device__ __forceinline__ double wave_shr1_d(double v) {
+    int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xF, 0xF, false);
+    int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Candidate key, compared as an unsigned integer: lowest tau-degree first
+// (20 bits, delta offset by 2^19), then the largest |r_pi|^2 (top 34 bits of the
+// non-negative double), then the pivot column (2 bits) and the lowest
+// slot/lane index (8 bits).  0 = no candidate.
+__device__ __forceinline__ unsigned long long cand_key(int delta, double a2, int piv, int idx) {
+    unsigned long long kd = (unsigned long long)((1 << 19) - delta) & 0xFFFFFull;
+    unsigned long long km = ((unsigned long long)__double_as_longlong(a2) >> 29) & 0x3FFFFFFFFull;
+    return (kd << 44) | (km << 10) | ((unsigned long long)piv << 8) | (unsigned long long)(255 - idx);
+}
+
+template <int R, int NR>
 __global__ __launch_bounds__(64) void k_leaf_loop(const LeafArgs a) {
-    const int64_t s = blockIdx.x;
+    constexpr int C = 4 + NR;
+    const int64_t g = blockIdx.x;
     const int lane = threadIdx.x;
     const int K = a.K;
     const int64_t nq = 2 * a.N;
     const int64_t q0 = (int64_t)a.leaf * K;
-    double2* ph = a.phi + s * a.phi_stride;
-    LeafRec* rec = a.rec + s * a.rec_stride;
-    double2 r[R][5];
+    double2* ph = a.phi + g * a.phi_stride;
+    LeafRec* rec = a.rec + g * a.rec_stride;
+    double2 r[R][C];
     double2 sg[R];
     bool alive[R];
 #pragma unroll
@@ -455,21 +505,20 @@ __global__ __launch_bounds__(64) void k_leaf_loop(const LeafArgs a) {
         alive[i] = h < K;
         if (alive[i]) {
 #pragma unroll
-            for (int c = 0; c < 5; ++c) r[i][c] = ph[c * nq + q0 + h];
+            for (int c = 0; c < C; ++c) r[i][c] = ph[c * nq + q0 + h];
             sg[i] = cond_node(q0 + h, a.N, a.M, a.p, K, a.tw, a.Q);
         } else {
 #pragma unroll
-            for (int c = 0; c < 5; ++c) r[i][c] = c2(0.0, 0.0);
+            for (int c = 0; c < C; ++c) r[i][c] = c2(0.0, 0.0);
             sg[i] = c2(0.0, 0.0);
         }
     }
     int dl[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) dl[c] = a.st[s].delta[c];
+    for (int c = 0; c < 4; ++c) dl[c] = a.st[g].delta[c];
     int info = 0;
     for (int step = 0; step < K; ++step) {
-        int bkey = INT_MAX, bi = -1, bp = -1;
-        double bmag = -1.0;
+        unsigned long long best = 0ull;
 #pragma unroll
         for (int i = 0; i < R; ++i) {
             if (!alive[i]) continue;
@@ -486,38 +535,40 @@ __global__ __launch_bounds__(64) void k_leaf_loop(const LeafArgs a) {
                     key = dl[c]; piv = c; pm = a2[c];
                 }
             }
-            if (piv >= 0 && (key < bkey || (key == bkey && pm > bmag))) { bkey = key; bmag = pm; bi = i; bp = piv; }
+            if (piv >= 0) {
+                unsigned long long k = cand_key(key, pm, piv, i * 64 + lane);
+                best = k > best ? k : best;
+            }
         }
-        const int wkey = wave_min_i(bkey);
-        if (wkey == INT_MAX) { info = 1; break; }      // no admissible pivot: breakdown
-        const double mine = (bkey == wkey) ? bmag : -1.0;
-        const double wmag = wave_max_d(mine);
-        const int cand = (bkey == wkey && bmag == wmag) ? lane : 64;
-        const int wl = wave_min_i(cand);
-        const int si = __shfl(bi, wl, 64);
-        const int piv = __shfl(bp, wl, 64);
-        double2 rc[5];
+        const unsigned long long wk = wave_max_u64(best);
+        if (wk == 0ull) { info = 1; break; }      // no admissible pivot: breakdown
+        const int idx = 255 - (int)(wk & 255ull);
+        const int piv = (int)((wk >> 8) & 3ull);
+        const int wl = idx & 63, si = idx >> 6;
+        double2 rc[C];
         double2 sc = c2(0.0, 0.0);
 #pragma unroll
         for (int i = 0; i < R; ++i) {
             if (i == si) {
 #pragma unroll
-                for (int c = 0; c < 5; ++c) rc[c] = c2(__shfl(r[i][c].x, wl, 64), __shfl(r[i][c].y, wl, 64));
-                sc = c2(__shfl(sg[i].x, wl, 64), __shfl(sg[i].y, wl, 64));
+                for (int c = 0; c < C; ++c) rc[c] = c2(readlane_d(r[i][c].x, wl), readlane_d(r[i][c].y, wl));
+                sc = c2(readlane_d(sg[i].x, wl), readlane_d(sg[i].y, wl));
                 if (lane == wl) alive[i] = false;
             }
         }
         double2 rp = rc[0];
 #pragma unroll
         for (int c = 1; c < 4; ++c) if (c == piv) rp = rc[c];
-        const double2 inv = cdiv(c2(-1.0, 0.0), rp);
-        double2 mu[5];
+        // -1 / r_pi
+        const double den = 1.0 / cabs2(rp);
+        const double2 inv = c2(-rp.x * den, rp.y * den);
+        double2 mu[C];
 #pragma unroll
-        for (int c = 0; c < 5; ++c) mu[c] = (c == piv) ? c2(0.0, 0.0) : cmul(rc[c], inv);
+        for (int c = 0; c < C; ++c) mu[c] = (c == piv) ? c2(0.0, 0.0) : cmul(rc[c], inv);
         if (lane == 0) {
             LeafRec& o = rec[step];
 #pragma unroll
-            for (int c = 0; c < 5; ++c) o.mu[c] = mu[c];
+            for (int c = 0; c < C; ++c) o.mu[c] = mu[c];
             o.sig = sc;
             o.piv = piv;
             o.q = (int)(q0 + si * 64 + wl);
@@ -529,7 +580,7 @@ __global__ __launch_bounds__(64) void k_leaf_loop(const LeafArgs a) {
 #pragma unroll
             for (int c = 1; c < 4; ++c) if (c == piv) rpv = r[i][c];
 #pragma unroll
-            for (int c = 0; c < 5; ++c) {
+            for (int c = 0; c < C; ++c) {
                 if (c == piv) r[i][c] = cmul(rpv, csub(sg[i], sc));
                 else r[i][c] = cfma(mu[c], rpv, r[i][c]);
             }
@@ -539,29 +590,30 @@ __global__ __launch_bounds__(64) void k_leaf_loop(const LeafArgs a) {
     }
     if (lane == 0) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) a.st[s].delta[c] = dl[c];
-        if (info) a.st[s].info |= info;
+        for (int c = 0; c < 4; ++c) a.st[g].delta[c] = dl[c];
+        if (info) a.st[g].info |= info;
     }
 }
 
 // Basis of one leaf from its step records: B = E_1 E_2 ... E_K with the
-// elementary factors of eq. (spbasis).  One wavefront per row of [B0 | v]
-// (4 waves), coefficient k of each polynomial on lane k%64, slot k/64.
+// elementary factors of eq. (spbasis).  One wavefront per row of [B0 | V]
+// (4 waves), coefficient k of each polynomial on lane k%64, slot k/64; the
+// records are staged in LDS, the shift by z is a DPP lane shift.
 struct BuildArgs {
     const SolveState* st;
     const LeafRec* rec;
     int64_t rec_stride;
-    double2* out;          // slot data [s][20][cap+1]
+    double2* out;          // slot data [g][4C][cap+1]
     int64_t out_stride;
     int64_t cap;
-    SlotMeta* meta;        // [s]
+    SlotMeta* meta;        // [g]
     int K;
 };
 
-template <int PIV, int S>
-__device__ __forceinline__ void build_step(double2 (&P)[5][S], const double2 (&mu)[5], double2 sg, int active, int lane) {
+template <int PIV, int S, int C>
+__device__ __forceinline__ void build_step(double2 (&P)[C][S], const double2 (&mu)[C], double2 sg, int active, int lane) {
 #pragma unroll
-    for (int c = 0; c < 5; ++c) {
+    for (int c = 0; c < C; ++c) {
         if (c == PIV) continue;
         if (!cnonzero(mu[c])) continue;
 #pragma unroll
@@ -572,47 +624,59 @@ __device__ __forceinline__ void build_step(double2 (&P)[5][S], const double2 (&m
 #pragma unroll
     for (int sl = 0; sl < S; ++sl) {
         if (sl <= active + 1) {
-            double ux = __shfl_up(P[PIV][sl].x, 1, 64), uy = __shfl_up(P[PIV][sl].y, 1, 64);
-            double cx = 0.0, cy = 0.0;
-            if (sl > 0) { cx = __shfl(P[PIV][sl - 1].x, 63, 64); cy = __shfl(P[PIV][sl - 1].y, 63, 64); }
-            double2 up = (lane == 0) ? c2(cx, cy) : c2(ux, uy);
-            nv[sl] = csub(up, cmul(sg, P[PIV][sl]));
+            double ux = wave_shr1_d(P[PIV][sl].x), uy = wave_shr1_d(P[PIV][sl].y);
+            if (sl > 0 && lane == 0) {
+                ux = readlane_d(P[PIV][sl - 1].x, 63);
+                uy = readlane_d(P[PIV][sl - 1].y, 63);
+            }
+            nv[sl] = csub(c2(ux, uy), cmul(sg, P[PIV][sl]));
         }
     }
 #pragma unroll
     for (int sl = 0; sl < S; ++sl) if (sl <= active + 1) P[PIV][sl] = nv[sl];
 }
 
-template <int S>
+template <int S, int NR>
 __global__ __launch_bounds__(256) void k_leaf_build(const BuildArgs a) {
-    const int64_t s = blockIdx.x;
+    constexpr int C = 4 + NR;
+    const int64_t g = blockIdx.x;
     const int row = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    const LeafRec* rec = a.rec + s * a.rec_stride;
-    double2 P[5][S];
+    __shared__ LeafRec lrec[LEAF_MAX];
+    {
+        const double2* src = (const double2*)(a.rec + g * a.rec_stride);
+        double2* dstp = (double2*)lrec;
+        const int nv = a.K * (int)(sizeof(LeafRec) / sizeof(double2));
+        for (int i = threadIdx.x; i < nv; i += 256) dstp[i] = src[i];
+    }
+    __syncthreads();
+    double2 P[C][S];
 #pragma unroll
-    for (int c = 0; c < 5; ++c)
+    for (int c = 0; c < C; ++c)
 #pragma unroll
         for (int sl = 0; sl < S; ++sl) P[c][sl] = c2((c == row && sl == 0 && lane == 0) ? 1.0 : 0.0, 0.0);
-    int deg[5] = {0, 0, 0, 0, -1};
+    int deg[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) deg[c] = c < 4 ? 0 : -1;
     int dmax = 0;
-    const bool broken = a.st[s].info != 0;
+    const bool broken = a.st[g].info != 0;
     for (int step = 0; step < a.K && !broken; ++step) {
-        const LeafRec& rr = rec[step];
+        const LeafRec& rr = lrec[step];
         const int piv = rr.piv;
         if (piv < 0) continue;
-        double2 mu[5];
+        double2 mu[C];
 #pragma unroll
-        for (int c = 0; c < 5; ++c) mu[c] = rr.mu[c];
+        for (int c = 0; c < C; ++c) mu[c] = rr.mu[c];
         const double2 sg = rr.sig;
         const int active = dmax >> 6;
         switch (piv) {
-            case 0: build_step<0, S>(P, mu, sg, active, lane); break;
-            case 1: build_step<1, S>(P, mu, sg, active, lane); break;
-            case 2: build_step<2, S>(P, mu, sg, active, lane); break;
-            default: build_step<3, S>(P, mu, sg, active, lane); break;
+            case 0: build_step<0, S, C>(P, mu, sg, active, lane); break;
+            case 1: build_step<1, S, C>(P, mu, sg, active, lane); break;
+            case 2: build_step<2, S, C>(P, mu, sg, active, lane); break;
+            default: build_step<3, S, C>(P, mu, sg, active, lane); break;
         }
-        for (int c = 0; c < 5; ++c)
+#pragma unroll
+        for (int c = 0; c < C; ++c)
             if (c != piv && cnonzero(mu[c])) deg[c] = max(deg[c], deg[piv]);
         deg[piv] += 1;
         dmax = max(dmax, deg[piv]);
@@ -628,11 +692,11 @@ __global__ __launch_bounds__(256) void k_leaf_build(const BuildArgs a) {
         if (lane == 0) cm[row][c] = mx;
     }
     __syncthreads();
-    double2* out = a.out + s * a.out_stride;
+    double2* out = a.out + g * a.out_stride;
     const int64_t cp1 = a.cap + 1;
 #pragma unroll
-    for (int c = 0; c < 5; ++c) {
-        double2* dst = out + (int64_t)(row * 5 + c) * cp1;
+    for (int c = 0; c < C; ++c) {
+        double2* dst = out + (int64_t)(row * C + c) * cp1;
 #pragma unroll
         for (int sl = 0; sl < S; ++sl) {
             int64_t k = lane + 64 * sl;
@@ -642,7 +706,8 @@ __global__ __launch_bounds__(256) void k_leaf_build(const BuildArgs a) {
     if (threadIdx.x == 0) {
         SlotMeta m;
         int bad = 0;
-        for (int c = 0; c < 5; ++c) {
+        for (int c = 0; c < MAXC; ++c) m.deg[c] = -1;
+        for (int c = 0; c < C; ++c) {
             if (deg[c] > a.cap) bad = 1;
             m.deg[c] = (int)min((int64_t)deg[c], a.cap);   // never read past the slot
         }
@@ -650,145 +715,301 @@ __global__ __launch_bounds__(256) void k_leaf_build(const BuildArgs a) {
             double mx = fmax(fmax(cm[0][c], cm[1][c]), fmax(cm[2][c], cm[3][c]));
             m.colmax_bits[c] = (unsigned long long)__double_as_longlong(sqrt(mx));
         }
-        m.pad[0] = m.pad[1] = m.pad[2] = 0;
-        a.meta[s] = m;
-        if (bad) atomicOr(&((SolveState*)a.st)[s].info, 2);
+        a.meta[g] = m;
+        if (bad) atomicOr(&((SolveState*)a.st)[g].info, 2);
     }
 }
 
 // ---------------------------------------------------------------- evaluation, Alg. 1 step 2
-// V[s][e][c][r] = sum_{i = r mod L, i <= deg} scale_col(e) B[e][i] w^{(o + c) i}
+// V[g][e][c][r] = sum_{i = r mod L, i <= deg} scale_col(e) B[e][i] w^{(o + c) i}
 // (twist by the coset offset and fold modulo the coset length L); an FFT of
 // length L then gives B_e at the nodes w^{o + c + j 2^{d+1}}, j < L.
-__global__ void k_twist_fold(const double2* __restrict__ B, int64_t b_stride, int64_t cp1,
+__global__ void k_twist_fold(const double2* __restrict__ B, int64_t b_stride, int64_t cp1, int C,
                              const SlotMeta* __restrict__ meta, double2* __restrict__ V, int64_t v_stride,
                              int64_t L, int64_t o, int64_t N, const double2* __restrict__ tw, int64_t Q) {
-    const int64_t s = blockIdx.z;
+    const int64_t g = blockIdx.z;
     const int ec = blockIdx.y;            // e*2 + c
     const int e = ec >> 1, c = ec & 1;
-    const int col = e % 5;
-    const SlotMeta mt = meta[s];
+    const int col = e % C;
+    const SlotMeta mt = meta[g];
     const int dg = mt.deg[col];
     const double sc = col < 4 ? pow2_inv_scale(mt.colmax_bits[col]) : 1.0;
-    const double2* src = B + s * b_stride + (int64_t)e * cp1;
+    const double2* src = B + g * b_stride + (int64_t)e * cp1;
     const int64_t oc = o + c;
     const int64_t twN = Q / N;
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < L; r += (int64_t)gridDim.x * blockDim.x) {
         double2 acc = c2(0.0, 0.0);
         for (int64_t i = r; i <= dg; i += L) acc = cfma(src[i], twq(tw, Q, (oc * i % N) * twN, +1), acc);
-        V[s * v_stride + (int64_t)ec * L + r] = cscale(acc, sc);
+        V[g * v_stride + (int64_t)ec * L + r] = cscale(acc, sc);
     }
 }
 
 // phi <- phi B_L(sigma) for every condition of the right subtree
 // (Alg. 1 step 2, with Thm. 1 giving the data phi_k B_kappa(sigma_k)).
 // The right subtree (depth d, coset offset oR) spans leaves [t0, t0 + 2^{p-d}).
+// V holds each line in four-step order: value j at (j % L1) * (L / L1) + j / L1.
+template <int NR>
 __global__ void k_eval_apply(double2* __restrict__ phi, int64_t phi_stride, const double2* __restrict__ V,
-                             int64_t v_stride, int64_t L, int64_t oR, int d, int64_t t0, int64_t nleaves,
+                             int64_t v_stride, int64_t L, int64_t L1, int64_t oR, int d, int64_t t0, int64_t nleaves,
                              int64_t N, int64_t M, int p, int K) {
-    const int64_t s = blockIdx.y;
+    constexpr int C = 4 + NR;
+    const int64_t g = blockIdx.y;
     const int64_t nq = 2 * N;
     const int64_t cnt = nleaves * K;
-    double2* ph = phi + s * phi_stride;
-    const double2* Vs = V + s * v_stride;
+    double2* ph = phi + g * phi_stride;
+    const double2* Vs = V + g * v_stride;
     for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < cnt; u += (int64_t)gridDim.x * blockDim.x) {
         const int64_t q = t0 * K + u;
         const int64_t t = q / K, h = q - t * K;
         const int64_t c = h / M, jhi = (h - c * M) >> 1;
         const int64_t ot = 2 * (int64_t)bitrev((int)t, p);
         const int64_t jlo = (ot - oR) >> (d + 1);
-        const int64_t j = jlo + (jhi << (p - d));
-        double2 f[5];
+        const int64_t jn = jlo + (jhi << (p - d));
+        const int64_t j = (jn % L1) * (L / L1) + jn / L1;
+        double2 f[C];
 #pragma unroll
-        for (int col = 0; col < 5; ++col) f[col] = ph[col * nq + q];
-        double2 o[5];
-        o[4] = f[4];
+        for (int col = 0; col < C; ++col) f[col] = ph[col * nq + q];
+        double2 o[C];
 #pragma unroll
-        for (int col = 0; col < 4; ++col) o[col] = c2(0.0, 0.0);
+        for (int col = 0; col < C; ++col) o[col] = col < 4 ? c2(0.0, 0.0) : f[col];
 #pragma unroll
         for (int row = 0; row < 4; ++row) {
 #pragma unroll
-            for (int col = 0; col < 5; ++col) {
-                double2 E = Vs[(int64_t)((row * 5 + col) * 2 + c) * L + j];
+            for (int col = 0; col < C; ++col) {
+                double2 E = Vs[(int64_t)((row * C + col) * 2 + c) * L + j];
                 o[col] = cfma(f[row], E, o[col]);
             }
         }
 #pragma unroll
-        for (int col = 0; col < 5; ++col) ph[col * nq + q] = o[col];
+        for (int col = 0; col < C; ++col) ph[col * nq + q] = o[col];
+    }
+}
+
+// Small subtrees: direct evaluation (Horner) of the completed left child at
+// the nodes of its right sibling and the update phi <- phi B_L(sigma), one
+// workgroup per group, one thread per node (two conditions per node).
+template <int NR>
+__global__ __launch_bounds__(256) void k_eval_direct(double2* __restrict__ phi, int64_t phi_stride,
+                                                     const double2* __restrict__ B, int64_t b_stride, int64_t cp1,
+                                                     const SlotMeta* __restrict__ meta, int64_t t0, int64_t nleaves,
+                                                     int64_t N, int64_t M, int p, int K,
+                                                     const double2* __restrict__ tw, int64_t Q) {
+    constexpr int C = 4 + NR;
+    const int64_t g = blockIdx.x;
+    const SlotMeta mt = meta[g];
+    double sc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) sc[c] = c < 4 ? pow2_inv_scale(mt.colmax_bits[c]) : 1.0;
+    const double2* Bs = B + g * b_stride;
+    double2* ph = phi + g * phi_stride;
+    const int64_t nq = 2 * N;
+    const int64_t nodes = nleaves * K / 2;
+    for (int64_t u = threadIdx.x; u < nodes; u += blockDim.x) {
+        const int64_t q = t0 * K + 2 * u;           // the F condition; q + 1 is the G condition of the same node
+        const double2 z = cond_node(q, N, M, p, K, tw, Q);
+        double2 f0[C], f1[C], o0[C], o1[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            f0[c] = ph[c * nq + q]; f1[c] = ph[c * nq + q + 1];
+            o0[c] = c < 4 ? c2(0.0, 0.0) : f0[c];
+            o1[c] = c < 4 ? c2(0.0, 0.0) : f1[c];
+        }
+#pragma unroll
+        for (int col = 0; col < C; ++col) {
+            const int dg = mt.deg[col];
+#pragma unroll
+            for (int row = 0; row < 4; ++row) {
+                const double2* src = Bs + (int64_t)(row * C + col) * cp1;
+                double2 acc = c2(0.0, 0.0);
+                for (int k = dg; k >= 0; --k) acc = cfma(acc, z, src[k]);
+                acc = cscale(acc, sc[col]);
+                o0[col] = cfma(f0[row], acc, o0[col]);
+                o1[col] = cfma(f1[row], acc, o1[col]);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) { ph[c * nq + q] = o0[c]; ph[c * nq + q + 1] = o1[c]; }
+    }
+}
+
+// Small subtrees: direct block product [[B0L, VL],[0,I]] [[B0R, VR],[0,I]]
+// = [[B0L B0R, B0L VR + VL],[0,I]] by convolution of the coefficient
+// sequences, one workgroup per group; writes the parent basis, its degrees
+// and its column maxima.
+__global__ __launch_bounds__(256) void k_prod_direct(const double2* __restrict__ BL, int64_t l_stride, int64_t lcp1,
+                                                     const SlotMeta* __restrict__ mL,
+                                                     const double2* __restrict__ BR, int64_t r_stride, int64_t rcp1,
+                                                     const SlotMeta* __restrict__ mR,
+                                                     double2* __restrict__ out, int64_t o_stride, int64_t ocp1,
+                                                     SlotMeta* __restrict__ mO, SolveState* __restrict__ st, int C) {
+    const int64_t g = blockIdx.x;
+    const SlotMeta a = mL[g], b = mR[g];
+    double sl[MAXC], sr[MAXC];
+    for (int c = 0; c < MAXC; ++c) {
+        sl[c] = c < 4 ? pow2_inv_scale(a.colmax_bits[c]) : 1.0;
+        sr[c] = c < 4 ? pow2_inv_scale(b.colmax_bits[c]) : 1.0;
+    }
+    int dl = -1;
+    for (int l = 0; l < 4; ++l) dl = max(dl, a.deg[l]);
+    int dout[MAXC];
+    int bad = 0;
+    for (int j = 0; j < MAXC; ++j) dout[j] = -1;
+    for (int j = 0; j < C; ++j) {
+        int dj = (b.deg[j] < 0 || dl < 0) ? -1 : dl + b.deg[j];
+        if (j >= 4) dj = max(dj, a.deg[j]);
+        if (dj >= ocp1) { bad = 1; dj = (int)ocp1 - 1; }
+        dout[j] = dj;
+    }
+    const double2* L = BL + g * l_stride;
+    const double2* R = BR + g * r_stride;
+    double2* O = out + g * o_stride;
+    double cmx[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < C; ++j) {
+        const int64_t cnt = 4 * (int64_t)(dout[j] + 1);
+        for (int64_t w = threadIdx.x; w < cnt; w += blockDim.x) {
+            const int i = (int)(w % 4);
+            const int k = (int)(w / 4);
+            double2 acc = c2(0.0, 0.0);
+            for (int l = 0; l < 4; ++l) {
+                const int dla = a.deg[l], dr = b.deg[j];
+                if (dla < 0 || dr < 0) continue;
+                const int t0 = max(0, k - dr), t1 = min(k, dla);
+                const double2* lp = L + (int64_t)(i * C + l) * lcp1;
+                const double2* rp = R + (int64_t)(l * C + j) * rcp1;
+                double2 part = c2(0.0, 0.0);
+                for (int t = t0; t <= t1; ++t) part = cfma(lp[t], rp[k - t], part);
+                acc = cfma(part, c2(sl[l] * sr[j], 0.0), acc);
+            }
+            if (j >= 4 && k <= a.deg[j]) acc = cadd(acc, L[(int64_t)(i * C + j) * lcp1 + k]);
+            O[(int64_t)(i * C + j) * ocp1 + k] = acc;
+            if (j < 4) cmx[j] = fmax(cmx[j], cabs2(acc));
+        }
+    }
+    __shared__ double red[4][256];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) red[c][threadIdx.x] = cmx[c];
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) red[c][threadIdx.x] = fmax(red[c][threadIdx.x], red[c][threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        SlotMeta m;
+        for (int j = 0; j < MAXC; ++j) m.deg[j] = dout[j];
+        for (int c = 0; c < 4; ++c) m.colmax_bits[c] = (unsigned long long)__double_as_longlong(sqrt(red[c][0]));
+        mO[g] = m;
+        if (bad) atomicOr(&st[g].info, 2);
     }
 }
 
 // ---------------------------------------------------------------- product, Alg. 1 step 4
 // Zero-padded, column-scaled copy of selected basis entries into FFT lines of length P.
-__global__ void k_prod_load(const double2* __restrict__ B, int64_t b_stride, int64_t cp1,
+__global__ void k_prod_load(const double2* __restrict__ B, int64_t b_stride, int64_t cp1, int C,
                             const SlotMeta* __restrict__ meta, const int* __restrict__ elist,
                             double2* __restrict__ F, int64_t f_stride, int64_t P) {
-    const int64_t s = blockIdx.z;
+    const int64_t g = blockIdx.z;
     const int li = blockIdx.y;
     const int e = elist[li];
-    const int col = e % 5;
-    const SlotMeta mt = meta[s];
+    const int col = e % C;
+    const SlotMeta mt = meta[g];
     const int dg = mt.deg[col];
     const double sc = col < 4 ? pow2_inv_scale(mt.colmax_bits[col]) : 1.0;
-    const double2* src = B + s * b_stride + (int64_t)e * cp1;
-    double2* dst = F + s * f_stride + (int64_t)li * P;
+    const double2* src = B + g * b_stride + (int64_t)e * cp1;
+    double2* dst = F + g * f_stride + (int64_t)li * P;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < P; k += (int64_t)gridDim.x * blockDim.x)
         dst[k] = k <= dg ? cscale(src[k], sc) : c2(0.0, 0.0);
 }
 
-// Pointwise block product [[B0L, vL],[0,1]] [[B0R, vR],[0,1]] = [[B0L B0R, B0L vR + vL],[0,1]].
-// FL holds all 20 entries of the left factor (or only row 0 in root mode),
-// FR the right factor's needed entries (all 20, or only column 5 in root mode).
+// Pointwise block product per frequency.  Full mode: FL and FR hold all 4C
+// entries (row-major, C columns); output all 4C entries.  Root mode: FL holds
+// row 0 (C entries), FR the columns 4..C-1 of rows 0..3 (4 NR entries, row-major);
+// output the NR solution polynomials (row 0, columns 4..C-1).
+template <int NR>
 __global__ void k_prod_mul(const double2* FL, const double2* __restrict__ FR,
                            double2* FO, int64_t f_stride, int64_t P, int root) {
-    const int64_t s = blockIdx.y;
-    const double2* L = FL + s * f_stride;
-    const double2* R = FR + s * f_stride;
-    double2* O = FO + s * f_stride;
+    constexpr int C = 4 + NR;
+    const int64_t g = blockIdx.y;
+    const double2* L = FL + g * f_stride;
+    const double2* R = FR + g * f_stride;
+    double2* O = FO + g * f_stride;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < P; k += (int64_t)gridDim.x * blockDim.x) {
         if (root) {
-            // L lines: entries (0,0..4); R lines: entries (0..3, 4); output: entry (0,4)
-            double2 acc = L[4 * P + k];
+            double2 l[C], r[4][NR];
 #pragma unroll
-            for (int l = 0; l < 4; ++l) acc = cfma(L[l * P + k], R[l * P + k], acc);
-            O[k] = acc;
-        } else {
-            double2 l[4][5], r[4][5];
+            for (int j = 0; j < C; ++j) l[j] = L[j * P + k];
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < 5; ++j) { l[i][j] = L[(i * 5 + j) * P + k]; r[i][j] = R[(i * 5 + j) * P + k]; }
+                for (int j = 0; j < NR; ++j) r[i][j] = R[(i * NR + j) * P + k];
+#pragma unroll
+            for (int j = 0; j < NR; ++j) {
+                double2 acc = l[4 + j];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) acc = cfma(l[t], r[t][j], acc);
+                O[j * P + k] = acc;
+            }
+        } else {
+            double2 l[4][C], r[4][C];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < C; ++j) { l[i][j] = L[(i * C + j) * P + k]; r[i][j] = R[(i * C + j) * P + k]; }
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
 #pragma unroll
-                for (int j = 0; j < 5; ++j) {
-                    double2 acc = (j == 4) ? l[i][4] : c2(0.0, 0.0);
+                for (int j = 0; j < C; ++j) {
+                    double2 acc = (j >= 4) ? l[i][j] : c2(0.0, 0.0);
 #pragma unroll
                     for (int t = 0; t < 4; ++t) acc = cfma(l[i][t], r[t][j], acc);
-                    O[(i * 5 + j) * P + k] = acc;
+                    O[(i * C + j) * P + k] = acc;
                 }
             }
         }
     }
 }
 
+// Largest product degree + 1 over a chunk of groups (sizes the product
+// transforms).  One workgroup of 256 threads.
+__global__ __launch_bounds__(256) void k_deg_need(const SlotMeta* __restrict__ mL, const SlotMeta* __restrict__ mR,
+                                                  int ngroup, int C, int* __restrict__ need) {
+    int v = 0;
+    for (int s = threadIdx.x; s < ngroup; s += 256) {
+        SlotMeta a = mL[s], b = mR[s];
+        int dl = -1, dr = -1, dv = -1;
+        for (int l = 0; l < 4; ++l) dl = max(dl, a.deg[l]);
+        for (int j = 0; j < C; ++j) dr = max(dr, b.deg[j]);
+        for (int j = 4; j < C; ++j) dv = max(dv, a.deg[j]);
+        v = max(v, max(dl + dr, dv) + 1);
+    }
+    __shared__ int red[256];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *need = red[0];
+}
+
 // Degrees of the product: column j of B0L B0R has degree <= max_l degL(l) + degR(j);
-// v: max(max_l degL(l) + degR(v), degL(v)).  Resets the column maxima.
+// V columns: max(max_l degL(l) + degR(j), degL(j)).  Resets the column maxima.
 __global__ void k_prod_meta(const SlotMeta* __restrict__ mL, const SlotMeta* __restrict__ mR,
-                            SlotMeta* __restrict__ mO, SolveState* __restrict__ st, int64_t cap, int nsolve) {
+                            SlotMeta* __restrict__ mO, SolveState* __restrict__ st, int64_t cap, int ngroup, int C) {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= nsolve) return;
+    if (s >= ngroup) return;
     SlotMeta a = mL[s], b = mR[s], o;
     int dl = -1;
     for (int l = 0; l < 4; ++l) dl = max(dl, a.deg[l]);
     int bad = 0;
-    for (int j = 0; j < 5; ++j) {
+    for (int j = 0; j < MAXC; ++j) o.deg[j] = -1;
+    for (int j = 0; j < C; ++j) {
         int dj = (b.deg[j] < 0 || dl < 0) ? -1 : dl + b.deg[j];
-        if (j == 4) dj = max(dj, a.deg[4]);
+        if (j >= 4) dj = max(dj, a.deg[j]);
         if (dj > cap) { bad = 1; dj = (int)cap; }
         o.deg[j] = dj;
     }
-    o.pad[0] = o.pad[1] = o.pad[2] = 0;
     for (int c = 0; c < 4; ++c) o.colmax_bits[c] = 0ull;
     mO[s] = o;
     if (bad) atomicOr(&st[s].info, 2);
@@ -798,16 +1019,16 @@ __global__ void k_prod_meta(const SlotMeta* __restrict__ mL, const SlotMeta* __r
 // the degree bound) and column maxima of B0 (for the power-of-two column
 // normalization applied by the next consumer).
 __global__ void k_prod_store(const double2* __restrict__ FO, int64_t f_stride, int64_t P,
-                             double2* __restrict__ out, int64_t o_stride, int64_t cp1,
-                             SlotMeta* __restrict__ meta, int nent, const int* __restrict__ elist) {
-    const int64_t s = blockIdx.z;
+                             double2* __restrict__ out, int64_t o_stride, int64_t cp1, int C,
+                             SlotMeta* __restrict__ meta, const int* __restrict__ elist) {
+    const int64_t g = blockIdx.z;
     const int li = blockIdx.y;
     const int e = elist[li];
-    const int col = e % 5;
-    const int dg = meta[s].deg[col];
+    const int col = e % C;
+    const int dg = meta[g].deg[col];
     const double inv = 1.0 / (double)P;
-    const double2* src = FO + s * f_stride + (int64_t)li * P;
-    double2* dst = out + s * o_stride + (int64_t)e * cp1;
+    const double2* src = FO + g * f_stride + (int64_t)li * P;
+    double2* dst = out + g * o_stride + (int64_t)e * cp1;
     double mx = 0.0;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k <= dg && k < cp1; k += (int64_t)gridDim.x * blockDim.x) {
         double2 v = cscale(src[k], inv);
@@ -817,43 +1038,49 @@ __global__ void k_prod_store(const double2* __restrict__ FO, int64_t f_stride, i
     if (col < 4) {
         mx = wave_max_d(mx);
         if ((threadIdx.x & 63) == 0 && mx > 0.0)
-            atomicMax(&meta[s].colmax_bits[col], (unsigned long long)__double_as_longlong(sqrt(mx)));
+            atomicMax(&meta[g].colmax_bits[col], (unsigned long long)__double_as_longlong(sqrt(mx)));
     }
 }
 
 // ---------------------------------------------------------------- extraction (Sec. 5)
-// x = B*_{1j} / B*_{5j} with j the tau-degree-0 column: with column 5 never
-// pivoted, j = 5 and B*_{55} = 1, so x_i = [z^i] v_1.  Accumulates into xacc
-// (refinement adds the correction) and checks the final degrees {1,1,1,1,0}.
-__global__ void k_extract(const SolveDesc* __restrict__ sd, SolveState* __restrict__ st,
+// x = B*_{1j} / B*_{5j} with j the tau-degree-0 column: the constant columns
+// are never pivoted, so for right-hand side r the solution column is 4 + r
+// with unit constant entry, and x_i = [z^i] V_{1r}.  Accumulates into xacc
+// (refinement adds the correction) and checks the final degrees {1,1,1,1,0..}.
+__global__ void k_extract(const SolveDesc* __restrict__ sd, int nr, SolveState* __restrict__ st,
                           const double2* __restrict__ B, int64_t b_stride, int64_t cp1,
                           const SlotMeta* __restrict__ meta, double2* __restrict__ xacc, int64_t x_stride,
                           int accumulate) {
     const int64_t s = blockIdx.y;
+    const int64_t g = s / nr;
+    const int r = (int)(s - g * nr);
     const SolveDesc d = sd[s];
-    const int dg = meta[s].deg[4];
-    const double2* v1 = B + s * b_stride + 4 * cp1;     // entry (row 0, column 5)
+    const int C = 4 + nr;
+    const int dg = meta[g].deg[4 + r];
+    const double2* v1 = B + g * b_stride + (int64_t)(4 + r) * cp1;     // entry (row 0, column 4 + r)
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < d.n; i += (int64_t)gridDim.x * blockDim.x) {
         double2 v = (i <= dg && i < cp1) ? v1[i] : c2(0.0, 0.0);
-        if (!isfinite(v.x) || !isfinite(v.y)) atomicOr(&st[s].info, 3);
+        if (!isfinite(v.x) || !isfinite(v.y)) atomicOr(&st[g].info, 3);
         xacc[s * x_stride + i] = accumulate ? cadd(xacc[s * x_stride + i], v) : v;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    (void)C;
+    if (r == 0 && blockIdx.x == 0 && threadIdx.x == 0) {
         for (int c = 0; c < 4; ++c)
-            if (st[s].delta[c] != 1) atomicOr(&st[s].info, 1);
+            if (st[g].delta[c] != 1) atomicOr(&st[g].info, 1);
     }
 }
 
-__global__ void k_store_x(const SolveDesc* __restrict__ sd, const double2* __restrict__ xacc, int64_t x_stride,
+__global__ void k_store_x(const SolveDesc* __restrict__ sd, int nr, const double2* __restrict__ xacc, int64_t x_stride,
                           const SolveState* __restrict__ st, int32_t* __restrict__ info) {
     const int64_t s = blockIdx.y;
     const SolveDesc d = sd[s];
+    if (!d.rhs) return;                        // padding solve
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < d.n; i += (int64_t)gridDim.x * blockDim.x) {
         double2 v = xacc[s * x_stride + i];
         if (d.cplx) ((double2*)d.x)[i] = v;
         else ((double*)d.x)[i] = v.x;
     }
-    if (info && blockIdx.x == 0 && threadIdx.x == 0) info[s] = st[s].info;
+    if (info && blockIdx.x == 0 && threadIdx.x == 0) info[d.orig] = st[s / nr].info;
 }
 
 // ---------------------------------------------------------------- adjoint (backward)
@@ -867,7 +1094,7 @@ __global__ void k_sub_from_b(const SolveDesc* __restrict__ sd, const double2* __
     const int64_t s = blockIdx.y;
     const SolveDesc d = sd[s];
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < d.m; i += (int64_t)gridDim.x * blockDim.x)
-        out[s * stride + i] = csub(load_elem(d.bin, i, d.cplx), v[s * stride + i]);
+        out[s * stride + i] = csub(d.rhs ? load_elem(d.bin, i, d.cplx) : c2(0.0, 0.0), v[s * stride + i]);
 }
 
 // dst = A * conj(B) (accumulate = 0) or dst -= A * conj(B) (accumulate = 1), length N
@@ -886,6 +1113,7 @@ __global__ void k_store_grads(const SolveDesc* __restrict__ sd, const double2* _
                               int64_t gstride, double invN, const double2* __restrict__ Tw, int64_t vstride) {
     const int64_t s = blockIdx.y;
     const SolveDesc d = sd[s];
+    if (!d.rhs) return;
     const int64_t tot = d.m + d.n + d.m;
     for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < tot; u += (int64_t)gridDim.x * blockDim.x) {
         double2 v;
@@ -900,11 +1128,12 @@ __global__ void k_store_grads(const SolveDesc* __restrict__ sd, const double2* _
 }
 
 // g_lam = -2 lam Re sum_j conj(w_j) x_j
-__global__ __launch_bounds__(256) void k_grad_lambda(const SolveDesc* __restrict__ sd, const double2* __restrict__ w,
-                                                     int64_t stride, SolveState* __restrict__ st,
-                                                     int32_t* __restrict__ info) {
+__global__ __launch_bounds__(256) void k_grad_lambda(const SolveDesc* __restrict__ sd, int nr,
+                                                     const double2* __restrict__ w, int64_t stride,
+                                                     SolveState* __restrict__ st, int32_t* __restrict__ info) {
     const int64_t s = blockIdx.x;
     const SolveDesc d = sd[s];
+    if (!d.rhs) return;
     double acc = 0.0;
     for (int64_t i = threadIdx.x; i < d.n; i += blockDim.x) {
         double2 wv = w[s * stride + i];
@@ -920,20 +1149,21 @@ __global__ __launch_bounds__(256) void k_grad_lambda(const SolveDesc* __restrict
     }
     if (threadIdx.x == 0) {
         *d.glam = -2.0 * d.lam * red[0];
-        if (info) info[s] = st[s].info;
+        if (info) info[d.orig] = st[s / nr].info;
     }
 }
 
-__global__ void k_init_state(const SolveDesc* __restrict__ sd, SolveState* __restrict__ st, int nsolve, int keep_info) {
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= nsolve) return;
-    const SolveDesc d = sd[s];
+__global__ void k_init_state(const SolveDesc* __restrict__ sd, int nr, SolveState* __restrict__ st, int ngroup,
+                             int keep_info) {
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ngroup) return;
+    const SolveDesc d = sd[(int64_t)g * nr];
     // delta = -tau, tau = [n-1, m-1, m+k-2, n+k-2, 0] (eq. (taudef) adapted to eq. (ex6))
-    st[s].delta[0] = -(int)(d.n - 1);
-    st[s].delta[1] = -(int)(d.m - 1);
-    st[s].delta[2] = -(int)(d.m + d.k - 2);
-    st[s].delta[3] = -(int)(d.n + d.k - 2);
-    if (!keep_info) st[s].info = 0;
+    st[g].delta[0] = -(int)(d.n - 1);
+    st[g].delta[1] = -(int)(d.m - 1);
+    st[g].delta[2] = -(int)(d.m + d.k - 2);
+    st[g].delta[3] = -(int)(d.n + d.k - 2);
+    if (!keep_info) st[g].info = 0;
 }
 
 }  // namespace tikh

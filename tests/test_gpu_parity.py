@@ -173,3 +173,32 @@ def test_nonfinite_input_reports_info(P):
     with pytest.raises(P.TikhError) as e:
         P.solve(dev(col), dev(np.ones(10)), dev(np.ones(20)), 0.5)
     assert e.value.code == -4
+
+
+@pytest.mark.parametrize("nrhs,cplx", [(3, False), (4, True), (5, False)])
+def test_batched_rhs_groups(P, nrhs, cplx):
+    """Right-hand sides of one (problem, lambda) share the pivot sequence and
+    ride along in one recursion (groups of 1, 2 or 4; the last group padded):
+    every solve must still match the oracle."""
+    rng = np.random.default_rng(700 + nrhs)
+    shapes = [(90, 64), (41, 77)]
+    lams = []
+    cols, rows, bs, probs = [], [], [], []
+    for (m, n) in shapes:
+        col, row, _ = W.random_problem(rng, m, n, cplx=cplx, L=9.0)
+        B = [rng.standard_normal(m) + (1j * rng.standard_normal(m) if cplx else 0) for _ in range(nrhs)]
+        L = [0.15, 0.6]
+        probs.append((col, row, B, L)); cols.append(col); rows.append(row); bs.extend(B); lams.extend(L)
+    x, info = P.solve_batched([s[0] for s in shapes], [s[1] for s in shapes], dev(np.concatenate(cols)),
+                              dev(np.concatenate(rows)), lams, nrhs, dev(np.concatenate(bs)), complex_data=cplx)
+    torch.cuda.synchronize()
+    assert (info.cpu().numpy() == 0).all()
+    x = x.cpu().numpy()
+    off = 0
+    for (col, row, B, L) in probs:
+        n = len(row)
+        for lam in L:
+            for b in B:
+                assert relerr(x[off:off + n], oracle.solve(col, row, b, lam)) <= TOL
+                off += n
+    assert off == len(x)
