@@ -29,34 +29,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 
-def fp64_leaf_loop_flops(K):
-    """Algorithmic FP64 flops of one leaf's serial loop (K conditions): at step c
-    the K-c remaining residual rows are scored (4 |r|^2, 12 flops) and updated
-    (4 complex multiply-adds + 1 complex multiply + 1 complex subtract, 40 flops)."""
-    return sum(52 * (K - c) for c in range(K))
-
-
-def fp64_leaf_build_flops(K):
-    """Algorithmic FP64 flops of forming one leaf basis from its K step records:
-    at step c the pivot column has degree ~c/4 (four pivot columns share the
-    steps); per row 4 complex multiply-adds and one complex shift-multiply per
-    coefficient, 4 rows: 160 (c/4 + 1) flops."""
-    return sum(160 * (c // 4 + 1) for c in range(K))
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--nprob", type=int, default=4, help="problems per step (each 8 lambdas x 4 RHS)")
+    ap.add_argument("--nprob", type=int, default=64, help="problems per step (each 8 lambdas x 4 RHS)")
     ap.add_argument("--nlam", type=int, default=8)
     ap.add_argument("--nrhs", type=int, default=4)
     ap.add_argument("--n", type=int, default=2 ** 14)
     ap.add_argument("--plain-solves", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=1536, help="size of the CPU-oracle sample")
-    ap.add_argument("--kernel", default="leaf_loop", help="dominant kernel for the roofline object")
+    ap.add_argument("--kernel", default="auto", help="kernel for the roofline object: fft, leaf_loop or auto "
+                                                     "(the one with the larger share of the step)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -105,26 +91,31 @@ def main():
     value = nsolve * args.steps / (ms_total / 1e3)
     info_max = int(max(info.max().item(), binfo.max().item()))
 
-    # dominant kernel: live launch timing over one more step
+    # dominant kernels: live launch timing over one more step each (HIP events on the library stream)
     st = P.get_stats()
-    P.profile_kernel(args.kernel)
-    step()
-    torch.cuda.synchronize()
-    k_ms, k_count = P.profile_read()
+    rl = {}
+    for kern in ("fft", "leaf_loop"):
+        P.profile_kernel(kern)
+        step()
+        torch.cuda.synchronize()
+        k_ms, k_count, units = P.profile_read()
+        rl[kern] = (k_ms, k_count, units)
     P.profile_kernel(None)
-    K = 2 * st["leaf_nodes"]
-    S_per_launch = nsolve  # every leaf launch covers all solves of the bucket
-    if args.kernel == "leaf_loop":
-        flops = fp64_leaf_loop_flops(K) * S_per_launch
+    main_kernel = args.kernel if args.kernel in rl else max(rl, key=lambda k: rl[k][0])
+    k_ms, k_count, units = rl[main_kernel]
+    avg_ms = k_ms / max(k_count, 1)
+    if main_kernel == "fft":
+        achieved = units / (k_ms / 1e3) / 1e9 if k_ms > 0 else 0.0
+        roofline = {"bound": "hbm", "kernel": "k_fft", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
+                    "frac": round(achieved / 8000.0, 4), "traffic": None, "avg_launch_ms": round(avg_ms, 4),
+                    "launches_per_step": k_count, "bytes_per_launch": round(units / max(k_count, 1))}
     else:
-        flops = fp64_leaf_build_flops(K) * S_per_launch
-    avg_s = (k_ms / max(k_count, 1)) / 1e3
-    achieved = flops / avg_s / 1e12 if avg_s > 0 else 0.0
-    peak = 78.6
-    roofline = {"bound": "alu", "kernel": args.kernel, "achieved": round(achieved, 3), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 5), "traffic": None,
-                "avg_launch_ms": round(k_ms / max(k_count, 1), 4), "launches_per_step": k_count,
-                "flops_per_launch": flops}
+        achieved = units / (k_ms / 1e3) / 1e12 if k_ms > 0 else 0.0
+        roofline = {"bound": "alu", "kernel": "k_leaf_loop", "achieved": round(achieved, 3), "peak": 78.6,
+                    "unit": "TFLOP/s", "frac": round(achieved / 78.6, 5), "traffic": None,
+                    "avg_launch_ms": round(avg_ms, 4), "launches_per_step": k_count,
+                    "flops_per_launch": round(units / max(k_count, 1))}
+    kernel_ms = {k: round(v[0], 1) for k, v in rl.items()}
 
     # plain method: single-problem C-ABI calls, one solve + one backward per call
     nplain = max(1, args.plain_solves)
@@ -183,6 +174,7 @@ def main():
         "batched_over_plain": round(value / plain, 2),
         "info_max": info_max,
         "roofline": roofline,
+        "kernel_ms_per_step": kernel_ms,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -95,6 +95,10 @@ int tikh_plan_info(int64_t m, int64_t n, int32_t n_lim, int64_t* N, int64_t* M, 
  */
 int tikh_profile_kernel(const char* name);
 int tikh_profile_read(double* total_ms, int64_t* count);
+/* Algorithmic work of the timed launches (host pointer): for "fft" the bytes
+ * of one read and one write of every transformed element, for "leaf_loop" the
+ * FP64 flops of the serial steps. */
+int tikh_profile_units(double* units);
 
 /* Library state.  tikh_init is optional (the first call initializes). */
 int tikh_init(void);

@@ -41,6 +41,7 @@ tikh_plan_info = _sig("tikh_plan_info", [_I64, _I64, ctypes.c_int32, ctypes.POIN
 _sig("tikh_release", [])
 _sig("tikh_profile_kernel", [ctypes.c_char_p])
 _sig("tikh_profile_read", [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)])
+_sig("tikh_profile_units", [ctypes.POINTER(ctypes.c_double)])
 _sig("tikh_set_stream", [_P])
 _sig("tikh_set_options", [ctypes.POINTER(_Opts)])
 _sig("tikh_get_options", [ctypes.POINTER(_Opts)])
@@ -107,10 +108,11 @@ def profile_kernel(name):
 
 
 def profile_read():
-    """(total_ms, launches) of the profiled kernel since profile_kernel()."""
-    t = ctypes.c_double(); c = ctypes.c_int64()
+    """(total_ms, launches, algorithmic units) of the profiled kernel since profile_kernel()."""
+    t = ctypes.c_double(); c = ctypes.c_int64(); u = ctypes.c_double()
     _check(lib.tikh_profile_read(ctypes.byref(t), ctypes.byref(c)), "tikh_profile_read")
-    return t.value, c.value
+    _check(lib.tikh_profile_units(ctypes.byref(u)), "tikh_profile_units")
+    return t.value, c.value, u.value
 
 
 def get_stats():

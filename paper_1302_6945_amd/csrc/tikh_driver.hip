@@ -53,6 +53,7 @@ struct KProf {
     size_t used = 0;
     double total_ms = 0.0;
     int64_t count = 0;
+    double units = 0.0;          // algorithmic work of the timed launches (bytes or flops, per kernel kind)
 };
 static KProf kprof;
 
@@ -67,6 +68,9 @@ static void prof_begin(const char* name) {
 static void prof_end(const char* name) {
     if (!prof_on(name)) return;
     if (kprof.used + 2 <= kprof.pool.size()) { (void)hipEventRecord(kprof.pool[kprof.used + 1], g.stream); kprof.used += 2; }
+}
+static void prof_units(const char* name, double u) {
+    if (prof_on(name)) kprof.units += u;
 }
 static void prof_collect() {
     if (kprof.used == 0) return;
@@ -371,26 +375,36 @@ enum FftOrder {
 
 static void fft_pass(double2* data, int64_t S, int64_t sstride, int64_t nlines, int64_t lines_inner,
                      int64_t line_stride, int64_t outer_stride, int64_t elem_stride, int64_t L, int sign,
-                     int64_t post_L, const double2* tw, int64_t Q, int lpw_cap) {
+                     int64_t post_L, const double2* tw, int64_t Q, int lpw_cap, const FftArgs* fuse = nullptr,
+                     bool first = true, bool last = true) {
     FftArgs a{};
+    if (fuse) {
+        a = *fuse;
+        if (!first) a.load_mode = 0;
+        if (!last) a.store_mode = 0;
+    }
     a.data = data; a.solve_stride = sstride; a.sign = sign; a.scale = 1.0; a.tw = tw; a.Q = Q;
     fft_plan(L, &a.pl);
     a.nlines = nlines; a.lines_inner = lines_inner; a.line_stride = line_stride; a.outer_stride = outer_stride;
     a.elem_stride = elem_stride; a.post_L = post_L;
     a.lpw = (int)std::max<int64_t>(1, std::min<int64_t>(FFT_LDS_MAX / L, lpw_cap));
     dim3 gr((unsigned)((nlines + a.lpw - 1) / a.lpw), (unsigned)S);
+    // algorithmic traffic: every element of every line read once and written once
+    prof_units("fft", 32.0 * (double)S * (double)nlines * (double)L);
     LAUNCH("fft", k_fft, gr, dim3(FFT_THREADS), a);
 }
 
 // In-place FFT of `nlines` contiguous lines of length Lf per item (line
-// stride Lf, item stride sstride), direction `sign`.
+// stride Lf, item stride sstride), direction `sign`.  `fuse` (optional)
+// carries a fused first-pass load and/or last-pass store.
 static int fft_lines(double2* data, int64_t S, int64_t sstride, int64_t nlines, int64_t Lf, int sign,
-                     const double2* tw, int64_t Q, double2* scratch, int64_t scr_stride, int order = FFT_NATURAL) {
-    if (Lf == 1) return TIKH_OK;
+                     const double2* tw, int64_t Q, double2* scratch, int64_t scr_stride, int order = FFT_NATURAL,
+                     const FftArgs* fuse = nullptr) {
     FftPlanDev chk;
     if (Lf <= FFT_LDS_MAX) {
         if (!fft_plan(Lf, &chk)) return TIKH_EINVAL;
-        fft_pass(data, S, sstride, nlines, nlines, Lf, 0, 1, Lf, sign, 0, tw, Q, 64);
+        // one original line per transformed line: o = line, offset = element index
+        fft_pass(data, S, sstride, nlines, 1, 0, Lf, 1, Lf, sign, 0, tw, Q, 64, fuse, true, true);
         return TIKH_OK;
     }
     const int64_t L1 = fft_split(Lf);
@@ -399,13 +413,13 @@ static int fft_lines(double2* data, int64_t S, int64_t sstride, int64_t nlines, 
     if (!fft_plan(L1, &chk) || !fft_plan(L2, &chk)) return TIKH_EINVAL;
     if (order == FFT_INV_T) {
         // rows j1 (contiguous, length L2) with twiddle w^{j1 k2}, then columns k2 (stride L2, length L1)
-        fft_pass(data, S, sstride, nlines * L1, L1, L2, Lf, 1, L2, sign, Lf, tw, Q, 64);
-        fft_pass(data, S, sstride, nlines * L2, L2, 1, Lf, L2, L1, sign, 0, tw, Q, 16);
+        fft_pass(data, S, sstride, nlines * L1, L1, L2, Lf, 1, L2, sign, Lf, tw, Q, 64, fuse, true, false);
+        fft_pass(data, S, sstride, nlines * L2, L2, 1, Lf, L2, L1, sign, 0, tw, Q, 16, fuse, false, true);
         return TIKH_OK;
     }
     // columns k2 (stride L2, length L1) with twiddle w^{j1 k2}, then rows j1 (contiguous, length L2)
-    fft_pass(data, S, sstride, nlines * L2, L2, 1, Lf, L2, L1, sign, Lf, tw, Q, 16);
-    fft_pass(data, S, sstride, nlines * L1, L1, L2, Lf, 1, L2, sign, 0, tw, Q, 64);
+    fft_pass(data, S, sstride, nlines * L2, L2, 1, Lf, L2, L1, sign, Lf, tw, Q, 16, fuse, true, false);
+    fft_pass(data, S, sstride, nlines * L1, L1, L2, Lf, 1, L2, sign, 0, tw, Q, 64, fuse, false, true);
     if (order == FFT_NATURAL) {
         hipLaunchKernelGGL(k_fourstep_unscramble, grid1(nlines * Lf, S), dim3(256), 0, g.stream, data, scratch,
                            sstride, scr_stride, Lf, nlines, L1, L2);
@@ -439,6 +453,12 @@ static int run_leaf(const Plan& pl, const Layout& L, const Bufs& b, int64_t G, i
     ba.st = b.st; ba.rec = b.rec; ba.rec_stride = pl.K; ba.out = dst; ba.out_stride = dstride;
     ba.cap = dcap; ba.meta = dmeta; ba.K = pl.K;
     const int slots = (int)((std::min<int64_t>(dcap, pl.K) + 1 + 63) / 64);
+    {
+        // leaf-loop flops: at step c the K-c remaining rows are scored (4 |r|^2, 12 flops) and
+        // K-c-1 are updated (C-1 complex multiply-adds, one complex multiply and subtract: 8C flops)
+        const double K = (double)pl.K, C = (double)L.C;
+        prof_units("leaf_loop", (double)G * (12.0 * K * (K + 1) / 2 + 8.0 * C * K * (K - 1) / 2));
+    }
     if (L.nr == 1) launch_leaf<1>(pl, la, ba, G, slots);
     else if (L.nr == 2) launch_leaf<2>(pl, la, ba, G, slots);
     else launch_leaf<4>(pl, la, ba, G, slots);
@@ -454,11 +474,11 @@ static int run_eval_chunk(const Plan& pl, const Layout& L, const Bufs& b, int64_
     const int64_t Lc = pl.N >> (d + 1);
     const int64_t cp1 = pl.cap[d] + 1;
     const int E = 4 * L.C;
-    hipLaunchKernelGGL(k_twist_fold, dim3((unsigned)std::min<int64_t>((Lc + 255) / 256, 1024), 2 * E, (unsigned)G),
-                       dim3(256), 0, g.stream, b.slotS[d], L.sslot[d], cp1, L.C, b.metaS[d], b.V, L.sV, Lc, oR, pl.N,
-                       tw, pl.Q);
-    g.launches++;
-    int rc = fft_lines(b.V, G, L.sV, 2 * E, Lc, +1, tw, pl.Q, b.scr, L.sscr, FFT_FWD_T);
+    // the transform reads the twisted, folded basis entries directly from the slot
+    FftArgs fu{};
+    fu.load_mode = 2; fu.src = b.slotS[d]; fu.src_stride = L.sslot[d]; fu.src_cp1 = cp1; fu.src_meta = b.metaS[d];
+    fu.C = L.C; fu.fold_L = Lc; fu.fold_o = oR; fu.fold_N = pl.N;
+    int rc = fft_lines(b.V, G, L.sV, 2 * E, Lc, +1, tw, pl.Q, b.scr, L.sscr, FFT_FWD_T, &fu);
     if (rc) return rc;
     const int64_t L1 = fft_split(Lc);
     const int64_t nleaves = (int64_t)1 << (pl.p - d);
@@ -499,25 +519,28 @@ static int run_product_chunk(const Plan& pl, const Layout& L, const Bufs& b, int
     const int* eO = b.elist + (root ? offsetof(EList, xout) : offsetof(EList, all)) / sizeof(int);
     hipLaunchKernelGGL(k_prod_meta, dim3((unsigned)((G + 63) / 64)), dim3(64), 0, g.stream, b.metaS[dc], b.metaT[dc],
                        dmeta, b.st, dcap, (int)G, C);
-    unsigned gx = (unsigned)std::min<int64_t>((P + 255) / 256, 1024);
-    hipLaunchKernelGGL(k_prod_load, dim3(gx, nL, (unsigned)G), dim3(256), 0, g.stream, b.slotS[dc], L.sslot[dc], cp1, C,
-                       b.metaS[dc], eL, b.FL, L.sF, P);
-    hipLaunchKernelGGL(k_prod_load, dim3(gx, nR, (unsigned)G), dim3(256), 0, g.stream, b.slotT[dc], L.sT, cp1, C,
-                       b.metaT[dc], eR, b.FR, L.sF, P);
-    g.launches += 3;
-    int rc = fft_lines(b.FL, G, L.sF, nL, P, -1, tw, pl.Q, b.scr, L.sscr, FFT_FWD_T);
+    g.launches += 1;
+    // forward transforms read the zero-padded, column-scaled entries directly from the slots
+    FftArgs fl{};
+    fl.load_mode = 1; fl.src = b.slotS[dc]; fl.src_stride = L.sslot[dc]; fl.src_cp1 = cp1; fl.src_meta = b.metaS[dc];
+    fl.elist = eL; fl.C = C;
+    int rc = fft_lines(b.FL, G, L.sF, nL, P, -1, tw, pl.Q, b.scr, L.sscr, FFT_FWD_T, &fl);
     if (rc) return rc;
-    rc = fft_lines(b.FR, G, L.sF, nR, P, -1, tw, pl.Q, b.scr, L.sscr, FFT_FWD_T);
+    FftArgs fr{};
+    fr.load_mode = 1; fr.src = b.slotT[dc]; fr.src_stride = L.sT; fr.src_cp1 = cp1; fr.src_meta = b.metaT[dc];
+    fr.elist = eR; fr.C = C;
+    rc = fft_lines(b.FR, G, L.sF, nR, P, -1, tw, pl.Q, b.scr, L.sscr, FFT_FWD_T, &fr);
     if (rc) return rc;
     // the pointwise product reads every input of a frequency before writing, so it runs in place over FL
     if (nr == 1) LAUNCH("prod_mul", k_prod_mul<1>, grid1(P, G), dim3(256), b.FL, b.FR, b.FL, L.sF, P, root ? 1 : 0);
     else if (nr == 2) LAUNCH("prod_mul", k_prod_mul<2>, grid1(P, G), dim3(256), b.FL, b.FR, b.FL, L.sF, P, root ? 1 : 0);
     else LAUNCH("prod_mul", k_prod_mul<4>, grid1(P, G), dim3(256), b.FL, b.FR, b.FL, L.sF, P, root ? 1 : 0);
-    rc = fft_lines(b.FL, G, L.sF, nO, P, +1, tw, pl.Q, b.scr, L.sscr, FFT_INV_T);
+    // the inverse transform writes the truncated, 1/P-scaled coefficients into the destination slot
+    FftArgs fo{};
+    fo.store_mode = 1; fo.dst = dst; fo.dst_stride = dstride; fo.dst_cp1 = dcap + 1; fo.dst_meta = dmeta;
+    fo.dst_elist = eO; fo.C = C; fo.dst_scale = 1.0 / (double)P;
+    rc = fft_lines(b.FL, G, L.sF, nO, P, +1, tw, pl.Q, b.scr, L.sscr, FFT_INV_T, &fo);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_prod_store, dim3(gx, nO, (unsigned)G), dim3(256), 0, g.stream, b.FL, L.sF, P, dst, dstride,
-                       dcap + 1, C, dmeta, eO);
-    g.launches++;
     return TIKH_OK;
 }
 
@@ -834,6 +857,7 @@ int tikh_profile_kernel(const char* name) {
     kprof.name = name ? std::string(name) : std::string();
     kprof.total_ms = 0.0;
     kprof.count = 0;
+    kprof.units = 0.0;
     return TIKH_OK;
 }
 
@@ -842,6 +866,12 @@ int tikh_profile_read(double* total_ms, int64_t* count) {
     prof_collect();
     *total_ms = kprof.total_ms;
     *count = kprof.count;
+    return TIKH_OK;
+}
+
+int tikh_profile_units(double* units) {
+    if (!units) return TIKH_EINVAL;
+    *units = kprof.units;
     return TIKH_OK;
 }
 

@@ -40,6 +40,31 @@ __device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
     }
 }
 
+// a / d for 0 <= a < 2^24, d >= 1, with a single-precision reciprocal estimate
+// (error < 1) corrected by one step
+__device__ __forceinline__ int fdiv(int a, float inv, int d) {
+    int q = (int)((float)a * inv);
+    int r = a - q * d;
+    if (r < 0) --q;
+    else if (r >= d) ++q;
+    return q;
+}
+
+// x mod n for 0 <= x < 2^53 via a double-precision quotient (exact after one correction)
+__device__ __forceinline__ int64_t mod_fast(int64_t x, int64_t n, double invn) {
+    int64_t q = (int64_t)((double)x * invn);
+    int64_t r = x - q * n;
+    if (r < 0) r += n;
+    else if (r >= n) r -= n;
+    return r;
+}
+
+// e^{sign * 2 pi i idx / Q} for 0 <= idx < Q
+__device__ __forceinline__ double2 twd(const double2* __restrict__ tw, int64_t idx, int sign) {
+    double2 t = tw[idx];
+    return sign > 0 ? t : cconj(t);
+}
+
 // e^{sign * 2 pi i idx / Q} from the table tw[q] = e^{2 pi i q / Q}
 __device__ __forceinline__ double2 twq(const double2* __restrict__ tw, int64_t Q, int64_t idx, int sign) {
     int64_t r = idx % Q;
@@ -130,12 +155,13 @@ __device__ void fft_stage(double2* buf, int L, int nl, int Ns, int sign,
     const int per = L / R;
     const int nb = nl * per;
     const int64_t tstep = Q / ((int64_t)Ns * R);    // table stride of e^{2 pi i/(Ns R)}
+    const float invper = 1.0f / (float)per, invNs = 1.0f / (float)Ns;
     double2 v[MB][R];
 #pragma unroll
     for (int it = 0; it < MB; ++it) {
         int b = threadIdx.x + it * FFT_THREADS;
         if (b < nb) {
-            int line = b / per, j = b - line * per;
+            int line = fdiv(b, invper, per), j = b - line * per;
             const double2* src = buf + line * L + j;
 #pragma unroll
             for (int r = 0; r < R; ++r) v[it][r] = src[r * per];
@@ -146,14 +172,15 @@ __device__ void fft_stage(double2* buf, int L, int nl, int Ns, int sign,
     for (int it = 0; it < MB; ++it) {
         int b = threadIdx.x + it * FFT_THREADS;
         if (b < nb) {
-            int line = b / per, j = b - line * per;
-            int k = j % Ns;
+            int line = fdiv(b, invper, per), j = b - line * per;
+            int blk = fdiv(j, invNs, Ns);
+            int k = j - blk * Ns;
             if (Ns > 1) {
 #pragma unroll
-                for (int r = 1; r < R; ++r) v[it][r] = cmul(v[it][r], twq(tw, Q, (int64_t)r * k * tstep, sign));
+                for (int r = 1; r < R; ++r) v[it][r] = cmul(v[it][r], twd(tw, (int64_t)(r * k) * tstep, sign));
             }
             bfly<R>(v[it], sign);
-            double2* dst = buf + line * L + (j / Ns) * Ns * R + k;
+            double2* dst = buf + line * L + blk * Ns * R + k;
 #pragma unroll
             for (int r = 0; r < R; ++r) dst[r * Ns] = v[it][r];
         }
@@ -180,10 +207,16 @@ __device__ void lds_fft(double2* buf, const FftPlanDev& pl, int nl, int sign, co
 }
 
 // Batched in-place FFT of lines held in global memory.
-// Line l of solve s starts at data + s*solve_stride + l*line_stride; element k
-// at + k*elem_stride.  lpw lines per workgroup (lpw*L <= FFT_LDS_MAX).
-// Optional four-step twiddle: output element j of line l multiplied by
-// e^{sign 2 pi i j l / post_L} (post_L = 0: none).
+// Line l of solve s starts at data + s*solve_stride + (l / lines_inner)*outer_stride
+// + (l % lines_inner)*line_stride; element k at + k*elem_stride.  lpw lines
+// per workgroup (lpw*L <= FFT_LDS_MAX).  Optional four-step twiddle: output
+// element j of line l multiplied by e^{sign 2 pi i j (l % lines_inner) / post_L}.
+//
+// The first pass of a transform can read its input directly from a stored
+// basis instead of `data` (load_mode), and the last pass of an inverse
+// product transform can write into a basis slot (store_mode); "original line"
+// o = l / lines_inner and "offset" = (l % lines_inner)*line_stride + k*elem_stride
+// index the transform of one basis entry.
 struct FftArgs {
     double2* data;
     int64_t solve_stride, line_stride, elem_stride, outer_stride;
@@ -195,32 +228,118 @@ struct FftArgs {
     const double2* tw;
     int64_t Q;
     FftPlanDev pl;
+    // fused load: 0 = data, 1 = zero-padded basis entry elist[o], 2 = twisted and folded
+    // basis entry o/2 at coset offset fold_o + (o & 1) (evaluation)
+    int load_mode;
+    const double2* src;
+    int64_t src_stride, src_cp1;
+    const SlotMeta* src_meta;
+    const int* elist;
+    int C;
+    int64_t fold_L, fold_o, fold_N;
+    // fused store: 0 = data, 1 = basis slot entry dst_elist[o], scaled by 1/L_total,
+    // offsets <= degree only, with column maxima
+    int store_mode;
+    double2* dst;
+    int64_t dst_stride, dst_cp1;
+    SlotMeta* dst_meta;
+    const int* dst_elist;
+    double dst_scale;
 };
+
+__device__ __forceinline__ double2 fft_fused_load(const FftArgs& a, int64_t s, int64_t o, int64_t off,
+                                                 const SlotMeta& mt) {
+    if (a.load_mode == 1) {
+        const int e = a.elist[o];
+        const int col = e % a.C;
+        if (off > mt.deg[col]) return c2(0.0, 0.0);
+        const double sc = col < 4 ? pow2_inv_scale(mt.colmax_bits[col]) : 1.0;
+        return cscale(a.src[s * a.src_stride + (int64_t)e * a.src_cp1 + off], sc);
+    }
+    // twisted and folded: sum over i = off + t L of B[i] w^{oc i}; w^{oc (off + t L)} = w^{oc off} (w^{oc L})^t
+    const int e = (int)(o >> 1);
+    const int64_t oc = a.fold_o + (o & 1);
+    const int col = e % a.C;
+    const int dg = mt.deg[col];
+    if (off > dg) return c2(0.0, 0.0);
+    const double sc = col < 4 ? pow2_inv_scale(mt.colmax_bits[col]) : 1.0;
+    const double2* src = a.src + s * a.src_stride + (int64_t)e * a.src_cp1;
+    const int64_t twN = a.Q / a.fold_N;
+    const double invN = 1.0 / (double)a.fold_N;
+    double2 w = a.tw[mod_fast(oc * off, a.fold_N, invN) * twN];
+    const double2 wstep = a.tw[mod_fast(oc * a.fold_L, a.fold_N, invN) * twN];
+    double2 acc = c2(0.0, 0.0);
+    for (int64_t i = off; i <= dg; i += a.fold_L) {
+        acc = cfma(src[i], w, acc);
+        w = cmul(w, wstep);
+    }
+    return cscale(acc, sc);
+}
 
 __global__ __launch_bounds__(FFT_THREADS) void k_fft(const FftArgs a) {
     __shared__ double2 sm[FFT_LDS_MAX];
+    __shared__ int64_t sh_base[64];
+    __shared__ int64_t sh_o[64];
+    __shared__ int sh_in[64];
     const int L = a.pl.L;
     const int64_t l0 = (int64_t)blockIdx.x * a.lpw;
     const int nl = (int)min((int64_t)a.lpw, a.nlines - l0);
-    double2* base = a.data + (int64_t)blockIdx.y * a.solve_stride;
+    const int64_t s = blockIdx.y;
+    double2* base = a.data + s * a.solve_stride;
+    if ((int)threadIdx.x < nl) {
+        const int64_t l = l0 + threadIdx.x, o = l / a.lines_inner, in = l - o * a.lines_inner;
+        sh_base[threadIdx.x] = o * a.outer_stride + in * a.line_stride;
+        sh_o[threadIdx.x] = o;
+        sh_in[threadIdx.x] = (int)in;
+    }
+    __syncthreads();
+    const SlotMeta* lm = a.load_mode ? &a.src_meta[s] : nullptr;
     const int tot = nl * L;
     const bool contig = (a.elem_stride == 1);
+    const float invL = 1.0f / (float)L, invnl = 1.0f / (float)nl;
     for (int i = threadIdx.x; i < tot; i += FFT_THREADS) {
         int g, k;
-        if (contig) { g = i / L; k = i - g * L; } else { k = i / nl; g = i - k * nl; }
-        const int64_t l = l0 + g, o = l / a.lines_inner, in = l - o * a.lines_inner;
-        sm[g * L + k] = base[o * a.outer_stride + in * a.line_stride + (int64_t)k * a.elem_stride];
+        if (contig) { g = fdiv(i, invL, L); k = i - g * L; } else { k = fdiv(i, invnl, nl); g = i - k * nl; }
+        double2 v;
+        if (a.load_mode) v = fft_fused_load(a, s, sh_o[g], (int64_t)sh_in[g] * a.line_stride + (int64_t)k * a.elem_stride, *lm);
+        else v = base[sh_base[g] + (int64_t)k * a.elem_stride];
+        sm[g * L + k] = v;
     }
     __syncthreads();
     lds_fft(sm, a.pl, nl, a.sign, a.tw, a.Q);
+    const int64_t ptstep = a.post_L ? a.Q / a.post_L : 0;
+    double cmx[4] = {0.0, 0.0, 0.0, 0.0};
     for (int i = threadIdx.x; i < tot; i += FFT_THREADS) {
         int g, k;
-        if (contig) { g = i / L; k = i - g * L; } else { k = i / nl; g = i - k * nl; }
-        const int64_t l = l0 + g, o = l / a.lines_inner, in = l - o * a.lines_inner;
+        if (contig) { g = fdiv(i, invL, L); k = i - g * L; } else { k = fdiv(i, invnl, nl); g = i - k * nl; }
         double2 v = sm[g * L + k];
-        if (a.post_L) v = cmul(v, twq(a.tw, a.Q, ((int64_t)k * in % a.post_L) * (a.Q / a.post_L), a.sign));
+        // k * in < post_L: k < L and in < post_L / L for both four-step passes
+        if (a.post_L) v = cmul(v, twd(a.tw, (int64_t)k * sh_in[g] * ptstep, a.sign));
         if (a.scale != 1.0) v = cscale(v, a.scale);
-        base[o * a.outer_stride + in * a.line_stride + (int64_t)k * a.elem_stride] = v;
+        if (a.store_mode) {
+            const int e = a.dst_elist[sh_o[g]];
+            const int col = e % a.C;
+            const int64_t off = (int64_t)sh_in[g] * a.line_stride + (int64_t)k * a.elem_stride;
+            if (off <= a.dst_meta[s].deg[col] && off < a.dst_cp1) {
+                v = cscale(v, a.dst_scale);
+                a.dst[s * a.dst_stride + (int64_t)e * a.dst_cp1 + off] = v;
+                if (col < 4) {
+                    const double m2 = cabs2(v);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) if (c == col) cmx[c] = fmax(cmx[c], m2);
+                }
+            }
+        } else {
+            base[sh_base[g] + (int64_t)k * a.elem_stride] = v;
+        }
+    }
+    if (a.store_mode) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const double mx = wave_max_d(cmx[c]);
+            if ((threadIdx.x & 63) == 0 && mx > 0.0)
+                atomicMax(&a.dst_meta[s].colmax_bits[c], (unsigned long long)__double_as_longlong(sqrt(mx)));
+        }
     }
 }
 
