@@ -384,6 +384,8 @@ static void fft_pass(double2* data, int64_t S, int64_t sstride, int64_t nlines, 
         if (!last) a.store_mode = 0;
     }
     a.data = data; a.solve_stride = sstride; a.sign = sign; a.scale = 1.0; a.tw = tw; a.Q = Q;
+    a.ltw = twiddles(L);              // per-length tables: contiguous twiddle reads
+    a.ptw = post_L ? twiddles(post_L) : nullptr;
     fft_plan(L, &a.pl);
     a.nlines = nlines; a.lines_inner = lines_inner; a.line_stride = line_stride; a.outer_stride = outer_stride;
     a.elem_stride = elem_stride; a.post_L = post_L;

@@ -148,13 +148,13 @@ template <> __device__ __forceinline__ void bfly<5>(double2* v, int sign) {
 
 // One in-place Stockham stage over `nl` lines of length L held in LDS.
 // Ns = product of the radices of the previous stages.
+// ltw[j] = e^{2 pi i j / L}.
 template <int R>
-__device__ void fft_stage(double2* buf, int L, int nl, int Ns, int sign,
-                          const double2* __restrict__ tw, int64_t Q) {
+__device__ void fft_stage(double2* buf, int L, int nl, int Ns, int sign, const double2* __restrict__ ltw) {
     constexpr int MB = (FFT_LDS_MAX / R + FFT_THREADS - 1) / FFT_THREADS;
     const int per = L / R;
     const int nb = nl * per;
-    const int64_t tstep = Q / ((int64_t)Ns * R);    // table stride of e^{2 pi i/(Ns R)}
+    const int tstep = L / (Ns * R);                 // table stride of e^{2 pi i/(Ns R)}
     const float invper = 1.0f / (float)per, invNs = 1.0f / (float)Ns;
     double2 v[MB][R];
 #pragma unroll
@@ -177,7 +177,7 @@ __device__ void fft_stage(double2* buf, int L, int nl, int Ns, int sign,
             int k = j - blk * Ns;
             if (Ns > 1) {
 #pragma unroll
-                for (int r = 1; r < R; ++r) v[it][r] = cmul(v[it][r], twd(tw, (int64_t)(r * k) * tstep, sign));
+                for (int r = 1; r < R; ++r) v[it][r] = cmul(v[it][r], twd(ltw, (int64_t)(r * k * tstep), sign));
             }
             bfly<R>(v[it], sign);
             double2* dst = buf + line * L + blk * Ns * R + k;
@@ -194,14 +194,14 @@ struct FftPlanDev {
     int radix[24];
 };
 
-__device__ void lds_fft(double2* buf, const FftPlanDev& pl, int nl, int sign, const double2* tw, int64_t Q) {
+__device__ void lds_fft(double2* buf, const FftPlanDev& pl, int nl, int sign, const double2* ltw) {
     int Ns = 1;
     for (int s = 0; s < pl.nst; ++s) {
         int R = pl.radix[s];
-        if (R == 4) fft_stage<4>(buf, pl.L, nl, Ns, sign, tw, Q);
-        else if (R == 2) fft_stage<2>(buf, pl.L, nl, Ns, sign, tw, Q);
-        else if (R == 3) fft_stage<3>(buf, pl.L, nl, Ns, sign, tw, Q);
-        else fft_stage<5>(buf, pl.L, nl, Ns, sign, tw, Q);
+        if (R == 4) fft_stage<4>(buf, pl.L, nl, Ns, sign, ltw);
+        else if (R == 2) fft_stage<2>(buf, pl.L, nl, Ns, sign, ltw);
+        else if (R == 3) fft_stage<3>(buf, pl.L, nl, Ns, sign, ltw);
+        else fft_stage<5>(buf, pl.L, nl, Ns, sign, ltw);
         Ns *= R;
     }
 }
@@ -225,8 +225,10 @@ struct FftArgs {
     int lpw;
     int64_t post_L;
     double scale;
-    const double2* tw;
+    const double2* tw;               // e^{2 pi i q / Q}, q < Q (fused twist of evaluation lines)
     int64_t Q;
+    const double2* ltw;              // e^{2 pi i j / L}, j < L (stages)
+    const double2* ptw;              // e^{2 pi i j / post_L}, j < post_L (four-step twiddle)
     FftPlanDev pl;
     // fused load: 0 = data, 1 = zero-padded basis entry elist[o], 2 = twisted and folded
     // basis entry o/2 at coset offset fold_o + (o & 1) (evaluation)
@@ -306,15 +308,14 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft(const FftArgs a) {
         sm[g * L + k] = v;
     }
     __syncthreads();
-    lds_fft(sm, a.pl, nl, a.sign, a.tw, a.Q);
-    const int64_t ptstep = a.post_L ? a.Q / a.post_L : 0;
+    lds_fft(sm, a.pl, nl, a.sign, a.ltw);
     double cmx[4] = {0.0, 0.0, 0.0, 0.0};
     for (int i = threadIdx.x; i < tot; i += FFT_THREADS) {
         int g, k;
         if (contig) { g = fdiv(i, invL, L); k = i - g * L; } else { k = fdiv(i, invnl, nl); g = i - k * nl; }
         double2 v = sm[g * L + k];
         // k * in < post_L: k < L and in < post_L / L for both four-step passes
-        if (a.post_L) v = cmul(v, twd(a.tw, (int64_t)k * sh_in[g] * ptstep, a.sign));
+        if (a.post_L) v = cmul(v, twd(a.ptw, (int64_t)k * sh_in[g], a.sign));
         if (a.scale != 1.0) v = cscale(v, a.scale);
         if (a.store_mode) {
             const int e = a.dst_elist[sh_o[g]];
