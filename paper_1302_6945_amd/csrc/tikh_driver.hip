@@ -157,8 +157,11 @@ static bool fft_plan(int64_t L, FftPlanDev* f) {
     if (L < 1 || L > FFT_LDS_MAX) return false;
     f->L = (int)L; f->nst = 0;
     int64_t v = L;
-    while (v % 4 == 0) { f->radix[f->nst++] = 4; v /= 4; }
-    while (v % 2 == 0) { f->radix[f->nst++] = 2; v /= 2; }
+    // radix-16 stages, then the remaining power of two as one stage of 8, 4 or 2
+    while (v % 16 == 0) { f->radix[f->nst++] = 16; v /= 16; }
+    if (v % 8 == 0) { f->radix[f->nst++] = 8; v /= 8; }
+    else if (v % 4 == 0) { f->radix[f->nst++] = 4; v /= 4; }
+    else if (v % 2 == 0) { f->radix[f->nst++] = 2; v /= 2; }
     while (v % 3 == 0) { f->radix[f->nst++] = 3; v /= 3; }
     while (v % 5 == 0) { f->radix[f->nst++] = 5; v /= 5; }
     return v == 1;

@@ -146,47 +146,89 @@ template <> __device__ __forceinline__ void bfly<5>(double2* v, int sign) {
     v[2] = cadd(m2, n2); v[3] = csub(m2, n2);
 }
 
-// One in-place Stockham stage over `nl` lines of length L held in LDS.
-// Ns = product of the radices of the previous stages.
-// ltw[j] = e^{2 pi i j / L}.
-template <int R>
-__device__ void fft_stage(double2* buf, int L, int nl, int Ns, int sign, const double2* __restrict__ ltw) {
-    constexpr int MB = (FFT_LDS_MAX / R + FFT_THREADS - 1) / FFT_THREADS;
-    const int per = L / R;
-    const int nb = nl * per;
-    const int tstep = L / (Ns * R);                 // table stride of e^{2 pi i/(Ns R)}
-    const float invper = 1.0f / (float)per, invNs = 1.0f / (float)Ns;
-    double2 v[MB][R];
-#pragma unroll
-    for (int it = 0; it < MB; ++it) {
-        int b = threadIdx.x + it * FFT_THREADS;
-        if (b < nb) {
-            int line = fdiv(b, invper, per), j = b - line * per;
-            const double2* src = buf + line * L + j;
-#pragma unroll
-            for (int r = 0; r < R; ++r) v[it][r] = src[r * per];
-        }
+// Split-radix butterfly of size R = R1 * R2 (R a divisor of 16): R2 DFTs of
+// size R1 over the inputs n = R2 n1 + n2, twiddles e^{sign 2 pi i n2 k1 / R},
+// then R1 DFTs of size R2, giving output k = k1 + R1 k2.
+__device__ __forceinline__ double2 rot16(double2 a, int e, int sign) {
+    // a * e^{sign 2 pi i e / 16}
+    e &= 15;
+    if (e == 0) return a;
+    if (e == 4) return sign > 0 ? c2(-a.y, a.x) : c2(a.y, -a.x);
+    if (e == 8) return cneg(a);
+    if (e == 12) return sign > 0 ? c2(a.y, -a.x) : c2(-a.y, a.x);
+    const double C1 = 0.92387953251128675613, S1 = 0.38268343236508977173, RH = 0.70710678118654752440;
+    double c, s;
+    switch (e) {
+        case 1: c = C1; s = S1; break;
+        case 2: c = RH; s = RH; break;
+        case 3: c = S1; s = C1; break;
+        case 5: c = -S1; s = C1; break;
+        case 6: c = -RH; s = RH; break;
+        case 7: c = -C1; s = S1; break;
+        case 9: c = -C1; s = -S1; break;
+        case 10: c = -RH; s = -RH; break;
+        case 11: c = -S1; s = -C1; break;
+        case 13: c = S1; s = -C1; break;
+        case 14: c = RH; s = -RH; break;
+        default: c = C1; s = -S1; break;   // 15
     }
-    __syncthreads();
-#pragma unroll
-    for (int it = 0; it < MB; ++it) {
-        int b = threadIdx.x + it * FFT_THREADS;
-        if (b < nb) {
-            int line = fdiv(b, invper, per), j = b - line * per;
-            int blk = fdiv(j, invNs, Ns);
-            int k = j - blk * Ns;
-            if (Ns > 1) {
-#pragma unroll
-                for (int r = 1; r < R; ++r) v[it][r] = cmul(v[it][r], twd(ltw, (int64_t)(r * k * tstep), sign));
-            }
-            bfly<R>(v[it], sign);
-            double2* dst = buf + line * L + blk * Ns * R + k;
-#pragma unroll
-            for (int r = 0; r < R; ++r) dst[r * Ns] = v[it][r];
-        }
-    }
-    __syncthreads();
+    return cmul(a, c2(c, sign > 0 ? s : -s));
 }
+
+template <int R1, int R2>
+__device__ __forceinline__ void bfly_split(double2* v, int sign) {
+    constexpr int R = R1 * R2;
+    double2 y[R];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) {
+        double2 t[R1];
+#pragma unroll
+        for (int n1 = 0; n1 < R1; ++n1) t[n1] = v[R2 * n1 + n2];
+        bfly<R1>(t, sign);
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) y[n2 * R1 + k1] = rot16(t[k1], n2 * k1 * (16 / R), sign);
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) {
+        double2 t[R2];
+#pragma unroll
+        for (int n2 = 0; n2 < R2; ++n2) t[n2] = y[n2 * R1 + k1];
+        bfly<R2>(t, sign);
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) v[k1 + R1 * k2] = t[k2];
+    }
+}
+template <> __device__ __forceinline__ void bfly<8>(double2* v, int sign) { bfly_split<2, 4>(v, sign); }
+template <> __device__ __forceinline__ void bfly<16>(double2* v, int sign) { bfly_split<4, 4>(v, sign); }
+
+// v[r] *= e^{sign 2 pi i r idx / L} for r = 1..R-1 (ltw[j] = e^{2 pi i j / L},
+// r idx < L).  For R = 8, 16 only the powers of two are read from the table;
+// the others are products of at most three of them.
+template <int R>
+__device__ __forceinline__ void stage_twiddle(double2* v, const double2* __restrict__ ltw, int idx, int sign) {
+    if (R <= 5) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[r] = cmul(v[r], twd(ltw, (int64_t)r * idx, sign));
+    } else {
+        double2 w[R];
+        w[1] = twd(ltw, idx, sign);
+        w[2] = twd(ltw, 2 * idx, sign);
+        w[4] = twd(ltw, 4 * idx, sign);
+        if (R == 16) w[8] = twd(ltw, 8 * idx, sign);
+#pragma unroll
+        for (int r = 3; r < R; ++r) {
+            const int h = r >= 8 ? 8 : (r >= 4 ? 4 : 2);
+            if (r != h) w[r] = cmul(w[h], w[r - h]);
+        }
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[r] = cmul(v[r], w[r]);
+    }
+}
+
+// LDS index with one padding element per 16: strided butterfly accesses of
+// 16-byte elements then fall on distinct banks.
+__device__ __forceinline__ int lds_ix(int i) { return i + (i >> 4); }
+constexpr int FFT_LDS_PAD = FFT_LDS_MAX + FFT_LDS_MAX / 16;
 
 struct FftPlanDev {
     int L;
@@ -194,16 +236,61 @@ struct FftPlanDev {
     int radix[24];
 };
 
-__device__ void lds_fft(double2* buf, const FftPlanDev& pl, int nl, int sign, const double2* ltw) {
-    int Ns = 1;
-    for (int s = 0; s < pl.nst; ++s) {
-        int R = pl.radix[s];
-        if (R == 4) fft_stage<4>(buf, pl.L, nl, Ns, sign, ltw);
-        else if (R == 2) fft_stage<2>(buf, pl.L, nl, Ns, sign, ltw);
-        else if (R == 3) fft_stage<3>(buf, pl.L, nl, Ns, sign, ltw);
-        else fft_stage<5>(buf, pl.L, nl, Ns, sign, ltw);
-        Ns *= R;
+// One Stockham stage of radix R over `nl` lines of length L (Ns = product of
+// the previous radices): butterfly j of a line reads elements j + r L/R and
+// writes (j / Ns) Ns R + (j % Ns) + r Ns.  The first stage reads its inputs
+// through `ld` (global memory) and the last writes through `st`; the stages
+// between go through LDS.  `linefast` maps consecutive threads to
+// consecutive lines (strided lines in global memory).
+template <int R, typename LD, typename ST>
+__device__ __forceinline__ void fft_stage(double2* sm, int L, int nl, int Ns, int sign, const double2* __restrict__ ltw, bool gin,
+                          bool gout, bool linefast, LD& ld, ST& st) {
+    constexpr int MB = (FFT_LDS_MAX / R + FFT_THREADS - 1) / FFT_THREADS;
+    const int per = L / R;
+    const int nb = nl * per;
+    const int tstep = L / (Ns * R);
+    const float invper = 1.0f / (float)per, invNs = 1.0f / (float)Ns, invnl = 1.0f / (float)nl;
+    const bool lf = linefast && (gin || gout);
+    double2 v[MB][R];
+#pragma unroll
+    for (int it = 0; it < MB; ++it) {
+        const int b = threadIdx.x + it * FFT_THREADS;
+        if (b < nb) {
+            int line, j;
+            if (lf) { j = fdiv(b, invnl, nl); line = b - j * nl; }
+            else { line = fdiv(b, invper, per); j = b - line * per; }
+            if (gin) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[it][r] = ld(line, j + r * per);
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[it][r] = sm[lds_ix(line * L + j + r * per)];
+            }
+        }
     }
+    if (!gin && !gout) __syncthreads();
+#pragma unroll
+    for (int it = 0; it < MB; ++it) {
+        const int b = threadIdx.x + it * FFT_THREADS;
+        if (b < nb) {
+            int line, j;
+            if (lf) { j = fdiv(b, invnl, nl); line = b - j * nl; }
+            else { line = fdiv(b, invper, per); j = b - line * per; }
+            const int blk = fdiv(j, invNs, Ns);
+            const int k = j - blk * Ns;
+            if (Ns > 1) stage_twiddle<R>(v[it], ltw, k * tstep, sign);
+            bfly<R>(v[it], sign);
+            const int ob = blk * Ns * R + k;
+            if (gout) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) st(line, ob + r * Ns, v[it][r]);
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) sm[lds_ix(line * L + ob + r * Ns)] = v[it][r];
+            }
+        }
+    }
+    if (!gout) __syncthreads();
 }
 
 // Batched in-place FFT of lines held in global memory.
@@ -278,8 +365,27 @@ __device__ __forceinline__ double2 fft_fused_load(const FftArgs& a, int64_t s, i
     return cscale(acc, sc);
 }
 
+__device__ __forceinline__ void fft_fused_store(const FftArgs& a, int64_t s, int64_t o, int64_t off, double2 v,
+                                                double* cmx) {
+    const int e = a.dst_elist[o];
+    const int col = e % a.C;
+    if (off <= a.dst_meta[s].deg[col] && off < a.dst_cp1) {
+        v = cscale(v, a.dst_scale);
+        a.dst[s * a.dst_stride + (int64_t)e * a.dst_cp1 + off] = v;
+        if (col < 4) {
+            const double m2 = cabs2(v);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) if (c == col) cmx[c] = fmax(cmx[c], m2);
+        }
+    }
+}
+
+// Batched FFT of lines (see FftArgs).  Plain passes read their inputs in the
+// first stage and write their outputs in the last stage directly between
+// registers and global memory; a fused load (or store) instead goes through
+// one LDS prologue (or epilogue) loop, which keeps the stage code small.
 __global__ __launch_bounds__(FFT_THREADS) void k_fft(const FftArgs a) {
-    __shared__ double2 sm[FFT_LDS_MAX];
+    __shared__ double2 sm[FFT_LDS_PAD];
     __shared__ int64_t sh_base[64];
     __shared__ int64_t sh_o[64];
     __shared__ int sh_in[64];
@@ -295,43 +401,54 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft(const FftArgs a) {
         sh_in[threadIdx.x] = (int)in;
     }
     __syncthreads();
-    const SlotMeta* lm = a.load_mode ? &a.src_meta[s] : nullptr;
+    const int nst = a.pl.nst;
+    const bool linefast = (a.elem_stride != 1);
+    const bool dload = (a.load_mode == 0) && nst > 0, dstore = (a.store_mode == 0) && nst > 0;
     const int tot = nl * L;
-    const bool contig = (a.elem_stride == 1);
     const float invL = 1.0f / (float)L, invnl = 1.0f / (float)nl;
-    for (int i = threadIdx.x; i < tot; i += FFT_THREADS) {
-        int g, k;
-        if (contig) { g = fdiv(i, invL, L); k = i - g * L; } else { k = fdiv(i, invnl, nl); g = i - k * nl; }
-        double2 v;
-        if (a.load_mode) v = fft_fused_load(a, s, sh_o[g], (int64_t)sh_in[g] * a.line_stride + (int64_t)k * a.elem_stride, *lm);
-        else v = base[sh_base[g] + (int64_t)k * a.elem_stride];
-        sm[g * L + k] = v;
-    }
-    __syncthreads();
-    lds_fft(sm, a.pl, nl, a.sign, a.ltw);
     double cmx[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int i = threadIdx.x; i < tot; i += FFT_THREADS) {
-        int g, k;
-        if (contig) { g = fdiv(i, invL, L); k = i - g * L; } else { k = fdiv(i, invnl, nl); g = i - k * nl; }
-        double2 v = sm[g * L + k];
+    if (!dload) {
+        const SlotMeta* lm = a.load_mode ? &a.src_meta[s] : nullptr;
+        for (int i = threadIdx.x; i < tot; i += FFT_THREADS) {
+            int g, k;
+            if (!linefast) { g = fdiv(i, invL, L); k = i - g * L; } else { k = fdiv(i, invnl, nl); g = i - k * nl; }
+            const int64_t off = (int64_t)sh_in[g] * a.line_stride + (int64_t)k * a.elem_stride;
+            sm[lds_ix(g * L + k)] = a.load_mode ? fft_fused_load(a, s, sh_o[g], off, *lm)
+                                                : base[sh_base[g] + (int64_t)k * a.elem_stride];
+        }
+        __syncthreads();
+    }
+    auto ld = [&](int g, int k) -> double2 { return base[sh_base[g] + (int64_t)k * a.elem_stride]; };
+    auto st = [&](int g, int k, double2 v) {
         // k * in < post_L: k < L and in < post_L / L for both four-step passes
         if (a.post_L) v = cmul(v, twd(a.ptw, (int64_t)k * sh_in[g], a.sign));
         if (a.scale != 1.0) v = cscale(v, a.scale);
-        if (a.store_mode) {
-            const int e = a.dst_elist[sh_o[g]];
-            const int col = e % a.C;
+        base[sh_base[g] + (int64_t)k * a.elem_stride] = v;
+    };
+    int Ns = 1;
+    for (int q = 0; q < nst; ++q) {
+        const int R = a.pl.radix[q];
+        const bool gin = (q == 0) && dload, gout = (q == nst - 1) && dstore;
+        switch (R) {
+            case 16: fft_stage<16>(sm, L, nl, Ns, a.sign, a.ltw, gin, gout, linefast, ld, st); break;
+            case 8: fft_stage<8>(sm, L, nl, Ns, a.sign, a.ltw, gin, gout, linefast, ld, st); break;
+            case 4: fft_stage<4>(sm, L, nl, Ns, a.sign, a.ltw, gin, gout, linefast, ld, st); break;
+            case 2: fft_stage<2>(sm, L, nl, Ns, a.sign, a.ltw, gin, gout, linefast, ld, st); break;
+            case 3: fft_stage<3>(sm, L, nl, Ns, a.sign, a.ltw, gin, gout, linefast, ld, st); break;
+            default: fft_stage<5>(sm, L, nl, Ns, a.sign, a.ltw, gin, gout, linefast, ld, st); break;
+        }
+        Ns *= R;
+    }
+    if (!dstore) {
+        for (int i = threadIdx.x; i < tot; i += FFT_THREADS) {
+            int g, k;
+            if (!linefast) { g = fdiv(i, invL, L); k = i - g * L; } else { k = fdiv(i, invnl, nl); g = i - k * nl; }
+            double2 v = sm[lds_ix(g * L + k)];
+            if (a.post_L) v = cmul(v, twd(a.ptw, (int64_t)k * sh_in[g], a.sign));
+            if (a.scale != 1.0) v = cscale(v, a.scale);
             const int64_t off = (int64_t)sh_in[g] * a.line_stride + (int64_t)k * a.elem_stride;
-            if (off <= a.dst_meta[s].deg[col] && off < a.dst_cp1) {
-                v = cscale(v, a.dst_scale);
-                a.dst[s * a.dst_stride + (int64_t)e * a.dst_cp1 + off] = v;
-                if (col < 4) {
-                    const double m2 = cabs2(v);
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) if (c == col) cmx[c] = fmax(cmx[c], m2);
-                }
-            }
-        } else {
-            base[sh_base[g] + (int64_t)k * a.elem_stride] = v;
+            if (a.store_mode) fft_fused_store(a, s, sh_o[g], off, v, cmx);
+            else base[sh_base[g] + (int64_t)k * a.elem_stride] = v;
         }
     }
     if (a.store_mode) {
