@@ -14,8 +14,10 @@ backward (adjoint solve + gradients w.r.t. generator, b and lambda).
 
 Prints ONE JSON line (rank 0).  `value` is whole-job fwd+bwd solves/s with the
 inputs resident in HBM; `roofline` reports the dominant kernel's live average
-launch duration (HIP events on the library stream) against the FP64 vector
-peak; `cpu_baseline` times the CPU oracle (dense Householder QR) on a bounded
+launch duration (HIP events on the library stream) against its bound (the FFT
+against HBM bandwidth, the leaf steps against the FP64 vector peak) and, when a
+counter summary taken on the current sources is committed, its measured HBM
+bytes per launch; `cpu_baseline` times the CPU oracle (dense Householder QR) on a bounded
 sample and scales it by the oracle's flop count to the benchmark size.
 """
 import argparse
@@ -27,6 +29,34 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+
+
+def source_digest(root):
+    """Digest of the kernel and driver sources: HBM counters taken on other sources do not apply."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("tikh_kernels.hip", "tikh_driver.hip", "tikh_internal.h"):
+        with open(os.path.join(root, "paper_1302_6945_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(root, kernel, args):
+    """HBM bytes per launch of `kernel` from the committed counter summary, when it was taken on
+    the current sources and at this workload; None otherwise."""
+    path = os.path.join(root, "profiles", "%s_hbm_traffic_headline_n16384.md" % kernel)
+    if not os.path.exists(path):
+        return None
+    rec = None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("traffic_json:"):
+                rec = json.loads(line.split(":", 1)[1])
+    if not rec or rec.get("source_digest") != source_digest(root):
+        return None
+    if rec.get("nprob") != args.nprob or rec.get("n") != args.n:
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def main():
@@ -43,6 +73,9 @@ def main():
     ap.add_argument("--cpu-n", type=int, default=1536, help="size of the CPU-oracle sample")
     ap.add_argument("--kernel", default="auto", help="kernel for the roofline object: fft, leaf_loop or auto "
                                                      "(the one with the larger share of the step)")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="after the run, negate a float64 buffer of this many MiB into another three times "
+                         "(a plain streaming kernel of known traffic that calibrates the HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -118,22 +151,23 @@ def main():
     kernel_ms = {k: round(v[0], 1) for k, v in rl.items()}
 
     # plain method: single-problem C-ABI calls, one solve + one backward per call
-    nplain = max(1, args.plain_solves)
-    p0 = probs[0]
-    c0 = torch.tensor(p0.col, device=dev)
-    r0 = torch.tensor(p0.row, device=dev)
-    b0 = torch.tensor(p0.b[0], device=dev)
-    xt0 = torch.tensor(p0.x_true, device=dev)
-    x0 = P.solve(c0, r0, b0, p0.lams[0])
-    P.backward(c0, r0, b0, p0.lams[0], x0, x0 - xt0)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(nplain):
-        lam = p0.lams[i % len(p0.lams)]
-        x0 = P.solve(c0, r0, b0, lam)
-        P.backward(c0, r0, b0, lam, x0, x0 - xt0)
-    torch.cuda.synchronize()
-    plain = nplain / (time.perf_counter() - t0)
+    plain = None
+    if args.plain_solves > 0:
+        p0 = probs[0]
+        c0 = torch.tensor(p0.col, device=dev)
+        r0 = torch.tensor(p0.row, device=dev)
+        b0 = torch.tensor(p0.b[0], device=dev)
+        xt0 = torch.tensor(p0.x_true, device=dev)
+        x0 = P.solve(c0, r0, b0, p0.lams[0])
+        P.backward(c0, r0, b0, p0.lams[0], x0, x0 - xt0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.plain_solves):
+            lam = p0.lams[i % len(p0.lams)]
+            x0 = P.solve(c0, r0, b0, lam)
+            P.backward(c0, r0, b0, lam, x0, x0 - xt0)
+        torch.cuda.synchronize()
+        plain = args.plain_solves / (time.perf_counter() - t0)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -154,6 +188,18 @@ def main():
                          "gradient sums) at n=%d, m=%d took %.2f s on %d threads; scaled by the QR flop "
                          "ratio %.1f to n=%d, m=%.0f" % (pc.n, pc.m, dt, cores, scale, args.n, m_avg)}
 
+    if args.copy_calib_mib > 0:
+        src = torch.ones(args.copy_calib_mib * 2 ** 20 // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+
+    traffic = measured_traffic(ROOT, roofline["kernel"], args)
+    if traffic is not None:
+        roofline["traffic"] = traffic
+
     out = {
         "metric": "batched regularized solves/s (fwd+bwd) at n=2^14 vs plain, rel err <= 1e-9",
         "value": round(value, 3),
@@ -170,8 +216,8 @@ def main():
         "config": {"workload": "headline n=2^14, m=n+U{0..n/4}, envelope generators, 8 lambdas x 4 rhs",
                    "problems": args.nprob, "solves_per_step": nsolve, "n": args.n, "m": ms,
                    "N": st["N"], "depth": st["depth"], "leaf_nodes": st["leaf_nodes"], "refine": 1},
-        "plain_solves_per_s": round(plain, 4),
-        "batched_over_plain": round(value / plain, 2),
+        "plain_solves_per_s": round(plain, 4) if plain else None,
+        "batched_over_plain": round(value / plain, 2) if plain else None,
         "info_max": info_max,
         "roofline": roofline,
         "kernel_ms_per_step": kernel_ms,

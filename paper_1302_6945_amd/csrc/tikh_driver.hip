@@ -259,7 +259,9 @@ struct Bufs {
     // merge scratch shared by the groups of one merge chunk
     double2* V;
     double2 *FL, *FR, *scr;
-    int64_t chunk;                   // groups per merge chunk
+    int64_t chunk;                   // groups per merge chunk at the largest level
+    double2* pool;                   // V, FL, FR and scr as one region (re-split per level)
+    int64_t pool_elems;
     int* elist;                      // device entry lists
 };
 
@@ -345,6 +347,8 @@ static int carve_bufs(const Plan& pl, const Layout& L, int64_t G, int64_t CH, Bu
     }
     b->V = cv(L.sV, CH);
     b->FL = cv(L.sF, CH); b->FR = cv(L.sF, CH); b->scr = cv(L.sscr, CH);
+    b->pool = b->V;
+    b->pool_elems = (int64_t)((p - (char*)b->V) / sizeof(double2));
     if ((size_t)(p - g.ws) > g.ws_size) return TIKH_ENOMEM;
     return TIKH_OK;
 }
@@ -565,9 +569,14 @@ static int run_eval(const Plan& pl, const Layout& L, const Bufs& b, int64_t G, i
                    pl.cap[d] + 1, b.metaS[d], t0, nleaves, pl.N, pl.M, pl.p, pl.K, tw, pl.Q);
         return TIKH_OK;
     }
-    for (int64_t c0 = 0; c0 < G; c0 += b.chunk) {
+    // the scratch pool is split for this level: as many groups per launch as fit
+    Layout Ld = L;
+    Ld.sV = 2 * (int64_t)(4 * L.C) * (pl.N >> (d + 1));
+    const int64_t ch = std::max<int64_t>(1, std::min<int64_t>(G, b.pool_elems / Ld.sV));
+    for (int64_t c0 = 0; c0 < G; c0 += ch) {
         Bufs bc = shift_bufs(b, L, pl, c0);
-        int rc = run_eval_chunk(pl, L, bc, std::min(b.chunk, G - c0), d, idx, tw);
+        bc.V = b.pool;
+        int rc = run_eval_chunk(pl, Ld, bc, std::min(ch, G - c0), d, idx, tw);
         if (rc) return rc;
     }
     return TIKH_OK;
@@ -582,9 +591,17 @@ static int run_product(const Plan& pl, const Layout& L, const Bufs& b, int64_t G
                b.metaS[dc], b.slotT[dc], L.sT, pl.cap[dc] + 1, b.metaT[dc], dst, dstride, dcap + 1, dmeta, b.st, L.C);
         return TIKH_OK;
     }
-    for (int64_t c0 = 0; c0 < G; c0 += b.chunk) {
+    // the scratch pool is split for this level: FL and FR hold the largest
+    // operand set at the level's bound on the product length
+    Layout Ld = L;
+    const int64_t lines = dp == 0 ? std::max<int64_t>(L.C, 4 * L.nr) : 4 * L.C;
+    Ld.sF = lines * pl.P[dp];
+    const int64_t ch = std::max<int64_t>(1, std::min<int64_t>(G, b.pool_elems / (2 * Ld.sF)));
+    for (int64_t c0 = 0; c0 < G; c0 += ch) {
         Bufs bc = shift_bufs(b, L, pl, c0);
-        int rc = run_product_chunk(pl, L, bc, std::min(b.chunk, G - c0), dp, dst + c0 * dstride, dstride, dmeta + c0,
+        bc.FL = b.pool;
+        bc.FR = b.pool + ch * Ld.sF;
+        int rc = run_product_chunk(pl, Ld, bc, std::min(ch, G - c0), dp, dst + c0 * dstride, dstride, dmeta + c0,
                                    dcap, tw);
         if (rc) return rc;
     }
