@@ -60,11 +60,22 @@ enum {
     TIKH_ENUMERIC = -4    /* a solve reported info != 0 (see above) */
 };
 
-/* Tunable options (Sec. 6.2: leaf cutoff N_lim; Sec. 7.2: refinement). */
+/*
+ * Tunable options (Sec. 6.2: leaf cutoff N_lim; Sec. 7.2: iterative
+ * refinement).  Every solve takes `refine` refinement steps; a solve whose
+ * estimated relative error is still above `refine_tol` takes further steps,
+ * up to `refine_max` in all (the estimate: e0 = ||dx_1|| / ||x|| of the
+ * first step approximates the first solve's error and the factor by which
+ * each step contracts it, so the error left after step k is taken as
+ * 1000 * e0 * ||dx_k|| / ||x||).  With refine = 0 no step is taken.
+ */
 typedef struct {
     int32_t n_lim;        /* max conditions per leaf (64..256, multiple of 64); default 256 */
-    int32_t refine;       /* iterative-refinement steps (0..4); default 1 */
-    int32_t reserved[6];
+    int32_t refine;       /* refinement steps for every solve (0..4); default 1 */
+    int32_t refine_max;   /* most refinement steps for a solve above the error target (0..4); default 3 */
+    int32_t reserved0;
+    double refine_tol;    /* target relative error of the adaptive steps (> 0, finite); default 1e-10 */
+    int32_t reserved[4];
 } tikh_opts;
 
 /* Per-solve statistics of the last call (host memory, filled by tikh_get_stats). */
@@ -75,6 +86,7 @@ typedef struct {
     int32_t leaf_nodes;   /* M: nodes per leaf (2M conditions) */
     int64_t solves;       /* number of solves in the last call */
     int64_t launches;     /* kernel launches enqueued by the last call */
+    int64_t refine_extra; /* refinement steps beyond `refine` taken by the last call, summed over solves */
 } tikh_stats;
 
 /*
@@ -99,6 +111,18 @@ int tikh_profile_read(double* total_ms, int64_t* count);
  * of one read and one write of every transformed element, for "leaf_loop" the
  * FP64 flops of the serial steps. */
 int tikh_profile_units(double* units);
+
+/*
+ * Batched complex FFT, the transform behind the evaluations at roots of unity
+ * of eq. (vandprod) and the polynomial products of Alg. 1: for each of `items`
+ * blocks of `nlines` contiguous lines of length `len` (device tikh_c64,
+ * in place, item stride nlines*len),
+ *     X_k = sum_j x_j exp(sign * 2 pi i j k / len),   sign = -1 or +1,
+ * unnormalized.  len must factor into 2, 3 and 5 and be at most 4096^2 (lines
+ * longer than 4096 take two passes plus a reordering through the library
+ * workspace); items <= 65535.  Asynchronous on the library stream.
+ */
+int tikh_fft_batched(void* data, int64_t items, int64_t nlines, int64_t len, int sign);
 
 /* Library state.  tikh_init is optional (the first call initializes). */
 int tikh_init(void);

@@ -19,12 +19,14 @@ _D = ctypes.c_double
 
 
 class _Opts(ctypes.Structure):
-    _fields_ = [("n_lim", ctypes.c_int32), ("refine", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+    _fields_ = [("n_lim", ctypes.c_int32), ("refine", ctypes.c_int32), ("refine_max", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("refine_tol", ctypes.c_double), ("reserved", ctypes.c_int32 * 4)]
 
 
 class _Stats(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int64), ("k", ctypes.c_int64), ("depth", ctypes.c_int32),
-                ("leaf_nodes", ctypes.c_int32), ("solves", ctypes.c_int64), ("launches", ctypes.c_int64)]
+                ("leaf_nodes", ctypes.c_int32), ("solves", ctypes.c_int64), ("launches", ctypes.c_int64),
+                ("refine_extra", ctypes.c_int64)]
 
 
 def _sig(name, args, res=ctypes.c_int):
@@ -39,6 +41,7 @@ tikh_plan_info = _sig("tikh_plan_info", [_I64, _I64, ctypes.c_int32, ctypes.POIN
                                          ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
                                          ctypes.POINTER(ctypes.c_int64)])
 _sig("tikh_release", [])
+tikh_fft_batched = _sig("tikh_fft_batched", [_P, _I64, _I64, _I64, ctypes.c_int])
 _sig("tikh_profile_kernel", [ctypes.c_char_p])
 _sig("tikh_profile_read", [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)])
 _sig("tikh_profile_units", [ctypes.POINTER(ctypes.c_double)])
@@ -78,20 +81,26 @@ def _stream():
     lib.tikh_set_stream(ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
 
 
-def set_options(n_lim=None, refine=None):
+def set_options(n_lim=None, refine=None, refine_max=None, refine_tol=None):
+    """Leaf cutoff, refinement steps for every solve, most refinement steps for a solve whose
+    estimated error is above the target (see tikh_opts in include/tikh.h)."""
     o = _Opts()
     _check(lib.tikh_get_options(ctypes.byref(o)), "tikh_get_options")
     if n_lim is not None:
         o.n_lim = int(n_lim)
     if refine is not None:
         o.refine = int(refine)
+    if refine_max is not None:
+        o.refine_max = int(refine_max)
+    if refine_tol is not None:
+        o.refine_tol = float(refine_tol)
     _check(lib.tikh_set_options(ctypes.byref(o)), "tikh_set_options")
 
 
 def get_options():
     o = _Opts()
     _check(lib.tikh_get_options(ctypes.byref(o)), "tikh_get_options")
-    return dict(n_lim=o.n_lim, refine=o.refine)
+    return dict(n_lim=o.n_lim, refine=o.refine, refine_max=o.refine_max, refine_tol=o.refine_tol)
 
 
 def plan_info(m, n, n_lim=256):
@@ -118,7 +127,8 @@ def profile_read():
 def get_stats():
     s = _Stats()
     _check(lib.tikh_get_stats(ctypes.byref(s)), "tikh_get_stats")
-    return dict(N=s.N, k=s.k, depth=s.depth, leaf_nodes=s.leaf_nodes, solves=s.solves, launches=s.launches)
+    return dict(N=s.N, k=s.k, depth=s.depth, leaf_nodes=s.leaf_nodes, solves=s.solves, launches=s.launches,
+                refine_extra=s.refine_extra)
 
 
 def _dev(t, dtype):
@@ -135,6 +145,18 @@ def _ptr(t):
 
 def _dtype_of(*ts):
     return torch.complex128 if any(t.is_complex() for t in ts) else torch.float64
+
+
+def fft_batched(x, sign=-1):
+    """In-place batched FFT of a complex128 device tensor of shape (items, lines, len) along the last
+    axis: X_k = sum_j x_j exp(sign 2 pi i j k / len), unnormalized.  Returns x."""
+    if not isinstance(x, torch.Tensor) or not x.is_cuda or x.dtype != torch.complex128 or x.dim() != 3:
+        raise TypeError("expected a complex128 HIP device tensor of shape (items, lines, len)")
+    if not x.is_contiguous():
+        raise ValueError("fft_batched works in place on a contiguous tensor")
+    _stream()
+    _check(tikh_fft_batched(_ptr(x), x.shape[0], x.shape[1], x.shape[2], int(sign)), "tikh_fft_batched")
+    return x
 
 
 def solve(col, row, b, lam):

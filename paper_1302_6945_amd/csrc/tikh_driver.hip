@@ -38,6 +38,7 @@ struct Ctx {
     char* ws = nullptr;
     size_t ws_size = 0;
     std::map<int64_t, double2*> tw;      // twiddle tables by size Q
+    std::map<int64_t, double2*> tw2;     // two-level twiddle tables by size
     int64_t launches = 0;
     int* dneed = nullptr;                // device / pinned host word for degree readback
     int* hneed = nullptr;
@@ -54,6 +55,10 @@ struct KProf {
     double total_ms = 0.0;
     int64_t count = 0;
     double units = 0.0;          // algorithmic work of the timed launches (bytes or flops, per kernel kind)
+    // per-shape breakdown, printed to stderr when TIKH_PROF_DETAIL is set
+    std::string label;           // shape label of the next launch
+    std::vector<std::string> labels;
+    std::map<std::string, std::pair<double, int64_t>> detail;
 };
 static KProf kprof;
 
@@ -67,7 +72,11 @@ static void prof_begin(const char* name) {
 }
 static void prof_end(const char* name) {
     if (!prof_on(name)) return;
-    if (kprof.used + 2 <= kprof.pool.size()) { (void)hipEventRecord(kprof.pool[kprof.used + 1], g.stream); kprof.used += 2; }
+    if (kprof.used + 2 <= kprof.pool.size()) {
+        (void)hipEventRecord(kprof.pool[kprof.used + 1], g.stream);
+        kprof.used += 2;
+        kprof.labels.push_back(kprof.label);
+    }
 }
 static void prof_units(const char* name, double u) {
     if (prof_on(name)) kprof.units += u;
@@ -77,9 +86,25 @@ static void prof_collect() {
     (void)hipStreamSynchronize(g.stream);
     for (size_t i = 0; i + 1 < kprof.used; i += 2) {
         float ms = 0.f;
-        if (hipEventElapsedTime(&ms, kprof.pool[i], kprof.pool[i + 1]) == hipSuccess) { kprof.total_ms += ms; kprof.count++; }
+        if (hipEventElapsedTime(&ms, kprof.pool[i], kprof.pool[i + 1]) == hipSuccess) {
+            kprof.total_ms += ms;
+            kprof.count++;
+            auto& d = kprof.detail[kprof.labels[i / 2]];
+            d.first += ms;
+            d.second++;
+        }
     }
     kprof.used = 0;
+    kprof.labels.clear();
+}
+static void prof_print_detail() {
+    if (!getenv("TIKH_PROF_DETAIL") || kprof.detail.empty()) return;
+    std::vector<std::pair<double, std::string>> v;
+    for (auto& kv : kprof.detail) v.push_back({kv.second.first, kv.first});
+    std::sort(v.rbegin(), v.rend());
+    for (auto& e : v)
+        fprintf(stderr, "[tikh prof] %-70s %10.3f ms %8lld launches\n", e.second.c_str(), e.first,
+                (long long)kprof.detail[e.second].second);
 }
 #define LAUNCH(kname, kern, grid, block, ...)                                              \
     do {                                                                                 \
@@ -93,6 +118,8 @@ static void ensure_init() {
     if (g.init) return;
     g.opts.n_lim = 256;
     g.opts.refine = 1;
+    g.opts.refine_max = 3;
+    g.opts.refine_tol = 1e-10;
     if (hipMalloc((void**)&g.dneed, sizeof(int)) != hipSuccess) g.dneed = nullptr;
     if (hipHostMalloc((void**)&g.hneed, sizeof(int), hipHostMallocDefault) != hipSuccess) g.hneed = nullptr;
     g.init = true;
@@ -153,18 +180,62 @@ static bool make_plan(int64_t N, int64_t M, int p, Plan* pl) {
     return true;
 }
 
+// Stages of an LDS transform of length L = 2^a 3^b 5^c <= 4096: radix 16
+// while possible, radix 9 per pair of threes, a single three merged with a
+// leftover 2 or 4 (radix 6 or 12), the remaining power of two as one stage,
+// then the fives.
 static bool fft_plan(int64_t L, FftPlanDev* f) {
     if (L < 1 || L > FFT_LDS_MAX) return false;
     f->L = (int)L; f->nst = 0;
     int64_t v = L;
-    // radix-16 stages, then the remaining power of two as one stage of 8, 4 or 2
-    while (v % 16 == 0) { f->radix[f->nst++] = 16; v /= 16; }
-    if (v % 8 == 0) { f->radix[f->nst++] = 8; v /= 8; }
-    else if (v % 4 == 0) { f->radix[f->nst++] = 4; v /= 4; }
-    else if (v % 2 == 0) { f->radix[f->nst++] = 2; v /= 2; }
-    while (v % 3 == 0) { f->radix[f->nst++] = 3; v /= 3; }
-    while (v % 5 == 0) { f->radix[f->nst++] = 5; v /= 5; }
-    return v == 1;
+    int a = 0, b = 0, c = 0;
+    while (v % 2 == 0) { v /= 2; ++a; }
+    while (v % 3 == 0) { v /= 3; ++b; }
+    while (v % 5 == 0) { v /= 5; ++c; }
+    if (v != 1) return false;
+    while (a >= 4) { f->radix[f->nst++] = 16; a -= 4; }
+    while (b >= 2) { f->radix[f->nst++] = 9; b -= 2; }
+    if (b == 1) {
+        if (a == 1) { f->radix[f->nst++] = 6; a = 0; }
+        else if (a == 2) { f->radix[f->nst++] = 12; a = 0; }
+        else f->radix[f->nst++] = 3;
+    }
+    if (a == 3) f->radix[f->nst++] = 8;
+    else if (a == 2) f->radix[f->nst++] = 4;
+    else if (a == 1) f->radix[f->nst++] = 2;
+    while (c-- > 0) f->radix[f->nst++] = 5;
+    return true;
+}
+
+// Two-level table of e^{2 pi i x / M}: [x < 2^bits | (x >> bits) <= (M - 1) >> bits].
+static int tw2_bits(int64_t M) {
+    int lg = 0;
+    while (((int64_t)1 << lg) < M) ++lg;
+    return std::max(1, (lg + 1) / 2);
+}
+static double2* twiddles2(int64_t M, int* bits) {
+    *bits = tw2_bits(M);
+    auto it = g.tw2.find(M);
+    if (it != g.tw2.end()) return it->second;
+    const int64_t nlo = (int64_t)1 << *bits, nhi = ((M - 1) >> *bits) + 1;
+    std::vector<double2> h(nlo + nhi);
+    const long double pi2 = 6.283185307179586476925286766559005768L;
+    for (int64_t j = 0; j < nlo; ++j) {
+        long double a = pi2 * (long double)j / (long double)M;
+        h[j] = make_double2((double)cosl(a), (double)sinl(a));
+    }
+    for (int64_t j = 0; j < nhi; ++j) {
+        long double a = pi2 * (long double)(j * nlo) / (long double)M;
+        h[nlo + j] = make_double2((double)cosl(a), (double)sinl(a));
+    }
+    double2* d = nullptr;
+    if (hipMalloc(&d, sizeof(double2) * h.size()) != hipSuccess) return nullptr;
+    if (hipMemcpy(d, h.data(), sizeof(double2) * h.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(d);
+        return nullptr;
+    }
+    g.tw2[M] = d;
+    return d;
 }
 
 static double2* twiddles(int64_t Q) {
@@ -182,6 +253,10 @@ static double2* twiddles(int64_t Q) {
     g.tw[Q] = d;
     return d;
 }
+
+// Adaptive refinement: the factor of the estimate cfac * e0 * ||dx|| / ||x||
+// of the error left after a step.
+static const double REFINE_CFAC = 1000.0;
 
 // subtrees with at most this many conditions are merged by the direct kernels
 static const int64_t DIRECT_MAX_COND = 256;
@@ -237,8 +312,9 @@ static void make_layout(const Plan& pl, int nr, int64_t mmax, int64_t nmax, Layo
         L->sT = std::max(L->sT, ((d & 1) ? L->tOff : 0) + sz);
     }
     tot += L->sT;
-    L->group_bytes = tot * sizeof(double2) + 2 * (pl.p + 1) * sizeof(SlotMeta) + sizeof(SolveState) + sizeof(double) + 256;
-    L->solve_bytes = (size_t)(4 * L->sN + 4 * L->sn) * sizeof(double2) + sizeof(SolveDesc) + 64;
+    L->group_bytes = tot * sizeof(double2) + 2 * (pl.p + 1) * sizeof(SlotMeta) + sizeof(SolveState) + sizeof(double) +
+                     sizeof(int32_t) + sizeof(int2) + 256;
+    L->solve_bytes = (size_t)(4 * L->sN + 4 * L->sn) * sizeof(double2) + sizeof(SolveDesc) + 2 * sizeof(double) + 64;
     L->temp_bytes = (size_t)(L->sV + 2 * L->sF + L->sscr) * sizeof(double2);
 }
 
@@ -259,6 +335,9 @@ struct Bufs {
     // merge scratch shared by the groups of one merge chunk
     double2* V;
     double2 *FL, *FR, *scr;
+    double* nrm;                     // [2S] refinement norms (correction, solution)
+    int32_t* flags;                  // [G] one more refinement step
+    int2* pairs;                     // [G] group exchanges of the compaction
     int64_t chunk;                   // groups per merge chunk at the largest level
     double2* pool;                   // V, FL, FR and scr as one region (re-split per level)
     int64_t pool_elems;
@@ -332,6 +411,9 @@ static int carve_bufs(const Plan& pl, const Layout& L, int64_t G, int64_t CH, Bu
     b->st = (SolveState*)carve(p, sizeof(SolveState) * G);
     b->rms = (double*)carve(p, sizeof(double) * G);
     b->elist = (int*)carve(p, sizeof(EList));
+    b->nrm = (double*)carve(p, sizeof(double) * 2 * S);
+    b->flags = (int32_t*)carve(p, sizeof(int32_t) * G);
+    b->pairs = (int2*)carve(p, sizeof(int2) * G);
     auto cv = [&](int64_t per, int64_t cnt) { return (double2*)carve(p, sizeof(double2) * per * cnt); };
     b->chat = cv(L.sN, G);
     b->bA = cv(L.sN, S); b->bB = cv(L.sN, S); b->bC = cv(L.sN, S); b->bS = cv(L.sN, S);
@@ -392,7 +474,8 @@ static void fft_pass(double2* data, int64_t S, int64_t sstride, int64_t nlines, 
     }
     a.data = data; a.solve_stride = sstride; a.sign = sign; a.scale = 1.0; a.tw = tw; a.Q = Q;
     a.ltw = twiddles(L);              // per-length tables: contiguous twiddle reads
-    a.ptw = post_L ? twiddles(post_L) : nullptr;
+    a.ptw = post_L ? twiddles2(post_L, &a.pbits) : nullptr;
+    if (a.load_mode == 2) a.ftw = twiddles2(a.fold_N, &a.fbits);
     fft_plan(L, &a.pl);
     a.nlines = nlines; a.lines_inner = lines_inner; a.line_stride = line_stride; a.outer_stride = outer_stride;
     a.elem_stride = elem_stride; a.post_L = post_L;
@@ -400,6 +483,12 @@ static void fft_pass(double2* data, int64_t S, int64_t sstride, int64_t nlines, 
     dim3 gr((unsigned)((nlines + a.lpw - 1) / a.lpw), (unsigned)S);
     // algorithmic traffic: every element of every line read once and written once
     prof_units("fft", 32.0 * (double)S * (double)nlines * (double)L);
+    if (prof_on("fft") && getenv("TIKH_PROF_DETAIL")) {
+        char lab[160];
+        snprintf(lab, sizeof lab, "L=%lld es=%lld lines=%lld S=%lld load=%d store=%d post=%d", (long long)L,
+                 (long long)elem_stride, (long long)nlines, (long long)S, a.load_mode, a.store_mode, post_L ? 1 : 0);
+        kprof.label = lab;
+    }
     LAUNCH("fft", k_fft, gr, dim3(FFT_THREADS), a);
 }
 
@@ -423,11 +512,11 @@ static int fft_lines(double2* data, int64_t S, int64_t sstride, int64_t nlines, 
     if (order == FFT_INV_T) {
         // rows j1 (contiguous, length L2) with twiddle w^{j1 k2}, then columns k2 (stride L2, length L1)
         fft_pass(data, S, sstride, nlines * L1, L1, L2, Lf, 1, L2, sign, Lf, tw, Q, 64, fuse, true, false);
-        fft_pass(data, S, sstride, nlines * L2, L2, 1, Lf, L2, L1, sign, 0, tw, Q, 16, fuse, false, true);
+        fft_pass(data, S, sstride, nlines * L2, L2, 1, Lf, L2, L1, sign, 0, tw, Q, 64, fuse, false, true);
         return TIKH_OK;
     }
     // columns k2 (stride L2, length L1) with twiddle w^{j1 k2}, then rows j1 (contiguous, length L2)
-    fft_pass(data, S, sstride, nlines * L2, L2, 1, Lf, L2, L1, sign, Lf, tw, Q, 16, fuse, true, false);
+    fft_pass(data, S, sstride, nlines * L2, L2, 1, Lf, L2, L1, sign, Lf, tw, Q, 64, fuse, true, false);
     fft_pass(data, S, sstride, nlines * L1, L1, L2, Lf, 1, L2, sign, 0, tw, Q, 64, fuse, false, true);
     if (order == FFT_NATURAL) {
         hipLaunchKernelGGL(k_fourstep_unscramble, grid1(nlines * Lf, S), dim3(256), 0, g.stream, data, scratch,
@@ -541,9 +630,9 @@ static int run_product_chunk(const Plan& pl, const Layout& L, const Bufs& b, int
     rc = fft_lines(b.FR, G, L.sF, nR, P, -1, tw, pl.Q, b.scr, L.sscr, FFT_FWD_T, &fr);
     if (rc) return rc;
     // the pointwise product reads every input of a frequency before writing, so it runs in place over FL
-    if (nr == 1) LAUNCH("prod_mul", k_prod_mul<1>, grid1(P, G), dim3(256), b.FL, b.FR, b.FL, L.sF, P, root ? 1 : 0);
-    else if (nr == 2) LAUNCH("prod_mul", k_prod_mul<2>, grid1(P, G), dim3(256), b.FL, b.FR, b.FL, L.sF, P, root ? 1 : 0);
-    else LAUNCH("prod_mul", k_prod_mul<4>, grid1(P, G), dim3(256), b.FL, b.FR, b.FL, L.sF, P, root ? 1 : 0);
+    if (nr == 1) LAUNCH("prod_mul", k_prod_mul<1>, grid1(P, G, 64), dim3(64), b.FL, b.FR, b.FL, L.sF, P, root ? 1 : 0);
+    else if (nr == 2) LAUNCH("prod_mul", k_prod_mul<2>, grid1(P, G, 64), dim3(64), b.FL, b.FR, b.FL, L.sF, P, root ? 1 : 0);
+    else LAUNCH("prod_mul", k_prod_mul<4>, grid1(P, G, 64), dim3(64), b.FL, b.FR, b.FL, L.sF, P, root ? 1 : 0);
     // the inverse transform writes the truncated, 1/P-scaled coefficients into the destination slot
     FftArgs fo{};
     fo.store_mode = 1; fo.dst = dst; fo.dst_stride = dstride; fo.dst_cp1 = dcap + 1; fo.dst_meta = dmeta;
@@ -692,42 +781,78 @@ static int run_chunk(const Plan& pl, int nr, const std::vector<SolveDesc>& sds, 
                            0, 1.0, b.yv, nmax, L.sn);
     }
     g.launches += 2;
-    const int steps = 1 + std::max(0, std::min(4, (int)g.opts.refine));
-    for (int it = 0; it < steps; ++it) {
+    // Refinement: `refine` steps for every group, then up to `refine_max` steps in
+    // all for the groups whose estimated error is still above refine_tol; those
+    // groups are first exchanged into a prefix [0, Ga) of the chunk.
+    const int steps_min = 1 + std::max(0, std::min(4, (int)g.opts.refine));
+    const int steps_max = g.opts.refine > 0 ? std::max(steps_min, 1 + std::min(4, (int)g.opts.refine_max)) : steps_min;
+    int64_t Ga = G, Sa = S;
+    std::vector<int32_t> hflags;
+    for (int it = 0; it < steps_max; ++it) {
+        if (it >= steps_min) {
+            // groups still above the tolerance after the last step
+            hflags.resize((size_t)Ga);
+            HIPCHK(hipMemcpyAsync(hflags.data(), b.flags, sizeof(int32_t) * Ga, hipMemcpyDeviceToHost, g.stream));
+            HIPCHK(hipStreamSynchronize(g.stream));
+            std::vector<int64_t> want, holes;
+            int64_t G2 = 0;
+            for (int64_t gi = 0; gi < Ga; ++gi) G2 += hflags[gi] ? 1 : 0;
+            if (G2 == 0) break;
+            for (int64_t gi = 0; gi < G2; ++gi) if (!hflags[gi]) holes.push_back(gi);
+            for (int64_t gi = G2; gi < Ga; ++gi) if (hflags[gi]) want.push_back(gi);
+            if (!holes.empty()) {
+                std::vector<int2> hp(holes.size());
+                for (size_t i = 0; i < holes.size(); ++i) hp[i] = make_int2((int)holes[i], (int)want[i]);
+                HIPCHK(hipMemcpyAsync(b.pairs, hp.data(), sizeof(int2) * hp.size(), hipMemcpyHostToDevice, g.stream));
+                HIPCHK(hipStreamSynchronize(g.stream));
+                hipLaunchKernelGGL(k_swap_groups, dim3(64, (unsigned)hp.size()), dim3(256), 0, g.stream, b.sd, b.st,
+                                   b.chat, L.sN, b.yv, b.xacc, L.sn, nr, b.pairs);
+                g.launches++;
+            }
+            Ga = G2;
+            Sa = G2 * nr;
+            g.stats.refine_extra += Sa;
+        }
         const double2* rhs = b.yv;
         if (it > 0) {
             // residual of the normal equations, r = y - (T^H T + lam^2) x (Sec. 7.2: iterative refinement)
-            hipLaunchKernelGGL(k_load_pad, grid1(N, S), dim3(256), 0, g.stream, b.sd, 0, b.xacc, L.sn, 1, 0, 1.0,
+            hipLaunchKernelGGL(k_load_pad, grid1(N, Sa), dim3(256), 0, g.stream, b.sd, 0, b.xacc, L.sn, 1, 0, 1.0,
                                b.bB, N, L.sN);
-            circ_apply(pl, L, b, S, b.bB, 0, tw);
-            hipLaunchKernelGGL(k_take_tail, grid1(mmax, S), dim3(256), 0, g.stream, b.sd, b.bB, N, L.sN, 0, invN,
+            circ_apply(pl, L, b, Sa, b.bB, 0, tw);
+            hipLaunchKernelGGL(k_take_tail, grid1(mmax, Sa), dim3(256), 0, g.stream, b.sd, b.bB, N, L.sN, 0, invN,
                                b.t1, L.sn);
-            hipLaunchKernelGGL(k_load_pad, grid1(N, S), dim3(256), 0, g.stream, b.sd, 0, b.t1, L.sn, 0, 0, 1.0, b.bB,
+            hipLaunchKernelGGL(k_load_pad, grid1(N, Sa), dim3(256), 0, g.stream, b.sd, 0, b.t1, L.sn, 0, 0, 1.0, b.bB,
                                N, L.sN);
-            circ_apply(pl, L, b, S, b.bB, 1, tw);
-            hipLaunchKernelGGL(k_take_tail, grid1(nmax, S), dim3(256), 0, g.stream, b.sd, b.bB, N, L.sN, 1, invN,
+            circ_apply(pl, L, b, Sa, b.bB, 1, tw);
+            hipLaunchKernelGGL(k_take_tail, grid1(nmax, Sa), dim3(256), 0, g.stream, b.sd, b.bB, N, L.sN, 1, invN,
                                b.t2, L.sn);
-            hipLaunchKernelGGL(k_normal_residual, grid1(nmax, S), dim3(256), 0, g.stream, b.sd, b.yv, b.t2, b.xacc,
+            hipLaunchKernelGGL(k_normal_residual, grid1(nmax, Sa), dim3(256), 0, g.stream, b.sd, b.yv, b.t2, b.xacc,
                                b.t1, L.sn);
-            hipLaunchKernelGGL(k_init_state, dim3((unsigned)((G + 63) / 64)), dim3(64), 0, g.stream, b.sd, nr, b.st,
-                               (int)G, 1);
-            g.launches += 6;
+            hipLaunchKernelGGL(k_init_state, dim3((unsigned)((Ga + 63) / 64)), dim3(64), 0, g.stream, b.sd, nr, b.st,
+                               (int)Ga, 1);
+            hipLaunchKernelGGL(k_zero_d, grid1(2 * Sa, 1), dim3(256), 0, g.stream, b.nrm, 2 * Sa);
+            g.launches += 7;
             rhs = b.t1;
         }
-        hipLaunchKernelGGL(k_load_pad, grid1(N, S), dim3(256), 0, g.stream, b.sd, 0, rhs, L.sn, 1, 0, 1.0, b.bA, N,
+        hipLaunchKernelGGL(k_load_pad, grid1(N, Sa), dim3(256), 0, g.stream, b.sd, 0, rhs, L.sn, 1, 0, 1.0, b.bA, N,
                            L.sN);
         g.launches++;
-        rc = fft_lines(b.bA, S, L.sN, 1, N, +1, tw, pl.Q, b.bS, L.sN);
+        rc = fft_lines(b.bA, Sa, L.sN, 1, N, +1, tw, pl.Q, b.bS, L.sN);
         if (rc) return rc;
-        hipLaunchKernelGGL(k_assemble, grid1(2 * N, G), dim3(256), 0, g.stream, b.sd, nr, b.chat, b.bA, L.sN, b.phi,
+        hipLaunchKernelGGL(k_assemble, grid1(2 * N, Ga), dim3(256), 0, g.stream, b.sd, nr, b.chat, b.bA, L.sN, b.phi,
                            L.sphi, N, pl.M, pl.p, pl.K, tw, pl.Q);
         g.launches++;
-        rc = run_recursion(pl, L, b, G, tw);
+        rc = run_recursion(pl, L, b, Ga, tw);
         if (rc) return rc;
         const int64_t xcp1 = pl.cap[0] + 1;
-        hipLaunchKernelGGL(k_extract, grid1(nmax, S), dim3(256), 0, g.stream, b.sd, nr, b.st, b.slotT[0], L.sT,
-                           pl.p == 0 ? xcp1 : xcp1, b.metaT[0], b.xacc, L.sn, it > 0 ? 1 : 0);
+        hipLaunchKernelGGL(k_extract, grid1(nmax, Sa), dim3(256), 0, g.stream, b.sd, nr, b.st, b.slotT[0], L.sT,
+                           xcp1, b.metaT[0], b.xacc, L.sn, it > 0 ? 1 : 0, b.nrm);
         g.launches++;
+        if (it > 0 && it + 1 < steps_max) {
+            hipLaunchKernelGGL(k_refine_decide, dim3((unsigned)((Ga + 63) / 64)), dim3(64), 0, g.stream, b.nrm, nr,
+                               b.st, (int)Ga, it == 1 ? 1 : 0, REFINE_CFAC, g.opts.refine_tol, b.flags);
+            g.launches++;
+        }
     }
     if (!sds[0].backward) {
         hipLaunchKernelGGL(k_store_x, grid1(nmax, S), dim3(256), 0, g.stream, b.sd, nr, b.xacc, L.sn, b.st, info);
@@ -785,6 +910,7 @@ static int run_chunk(const Plan& pl, int nr, const std::vector<SolveDesc>& sds, 
 static int run_solves(std::vector<SolveDesc>& sds, int nr, int32_t* info) {
     ensure_init();
     g.launches = 0;
+    g.stats.refine_extra = 0;
     if (sds.empty()) return TIKH_OK;
     if (nr != 1 && nr != 2 && nr != 4) return TIKH_EINVAL;
     const int64_t G = (int64_t)sds.size() / nr;
@@ -876,6 +1002,9 @@ int tikh_init(void) { ensure_init(); return TIKH_OK; }
 int tikh_profile_kernel(const char* name) {
     ensure_init();
     prof_collect();
+    prof_print_detail();
+    kprof.detail.clear();
+    kprof.label.clear();
     kprof.name = name ? std::string(name) : std::string();
     kprof.total_ms = 0.0;
     kprof.count = 0;
@@ -906,10 +1035,33 @@ int tikh_plan_info(int64_t m, int64_t n, int32_t n_lim, int64_t* N, int64_t* M, 
     return TIKH_OK;
 }
 
+int tikh_fft_batched(void* data, int64_t items, int64_t nlines, int64_t len, int sign) {
+    ensure_init();
+    if (!data || items < 1 || items > 65535 || nlines < 1 || len < 1 || (sign != 1 && sign != -1)) return TIKH_EINVAL;
+    if (!smooth5(len) || len > (int64_t)FFT_LDS_MAX * FFT_LDS_MAX || nlines > ((int64_t)1 << 40) / len)
+        return TIKH_EINVAL;
+    if (len > FFT_LDS_MAX && fft_split(len) == 0) return TIKH_EINVAL;
+    const double2* tw = twiddles(len);
+    if (!tw) return TIKH_ENOMEM;
+    double2* scr = nullptr;
+    if (len > FFT_LDS_MAX) {
+        // the four-step reordering goes through a scratch copy
+        int rc = ensure_ws((size_t)items * nlines * len * sizeof(double2));
+        if (rc) return rc;
+        scr = (double2*)g.ws;
+    }
+    g.launches = 0;
+    int rc = fft_lines((double2*)data, items, nlines * len, nlines, len, sign, tw, len, scr, nlines * len);
+    if (rc) return rc;
+    return hipGetLastError() == hipSuccess ? TIKH_OK : TIKH_EHIP;
+}
+
 int tikh_release(void) {
     if (g.ws) { hipStreamSynchronize(g.stream); hipFree(g.ws); g.ws = nullptr; g.ws_size = 0; }
-    for (auto& kv : g.tw) hipFree(kv.second);
+    for (auto& kv : g.tw) (void)hipFree(kv.second);
     g.tw.clear();
+    for (auto& kv : g.tw2) (void)hipFree(kv.second);
+    g.tw2.clear();
     return TIKH_OK;
 }
 
@@ -918,7 +1070,9 @@ int tikh_set_stream(void* s) { ensure_init(); g.stream = (hipStream_t)s; return 
 int tikh_set_options(const tikh_opts* o) {
     ensure_init();
     if (!o) return TIKH_EINVAL;
-    if (o->n_lim < 64 || o->n_lim > LEAF_MAX || o->refine < 0 || o->refine > 4) return TIKH_EINVAL;
+    if (o->n_lim < 64 || o->n_lim > LEAF_MAX || o->refine < 0 || o->refine > 4 || o->refine_max < 0 ||
+        o->refine_max > 4 || !(o->refine_tol > 0.0) || !std::isfinite(o->refine_tol))
+        return TIKH_EINVAL;
     g.opts = *o;
     return TIKH_OK;
 }

@@ -45,7 +45,8 @@ struct SolveDesc {
 struct SolveState {
     int32_t delta[4];  // tau-degrees of basis columns 1..4 (column 5 stays 0)
     int32_t info;      // 0 ok, 1 breakdown, 2 degree bound, 3 non-finite
-    int32_t pad[3];
+    int32_t pad;
+    double e0;         // relative size of the first refinement correction (error estimate of the first solve)
 };
 
 // Per-group metadata of a stored basis (one per slot).

@@ -73,6 +73,13 @@ __device__ __forceinline__ double2 twq(const double2* __restrict__ tw, int64_t Q
     return sign > 0 ? t : cconj(t);
 }
 
+// e^{2 pi i x / M} (0 <= x < M) from a two-level table
+// t = [e^{2 pi i j / M}, j < 2^bits | e^{2 pi i j 2^bits / M}, j <= (M - 1) >> bits]:
+// both parts are small, so scattered indices stay in cache
+__device__ __forceinline__ double2 tw2(const double2* __restrict__ t, int bits, int64_t x) {
+    return cmul(t[((int64_t)1 << bits) + (x >> bits)], t[x & (((int64_t)1 << bits) - 1)]);
+}
+
 __device__ __forceinline__ double2 load_elem(const void* p, int64_t i, int cplx) {
     if (cplx) return ((const double2*)p)[i];
     return c2(((const double*)p)[i], 0.0);
@@ -175,6 +182,51 @@ __device__ __forceinline__ double2 rot16(double2 a, int e, int sign) {
     return cmul(a, c2(c, sign > 0 ? s : -s));
 }
 
+// a * e^{sign 2 pi i e / R} for R = 6, 8, 9, 12, 16 (quarter turns exactly)
+template <int R>
+__device__ __forceinline__ double2 rotR(double2 a, int e, int sign) {
+    e %= R;
+    if (e == 0) return a;
+    if (R == 16) return rot16(a, e, sign);
+    if (R == 8) return rot16(a, 2 * e, sign);
+    if ((4 * e) % R == 0) {
+        const int q = 4 * e / R;
+        if (q == 2) return cneg(a);
+        const bool pos = (q == 1) == (sign > 0);
+        return pos ? c2(-a.y, a.x) : c2(a.y, -a.x);
+    }
+    const double H = 0.5, T = 0.866025403784438646764;
+    double c = 1.0, s = 0.0;
+    if (R == 6 || R == 12) {
+        const int e12 = R == 6 ? 2 * e : e;
+        switch (e12) {
+            case 1: c = T; s = H; break;
+            case 2: c = H; s = T; break;
+            case 4: c = -H; s = T; break;
+            case 5: c = -T; s = H; break;
+            case 7: c = -T; s = -H; break;
+            case 8: c = -H; s = -T; break;
+            case 10: c = H; s = -T; break;
+            default: c = T; s = -H; break;   // 11
+        }
+    } else {   // R == 9
+        const double C1 = 0.766044443118978035202, S1 = 0.642787609686539326323;
+        const double C2 = 0.173648177666930348852, S2 = 0.984807753012208059367;
+        const double C4 = -0.939692620785908384054, S4 = 0.342020143325668733044;
+        switch (e) {
+            case 1: c = C1; s = S1; break;
+            case 2: c = C2; s = S2; break;
+            case 3: c = -H; s = T; break;
+            case 4: c = C4; s = S4; break;
+            case 5: c = C4; s = -S4; break;
+            case 6: c = -H; s = -T; break;
+            case 7: c = C2; s = -S2; break;
+            default: c = C1; s = -S1; break;  // 8
+        }
+    }
+    return cmul(a, c2(c, sign > 0 ? s : -s));
+}
+
 template <int R1, int R2>
 __device__ __forceinline__ void bfly_split(double2* v, int sign) {
     constexpr int R = R1 * R2;
@@ -186,7 +238,7 @@ __device__ __forceinline__ void bfly_split(double2* v, int sign) {
         for (int n1 = 0; n1 < R1; ++n1) t[n1] = v[R2 * n1 + n2];
         bfly<R1>(t, sign);
 #pragma unroll
-        for (int k1 = 0; k1 < R1; ++k1) y[n2 * R1 + k1] = rot16(t[k1], n2 * k1 * (16 / R), sign);
+        for (int k1 = 0; k1 < R1; ++k1) y[n2 * R1 + k1] = rotR<R>(t[k1], n2 * k1, sign);
     }
 #pragma unroll
     for (int k1 = 0; k1 < R1; ++k1) {
@@ -198,12 +250,15 @@ __device__ __forceinline__ void bfly_split(double2* v, int sign) {
         for (int k2 = 0; k2 < R2; ++k2) v[k1 + R1 * k2] = t[k2];
     }
 }
+template <> __device__ __forceinline__ void bfly<6>(double2* v, int sign) { bfly_split<2, 3>(v, sign); }
 template <> __device__ __forceinline__ void bfly<8>(double2* v, int sign) { bfly_split<2, 4>(v, sign); }
+template <> __device__ __forceinline__ void bfly<9>(double2* v, int sign) { bfly_split<3, 3>(v, sign); }
+template <> __device__ __forceinline__ void bfly<12>(double2* v, int sign) { bfly_split<4, 3>(v, sign); }
 template <> __device__ __forceinline__ void bfly<16>(double2* v, int sign) { bfly_split<4, 4>(v, sign); }
 
 // v[r] *= e^{sign 2 pi i r idx / L} for r = 1..R-1 (ltw[j] = e^{2 pi i j / L},
-// r idx < L).  For R = 8, 16 only the powers of two are read from the table;
-// the others are products of at most three of them.
+// r idx < L).  For R > 5 only the powers of two below R are read from the
+// table; the others are products of at most three of them.
 template <int R>
 __device__ __forceinline__ void stage_twiddle(double2* v, const double2* __restrict__ ltw, int idx, int sign) {
     if (R <= 5) {
@@ -211,10 +266,8 @@ __device__ __forceinline__ void stage_twiddle(double2* v, const double2* __restr
         for (int r = 1; r < R; ++r) v[r] = cmul(v[r], twd(ltw, (int64_t)r * idx, sign));
     } else {
         double2 w[R];
-        w[1] = twd(ltw, idx, sign);
-        w[2] = twd(ltw, 2 * idx, sign);
-        w[4] = twd(ltw, 4 * idx, sign);
-        if (R == 16) w[8] = twd(ltw, 8 * idx, sign);
+#pragma unroll
+        for (int h = 1; h < R; h *= 2) w[h] = twd(ltw, (int64_t)h * idx, sign);
 #pragma unroll
         for (int r = 3; r < R; ++r) {
             const int h = r >= 8 ? 8 : (r >= 4 ? 4 : 2);
@@ -315,7 +368,10 @@ struct FftArgs {
     const double2* tw;               // e^{2 pi i q / Q}, q < Q (fused twist of evaluation lines)
     int64_t Q;
     const double2* ltw;              // e^{2 pi i j / L}, j < L (stages)
-    const double2* ptw;              // e^{2 pi i j / post_L}, j < post_L (four-step twiddle)
+    const double2* ptw;              // two-level table of e^{2 pi i j / post_L} (four-step twiddle)
+    int pbits;
+    const double2* ftw;              // two-level table of e^{2 pi i j / fold_N} (evaluation twist)
+    int fbits;
     FftPlanDev pl;
     // fused load: 0 = data, 1 = zero-padded basis entry elist[o], 2 = twisted and folded
     // basis entry o/2 at coset offset fold_o + (o & 1) (evaluation)
@@ -336,59 +392,82 @@ struct FftArgs {
     double dst_scale;
 };
 
-__device__ __forceinline__ double2 fft_fused_load(const FftArgs& a, int64_t s, int64_t o, int64_t off,
-                                                 const SlotMeta& mt) {
-    if (a.load_mode == 1) {
-        const int e = a.elist[o];
+// Per-line descriptors of the fused loads and stores, computed once per
+// workgroup.  Fused load 1: element k of the line is
+// src[lsrc + k*es] * lsc if k*es <= llim, else 0.  Fused load 2: entry
+// src[lsrc + i] folded over i = off + t*fold_L (off = in*line_stride + k*es,
+// i <= llim) and twisted by w^{loc*i}.  Fused store: element k goes to
+// dst[dbase + k*es] (scaled by dst_scale) if k*es <= dlim.
+struct FftLineInfo {
+    int64_t lsrc, llim, loc;
+    double lsc;
+    double2 lstep;                   // fused load 2: w^{loc fold_L}
+    int64_t dbase, dlim;
+    int dcol;
+};
+
+__device__ __forceinline__ void fft_line_info(const FftArgs& a, int64_t s, int64_t o, int64_t in, FftLineInfo& li) {
+    const int64_t inoff = in * a.line_stride;
+    if (a.load_mode) {
+        const SlotMeta& mt = a.src_meta[s];
+        const int e = a.load_mode == 1 ? a.elist[o] : (int)(o >> 1);
         const int col = e % a.C;
-        if (off > mt.deg[col]) return c2(0.0, 0.0);
-        const double sc = col < 4 ? pow2_inv_scale(mt.colmax_bits[col]) : 1.0;
-        return cscale(a.src[s * a.src_stride + (int64_t)e * a.src_cp1 + off], sc);
+        li.lsc = col < 4 ? pow2_inv_scale(mt.colmax_bits[col]) : 1.0;
+        li.lsrc = s * a.src_stride + (int64_t)e * a.src_cp1 + (a.load_mode == 1 ? inoff : 0);
+        li.llim = a.load_mode == 1 ? (int64_t)mt.deg[col] - inoff : (int64_t)mt.deg[col];
+        li.loc = a.load_mode == 2 ? a.fold_o + (o & 1) : 0;
+        if (a.load_mode == 2)
+            li.lstep = tw2(a.ftw, a.fbits, mod_fast(li.loc * a.fold_L, a.fold_N, 1.0 / (double)a.fold_N));
     }
-    // twisted and folded: sum over i = off + t L of B[i] w^{oc i}; w^{oc (off + t L)} = w^{oc off} (w^{oc L})^t
-    const int e = (int)(o >> 1);
-    const int64_t oc = a.fold_o + (o & 1);
-    const int col = e % a.C;
-    const int dg = mt.deg[col];
-    if (off > dg) return c2(0.0, 0.0);
-    const double sc = col < 4 ? pow2_inv_scale(mt.colmax_bits[col]) : 1.0;
-    const double2* src = a.src + s * a.src_stride + (int64_t)e * a.src_cp1;
-    const int64_t twN = a.Q / a.fold_N;
-    const double invN = 1.0 / (double)a.fold_N;
-    double2 w = a.tw[mod_fast(oc * off, a.fold_N, invN) * twN];
-    const double2 wstep = a.tw[mod_fast(oc * a.fold_L, a.fold_N, invN) * twN];
-    double2 acc = c2(0.0, 0.0);
-    for (int64_t i = off; i <= dg; i += a.fold_L) {
-        acc = cfma(src[i], w, acc);
-        w = cmul(w, wstep);
+    if (a.store_mode) {
+        const int e = a.dst_elist[o];
+        const int col = e % a.C;
+        li.dcol = col;
+        li.dbase = s * a.dst_stride + (int64_t)e * a.dst_cp1 + inoff;
+        li.dlim = min((int64_t)a.dst_meta[s].deg[col], a.dst_cp1 - 1) - inoff;
     }
-    return cscale(acc, sc);
 }
 
-__device__ __forceinline__ void fft_fused_store(const FftArgs& a, int64_t s, int64_t o, int64_t off, double2 v,
-                                                double* cmx) {
-    const int e = a.dst_elist[o];
-    const int col = e % a.C;
-    if (off <= a.dst_meta[s].deg[col] && off < a.dst_cp1) {
-        v = cscale(v, a.dst_scale);
-        a.dst[s * a.dst_stride + (int64_t)e * a.dst_cp1 + off] = v;
-        if (col < 4) {
-            const double m2 = cabs2(v);
-#pragma unroll
-            for (int c = 0; c < 4; ++c) if (c == col) cmx[c] = fmax(cmx[c], m2);
+// twisted and folded evaluation input: sum over i = off + t L <= deg of B[i] w^{oc i},
+// with w^{oc (off + t L)} = w^{oc off} (w^{oc L})^t.  Split into the first
+// term (its loads are independent of other elements, so several elements
+// issue them together) and the remaining terms.
+struct FoldTerm {
+    double2 acc, w;
+    int64_t off;
+};
+__device__ __forceinline__ FoldTerm fft_fold_first(const FftArgs& a, const FftLineInfo& li, int64_t off) {
+    FoldTerm f;
+    f.off = off;
+    f.acc = c2(0.0, 0.0);
+    f.w = c2(1.0, 0.0);
+    if (off <= li.llim) {
+        const double invN = 1.0 / (double)a.fold_N;
+        f.w = tw2(a.ftw, a.fbits, mod_fast(li.loc * off, a.fold_N, invN));
+        f.acc = cmul(a.src[li.lsrc + off], f.w);
+    }
+    return f;
+}
+__device__ __forceinline__ double2 fft_fold_rest(const FftArgs& a, const FftLineInfo& li, FoldTerm f) {
+    if (f.off + a.fold_L <= li.llim) {
+        const double2 wstep = li.lstep;
+        for (int64_t i = f.off + a.fold_L; i <= li.llim; i += a.fold_L) {
+            f.w = cmul(f.w, wstep);
+            f.acc = cfma(a.src[li.lsrc + i], f.w, f.acc);
         }
     }
+    return cscale(f.acc, li.lsc);
 }
 
-// Batched FFT of lines (see FftArgs).  Plain passes read their inputs in the
-// first stage and write their outputs in the last stage directly between
-// registers and global memory; a fused load (or store) instead goes through
-// one LDS prologue (or epilogue) loop, which keeps the stage code small.
+// Batched FFT of lines (see FftArgs).  The first stage reads its inputs and
+// the last stage writes its outputs directly between registers and global
+// memory (plain lines, zero-padded slot entries, slot stores); the folded
+// evaluation input goes through one LDS prologue loop.
 __global__ __launch_bounds__(FFT_THREADS) void k_fft(const FftArgs a) {
     __shared__ double2 sm[FFT_LDS_PAD];
     __shared__ int64_t sh_base[64];
-    __shared__ int64_t sh_o[64];
     __shared__ int sh_in[64];
+    __shared__ FftLineInfo sh_li[64];
     const int L = a.pl.L;
     const int64_t l0 = (int64_t)blockIdx.x * a.lpw;
     const int nl = (int)min((int64_t)a.lpw, a.nlines - l0);
@@ -397,59 +476,95 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft(const FftArgs a) {
     if ((int)threadIdx.x < nl) {
         const int64_t l = l0 + threadIdx.x, o = l / a.lines_inner, in = l - o * a.lines_inner;
         sh_base[threadIdx.x] = o * a.outer_stride + in * a.line_stride;
-        sh_o[threadIdx.x] = o;
         sh_in[threadIdx.x] = (int)in;
+        if (a.load_mode || a.store_mode) fft_line_info(a, s, o, in, sh_li[threadIdx.x]);
     }
     __syncthreads();
     const int nst = a.pl.nst;
     const bool linefast = (a.elem_stride != 1);
-    const bool dload = (a.load_mode == 0) && nst > 0, dstore = (a.store_mode == 0) && nst > 0;
+    const bool dload = (a.load_mode != 2) && nst > 0, dstore = nst > 0;
     const int tot = nl * L;
     const float invL = 1.0f / (float)L, invnl = 1.0f / (float)nl;
+    const int64_t es = a.elem_stride;
     double cmx[4] = {0.0, 0.0, 0.0, 0.0};
-    if (!dload) {
-        const SlotMeta* lm = a.load_mode ? &a.src_meta[s] : nullptr;
-        for (int i = threadIdx.x; i < tot; i += FFT_THREADS) {
-            int g, k;
-            if (!linefast) { g = fdiv(i, invL, L); k = i - g * L; } else { k = fdiv(i, invnl, nl); g = i - k * nl; }
-            const int64_t off = (int64_t)sh_in[g] * a.line_stride + (int64_t)k * a.elem_stride;
-            sm[lds_ix(g * L + k)] = a.load_mode ? fft_fused_load(a, s, sh_o[g], off, *lm)
-                                                : base[sh_base[g] + (int64_t)k * a.elem_stride];
+    auto ld = [&](int g, int k) -> double2 {
+        if (a.load_mode == 1) {
+            const FftLineInfo& li = sh_li[g];
+            const int64_t off = (int64_t)k * es;
+            return off <= li.llim ? cscale(a.src[li.lsrc + off], li.lsc) : c2(0.0, 0.0);
         }
-        __syncthreads();
-    }
-    auto ld = [&](int g, int k) -> double2 { return base[sh_base[g] + (int64_t)k * a.elem_stride]; };
+        return base[sh_base[g] + (int64_t)k * es];
+    };
     auto st = [&](int g, int k, double2 v) {
         // k * in < post_L: k < L and in < post_L / L for both four-step passes
-        if (a.post_L) v = cmul(v, twd(a.ptw, (int64_t)k * sh_in[g], a.sign));
+        if (a.post_L) {
+            const double2 t = tw2(a.ptw, a.pbits, (int64_t)k * sh_in[g]);
+            v = cmul(v, a.sign > 0 ? t : cconj(t));
+        }
         if (a.scale != 1.0) v = cscale(v, a.scale);
-        base[sh_base[g] + (int64_t)k * a.elem_stride] = v;
+        if (a.store_mode) {
+            const FftLineInfo& li = sh_li[g];
+            const int64_t off = (int64_t)k * es;
+            if (off <= li.dlim) {
+                v = cscale(v, a.dst_scale);
+                a.dst[li.dbase + off] = v;
+                const int col = li.dcol;
+                if (col < 4) {
+                    const double m2 = cabs2(v);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) if (c == col) cmx[c] = fmax(cmx[c], m2);
+                }
+            }
+        } else {
+            base[sh_base[g] + (int64_t)k * es] = v;
+        }
     };
+    if (!dload) {
+        // four elements per thread at a time: their first loads are issued together
+        constexpr int U = 4;
+        for (int i0 = threadIdx.x; i0 < tot; i0 += U * FFT_THREADS) {
+            FoldTerm f[U];
+            int gg[U], kk[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = min(i0 + u * FFT_THREADS, tot - 1);
+                int g, k;
+                if (!linefast) { g = fdiv(i, invL, L); k = i - g * L; } else { k = fdiv(i, invnl, nl); g = i - k * nl; }
+                gg[u] = g; kk[u] = k;
+                if (a.load_mode == 2)
+                    f[u] = fft_fold_first(a, sh_li[g], (int64_t)sh_in[g] * a.line_stride + (int64_t)k * es);
+                else
+                    f[u].acc = ld(g, k);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (i0 + u * FFT_THREADS < tot) {
+                    const double2 v = a.load_mode == 2 ? fft_fold_rest(a, sh_li[gg[u]], f[u]) : f[u].acc;
+                    if (nst == 0) st(gg[u], kk[u], v);
+                    else sm[lds_ix(gg[u] * L + kk[u])] = v;
+                }
+            }
+        }
+        __syncthreads();
+    } else if (nst == 0) {
+        for (int g = threadIdx.x; g < nl; g += FFT_THREADS) st(g, 0, ld(g, 0));
+    }
     int Ns = 1;
     for (int q = 0; q < nst; ++q) {
         const int R = a.pl.radix[q];
         const bool gin = (q == 0) && dload, gout = (q == nst - 1) && dstore;
         switch (R) {
             case 16: fft_stage<16>(sm, L, nl, Ns, a.sign, a.ltw, gin, gout, linefast, ld, st); break;
+            case 12: fft_stage<12>(sm, L, nl, Ns, a.sign, a.ltw, gin, gout, linefast, ld, st); break;
+            case 9: fft_stage<9>(sm, L, nl, Ns, a.sign, a.ltw, gin, gout, linefast, ld, st); break;
             case 8: fft_stage<8>(sm, L, nl, Ns, a.sign, a.ltw, gin, gout, linefast, ld, st); break;
+            case 6: fft_stage<6>(sm, L, nl, Ns, a.sign, a.ltw, gin, gout, linefast, ld, st); break;
             case 4: fft_stage<4>(sm, L, nl, Ns, a.sign, a.ltw, gin, gout, linefast, ld, st); break;
             case 2: fft_stage<2>(sm, L, nl, Ns, a.sign, a.ltw, gin, gout, linefast, ld, st); break;
             case 3: fft_stage<3>(sm, L, nl, Ns, a.sign, a.ltw, gin, gout, linefast, ld, st); break;
             default: fft_stage<5>(sm, L, nl, Ns, a.sign, a.ltw, gin, gout, linefast, ld, st); break;
         }
         Ns *= R;
-    }
-    if (!dstore) {
-        for (int i = threadIdx.x; i < tot; i += FFT_THREADS) {
-            int g, k;
-            if (!linefast) { g = fdiv(i, invL, L); k = i - g * L; } else { k = fdiv(i, invnl, nl); g = i - k * nl; }
-            double2 v = sm[lds_ix(g * L + k)];
-            if (a.post_L) v = cmul(v, twd(a.ptw, (int64_t)k * sh_in[g], a.sign));
-            if (a.scale != 1.0) v = cscale(v, a.scale);
-            const int64_t off = (int64_t)sh_in[g] * a.line_stride + (int64_t)k * a.elem_stride;
-            if (a.store_mode) fft_fused_store(a, s, sh_o[g], off, v, cmx);
-            else base[sh_base[g] + (int64_t)k * a.elem_stride] = v;
-        }
     }
     if (a.store_mode) {
 #pragma unroll
@@ -958,28 +1073,9 @@ __global__ __launch_bounds__(256) void k_leaf_build(const BuildArgs a) {
 }
 
 // ---------------------------------------------------------------- evaluation, Alg. 1 step 2
-// V[g][e][c][r] = sum_{i = r mod L, i <= deg} scale_col(e) B[e][i] w^{(o + c) i}
-// (twist by the coset offset and fold modulo the coset length L); an FFT of
-// length L then gives B_e at the nodes w^{o + c + j 2^{d+1}}, j < L.
-__global__ void k_twist_fold(const double2* __restrict__ B, int64_t b_stride, int64_t cp1, int C,
-                             const SlotMeta* __restrict__ meta, double2* __restrict__ V, int64_t v_stride,
-                             int64_t L, int64_t o, int64_t N, const double2* __restrict__ tw, int64_t Q) {
-    const int64_t g = blockIdx.z;
-    const int ec = blockIdx.y;            // e*2 + c
-    const int e = ec >> 1, c = ec & 1;
-    const int col = e % C;
-    const SlotMeta mt = meta[g];
-    const int dg = mt.deg[col];
-    const double sc = col < 4 ? pow2_inv_scale(mt.colmax_bits[col]) : 1.0;
-    const double2* src = B + g * b_stride + (int64_t)e * cp1;
-    const int64_t oc = o + c;
-    const int64_t twN = Q / N;
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < L; r += (int64_t)gridDim.x * blockDim.x) {
-        double2 acc = c2(0.0, 0.0);
-        for (int64_t i = r; i <= dg; i += L) acc = cfma(src[i], twq(tw, Q, (oc * i % N) * twN, +1), acc);
-        V[g * v_stride + (int64_t)ec * L + r] = cscale(acc, sc);
-    }
-}
+// The completed left child is evaluated at the nodes of its right sibling by
+// the batched FFT: its first pass reads each basis entry twisted by the coset
+// offset and folded modulo the coset length (FftArgs load mode 2).
 
 // phi <- phi B_L(sigma) for every condition of the right subtree
 // (Alg. 1 step 2, with Thm. 1 giving the data phi_k B_kappa(sigma_k)).
@@ -1022,9 +1118,15 @@ __global__ void k_eval_apply(double2* __restrict__ phi, int64_t phi_stride, cons
     }
 }
 
-// Small subtrees: direct evaluation (Horner) of the completed left child at
-// the nodes of its right sibling and the update phi <- phi B_L(sigma), one
-// workgroup per group, one thread per node (two conditions per node).
+// Direct evaluation of a completed left child at the nodes of its right
+// sibling subtree (small subtrees), updating the residual rows in place:
+// phi_c <- sum_row phi_row B[row][c](z) (+ phi_c for the constant columns).
+// One workgroup per group.  The column-scaled coefficients and the subtree's
+// residual rows are staged in LDS; each thread evaluates one (node, column)
+// item as four independent Horner chains (rows 0..3).  Groups whose degrees
+// exceed the LDS budget evaluate from global memory, one node per thread.
+constexpr int ED_LDS = 4608;       // complex elements of LDS staging
+
 template <int NR>
 __global__ __launch_bounds__(256) void k_eval_direct(double2* __restrict__ phi, int64_t phi_stride,
                                                      const double2* __restrict__ B, int64_t b_stride, int64_t cp1,
@@ -1032,17 +1134,63 @@ __global__ __launch_bounds__(256) void k_eval_direct(double2* __restrict__ phi, 
                                                      int64_t N, int64_t M, int p, int K,
                                                      const double2* __restrict__ tw, int64_t Q) {
     constexpr int C = 4 + NR;
+    __shared__ double2 sh[ED_LDS];
+    __shared__ int sdeg[C];
+    __shared__ double ssc[C];
     const int64_t g = blockIdx.x;
-    const SlotMeta mt = meta[g];
-    double sc[C];
-#pragma unroll
-    for (int c = 0; c < C; ++c) sc[c] = c < 4 ? pow2_inv_scale(mt.colmax_bits[c]) : 1.0;
+    if (threadIdx.x < C) {
+        const SlotMeta& mt = meta[g];
+        sdeg[threadIdx.x] = mt.deg[threadIdx.x];
+        ssc[threadIdx.x] = threadIdx.x < 4 ? pow2_inv_scale(mt.colmax_bits[threadIdx.x]) : 1.0;
+    }
+    __syncthreads();
     const double2* Bs = B + g * b_stride;
     double2* ph = phi + g * phi_stride;
     const int64_t nq = 2 * N;
-    const int64_t nodes = nleaves * K / 2;
-    for (int64_t u = threadIdx.x; u < nodes; u += blockDim.x) {
-        const int64_t q = t0 * K + 2 * u;           // the F condition; q + 1 is the G condition of the same node
+    const int nodes = (int)(nleaves * K / 2);
+    const int64_t qb = t0 * K;                       // first condition of the subtree
+    int dmax = -1;
+#pragma unroll
+    for (int c = 0; c < C; ++c) dmax = max(dmax, sdeg[c]);
+    const int bs = dmax + 1;                         // coefficient stride of an entry in LDS
+    const bool staged = 4 * C * max(bs, 0) + 2 * C * nodes <= ED_LDS;
+    if (staged) {
+        double2* shB = sh;                           // [4C][bs], entry row*C + col
+        double2* shF = sh + 4 * C * bs;              // [C][2*nodes] residual rows of the subtree
+        for (int w = threadIdx.x; w < 4 * C * bs; w += blockDim.x) {
+            const int e = w / bs, t = w - e * bs;
+            const int col = e % C;
+            shB[w] = t <= sdeg[col] ? cscale(Bs[(int64_t)e * cp1 + t], ssc[col]) : c2(0.0, 0.0);
+        }
+        for (int w = threadIdx.x; w < 2 * C * nodes; w += blockDim.x) {
+            const int c = w / (2 * nodes), h = w - c * 2 * nodes;
+            shF[w] = ph[c * nq + qb + h];
+        }
+        __syncthreads();
+        for (int w = threadIdx.x; w < C * nodes; w += blockDim.x) {
+            const int u = w / C, col = w - u * C;
+            const int64_t q = qb + 2 * u;            // the F condition; q + 1 is the G condition of the same node
+            const double2 z = cond_node(q, N, M, p, K, tw, Q);
+            const int dg = sdeg[col];
+            double2 acc[4] = {c2(0.0, 0.0), c2(0.0, 0.0), c2(0.0, 0.0), c2(0.0, 0.0)};
+            for (int k = dg; k >= 0; --k) {
+#pragma unroll
+                for (int row = 0; row < 4; ++row) acc[row] = cfma(acc[row], z, shB[(row * C + col) * bs + k]);
+            }
+            double2 o0 = col < 4 ? c2(0.0, 0.0) : shF[col * 2 * nodes + 2 * u];
+            double2 o1 = col < 4 ? c2(0.0, 0.0) : shF[col * 2 * nodes + 2 * u + 1];
+#pragma unroll
+            for (int row = 0; row < 4; ++row) {
+                o0 = cfma(shF[row * 2 * nodes + 2 * u], acc[row], o0);
+                o1 = cfma(shF[row * 2 * nodes + 2 * u + 1], acc[row], o1);
+            }
+            ph[col * nq + q] = o0;
+            ph[col * nq + q + 1] = o1;
+        }
+        return;
+    }
+    for (int u = threadIdx.x; u < nodes; u += blockDim.x) {
+        const int64_t q = qb + 2 * u;
         const double2 z = cond_node(q, N, M, p, K, tw, Q);
         double2 f0[C], f1[C], o0[C], o1[C];
 #pragma unroll
@@ -1053,13 +1201,13 @@ __global__ __launch_bounds__(256) void k_eval_direct(double2* __restrict__ phi, 
         }
 #pragma unroll
         for (int col = 0; col < C; ++col) {
-            const int dg = mt.deg[col];
+            const int dg = sdeg[col];
 #pragma unroll
             for (int row = 0; row < 4; ++row) {
                 const double2* src = Bs + (int64_t)(row * C + col) * cp1;
                 double2 acc = c2(0.0, 0.0);
                 for (int k = dg; k >= 0; --k) acc = cfma(acc, z, src[k]);
-                acc = cscale(acc, sc[col]);
+                acc = cscale(acc, ssc[col]);
                 o0[col] = cfma(f0[row], acc, o0[col]);
                 o1[col] = cfma(f1[row], acc, o1[col]);
             }
@@ -1072,57 +1220,138 @@ __global__ __launch_bounds__(256) void k_eval_direct(double2* __restrict__ phi, 
 // Small subtrees: direct block product [[B0L, VL],[0,I]] [[B0R, VR],[0,I]]
 // = [[B0L B0R, B0L VR + VL],[0,I]] by convolution of the coefficient
 // sequences, one workgroup per group; writes the parent basis, its degrees
-// and its column maxima.
+// and its column maxima.  The column-scaled B0L block and, one output column
+// at a time, the zero-padded rows 0..3 of that column of the right factor are
+// staged in LDS; each thread forms four consecutive output coefficients of
+// one entry from a sliding window of right-factor coefficients.  Groups whose
+// degrees exceed the LDS budget read the factors from global memory instead.
+constexpr int PD_LDS = 4096;       // complex elements of LDS staging
+constexpr int PD_PAD = 3;          // zero padding on each side of a right-factor entry
+
 __global__ __launch_bounds__(256) void k_prod_direct(const double2* __restrict__ BL, int64_t l_stride, int64_t lcp1,
                                                      const SlotMeta* __restrict__ mL,
                                                      const double2* __restrict__ BR, int64_t r_stride, int64_t rcp1,
                                                      const SlotMeta* __restrict__ mR,
                                                      double2* __restrict__ out, int64_t o_stride, int64_t ocp1,
                                                      SlotMeta* __restrict__ mO, SolveState* __restrict__ st, int C) {
+    __shared__ double2 sh[PD_LDS];
+    __shared__ double red[4][256];
+    __shared__ int sdl[MAXC], sdr[MAXC], sdout[MAXC];
+    __shared__ double ssl[MAXC], ssr[MAXC];
+    __shared__ int sbad;
     const int64_t g = blockIdx.x;
-    const SlotMeta a = mL[g], b = mR[g];
-    double sl[MAXC], sr[MAXC];
-    for (int c = 0; c < MAXC; ++c) {
-        sl[c] = c < 4 ? pow2_inv_scale(a.colmax_bits[c]) : 1.0;
-        sr[c] = c < 4 ? pow2_inv_scale(b.colmax_bits[c]) : 1.0;
+    if (threadIdx.x == 0) {
+        const SlotMeta a = mL[g], b = mR[g];
+        int dl = -1;
+        for (int l = 0; l < 4; ++l) dl = max(dl, a.deg[l]);
+        int bad = 0;
+        for (int j = 0; j < MAXC; ++j) {
+            ssl[j] = j < 4 ? pow2_inv_scale(a.colmax_bits[j]) : 1.0;
+            ssr[j] = j < 4 ? pow2_inv_scale(b.colmax_bits[j]) : 1.0;
+            sdl[j] = a.deg[j];
+            sdr[j] = b.deg[j];
+            int dj = -1;
+            if (j < C) {
+                dj = (b.deg[j] < 0 || dl < 0) ? -1 : dl + b.deg[j];
+                if (j >= 4) dj = max(dj, a.deg[j]);
+                if (dj >= ocp1) { bad = 1; dj = (int)ocp1 - 1; }
+            }
+            sdout[j] = dj;
+        }
+        sbad = bad;
     }
-    int dl = -1;
-    for (int l = 0; l < 4; ++l) dl = max(dl, a.deg[l]);
-    int dout[MAXC];
-    int bad = 0;
-    for (int j = 0; j < MAXC; ++j) dout[j] = -1;
-    for (int j = 0; j < C; ++j) {
-        int dj = (b.deg[j] < 0 || dl < 0) ? -1 : dl + b.deg[j];
-        if (j >= 4) dj = max(dj, a.deg[j]);
-        if (dj >= ocp1) { bad = 1; dj = (int)ocp1 - 1; }
-        dout[j] = dj;
-    }
+    __syncthreads();
+    int dl = -1, drm = -1;
+    for (int l = 0; l < 4; ++l) dl = max(dl, sdl[l]);
+    for (int j = 0; j < C; ++j) drm = max(drm, sdr[j]);
     const double2* L = BL + g * l_stride;
     const double2* R = BR + g * r_stride;
     double2* O = out + g * o_stride;
-    double cmx[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int j = 0; j < C; ++j) {
-        const int64_t cnt = 4 * (int64_t)(dout[j] + 1);
-        for (int64_t w = threadIdx.x; w < cnt; w += blockDim.x) {
-            const int i = (int)(w % 4);
-            const int k = (int)(w / 4);
-            double2 acc = c2(0.0, 0.0);
-            for (int l = 0; l < 4; ++l) {
-                const int dla = a.deg[l], dr = b.deg[j];
-                if (dla < 0 || dr < 0) continue;
-                const int t0 = max(0, k - dr), t1 = min(k, dla);
-                const double2* lp = L + (int64_t)(i * C + l) * lcp1;
-                const double2* rp = R + (int64_t)(l * C + j) * rcp1;
-                double2 part = c2(0.0, 0.0);
-                for (int t = t0; t <= t1; ++t) part = cfma(lp[t], rp[k - t], part);
-                acc = cfma(part, c2(sl[l] * sr[j], 0.0), acc);
-            }
-            if (j >= 4 && k <= a.deg[j]) acc = cadd(acc, L[(int64_t)(i * C + j) * lcp1 + k]);
-            O[(int64_t)(i * C + j) * ocp1 + k] = acc;
-            if (j < 4) cmx[j] = fmax(cmx[j], cabs2(acc));
+    // LDS staging: the B0 block of the left factor [16][ls] (entry i*4 + l), then
+    // one column j of the right factor at a time, rows 0..3 of length rs with
+    // PD_PAD zeros on both sides
+    const int ls = dl + 1, rs = drm + 1 + 2 * PD_PAD;
+    const bool staged = dl >= 0 && drm >= 0 && 16 * ls + 4 * rs <= PD_LDS;
+    double2* shL = sh;
+    double2* shR = sh + 16 * max(ls, 0);
+    if (staged) {
+        for (int w = threadIdx.x; w < 16 * ls; w += blockDim.x) {
+            const int e = w / ls, t = w - e * ls;
+            const int i = e >> 2, l = e & 3;
+            shL[w] = t <= sdl[l] ? cscale(L[(int64_t)(i * C + l) * lcp1 + t], ssl[l]) : c2(0.0, 0.0);
         }
     }
-    __shared__ double red[4][256];
+    double cmx[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < C; ++j) {
+        const int doj = sdout[j];
+        if (doj < 0) continue;
+        const int dr = sdr[j];
+        if (staged) {
+            __syncthreads();                         // previous column's readers are done
+            for (int w = threadIdx.x; w < 4 * rs; w += blockDim.x) {
+                const int l = w / rs, t = w - l * rs - PD_PAD;
+                shR[w] = (t >= 0 && t <= dr) ? cscale(R[(int64_t)(l * C + j) * rcp1 + t], ssr[j]) : c2(0.0, 0.0);
+            }
+            __syncthreads();
+        }
+        const int nblk = (doj + 4) / 4;              // blocks of four coefficients
+        for (int w = threadIdx.x; w < 4 * nblk; w += blockDim.x) {
+            const int i = w & 3;
+            const int k0 = (w >> 2) * 4;
+            double2 acc[4] = {c2(0.0, 0.0), c2(0.0, 0.0), c2(0.0, 0.0), c2(0.0, 0.0)};
+            if (staged) {
+                if (dr >= 0) {
+                    for (int l = 0; l < 4; ++l) {
+                        const int dla = sdl[l];
+                        if (dla < 0) continue;
+                        const int t0 = max(0, k0 - dr), t1 = min(dla, k0 + 3);
+                        if (t0 > t1) continue;
+                        const double2* lp = shL + (i * 4 + l) * ls;
+                        const double2* rp = shR + l * rs + PD_PAD + k0;   // rp[u - t] = R[k0 + u - t]
+                        // window win[u] = R[k0 + u - t], starting at t = t1, t decreasing
+                        double2 win[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) win[u] = rp[u - t1];
+                        for (int t = t1; t >= t0; --t) {
+                            const double2 lv = lp[t];
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) acc[u] = cfma(lv, win[u], acc[u]);
+                            if (t > t0) {
+#pragma unroll
+                                for (int u = 0; u < 3; ++u) win[u] = win[u + 1];
+                                win[3] = rp[4 - t];
+                            }
+                        }
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int k = k0 + u;
+                    for (int l = 0; l < 4; ++l) {
+                        const int dla = sdl[l];
+                        if (dla < 0 || dr < 0) continue;
+                        const int t0 = max(0, k - dr), t1 = min(k, dla);
+                        const double2* lp = L + (int64_t)(i * C + l) * lcp1;
+                        const double2* rp = R + (int64_t)(l * C + j) * rcp1;
+                        double2 part = c2(0.0, 0.0);
+                        for (int t = t0; t <= t1; ++t) part = cfma(lp[t], rp[k - t], part);
+                        acc[u] = cfma(part, c2(ssl[l] * ssr[j], 0.0), acc[u]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = k0 + u;
+                if (k > doj) break;
+                double2 v = acc[u];
+                if (j >= 4 && k <= sdl[j]) v = cadd(v, L[(int64_t)(i * C + j) * lcp1 + k]);
+                O[(int64_t)(i * C + j) * ocp1 + k] = v;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) if (c == j) cmx[c] = fmax(cmx[c], cabs2(v));
+            }
+        }
+    }
 #pragma unroll
     for (int c = 0; c < 4; ++c) red[c][threadIdx.x] = cmx[c];
     __syncthreads();
@@ -1134,37 +1363,25 @@ __global__ __launch_bounds__(256) void k_prod_direct(const double2* __restrict__
     }
     if (threadIdx.x == 0) {
         SlotMeta m;
-        for (int j = 0; j < MAXC; ++j) m.deg[j] = dout[j];
+        for (int j = 0; j < MAXC; ++j) m.deg[j] = sdout[j];
         for (int c = 0; c < 4; ++c) m.colmax_bits[c] = (unsigned long long)__double_as_longlong(sqrt(red[c][0]));
         mO[g] = m;
-        if (bad) atomicOr(&st[g].info, 2);
+        if (sbad) atomicOr(&st[g].info, 2);
     }
 }
 
 // ---------------------------------------------------------------- product, Alg. 1 step 4
-// Zero-padded, column-scaled copy of selected basis entries into FFT lines of length P.
-__global__ void k_prod_load(const double2* __restrict__ B, int64_t b_stride, int64_t cp1, int C,
-                            const SlotMeta* __restrict__ meta, const int* __restrict__ elist,
-                            double2* __restrict__ F, int64_t f_stride, int64_t P) {
-    const int64_t g = blockIdx.z;
-    const int li = blockIdx.y;
-    const int e = elist[li];
-    const int col = e % C;
-    const SlotMeta mt = meta[g];
-    const int dg = mt.deg[col];
-    const double sc = col < 4 ? pow2_inv_scale(mt.colmax_bits[col]) : 1.0;
-    const double2* src = B + g * b_stride + (int64_t)e * cp1;
-    double2* dst = F + g * f_stride + (int64_t)li * P;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < P; k += (int64_t)gridDim.x * blockDim.x)
-        dst[k] = k <= dg ? cscale(src[k], sc) : c2(0.0, 0.0);
-}
+// B = B_L B_R: the forward transforms read the zero-padded, column-scaled
+// basis entries (FftArgs load mode 1), the pointwise block product runs per
+// frequency, and the inverse transform writes the truncated, 1/P-scaled
+// entries into the destination slot (store mode 1).
 
 // Pointwise block product per frequency.  Full mode: FL and FR hold all 4C
 // entries (row-major, C columns); output all 4C entries.  Root mode: FL holds
 // row 0 (C entries), FR the columns 4..C-1 of rows 0..3 (4 NR entries, row-major);
 // output the NR solution polynomials (row 0, columns 4..C-1).
 template <int NR>
-__global__ void k_prod_mul(const double2* FL, const double2* __restrict__ FR,
+__global__ __launch_bounds__(64) void k_prod_mul(const double2* FL, const double2* __restrict__ FR,
                            double2* FO, int64_t f_stride, int64_t P, int root) {
     constexpr int C = 4 + NR;
     const int64_t g = blockIdx.y;
@@ -1188,18 +1405,23 @@ __global__ void k_prod_mul(const double2* FL, const double2* __restrict__ FR,
                 O[j * P + k] = acc;
             }
         } else {
-            double2 l[4][C], r[4][C];
+            // the right factor stays in registers; the left factor streams row by row
+            // (row i of the output overwrites only row i of the left factor, already read)
+            double2 r[4][C];
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < C; ++j) { l[i][j] = L[(i * C + j) * P + k]; r[i][j] = R[(i * C + j) * P + k]; }
+                for (int j = 0; j < C; ++j) r[i][j] = R[(i * C + j) * P + k];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
+                double2 l[C];
+#pragma unroll
+                for (int j = 0; j < C; ++j) l[j] = L[(i * C + j) * P + k];
 #pragma unroll
                 for (int j = 0; j < C; ++j) {
-                    double2 acc = (j >= 4) ? l[i][j] : c2(0.0, 0.0);
+                    double2 acc = (j >= 4) ? l[j] : c2(0.0, 0.0);
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) acc = cfma(l[i][t], r[t][j], acc);
+                    for (int t = 0; t < 4; ++t) acc = cfma(l[t], r[t][j], acc);
                     O[(i * C + j) * P + k] = acc;
                 }
             }
@@ -1252,55 +1474,41 @@ __global__ void k_prod_meta(const SlotMeta* __restrict__ mL, const SlotMeta* __r
     if (bad) atomicOr(&st[s].info, 2);
 }
 
-// Inverse-transformed product lines -> output slot (scale 1/P, truncate to
-// the degree bound) and column maxima of B0 (for the power-of-two column
-// normalization applied by the next consumer).
-__global__ void k_prod_store(const double2* __restrict__ FO, int64_t f_stride, int64_t P,
-                             double2* __restrict__ out, int64_t o_stride, int64_t cp1, int C,
-                             SlotMeta* __restrict__ meta, const int* __restrict__ elist) {
-    const int64_t g = blockIdx.z;
-    const int li = blockIdx.y;
-    const int e = elist[li];
-    const int col = e % C;
-    const int dg = meta[g].deg[col];
-    const double inv = 1.0 / (double)P;
-    const double2* src = FO + g * f_stride + (int64_t)li * P;
-    double2* dst = out + g * o_stride + (int64_t)e * cp1;
-    double mx = 0.0;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k <= dg && k < cp1; k += (int64_t)gridDim.x * blockDim.x) {
-        double2 v = cscale(src[k], inv);
-        dst[k] = v;
-        mx = fmax(mx, cabs2(v));
-    }
-    if (col < 4) {
-        mx = wave_max_d(mx);
-        if ((threadIdx.x & 63) == 0 && mx > 0.0)
-            atomicMax(&meta[g].colmax_bits[col], (unsigned long long)__double_as_longlong(sqrt(mx)));
-    }
-}
-
 // ---------------------------------------------------------------- extraction (Sec. 5)
 // x = B*_{1j} / B*_{5j} with j the tau-degree-0 column: the constant columns
 // are never pivoted, so for right-hand side r the solution column is 4 + r
 // with unit constant entry, and x_i = [z^i] V_{1r}.  Accumulates into xacc
 // (refinement adds the correction) and checks the final degrees {1,1,1,1,0..}.
-__global__ void k_extract(const SolveDesc* __restrict__ sd, int nr, SolveState* __restrict__ st,
+// x (or, when accumulating, the refinement correction added to x) from
+// the final basis, Sec. 5.  When accumulating, the squared norms of the
+// correction and of the updated x are added to nrm[2s], nrm[2s+1].
+__global__ __launch_bounds__(256) void k_extract(const SolveDesc* __restrict__ sd, int nr, SolveState* __restrict__ st,
                           const double2* __restrict__ B, int64_t b_stride, int64_t cp1,
                           const SlotMeta* __restrict__ meta, double2* __restrict__ xacc, int64_t x_stride,
-                          int accumulate) {
+                          int accumulate, double* __restrict__ nrm) {
     const int64_t s = blockIdx.y;
     const int64_t g = s / nr;
     const int r = (int)(s - g * nr);
     const SolveDesc d = sd[s];
-    const int C = 4 + nr;
     const int dg = meta[g].deg[4 + r];
     const double2* v1 = B + g * b_stride + (int64_t)(4 + r) * cp1;     // entry (row 0, column 4 + r)
+    double ndx = 0.0, nx = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < d.n; i += (int64_t)gridDim.x * blockDim.x) {
         double2 v = (i <= dg && i < cp1) ? v1[i] : c2(0.0, 0.0);
         if (!isfinite(v.x) || !isfinite(v.y)) atomicOr(&st[g].info, 3);
-        xacc[s * x_stride + i] = accumulate ? cadd(xacc[s * x_stride + i], v) : v;
+        if (accumulate) {
+            const double2 xn = cadd(xacc[s * x_stride + i], v);
+            ndx += cabs2(v);
+            nx += cabs2(xn);
+            xacc[s * x_stride + i] = xn;
+        } else {
+            xacc[s * x_stride + i] = v;
+        }
     }
-    (void)C;
+    if (accumulate) {
+        for (int o = 32; o > 0; o >>= 1) { ndx += __shfl_xor(ndx, o, 64); nx += __shfl_xor(nx, o, 64); }
+        if ((threadIdx.x & 63) == 0) { atomicAdd(&nrm[2 * s], ndx); atomicAdd(&nrm[2 * s + 1], nx); }
+    }
     if (r == 0 && blockIdx.x == 0 && threadIdx.x == 0) {
         for (int c = 0; c < 4; ++c)
             if (st[g].delta[c] != 1) atomicOr(&st[g].info, 1);
@@ -1387,6 +1595,66 @@ __global__ __launch_bounds__(256) void k_grad_lambda(const SolveDesc* __restrict
     if (threadIdx.x == 0) {
         *d.glam = -2.0 * d.lam * red[0];
         if (info) info[d.orig] = st[s / nr].info;
+    }
+}
+
+// Adaptive refinement (Sec. 7.2 mentions iterative refinement; the stopping
+// rule is ours).  After refinement step `it`, with rel = max over the group's
+// right-hand sides of ||dx|| / ||x||: the first step's rel is e0, an
+// estimate of the first solve's error; the error left after step it is
+// estimated as cfac * e0 * rel (refinement contracts the error by a factor
+// of about the first solve's relative error).  flags[g] = 1 asks for one
+// more step.
+__global__ void k_refine_decide(const double* __restrict__ nrm, int nr, SolveState* __restrict__ st, int ngroup,
+                                int first, double cfac, double tol, int32_t* __restrict__ flags) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ngroup) return;
+    double rel = 0.0;
+    for (int r = 0; r < nr; ++r) {
+        const double dx2 = nrm[2 * ((int64_t)g * nr + r)], x2 = nrm[2 * ((int64_t)g * nr + r) + 1];
+        if (x2 > 0.0) rel = fmax(rel, sqrt(dx2 / x2));
+        else if (dx2 > 0.0) rel = INFINITY;
+    }
+    if (first) st[g].e0 = rel;
+    const double est = cfac * st[g].e0 * rel;
+    flags[g] = (est > tol || !(est == est)) && st[g].info == 0 ? 1 : 0;
+}
+
+__global__ void k_zero_d(double* __restrict__ p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+// Exchange the refinement state of the group pairs (a, b) = pairs[y]: solve
+// descriptors, state, symbol, right-hand side and current solution.
+__global__ void k_swap_groups(SolveDesc* __restrict__ sd, SolveState* __restrict__ st, double2* __restrict__ chat,
+                              int64_t sN, double2* __restrict__ yv, double2* __restrict__ xacc, int64_t sn, int nr,
+                              const int2* __restrict__ pairs) {
+    const int2 pr = pairs[blockIdx.y];
+    const int64_t a = pr.x, b = pr.y;
+    const int64_t tot = sN + 2 * nr * sn;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+        double2 *pa, *pb;
+        if (i < sN) { pa = chat + a * sN + i; pb = chat + b * sN + i; }
+        else {
+            const int64_t j = i - sN, which = j / (nr * sn), rem = j - which * nr * sn;
+            double2* base = which == 0 ? yv : xacc;
+            pa = base + a * nr * sn + rem;
+            pb = base + b * nr * sn + rem;
+        }
+        const double2 t = *pa;
+        *pa = *pb;
+        *pb = t;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        for (int r = 0; r < nr; ++r) {
+            const SolveDesc t = sd[a * nr + r];
+            sd[a * nr + r] = sd[b * nr + r];
+            sd[b * nr + r] = t;
+        }
+        const SolveState t = st[a];
+        st[a] = st[b];
+        st[b] = t;
     }
 }
 

@@ -119,6 +119,43 @@ def test_batched_ragged(P):
     assert off == len(x)
 
 
+def test_adaptive_refinement_batched(P):
+    """Groups whose estimated error is still above the target after the
+    mandatory refinement step take more steps, after being exchanged to the
+    front of the batch; the others stop.  Over a lambda path (kappa from about
+    1 to 1e6) a sweep of targets flags ragged subsets; the number of extra
+    steps never grows as the target loosens, and every solve of every run
+    must match the oracle at its own output position."""
+    probs = [W.headline(i, n=1024, nrhs=2, nlam=8) for i in range(3)]
+    ms = [p.m for p in probs]
+    ns = [p.n for p in probs]
+    args = (ms, ns, dev(np.concatenate([p.col for p in probs])), dev(np.concatenate([p.row for p in probs])),
+            [l for p in probs for l in p.lams], 2, dev(np.concatenate([np.concatenate(p.b) for p in probs])))
+    nsolve = 3 * 8 * 2
+    ref = [oracle.solve(p.col, p.row, b, lam) for p in probs for lam in p.lams for b in p.b]
+    extras = []
+    for tol in (1e-10, 1e-16, 1e-20, 1e-24, 1e-28):
+        P.set_options(refine=1, refine_max=3, refine_tol=tol)
+        try:
+            x, info = P.solve_batched(*args)
+            torch.cuda.synchronize()
+            extra = P.get_stats()["refine_extra"]
+        finally:
+            P.set_options(refine=1, refine_max=3, refine_tol=1e-10)
+        x = x.cpu().numpy()
+        assert (info.cpu().numpy() == 0).all()
+        off = 0
+        for i, xr in enumerate(ref):
+            n = len(xr)
+            assert relerr(x[off:off + n], xr) <= TOL, (tol, i)
+            off += n
+        assert off == len(x)
+        extras.append(extra)
+    print("extra refinement steps per target:", extras)
+    assert all(a <= b for a, b in zip(extras, extras[1:])), extras
+    assert any(0 < e < 2 * nsolve for e in extras), extras
+
+
 def _ld_T(col, row, v):
     """T v in 80-bit long double (direct sums), for constructing exact right-hand sides."""
     col = np.asarray(col, np.longdouble); row = np.asarray(row, np.longdouble); v = np.asarray(v, np.longdouble)
