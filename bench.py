@@ -64,10 +64,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--nprob", type=int, default=64, help="problems per step (each 8 lambdas x 4 RHS)")
+    ap.add_argument("--nprob", type=int, default=256, help="problems per step (each 8 lambdas x 4 RHS)")
     ap.add_argument("--nlam", type=int, default=8)
     ap.add_argument("--nrhs", type=int, default=4)
     ap.add_argument("--n", type=int, default=2 ** 14)
+    ap.add_argument("--nlim", type=int, default=256, help="leaf cutoff N_lim (Alg. 2)")
     ap.add_argument("--plain-solves", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=1536, help="size of the CPU-oracle sample")
@@ -90,7 +91,7 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    P.set_options(n_lim=256, refine=1)
+    P.set_options(n_lim=args.nlim, refine=1)
 
     probs = [W.headline(i, n=args.n, nrhs=args.nrhs, nlam=args.nlam) for i in range(args.nprob)]
     ms = [p.m for p in probs]
@@ -215,7 +216,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "headline n=2^14, m=n+U{0..n/4}, envelope generators, 8 lambdas x 4 rhs",
                    "problems": args.nprob, "solves_per_step": nsolve, "n": args.n, "m": ms,
-                   "N": st["N"], "depth": st["depth"], "leaf_nodes": st["leaf_nodes"], "refine": 1},
+                   "N": st["N"], "depth": st["depth"], "leaf_nodes": st["leaf_nodes"], "n_lim": args.nlim, "refine": 1},
         "plain_solves_per_s": round(plain, 4) if plain else None,
         "batched_over_plain": round(value / plain, 2) if plain else None,
         "info_max": info_max,

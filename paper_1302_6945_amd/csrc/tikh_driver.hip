@@ -531,10 +531,8 @@ static int fft_lines(double2* data, int64_t S, int64_t sstride, int64_t nlines, 
 // ---------------------------------------------------------------- recursion (Alg. 1)
 template <int NR>
 static void launch_leaf(const Plan& pl, const LeafArgs& la, const BuildArgs& ba, int64_t G, int slots) {
-    if (pl.K <= 64) LAUNCH("leaf_loop", (k_leaf_loop<1, NR>), dim3((unsigned)G), dim3(64), la);
-    else if (pl.K <= 128) LAUNCH("leaf_loop", (k_leaf_loop<2, NR>), dim3((unsigned)G), dim3(64), la);
-    else if (pl.K <= 192) LAUNCH("leaf_loop", (k_leaf_loop<3, NR>), dim3((unsigned)G), dim3(64), la);
-    else LAUNCH("leaf_loop", (k_leaf_loop<4, NR>), dim3((unsigned)G), dim3(64), la);
+    const int waves = (pl.K + 63) / 64;           // one wavefront per 64 conditions (K <= 256)
+    LAUNCH("leaf_loop", k_leaf_loop<NR>, dim3((unsigned)G), dim3(64 * waves), la);
     if (slots <= 1) LAUNCH("leaf_build", (k_leaf_build<1, NR>), dim3((unsigned)G), dim3(256), ba);
     else if (slots <= 2) LAUNCH("leaf_build", (k_leaf_build<2, NR>), dim3((unsigned)G), dim3(256), ba);
     else if (slots <= 3) LAUNCH("leaf_build", (k_leaf_build<3, NR>), dim3((unsigned)G), dim3(256), ba);

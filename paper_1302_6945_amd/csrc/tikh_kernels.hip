@@ -768,8 +768,13 @@ __device__ __forceinline__ double2 cond_node(int64_t q, int64_t N, int64_t M, in
 }
 
 // ---------------------------------------------------------------- leaf: serial TanInt
-// The fast-only construction of Sec. 4.3 on one leaf's K conditions, one
-// wavefront per group, residuals in registers (R per lane).  Each step
+// The fast-only construction of Sec. 4.3 on one leaf's K conditions: one
+// workgroup per group with one wavefront per 64 conditions, residuals in
+// registers (one condition per lane).  Each wave finds its best candidate
+// with DPP reductions and leaves the key, residual row and node in LDS; after
+// one barrier every wave takes the overall best and updates its own
+// conditions (the LDS records alternate with the step parity, so a wave may
+// write step s+1 while another still reads step s).  Each step
 // processes one condition with the single-condition basis of eq. (spbasis):
 //   pivot column pi = the lowest tau-degree among columns 1..4 whose residual
 //   entry is not negligible (|r_i| > ZTOL max_j |r_j|), ties to the largest
@@ -838,76 +843,73 @@ __device__ __forceinline__ unsigned long long cand_key(int delta, double a2, int
     return (kd << 44) | (km << 10) | ((unsigned long long)piv << 8) | (unsigned long long)(255 - idx);
 }
 
-template <int R, int NR>
-__global__ __launch_bounds__(64) void k_leaf_loop(const LeafArgs a) {
+template <int NR>
+__global__ __launch_bounds__(256) void k_leaf_loop(const LeafArgs a) {
     constexpr int C = 4 + NR;
+    // per step parity and wave: the wave's best candidate key and its residual row and node
+    __shared__ unsigned long long skey[2][4];
+    __shared__ double2 srow[2][4][C + 1];
     const int64_t g = blockIdx.x;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int W = blockDim.x >> 6;
     const int K = a.K;
+    const int h = wv * 64 + lane;                    // condition of this lane within the leaf
     const int64_t nq = 2 * a.N;
     const int64_t q0 = (int64_t)a.leaf * K;
     double2* ph = a.phi + g * a.phi_stride;
     LeafRec* rec = a.rec + g * a.rec_stride;
-    double2 r[R][C];
-    double2 sg[R];
-    bool alive[R];
+    double2 r[C];
+    double2 sg = c2(0.0, 0.0);
+    bool alive = h < K;
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
-        int h = lane + 64 * i;
-        alive[i] = h < K;
-        if (alive[i]) {
-#pragma unroll
-            for (int c = 0; c < C; ++c) r[i][c] = ph[c * nq + q0 + h];
-            sg[i] = cond_node(q0 + h, a.N, a.M, a.p, K, a.tw, a.Q);
-        } else {
-#pragma unroll
-            for (int c = 0; c < C; ++c) r[i][c] = c2(0.0, 0.0);
-            sg[i] = c2(0.0, 0.0);
-        }
-    }
+    for (int c = 0; c < C; ++c) r[c] = alive ? ph[c * nq + q0 + h] : c2(0.0, 0.0);
+    if (alive) sg = cond_node(q0 + h, a.N, a.M, a.p, K, a.tw, a.Q);
     int dl[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) dl[c] = a.st[g].delta[c];
+    // keys of absent waves stay 0
+    if (threadIdx.x < 8 && (int)(threadIdx.x & 3) >= W) skey[threadIdx.x >> 2][threadIdx.x & 3] = 0ull;
+    __syncthreads();
     int info = 0;
     for (int step = 0; step < K; ++step) {
-        unsigned long long best = 0ull;
-#pragma unroll
-        for (int i = 0; i < R; ++i) {
-            if (!alive[i]) continue;
+        const int par = step & 1;
+        unsigned long long key = 0ull;
+        if (alive) {
             double a2[4];
             double amax = 0.0;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) { a2[c] = cabs2(r[i][c]); amax = fmax(amax, a2[c]); }
+            for (int c = 0; c < 4; ++c) { a2[c] = cabs2(r[c]); amax = fmax(amax, a2[c]); }
             const double thr = TIKH_ZTOL2 * amax;
-            int key = INT_MAX, piv = -1;
+            int kd = INT_MAX, piv = -1;
             double pm = -1.0;
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                if (a2[c] > thr && a2[c] > 0.0 && (dl[c] < key || (dl[c] == key && a2[c] > pm))) {
-                    key = dl[c]; piv = c; pm = a2[c];
+                if (a2[c] > thr && a2[c] > 0.0 && (dl[c] < kd || (dl[c] == kd && a2[c] > pm))) {
+                    kd = dl[c]; piv = c; pm = a2[c];
                 }
             }
-            if (piv >= 0) {
-                unsigned long long k = cand_key(key, pm, piv, i * 64 + lane);
-                best = k > best ? k : best;
-            }
+            if (piv >= 0) key = cand_key(kd, pm, piv, h);
         }
-        const unsigned long long wk = wave_max_u64(best);
-        if (wk == 0ull) { info = 1; break; }      // no admissible pivot: breakdown
-        const int idx = 255 - (int)(wk & 255ull);
-        const int piv = (int)((wk >> 8) & 3ull);
-        const int wl = idx & 63, si = idx >> 6;
+        const unsigned long long wk = wave_max_u64(key);
+        if (wk != 0ull && h == 255 - (int)(wk & 255ull)) {
+#pragma unroll
+            for (int c = 0; c < C; ++c) srow[par][wv][c] = r[c];
+            srow[par][wv][C] = sg;
+        }
+        if (lane == 0) skey[par][wv] = wk;
+        __syncthreads();
+        unsigned long long best = 0ull;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) { const unsigned long long t = skey[par][w]; best = t > best ? t : best; }
+        if (best == 0ull) { info = 1; break; }      // no admissible pivot: breakdown
+        const int idx = 255 - (int)(best & 255ull);
+        const int piv = (int)((best >> 8) & 3ull);
+        const int ww = idx >> 6;
         double2 rc[C];
-        double2 sc = c2(0.0, 0.0);
 #pragma unroll
-        for (int i = 0; i < R; ++i) {
-            if (i == si) {
-#pragma unroll
-                for (int c = 0; c < C; ++c) rc[c] = c2(readlane_d(r[i][c].x, wl), readlane_d(r[i][c].y, wl));
-                sc = c2(readlane_d(sg[i].x, wl), readlane_d(sg[i].y, wl));
-                if (lane == wl) alive[i] = false;
-            }
-        }
+        for (int c = 0; c < C; ++c) rc[c] = srow[par][ww][c];
+        const double2 sc = srow[par][ww][C];
+        if (h == idx) alive = false;
         double2 rp = rc[0];
 #pragma unroll
         for (int c = 1; c < 4; ++c) if (c == piv) rp = rc[c];
@@ -917,30 +919,37 @@ __global__ __launch_bounds__(64) void k_leaf_loop(const LeafArgs a) {
         double2 mu[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) mu[c] = (c == piv) ? c2(0.0, 0.0) : cmul(rc[c], inv);
-        if (lane == 0) {
+        if (threadIdx.x == 0) {
             LeafRec& o = rec[step];
 #pragma unroll
             for (int c = 0; c < C; ++c) o.mu[c] = mu[c];
             o.sig = sc;
             o.piv = piv;
-            o.q = (int)(q0 + si * 64 + wl);
+            o.q = (int)(q0 + idx);
         }
+        if (alive) {
+            double2 rpv;
+            switch (piv) {
+                case 0: rpv = r[0]; break;
+                case 1: rpv = r[1]; break;
+                case 2: rpv = r[2]; break;
+                default: rpv = r[3]; break;
+            }
+            // mu[piv] = 0 leaves the pivot column unchanged here
 #pragma unroll
-        for (int i = 0; i < R; ++i) {
-            if (!alive[i]) continue;
-            double2 rpv = r[i][0];
-#pragma unroll
-            for (int c = 1; c < 4; ++c) if (c == piv) rpv = r[i][c];
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                if (c == piv) r[i][c] = cmul(rpv, csub(sg[i], sc));
-                else r[i][c] = cfma(mu[c], rpv, r[i][c]);
+            for (int c = 0; c < C; ++c) r[c] = cfma(mu[c], rpv, r[c]);
+            const double2 np = cmul(rpv, csub(sg, sc));
+            switch (piv) {
+                case 0: r[0] = np; break;
+                case 1: r[1] = np; break;
+                case 2: r[2] = np; break;
+                default: r[3] = np; break;
             }
         }
 #pragma unroll
         for (int c = 0; c < 4; ++c) if (c == piv) dl[c] += 1;
     }
-    if (lane == 0) {
+    if (threadIdx.x == 0) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) a.st[g].delta[c] = dl[c];
         if (info) a.st[g].info |= info;
@@ -962,30 +971,10 @@ struct BuildArgs {
     int K;
 };
 
-template <int PIV, int S, int C>
-__device__ __forceinline__ void build_step(double2 (&P)[C][S], const double2 (&mu)[C], double2 sg, int active, int lane) {
+template <int S>
+__device__ __forceinline__ void pick_slots(double2 (&dst)[S], const double2 (&src)[S]) {
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
-        if (c == PIV) continue;
-        if (!cnonzero(mu[c])) continue;
-#pragma unroll
-        for (int sl = 0; sl < S; ++sl)
-            if (sl <= active) P[c][sl] = cfma(mu[c], P[PIV][sl], P[c][sl]);
-    }
-    double2 nv[S];
-#pragma unroll
-    for (int sl = 0; sl < S; ++sl) {
-        if (sl <= active + 1) {
-            double ux = wave_shr1_d(P[PIV][sl].x), uy = wave_shr1_d(P[PIV][sl].y);
-            if (sl > 0 && lane == 0) {
-                ux = readlane_d(P[PIV][sl - 1].x, 63);
-                uy = readlane_d(P[PIV][sl - 1].y, 63);
-            }
-            nv[sl] = csub(c2(ux, uy), cmul(sg, P[PIV][sl]));
-        }
-    }
-#pragma unroll
-    for (int sl = 0; sl < S; ++sl) if (sl <= active + 1) P[PIV][sl] = nv[sl];
+    for (int sl = 0; sl < S; ++sl) dst[sl] = src[sl];
 }
 
 template <int S, int NR>
@@ -1010,28 +999,62 @@ __global__ __launch_bounds__(256) void k_leaf_build(const BuildArgs a) {
     int deg[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) deg[c] = c < 4 ? 0 : -1;
-    int dmax = 0;
     const bool broken = a.st[g].info != 0;
     for (int step = 0; step < a.K && !broken; ++step) {
         const LeafRec& rr = lrec[step];
         const int piv = rr.piv;
         if (piv < 0) continue;
-        double2 mu[C];
+        double2 mu[C];                               // mu[piv] = 0
 #pragma unroll
         for (int c = 0; c < C; ++c) mu[c] = rr.mu[c];
         const double2 sg = rr.sig;
-        const int active = dmax >> 6;
+        int dp = deg[0];
+#pragma unroll
+        for (int c = 1; c < 4; ++c) if (c == piv) dp = deg[c];
+        // the pivot column (its coefficients beyond slot dp >> 6 are zero)
+        double2 pv[S];
         switch (piv) {
-            case 0: build_step<0, S, C>(P, mu, sg, active, lane); break;
-            case 1: build_step<1, S, C>(P, mu, sg, active, lane); break;
-            case 2: build_step<2, S, C>(P, mu, sg, active, lane); break;
-            default: build_step<3, S, C>(P, mu, sg, active, lane); break;
+            case 0: pick_slots<S>(pv, P[0]); break;
+            case 1: pick_slots<S>(pv, P[1]); break;
+            case 2: pick_slots<S>(pv, P[2]); break;
+            default: pick_slots<S>(pv, P[3]); break;
+        }
+        const int act = dp >> 6, act2 = (dp + 1) >> 6;
+        // B_:c += mu_c B_:pi for every column (unchanged for c = pi)
+#pragma unroll
+        for (int sl = 0; sl < S; ++sl) {
+            if (sl <= act) {
+#pragma unroll
+                for (int c = 0; c < C; ++c) P[c][sl] = cfma(mu[c], pv[sl], P[c][sl]);
+            }
+        }
+        // B_:pi *= (z - sigma): coefficient k becomes B[k-1] - sigma B[k]; the shift by
+        // one coefficient is a lane shift, with lane 63 of the previous slot entering lane 0
+        double2 nv[S];
+#pragma unroll
+        for (int sl = 0; sl < S; ++sl) {
+            if (sl <= act2) {
+                double ux = wave_shr1_d(pv[sl].x), uy = wave_shr1_d(pv[sl].y);
+                if (sl > 0 && lane == 0) {
+                    ux = readlane_d(pv[sl - 1].x, 63);
+                    uy = readlane_d(pv[sl - 1].y, 63);
+                }
+                nv[sl] = csub(c2(ux, uy), cmul(sg, pv[sl]));
+            } else {
+                nv[sl] = c2(0.0, 0.0);
+            }
+        }
+        switch (piv) {
+            case 0: pick_slots<S>(P[0], nv); break;
+            case 1: pick_slots<S>(P[1], nv); break;
+            case 2: pick_slots<S>(P[2], nv); break;
+            default: pick_slots<S>(P[3], nv); break;
         }
 #pragma unroll
         for (int c = 0; c < C; ++c)
-            if (c != piv && cnonzero(mu[c])) deg[c] = max(deg[c], deg[piv]);
-        deg[piv] += 1;
-        dmax = max(dmax, deg[piv]);
+            if (cnonzero(mu[c])) deg[c] = max(deg[c], dp);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) if (c == piv) deg[c] = dp + 1;
     }
     // column maxima of B0 over the 4 rows
     __shared__ double cm[4][4];
