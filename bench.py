@@ -71,7 +71,7 @@ def main():
     ap.add_argument("--nlim", type=int, default=256, help="leaf cutoff N_lim (Alg. 2)")
     ap.add_argument("--plain-solves", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-n", type=int, default=1536, help="size of the CPU-oracle sample")
+    ap.add_argument("--cpu-n", type=int, default=4096, help="size of the CPU-oracle sample (about 15 s on 16 cores)")
     ap.add_argument("--kernel", default="auto", help="kernel for the roofline object: fft, leaf_loop or auto "
                                                      "(the one with the larger share of the step)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
@@ -215,8 +215,9 @@ def main():
         "dtype": "c128",
         "data": "synthetic",
         "config": {"workload": "headline n=2^14, m=n+U{0..n/4}, envelope generators, 8 lambdas x 4 rhs",
-                   "problems": args.nprob, "solves_per_step": nsolve, "n": args.n, "m": ms,
+                   "problems": args.nprob, "solves_per_step": nsolve, "n": args.n, "m_range": [min(ms), max(ms)],
                    "N": st["N"], "depth": st["depth"], "leaf_nodes": st["leaf_nodes"], "n_lim": args.nlim, "refine": 1},
+        "n_log2n_sq_rate": round(value * args.n * math.log2(args.n) ** 2, 1),
         "plain_solves_per_s": round(plain, 4) if plain else None,
         "batched_over_plain": round(value / plain, 2) if plain else None,
         "info_max": info_max,

@@ -36,7 +36,8 @@
  * tikh_strerror() describes it.  On error the outputs are undefined.  The
  * numerical status of each solve is reported in an info word: 0 = OK,
  * 1 = breakdown (no admissible pivot / final tau-degrees not {1,1,1,1,0}),
- * 2 = a basis degree exceeded its storage bound, 3 = non-finite values.
+ * 2 = a basis degree exceeded its storage bound, 3 = non-finite values,
+ * 4 = more deferred difficult conditions than a solve can hold (bits may combine).
  * Single-problem calls synchronize the stream and return TIKH_ENUMERIC when
  * info != 0.  Calls are not thread safe (one host thread per library state).
  */
@@ -75,7 +76,11 @@ typedef struct {
     int32_t refine_max;   /* most refinement steps for a solve above the error target (0..4); default 3 */
     int32_t reserved0;
     double refine_tol;    /* target relative error of the adaptive steps (> 0, finite); default 1e-10 */
-    int32_t reserved[4];
+    double defer_tol;     /* difficult points (Sec. 5): a chosen condition whose pivot entry is below
+                             defer_tol times its largest entry among columns 1..4 is set aside and
+                             processed after the root, against the final basis (0 <= defer_tol < 1;
+                             0 = off, the default; at most 64 per solve, else info bit 4) */
+    int32_t reserved[2];
 } tikh_opts;
 
 /* Per-solve statistics of the last call (host memory, filled by tikh_get_stats). */
@@ -87,6 +92,7 @@ typedef struct {
     int64_t solves;       /* number of solves in the last call */
     int64_t launches;     /* kernel launches enqueued by the last call */
     int64_t refine_extra; /* refinement steps beyond `refine` taken by the last call, summed over solves */
+    int64_t deferred;     /* difficult conditions deferred by the last call, summed over groups and steps */
 } tikh_stats;
 
 /*

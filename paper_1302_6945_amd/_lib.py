@@ -20,13 +20,14 @@ _D = ctypes.c_double
 
 class _Opts(ctypes.Structure):
     _fields_ = [("n_lim", ctypes.c_int32), ("refine", ctypes.c_int32), ("refine_max", ctypes.c_int32),
-                ("reserved0", ctypes.c_int32), ("refine_tol", ctypes.c_double), ("reserved", ctypes.c_int32 * 4)]
+                ("reserved0", ctypes.c_int32), ("refine_tol", ctypes.c_double), ("defer_tol", ctypes.c_double),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class _Stats(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int64), ("k", ctypes.c_int64), ("depth", ctypes.c_int32),
                 ("leaf_nodes", ctypes.c_int32), ("solves", ctypes.c_int64), ("launches", ctypes.c_int64),
-                ("refine_extra", ctypes.c_int64)]
+                ("refine_extra", ctypes.c_int64), ("deferred", ctypes.c_int64)]
 
 
 def _sig(name, args, res=ctypes.c_int):
@@ -81,7 +82,7 @@ def _stream():
     lib.tikh_set_stream(ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
 
 
-def set_options(n_lim=None, refine=None, refine_max=None, refine_tol=None):
+def set_options(n_lim=None, refine=None, refine_max=None, refine_tol=None, defer_tol=None):
     """Leaf cutoff, refinement steps for every solve, most refinement steps for a solve whose
     estimated error is above the target (see tikh_opts in include/tikh.h)."""
     o = _Opts()
@@ -94,13 +95,16 @@ def set_options(n_lim=None, refine=None, refine_max=None, refine_tol=None):
         o.refine_max = int(refine_max)
     if refine_tol is not None:
         o.refine_tol = float(refine_tol)
+    if defer_tol is not None:
+        o.defer_tol = float(defer_tol)
     _check(lib.tikh_set_options(ctypes.byref(o)), "tikh_set_options")
 
 
 def get_options():
     o = _Opts()
     _check(lib.tikh_get_options(ctypes.byref(o)), "tikh_get_options")
-    return dict(n_lim=o.n_lim, refine=o.refine, refine_max=o.refine_max, refine_tol=o.refine_tol)
+    return dict(n_lim=o.n_lim, refine=o.refine, refine_max=o.refine_max, refine_tol=o.refine_tol,
+                defer_tol=o.defer_tol)
 
 
 def plan_info(m, n, n_lim=256):
@@ -128,7 +132,7 @@ def get_stats():
     s = _Stats()
     _check(lib.tikh_get_stats(ctypes.byref(s)), "tikh_get_stats")
     return dict(N=s.N, k=s.k, depth=s.depth, leaf_nodes=s.leaf_nodes, solves=s.solves, launches=s.launches,
-                refine_extra=s.refine_extra)
+                refine_extra=s.refine_extra, deferred=s.deferred)
 
 
 def _dev(t, dtype):

@@ -120,6 +120,7 @@ static void ensure_init() {
     g.opts.refine = 1;
     g.opts.refine_max = 3;
     g.opts.refine_tol = 1e-10;
+    g.opts.defer_tol = 0.0;
     if (hipMalloc((void**)&g.dneed, sizeof(int)) != hipSuccess) g.dneed = nullptr;
     if (hipHostMalloc((void**)&g.hneed, sizeof(int), hipHostMallocDefault) != hipSuccess) g.hneed = nullptr;
     g.init = true;
@@ -258,6 +259,10 @@ static double2* twiddles(int64_t Q) {
 // of the error left after a step.
 static const double REFINE_CFAC = 1000.0;
 
+// Deferred (difficult) conditions held per group and solve; more set info bit 4.
+static const int DEFER_CAP = 64;
+static bool defer_on() { return g.opts.defer_tol > 0.0; }
+
 // subtrees with at most this many conditions are merged by the direct kernels
 static const int64_t DIRECT_MAX_COND = 256;
 
@@ -290,7 +295,8 @@ static void make_layout(const Plan& pl, int nr, int64_t mmax, int64_t nmax, Layo
     L->Lmax = pl.p >= 1 ? pl.N / 4 : 1;
     L->sV = 2 * E * L->Lmax;
     int64_t fmax = 1;
-    for (int d = 0; d < pl.p; ++d) fmax = std::max(fmax, (d == 0 ? std::max<int64_t>(L->C, 4 * nr) : E) * pl.P[d]);
+    for (int d = 0; d < pl.p; ++d)
+        fmax = std::max(fmax, (d == 0 && !defer_on() ? std::max<int64_t>(L->C, 4 * nr) : E) * pl.P[d]);
     L->sF = fmax;
     L->sscr = std::max(L->sV, L->sF);
     size_t tot = 0;
@@ -313,7 +319,7 @@ static void make_layout(const Plan& pl, int nr, int64_t mmax, int64_t nmax, Layo
     }
     tot += L->sT;
     L->group_bytes = tot * sizeof(double2) + 2 * (pl.p + 1) * sizeof(SlotMeta) + sizeof(SolveState) + sizeof(double) +
-                     sizeof(int32_t) + sizeof(int2) + 256;
+                     sizeof(int32_t) + sizeof(int2) + DEFER_CAP * (sizeof(int32_t) + (1 + L->C) * sizeof(double2)) + 256;
     L->solve_bytes = (size_t)(4 * L->sN + 4 * L->sn) * sizeof(double2) + sizeof(SolveDesc) + 2 * sizeof(double) + 64;
     L->temp_bytes = (size_t)(L->sV + 2 * L->sF + L->sscr) * sizeof(double2);
 }
@@ -335,6 +341,7 @@ struct Bufs {
     // merge scratch shared by the groups of one merge chunk
     double2* V;
     double2 *FL, *FR, *scr;
+    DeferList dl;                    // deferred (difficult) conditions, [G][DEFER_CAP]
     double* nrm;                     // [2S] refinement norms (correction, solution)
     int32_t* flags;                  // [G] one more refinement step
     int2* pairs;                     // [G] group exchanges of the compaction
@@ -411,6 +418,11 @@ static int carve_bufs(const Plan& pl, const Layout& L, int64_t G, int64_t CH, Bu
     b->st = (SolveState*)carve(p, sizeof(SolveState) * G);
     b->rms = (double*)carve(p, sizeof(double) * G);
     b->elist = (int*)carve(p, sizeof(EList));
+    b->dl.cap = DEFER_CAP;
+    b->dl.C = L.C;
+    b->dl.q = (int32_t*)carve(p, sizeof(int32_t) * G * DEFER_CAP);
+    b->dl.node = (double2*)carve(p, sizeof(double2) * G * DEFER_CAP);
+    b->dl.res = (double2*)carve(p, sizeof(double2) * G * DEFER_CAP * L.C);
     b->nrm = (double*)carve(p, sizeof(double) * 2 * S);
     b->flags = (int32_t*)carve(p, sizeof(int32_t) * G);
     b->pairs = (int2*)carve(p, sizeof(int2) * G);
@@ -545,6 +557,8 @@ static int run_leaf(const Plan& pl, const Layout& L, const Bufs& b, int64_t G, i
     LeafArgs la{};
     la.sd = b.sd; la.st = b.st; la.phi = b.phi; la.phi_stride = L.sphi; la.rec = b.rec;
     la.rec_stride = pl.K; la.N = pl.N; la.M = pl.M; la.p = pl.p; la.K = pl.K; la.leaf = t; la.tw = tw; la.Q = pl.Q;
+    la.defer_tol2 = defer_on() ? g.opts.defer_tol * g.opts.defer_tol : 0.0;
+    la.dl = b.dl;
     BuildArgs ba{};
     ba.st = b.st; ba.rec = b.rec; ba.rec_stride = pl.K; ba.out = dst; ba.out_stride = dstride;
     ba.cap = dcap; ba.meta = dmeta; ba.K = pl.K;
@@ -609,10 +623,15 @@ static int run_product_chunk(const Plan& pl, const Layout& L, const Bufs& b, int
     }
     const int64_t cp1 = pl.cap[dc] + 1;
     const bool root = (dp == 0);
-    const int nL = root ? C : 4 * C, nR = root ? 4 * nr : 4 * C, nO = root ? nr : 4 * C;
+    // the root forms row 0 only: the solution columns, or every column when deferred
+    // conditions are still to be processed against it
+    const bool full_root = root && defer_on();
+    const int nL = root ? C : 4 * C, nR = root && !full_root ? 4 * nr : 4 * C, nO = root ? (full_root ? C : nr) : 4 * C;
     const int* eL = b.elist + (root ? offsetof(EList, row0) : offsetof(EList, all)) / sizeof(int);
-    const int* eR = b.elist + (root ? offsetof(EList, vcols) : offsetof(EList, all)) / sizeof(int);
-    const int* eO = b.elist + (root ? offsetof(EList, xout) : offsetof(EList, all)) / sizeof(int);
+    const int* eR = b.elist + (root && !full_root ? offsetof(EList, vcols) : offsetof(EList, all)) / sizeof(int);
+    const int* eO = b.elist + (root ? (full_root ? offsetof(EList, row0) : offsetof(EList, xout)) : offsetof(EList, all)) /
+                    sizeof(int);
+    const int pmode = full_root ? 2 : (root ? 1 : 0);
     hipLaunchKernelGGL(k_prod_meta, dim3((unsigned)((G + 63) / 64)), dim3(64), 0, g.stream, b.metaS[dc], b.metaT[dc],
                        dmeta, b.st, dcap, (int)G, C);
     g.launches += 1;
@@ -628,9 +647,9 @@ static int run_product_chunk(const Plan& pl, const Layout& L, const Bufs& b, int
     rc = fft_lines(b.FR, G, L.sF, nR, P, -1, tw, pl.Q, b.scr, L.sscr, FFT_FWD_T, &fr);
     if (rc) return rc;
     // the pointwise product reads every input of a frequency before writing, so it runs in place over FL
-    if (nr == 1) LAUNCH("prod_mul", k_prod_mul<1>, grid1(P, G, 64), dim3(64), b.FL, b.FR, b.FL, L.sF, P, root ? 1 : 0);
-    else if (nr == 2) LAUNCH("prod_mul", k_prod_mul<2>, grid1(P, G, 64), dim3(64), b.FL, b.FR, b.FL, L.sF, P, root ? 1 : 0);
-    else LAUNCH("prod_mul", k_prod_mul<4>, grid1(P, G, 64), dim3(64), b.FL, b.FR, b.FL, L.sF, P, root ? 1 : 0);
+    if (nr == 1) LAUNCH("prod_mul", k_prod_mul<1>, grid1(P, G, 64), dim3(64), b.FL, b.FR, b.FL, L.sF, P, pmode);
+    else if (nr == 2) LAUNCH("prod_mul", k_prod_mul<2>, grid1(P, G, 64), dim3(64), b.FL, b.FR, b.FL, L.sF, P, pmode);
+    else LAUNCH("prod_mul", k_prod_mul<4>, grid1(P, G, 64), dim3(64), b.FL, b.FR, b.FL, L.sF, P, pmode);
     // the inverse transform writes the truncated, 1/P-scaled coefficients into the destination slot
     FftArgs fo{};
     fo.store_mode = 1; fo.dst = dst; fo.dst_stride = dstride; fo.dst_cp1 = dcap + 1; fo.dst_meta = dmeta;
@@ -670,9 +689,22 @@ static int run_eval(const Plan& pl, const Layout& L, const Bufs& b, int64_t G, i
 }
 
 // dst / dmeta are given for group 0 with per-group stride dstride
-static int run_product(const Plan& pl, const Layout& L, const Bufs& b, int64_t G, int dp, double2* dst,
+static int run_product(const Plan& pl, const Layout& L, const Bufs& b, int64_t G, int dp, int64_t pidx, double2* dst,
                        int64_t dstride, SlotMeta* dmeta, int64_t dcap, const double2* tw) {
     const int dc = dp + 1;
+    if (defer_on()) {
+        // deferred conditions of this subtree: residuals with respect to the product (Sec. 5)
+        const int64_t nl = (int64_t)1 << (pl.p - dp), lo = pidx * nl, mid = lo + nl / 2, hi = lo + nl;
+        if (L.nr == 1)
+            LAUNCH("defer_update", k_defer_update<1>, dim3((unsigned)G), dim3(256), b.dl, b.st, b.metaS[dc],
+                   b.slotT[dc], L.sT, pl.cap[dc] + 1, b.metaT[dc], pl.K, lo, mid, hi);
+        else if (L.nr == 2)
+            LAUNCH("defer_update", k_defer_update<2>, dim3((unsigned)G), dim3(256), b.dl, b.st, b.metaS[dc],
+                   b.slotT[dc], L.sT, pl.cap[dc] + 1, b.metaT[dc], pl.K, lo, mid, hi);
+        else
+            LAUNCH("defer_update", k_defer_update<4>, dim3((unsigned)G), dim3(256), b.dl, b.st, b.metaS[dc],
+                   b.slotT[dc], L.sT, pl.cap[dc] + 1, b.metaT[dc], pl.K, lo, mid, hi);
+    }
     if (dp > 0 && dc == pl.p) {
         LAUNCH("prod_direct", k_prod_direct, dim3((unsigned)G), dim3(256), b.slotS[dc], L.sslot[dc], pl.cap[dc] + 1,
                b.metaS[dc], b.slotT[dc], L.sT, pl.cap[dc] + 1, b.metaT[dc], dst, dstride, dcap + 1, dmeta, b.st, L.C);
@@ -681,7 +713,7 @@ static int run_product(const Plan& pl, const Layout& L, const Bufs& b, int64_t G
     // the scratch pool is split for this level: FL and FR hold the largest
     // operand set at the level's bound on the product length
     Layout Ld = L;
-    const int64_t lines = dp == 0 ? std::max<int64_t>(L.C, 4 * L.nr) : 4 * L.C;
+    const int64_t lines = dp == 0 && !defer_on() ? std::max<int64_t>(L.C, 4 * L.nr) : 4 * L.C;
     Ld.sF = lines * pl.P[dp];
     const int64_t ch = std::max<int64_t>(1, std::min<int64_t>(G, b.pool_elems / (2 * Ld.sF)));
     for (int64_t c0 = 0; c0 < G; c0 += ch) {
@@ -722,7 +754,7 @@ static int run_recursion(const Plan& pl, const Layout& L, const Bufs& b, int64_t
             SlotMeta* pm;
             if (dp == 0 || (pidx & 1)) { pdst = b.slotT[dp]; pm = b.metaT[dp]; pstr = L.sT; }
             else { pdst = b.slotS[dp]; pm = b.metaS[dp]; pstr = L.sslot[dp]; }
-            rc = run_product(pl, L, b, G, dp, pdst, pstr, pm, pl.cap[dp], tw);
+            rc = run_product(pl, L, b, G, dp, pidx, pdst, pstr, pm, pl.cap[dp], tw);
             if (rc) return rc;
             d = dp;
             idx = pidx;
@@ -843,6 +875,23 @@ static int run_chunk(const Plan& pl, int nr, const std::vector<SolveDesc>& sds, 
         rc = run_recursion(pl, L, b, Ga, tw);
         if (rc) return rc;
         const int64_t xcp1 = pl.cap[0] + 1;
+        if (defer_on()) {
+            // deferred conditions, one step each on the final basis (Sec. 5)
+            if (nr == 1)
+                LAUNCH("defer_complete", k_defer_complete<1>, dim3((unsigned)Ga), dim3(256), b.dl, b.st, b.slotT[0],
+                       L.sT, xcp1, b.metaT[0]);
+            else if (nr == 2)
+                LAUNCH("defer_complete", k_defer_complete<2>, dim3((unsigned)Ga), dim3(256), b.dl, b.st, b.slotT[0],
+                       L.sT, xcp1, b.metaT[0]);
+            else
+                LAUNCH("defer_complete", k_defer_complete<4>, dim3((unsigned)Ga), dim3(256), b.dl, b.st, b.slotT[0],
+                       L.sT, xcp1, b.metaT[0]);
+            // count them for the statistics
+            std::vector<SolveState> hst((size_t)Ga);
+            HIPCHK(hipMemcpyAsync(hst.data(), b.st, sizeof(SolveState) * Ga, hipMemcpyDeviceToHost, g.stream));
+            HIPCHK(hipStreamSynchronize(g.stream));
+            for (const SolveState& x : hst) g.stats.deferred += x.ndef;
+        }
         hipLaunchKernelGGL(k_extract, grid1(nmax, Sa), dim3(256), 0, g.stream, b.sd, nr, b.st, b.slotT[0], L.sT,
                            xcp1, b.metaT[0], b.xacc, L.sn, it > 0 ? 1 : 0, b.nrm);
         g.launches++;
@@ -909,6 +958,7 @@ static int run_solves(std::vector<SolveDesc>& sds, int nr, int32_t* info) {
     ensure_init();
     g.launches = 0;
     g.stats.refine_extra = 0;
+    g.stats.deferred = 0;
     if (sds.empty()) return TIKH_OK;
     if (nr != 1 && nr != 2 && nr != 4) return TIKH_EINVAL;
     const int64_t G = (int64_t)sds.size() / nr;
@@ -1069,7 +1119,8 @@ int tikh_set_options(const tikh_opts* o) {
     ensure_init();
     if (!o) return TIKH_EINVAL;
     if (o->n_lim < 64 || o->n_lim > LEAF_MAX || o->refine < 0 || o->refine > 4 || o->refine_max < 0 ||
-        o->refine_max > 4 || !(o->refine_tol > 0.0) || !std::isfinite(o->refine_tol))
+        o->refine_max > 4 || !(o->refine_tol > 0.0) || !std::isfinite(o->refine_tol) || !(o->defer_tol >= 0.0) ||
+        !(o->defer_tol < 1.0))
         return TIKH_EINVAL;
     g.opts = *o;
     return TIKH_OK;

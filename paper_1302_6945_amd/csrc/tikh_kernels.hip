@@ -786,6 +786,17 @@ __device__ __forceinline__ double2 cond_node(int64_t q, int64_t N, int64_t M, in
 //   mu_i = -r_i / r_pi;  B_:i += mu_i B_:pi (i != pi);  B_:pi *= (z - sigma);
 //   remaining residuals r_i += mu_i r_pi,  r_pi *= (sigma_q - sigma);  delta_pi += 1.
 // The basis itself is formed afterwards from the step records (k_leaf_build).
+// Deferred (difficult) conditions of each group, Sec. 5: condition index,
+// node and residual row (C entries) with respect to the part of the basis
+// built so far; count in SolveState.ndef.
+struct DeferList {
+    int32_t* q;            // [G][cap]
+    double2* node;         // [G][cap]
+    double2* res;          // [G][cap][C]
+    int32_t cap;
+    int32_t C;
+};
+
 struct LeafArgs {
     const SolveDesc* sd;
     SolveState* st;
@@ -797,6 +808,10 @@ struct LeafArgs {
     int p, K, leaf;
     const double2* tw;
     int64_t Q;
+    // difficult points: a chosen condition whose pivot entry satisfies
+    // |r_pi|^2 < defer_tol2 max_{j<4} |r_j|^2 is deferred (0 disables)
+    double defer_tol2;
+    DeferList dl;
 };
 
 #define TIKH_ZTOL2 1e-22   // (1e-11)^2: relative size below which a residual entry counts as zero
@@ -861,6 +876,7 @@ __global__ __launch_bounds__(256) void k_leaf_loop(const LeafArgs a) {
     double2 r[C];
     double2 sg = c2(0.0, 0.0);
     bool alive = h < K;
+    bool passive = false;                            // deferred: updated, never chosen
 #pragma unroll
     for (int c = 0; c < C; ++c) r[c] = alive ? ph[c * nq + q0 + h] : c2(0.0, 0.0);
     if (alive) sg = cond_node(q0 + h, a.N, a.M, a.p, K, a.tw, a.Q);
@@ -909,10 +925,21 @@ __global__ __launch_bounds__(256) void k_leaf_loop(const LeafArgs a) {
 #pragma unroll
         for (int c = 0; c < C; ++c) rc[c] = srow[par][ww][c];
         const double2 sc = srow[par][ww][C];
-        if (h == idx) alive = false;
         double2 rp = rc[0];
 #pragma unroll
         for (int c = 1; c < 4; ++c) if (c == piv) rp = rc[c];
+        if (a.defer_tol2 > 0.0) {
+            double amax = 0.0;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) amax = fmax(amax, cabs2(rc[c]));
+            if (cabs2(rp) < a.defer_tol2 * amax) {
+                // difficult point: set aside for the end of the solve; no step is taken
+                if (h == idx) { alive = false; passive = true; }
+                if (threadIdx.x == 0) rec[step].piv = -1;
+                continue;
+            }
+        }
+        if (h == idx) alive = false;
         // -1 / r_pi
         const double den = 1.0 / cabs2(rp);
         const double2 inv = c2(-rp.x * den, rp.y * den);
@@ -927,7 +954,7 @@ __global__ __launch_bounds__(256) void k_leaf_loop(const LeafArgs a) {
             o.piv = piv;
             o.q = (int)(q0 + idx);
         }
-        if (alive) {
+        if (alive || passive) {
             double2 rpv;
             switch (piv) {
                 case 0: rpv = r[0]; break;
@@ -948,6 +975,29 @@ __global__ __launch_bounds__(256) void k_leaf_loop(const LeafArgs a) {
         }
 #pragma unroll
         for (int c = 0; c < 4; ++c) if (c == piv) dl[c] += 1;
+    }
+    if (a.defer_tol2 > 0.0) {
+        // append the deferred conditions of this leaf with their current residual rows
+        __shared__ int sh_nd;
+        if (threadIdx.x == 0) sh_nd = 0;
+        __syncthreads();
+        const int nd0 = a.st[g].ndef;
+        if (passive) {
+            const int pos = nd0 + atomicAdd(&sh_nd, 1);
+            if (pos < a.dl.cap) {
+                const int64_t e = g * a.dl.cap + pos;
+                a.dl.q[e] = (int32_t)(q0 + h);
+                a.dl.node[e] = sg;
+#pragma unroll
+                for (int c = 0; c < C; ++c) a.dl.res[e * C + c] = r[c];
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const int nd = nd0 + sh_nd;
+            a.st[g].ndef = min(nd, a.dl.cap);
+            if (nd > a.dl.cap) info |= 4;
+        }
     }
     if (threadIdx.x == 0) {
 #pragma unroll
@@ -1412,7 +1462,19 @@ __global__ __launch_bounds__(64) void k_prod_mul(const double2* FL, const double
     const double2* R = FR + g * f_stride;
     double2* O = FO + g * f_stride;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < P; k += (int64_t)gridDim.x * blockDim.x) {
-        if (root) {
+        if (root == 2) {
+            // row 0 of every column: FL = row 0 (C entries), FR = all 4C entries
+            double2 l[C];
+#pragma unroll
+            for (int j = 0; j < C; ++j) l[j] = L[j * P + k];
+#pragma unroll
+            for (int j = 0; j < C; ++j) {
+                double2 acc = (j >= 4) ? l[j] : c2(0.0, 0.0);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) acc = cfma(l[t], R[(t * C + j) * P + k], acc);
+                O[j * P + k] = acc;
+            }
+        } else if (root) {
             double2 l[C], r[4][NR];
 #pragma unroll
             for (int j = 0; j < C; ++j) l[j] = L[j * P + k];
@@ -1495,6 +1557,152 @@ __global__ void k_prod_meta(const SlotMeta* __restrict__ mL, const SlotMeta* __r
     for (int c = 0; c < 4; ++c) o.colmax_bits[c] = 0ull;
     mO[s] = o;
     if (bad) atomicOr(&st[s].info, 2);
+}
+
+// ---------------------------------------------------------------- difficult points (Sec. 5)
+// Before the product B = (B_L S_L)(B_R S_R) of the children of a subtree
+// (S = the power-of-two column scales its consumers apply), bring the
+// residual of every deferred condition of that subtree up to date: a
+// condition of the left child has seen B_L only, r <- (r S_L) B_R(z) S_R; one
+// of the right child has seen B_L S_L (through the evaluation) and B_R,
+// r <- r S_R.  Leaves [lo, mid) form the left child, [mid, hi) the right one.
+// One workgroup per group; one thread per (deferred condition, column).
+template <int NR>
+__global__ __launch_bounds__(256) void k_defer_update(DeferList dl, const SolveState* __restrict__ st,
+                                                      const SlotMeta* __restrict__ mL, const double2* __restrict__ BR,
+                                                      int64_t r_stride, int64_t rcp1, const SlotMeta* __restrict__ mR,
+                                                      int K, int64_t lo, int64_t mid, int64_t hi) {
+    constexpr int C = 4 + NR;
+    const int64_t g = blockIdx.x;
+    const int nd = st[g].ndef;
+    if (nd == 0) return;
+    __shared__ double2 sres[64][C];
+    __shared__ double sl[C], sr[C];
+    __shared__ int sdeg[C];
+    if (threadIdx.x < C) {
+        const int c = threadIdx.x;
+        sl[c] = c < 4 ? pow2_inv_scale(mL[g].colmax_bits[c]) : 1.0;
+        sr[c] = c < 4 ? pow2_inv_scale(mR[g].colmax_bits[c]) : 1.0;
+        sdeg[c] = mR[g].deg[c];
+    }
+    const int64_t e0 = g * dl.cap;
+    for (int w = threadIdx.x; w < nd * C; w += blockDim.x) sres[w / C][w % C] = dl.res[(e0 + w / C) * C + w % C];
+    __syncthreads();
+    const double2* Bs = BR + g * r_stride;
+    for (int w = threadIdx.x; w < nd * C; w += blockDim.x) {
+        const int j = w / C, c = w - j * C;
+        const int64_t t = dl.q[e0 + j] / K;
+        if (t < lo || t >= hi) continue;
+        double2 v;
+        if (t < mid) {
+            const double2 z = dl.node[e0 + j];
+            const int dg = sdeg[c];
+            double2 acc[4] = {c2(0.0, 0.0), c2(0.0, 0.0), c2(0.0, 0.0), c2(0.0, 0.0)};
+            for (int k = dg; k >= 0; --k) {
+#pragma unroll
+                for (int row = 0; row < 4; ++row) acc[row] = cfma(acc[row], z, Bs[(int64_t)(row * C + c) * rcp1 + k]);
+            }
+            v = c >= 4 ? cscale(sres[j][c], sl[c]) : c2(0.0, 0.0);
+#pragma unroll
+            for (int row = 0; row < 4; ++row) v = cfma(cscale(sres[j][row], sl[row]), acc[row], v);
+        } else {
+            v = sres[j][c];
+        }
+        dl.res[(e0 + j) * C + c] = cscale(v, sr[c]);
+    }
+}
+
+// After the root: each deferred condition, in order, takes one step of
+// eq. (spbasis) on the final basis (pivot rule as in the leaves), applied to
+// row 0 of every column (all that the solution needs), to the residuals of
+// the deferred conditions still waiting, and to the tau-degrees.  Row 0 of
+// the root basis is R[c][0..cap] with degrees in meta.  One workgroup per group.
+template <int NR>
+__global__ __launch_bounds__(256) void k_defer_complete(DeferList dl, SolveState* __restrict__ st,
+                                                        double2* __restrict__ R, int64_t r_stride, int64_t rcp1,
+                                                        SlotMeta* __restrict__ meta) {
+    constexpr int C = 4 + NR;
+    const int64_t g = blockIdx.x;
+    const int nd = st[g].ndef;
+    if (nd == 0 || st[g].info != 0) return;
+    __shared__ double2 sres[64][C];
+    __shared__ double2 snode[64];
+    __shared__ double2 smu[C];
+    __shared__ int sdeg[C], sdl[4], spiv;
+    const int64_t e0 = g * dl.cap;
+    for (int w = threadIdx.x; w < nd * C; w += blockDim.x) sres[w / C][w % C] = dl.res[(e0 + w / C) * C + w % C];
+    for (int w = threadIdx.x; w < nd; w += blockDim.x) snode[w] = dl.node[e0 + w];
+    if (threadIdx.x < C) sdeg[threadIdx.x] = meta[g].deg[threadIdx.x];
+    if (threadIdx.x < 4) sdl[threadIdx.x] = st[g].delta[threadIdx.x];
+    __syncthreads();
+    double2* Rg = R + g * r_stride;
+    int info = 0;
+    for (int j = 0; j < nd; ++j) {
+        if (threadIdx.x == 0) {
+            double a2[4], amax = 0.0;
+            for (int c = 0; c < 4; ++c) { a2[c] = cabs2(sres[j][c]); amax = fmax(amax, a2[c]); }
+            const double thr = TIKH_ZTOL2 * amax;
+            int kd = INT_MAX, piv = -1;
+            double pm = -1.0;
+            for (int c = 0; c < 4; ++c)
+                if (a2[c] > thr && a2[c] > 0.0 && (sdl[c] < kd || (sdl[c] == kd && a2[c] > pm))) { kd = sdl[c]; piv = c; pm = a2[c]; }
+            spiv = piv;
+            if (piv >= 0) {
+                const double2 rp = sres[j][piv];
+                const double den = 1.0 / cabs2(rp);
+                const double2 inv = c2(-rp.x * den, rp.y * den);
+                for (int c = 0; c < C; ++c) smu[c] = c == piv ? c2(0.0, 0.0) : cmul(sres[j][c], inv);
+            }
+        }
+        __syncthreads();
+        const int piv = spiv;
+        if (piv < 0) { info = 1; break; }
+        const double2 sg = snode[j];
+        const int dp = sdeg[piv];
+        if (dp + 1 >= rcp1) { info = 2; break; }
+        // row 0: B_c += mu_c B_pi (c != pi), then B_pi <- (z - sigma) B_pi, in chunks of
+        // blockDim coefficients from the top down (each chunk reads before it writes)
+        double2 mu[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) mu[c] = smu[c];
+        double2* Bp = Rg + (int64_t)piv * rcp1;
+        for (int k0 = ((dp + 1) / (int)blockDim.x) * (int)blockDim.x; k0 >= 0; k0 -= (int)blockDim.x) {
+            const int k = k0 + (int)threadIdx.x;
+            double2 cur = c2(0.0, 0.0), prv = c2(0.0, 0.0);
+            if (k <= dp + 1) {
+                cur = k <= dp ? Bp[k] : c2(0.0, 0.0);
+                prv = k >= 1 ? Bp[k - 1] : c2(0.0, 0.0);
+            }
+            __syncthreads();
+            if (k <= dp + 1) {
+                if (k <= dp) {
+#pragma unroll
+                    for (int c = 0; c < C; ++c)
+                        if (c != piv && cnonzero(mu[c])) Rg[(int64_t)c * rcp1 + k] = cfma(mu[c], cur, Rg[(int64_t)c * rcp1 + k]);
+                }
+                Bp[k] = csub(prv, cmul(sg, cur));
+            }
+            __syncthreads();
+        }
+        // the deferred conditions still waiting
+        for (int w = j + 1 + (int)threadIdx.x; w < nd; w += blockDim.x) {
+            const double2 rpv = sres[w][piv];
+#pragma unroll
+            for (int c = 0; c < C; ++c) if (c != piv) sres[w][c] = cfma(mu[c], rpv, sres[w][c]);
+            sres[w][piv] = cmul(rpv, csub(snode[w], sg));
+        }
+        if (threadIdx.x == 0) {
+            for (int c = 0; c < C; ++c) if (c != piv && cnonzero(mu[c])) sdeg[c] = max(sdeg[c], dp);
+            sdeg[piv] = dp + 1;
+            sdl[piv] += 1;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        for (int c = 0; c < C; ++c) meta[g].deg[c] = sdeg[c];
+        for (int c = 0; c < 4; ++c) st[g].delta[c] = sdl[c];
+        if (info) atomicOr(&st[g].info, info);
+    }
 }
 
 // ---------------------------------------------------------------- extraction (Sec. 5)
@@ -1691,6 +1899,7 @@ __global__ void k_init_state(const SolveDesc* __restrict__ sd, int nr, SolveStat
     st[g].delta[1] = -(int)(d.m - 1);
     st[g].delta[2] = -(int)(d.m + d.k - 2);
     st[g].delta[3] = -(int)(d.n + d.k - 2);
+    st[g].ndef = 0;
     if (!keep_info) st[g].info = 0;
 }
 

@@ -156,6 +156,43 @@ def test_adaptive_refinement_batched(P):
     assert any(0 < e < 2 * nsolve for e in extras), extras
 
 
+@pytest.mark.parametrize("defer_tol", [1e-3, 2e-3])
+@pytest.mark.parametrize("nlim", [64, 256])
+def test_difficult_points_deferred(P, defer_tol, nlim):
+    """Difficult points (Sec. 5): with a deferral threshold, chosen conditions
+    whose pivot entry is small relative to their row are set aside, carried
+    through the products, and processed after the root against the final
+    basis.  Headline-shaped problems (m - n spread, lambda path) have pivot
+    ratios down to about 1e-5; every solve must still match the oracle."""
+    pr = W.headline(0, n=512, nrhs=1, nlam=8)
+    rng = np.random.default_rng(11)
+    colc, rowc, bc = W.random_problem(rng, 300, 211, cplx=True, L=20.0)
+    cases = [(pr.col, pr.row, pr.b[0], pr.lams[j]) for j in (0, 3, 7)] + [(colc, rowc, bc, 0.05)]
+    P.set_options(n_lim=nlim, defer_tol=defer_tol)
+    try:
+        deferred = 0
+        for col, row, b, lam in cases:
+            x = P.solve(dev(col), dev(row), dev(b), lam).cpu().numpy()
+            deferred += P.get_stats()["deferred"]
+            assert relerr(x, oracle.solve(col, row, b, lam)) <= TOL, (len(col), len(row), lam)
+    finally:
+        P.set_options(n_lim=256, defer_tol=0.0)
+    assert deferred > 0
+
+
+def test_difficult_points_capacity(P):
+    """More deferred conditions than a solve holds is reported (info bit 4),
+    not silently dropped."""
+    rng = np.random.default_rng(5)
+    col, row, b = W.random_problem(rng, 300, 211, L=20.0)
+    P.set_options(n_lim=256, defer_tol=0.9)
+    try:
+        with pytest.raises(P.TikhError):
+            P.solve(dev(col), dev(row), dev(b), 0.2)
+    finally:
+        P.set_options(n_lim=256, defer_tol=0.0)
+
+
 def _ld_T(col, row, v):
     """T v in 80-bit long double (direct sums), for constructing exact right-hand sides."""
     col = np.asarray(col, np.longdouble); row = np.asarray(row, np.longdouble); v = np.asarray(v, np.longdouble)
