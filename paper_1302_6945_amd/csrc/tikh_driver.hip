@@ -976,7 +976,7 @@ static int run_solves(std::vector<SolveDesc>& sds, int nr, int32_t* info) {
     }
     size_t freeb = 0, totb = 0;
     (void)hipMemGetInfo(&freeb, &totb);
-    size_t budget = std::max<size_t>((size_t)1 << 30, (size_t)((double)(freeb + g.ws_size) * 0.6));
+    size_t budget = std::max<size_t>((size_t)1 << 30, (size_t)((double)(freeb + g.ws_size) * 0.85));
     for (auto& kv : buckets) {
         Plan pl;
         if (!make_plan(kv.first, shapes[kv.first].first, shapes[kv.first].second, &pl)) return TIKH_EINVAL;
@@ -985,11 +985,18 @@ static int run_solves(std::vector<SolveDesc>& sds, int nr, int32_t* info) {
         for (int64_t gi : idx) { mmax = std::max(mmax, sds[gi * nr].m); nmax = std::max(nmax, sds[gi * nr].n); }
         Layout L;
         make_layout(pl, nr, mmax, nmax, &L);
-        // merge scratch for up to 256 groups (at most a quarter of the budget), the rest held per group
-        int64_t mchunk = std::max<int64_t>(1, std::min<int64_t>(256, (int64_t)(budget / 4 / L.temp_bytes)));
+        // merge scratch for up to 128 groups at the largest level (at most a quarter of the
+        // budget; smaller levels fit more), the rest held per group
+        int64_t mchunk = std::max<int64_t>(1, std::min<int64_t>(128, (int64_t)(budget / 4 / L.temp_bytes)));
         const size_t per_group = L.group_bytes + (size_t)nr * L.solve_bytes;
         int64_t chunk = std::max<int64_t>(1, (int64_t)((budget - (size_t)mchunk * L.temp_bytes) / per_group));
         chunk = std::min<int64_t>(chunk, 65535);
+        // equal chunks: a small remainder chunk would repeat the whole serial recursion
+        // for a handful of groups
+        {
+            const int64_t nch = ((int64_t)idx.size() + chunk - 1) / chunk;
+            chunk = ((int64_t)idx.size() + nch - 1) / nch;
+        }
         for (size_t c0 = 0; c0 < idx.size(); c0 += (size_t)chunk) {
             size_t c1 = std::min(idx.size(), c0 + (size_t)chunk);
             std::vector<SolveDesc> part;
