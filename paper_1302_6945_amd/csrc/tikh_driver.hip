@@ -182,11 +182,13 @@ static bool make_plan(int64_t N, int64_t M, int p, Plan* pl) {
 }
 
 // Stages of an LDS transform of length L = 2^a 3^b 5^c <= 4096: radix 16
-// while possible, radix 9 per pair of threes, a single three merged with a
-// leftover 2 or 4 (radix 6 or 12), the remaining power of two as one stage,
-// then the fives.
-static bool fft_plan(int64_t L, FftPlanDev* f) {
-    if (L < 1 || L > FFT_LDS_MAX) return false;
+// while possible (radix 8 when the line fits the 2048-point kernel, which
+// holds at most 9 values per butterfly), radix 9 per pair of threes, a single
+// three merged with a leftover 2 or 4 (radix 6, or 12 in the large kernel),
+// the remaining power of two as one stage, then the fives.
+static const int FFT_SMALL_CAP = 2048;
+static bool fft_plan(int64_t L, FftPlanDev* f, bool small) {
+    if (L < 1 || L > (small ? FFT_SMALL_CAP : FFT_LDS_MAX)) return false;
     f->L = (int)L; f->nst = 0;
     int64_t v = L;
     int a = 0, b = 0, c = 0;
@@ -194,11 +196,15 @@ static bool fft_plan(int64_t L, FftPlanDev* f) {
     while (v % 3 == 0) { v /= 3; ++b; }
     while (v % 5 == 0) { v /= 5; ++c; }
     if (v != 1) return false;
-    while (a >= 4) { f->radix[f->nst++] = 16; a -= 4; }
+    if (small) {
+        while (a >= 3) { f->radix[f->nst++] = 8; a -= 3; }
+    } else {
+        while (a >= 4) { f->radix[f->nst++] = 16; a -= 4; }
+    }
     while (b >= 2) { f->radix[f->nst++] = 9; b -= 2; }
     if (b == 1) {
         if (a == 1) { f->radix[f->nst++] = 6; a = 0; }
-        else if (a == 2) { f->radix[f->nst++] = 12; a = 0; }
+        else if (a == 2 && !small) { f->radix[f->nst++] = 12; a = 0; }
         else f->radix[f->nst++] = 3;
     }
     if (a == 3) f->radix[f->nst++] = 8;
@@ -207,6 +213,7 @@ static bool fft_plan(int64_t L, FftPlanDev* f) {
     while (c-- > 0) f->radix[f->nst++] = 5;
     return true;
 }
+static bool fft_plan(int64_t L, FftPlanDev* f) { return fft_plan(L, f, false); }
 
 // Two-level table of e^{2 pi i x / M}: [x < 2^bits | (x >> bits) <= (M - 1) >> bits].
 static int tw2_bits(int64_t M) {
@@ -488,10 +495,13 @@ static void fft_pass(double2* data, int64_t S, int64_t sstride, int64_t nlines, 
     a.ltw = twiddles(L);              // per-length tables: contiguous twiddle reads
     a.ptw = post_L ? twiddles2(post_L, &a.pbits) : nullptr;
     if (a.load_mode == 2) a.ftw = twiddles2(a.fold_N, &a.fbits);
-    fft_plan(L, &a.pl);
+    // lines of at most 2048 points use the smaller kernel: twice the workgroups per CU
+    // outweigh its extra stage for some lengths (measured in the solver's fused passes)
+    const bool small = L <= FFT_SMALL_CAP;
+    fft_plan(L, &a.pl, small);
     a.nlines = nlines; a.lines_inner = lines_inner; a.line_stride = line_stride; a.outer_stride = outer_stride;
     a.elem_stride = elem_stride; a.post_L = post_L;
-    a.lpw = (int)std::max<int64_t>(1, std::min<int64_t>(FFT_LDS_MAX / L, lpw_cap));
+    a.lpw = (int)std::max<int64_t>(1, std::min<int64_t>((small ? FFT_SMALL_CAP : FFT_LDS_MAX) / L, lpw_cap));
     dim3 gr((unsigned)((nlines + a.lpw - 1) / a.lpw), (unsigned)S);
     // algorithmic traffic: every element of every line read once and written once
     prof_units("fft", 32.0 * (double)S * (double)nlines * (double)L);
@@ -501,7 +511,8 @@ static void fft_pass(double2* data, int64_t S, int64_t sstride, int64_t nlines, 
                  (long long)elem_stride, (long long)nlines, (long long)S, a.load_mode, a.store_mode, post_L ? 1 : 0);
         kprof.label = lab;
     }
-    LAUNCH("fft", k_fft, gr, dim3(FFT_THREADS), a);
+    if (small) LAUNCH("fft", k_fft<FFT_SMALL_CAP>, gr, dim3(FFT_THREADS), a);
+    else LAUNCH("fft", k_fft<FFT_LDS_MAX>, gr, dim3(FFT_THREADS), a);
 }
 
 // In-place FFT of `nlines` contiguous lines of length Lf per item (line

@@ -281,7 +281,6 @@ __device__ __forceinline__ void stage_twiddle(double2* v, const double2* __restr
 // LDS index with one padding element per 16: strided butterfly accesses of
 // 16-byte elements then fall on distinct banks.
 __device__ __forceinline__ int lds_ix(int i) { return i + (i >> 4); }
-constexpr int FFT_LDS_PAD = FFT_LDS_MAX + FFT_LDS_MAX / 16;
 
 struct FftPlanDev {
     int L;
@@ -295,10 +294,10 @@ struct FftPlanDev {
 // through `ld` (global memory) and the last writes through `st`; the stages
 // between go through LDS.  `linefast` maps consecutive threads to
 // consecutive lines (strided lines in global memory).
-template <int R, typename LD, typename ST>
+template <int R, int CAP, typename LD, typename ST>
 __device__ __forceinline__ void fft_stage(double2* sm, int L, int nl, int Ns, int sign, const double2* __restrict__ ltw, bool gin,
                           bool gout, bool linefast, LD& ld, ST& st) {
-    constexpr int MB = (FFT_LDS_MAX / R + FFT_THREADS - 1) / FFT_THREADS;
+    constexpr int MB = (CAP / R + FFT_THREADS - 1) / FFT_THREADS;
     const int per = L / R;
     const int nb = nl * per;
     const int tstep = L / (Ns * R);
@@ -349,7 +348,7 @@ __device__ __forceinline__ void fft_stage(double2* sm, int L, int nl, int Ns, in
 // Batched in-place FFT of lines held in global memory.
 // Line l of solve s starts at data + s*solve_stride + (l / lines_inner)*outer_stride
 // + (l % lines_inner)*line_stride; element k at + k*elem_stride.  lpw lines
-// per workgroup (lpw*L <= FFT_LDS_MAX).  Optional four-step twiddle: output
+// per workgroup (lpw*L <= the kernel's capacity).  Optional four-step twiddle: output
 // element j of line l multiplied by e^{sign 2 pi i j (l % lines_inner) / post_L}.
 //
 // The first pass of a transform can read its input directly from a stored
@@ -463,8 +462,11 @@ __device__ __forceinline__ double2 fft_fold_rest(const FftArgs& a, const FftLine
 // the last stage writes its outputs directly between registers and global
 // memory (plain lines, zero-padded slot entries, slot stores); the folded
 // evaluation input goes through one LDS prologue loop.
-__global__ __launch_bounds__(FFT_THREADS) void k_fft(const FftArgs a) {
-    __shared__ double2 sm[FFT_LDS_PAD];
+// CAP = points held by one workgroup: 4096 (radices up to 16) or 2048 (radices up
+// to 9: half the LDS and registers, so twice the workgroups per CU).
+template <int CAP>
+__global__ __launch_bounds__(FFT_THREADS, CAP <= 2048 ? 4 : 1) void k_fft(const FftArgs a) {
+    __shared__ double2 sm[CAP + CAP / 16];
     __shared__ int64_t sh_base[64];
     __shared__ int sh_in[64];
     __shared__ FftLineInfo sh_li[64];
@@ -553,17 +555,15 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft(const FftArgs a) {
     for (int q = 0; q < nst; ++q) {
         const int R = a.pl.radix[q];
         const bool gin = (q == 0) && dload, gout = (q == nst - 1) && dstore;
-        switch (R) {
-            case 16: fft_stage<16>(sm, L, nl, Ns, a.sign, a.ltw, gin, gout, linefast, ld, st); break;
-            case 12: fft_stage<12>(sm, L, nl, Ns, a.sign, a.ltw, gin, gout, linefast, ld, st); break;
-            case 9: fft_stage<9>(sm, L, nl, Ns, a.sign, a.ltw, gin, gout, linefast, ld, st); break;
-            case 8: fft_stage<8>(sm, L, nl, Ns, a.sign, a.ltw, gin, gout, linefast, ld, st); break;
-            case 6: fft_stage<6>(sm, L, nl, Ns, a.sign, a.ltw, gin, gout, linefast, ld, st); break;
-            case 4: fft_stage<4>(sm, L, nl, Ns, a.sign, a.ltw, gin, gout, linefast, ld, st); break;
-            case 2: fft_stage<2>(sm, L, nl, Ns, a.sign, a.ltw, gin, gout, linefast, ld, st); break;
-            case 3: fft_stage<3>(sm, L, nl, Ns, a.sign, a.ltw, gin, gout, linefast, ld, st); break;
-            default: fft_stage<5>(sm, L, nl, Ns, a.sign, a.ltw, gin, gout, linefast, ld, st); break;
-        }
+        if (CAP > 2048 && R == 16) fft_stage<16, CAP>(sm, L, nl, Ns, a.sign, a.ltw, gin, gout, linefast, ld, st);
+        else if (CAP > 2048 && R == 12) fft_stage<12, CAP>(sm, L, nl, Ns, a.sign, a.ltw, gin, gout, linefast, ld, st);
+        else if (R == 9) fft_stage<9, CAP>(sm, L, nl, Ns, a.sign, a.ltw, gin, gout, linefast, ld, st);
+        else if (R == 8) fft_stage<8, CAP>(sm, L, nl, Ns, a.sign, a.ltw, gin, gout, linefast, ld, st);
+        else if (R == 6) fft_stage<6, CAP>(sm, L, nl, Ns, a.sign, a.ltw, gin, gout, linefast, ld, st);
+        else if (R == 4) fft_stage<4, CAP>(sm, L, nl, Ns, a.sign, a.ltw, gin, gout, linefast, ld, st);
+        else if (R == 2) fft_stage<2, CAP>(sm, L, nl, Ns, a.sign, a.ltw, gin, gout, linefast, ld, st);
+        else if (R == 3) fft_stage<3, CAP>(sm, L, nl, Ns, a.sign, a.ltw, gin, gout, linefast, ld, st);
+        else fft_stage<5, CAP>(sm, L, nl, Ns, a.sign, a.ltw, gin, gout, linefast, ld, st);
         Ns *= R;
     }
     if (a.store_mode) {
