@@ -68,7 +68,9 @@ def main():
     ap.add_argument("--nlam", type=int, default=8)
     ap.add_argument("--nrhs", type=int, default=4)
     ap.add_argument("--n", type=int, default=2 ** 14)
-    ap.add_argument("--nlim", type=int, default=256, help="leaf cutoff N_lim (Alg. 2)")
+    ap.add_argument("--nlim", default="auto",
+                    help="leaf cutoff N_lim (Alg. 2), or 'auto': picked by the library's autotuner on 256 groups "
+                         "of the workload's shape before the timed steps")
     ap.add_argument("--plain-solves", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=4096, help="size of the CPU-oracle sample (about 15 s on 16 cores)")
@@ -91,10 +93,16 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    P.set_options(n_lim=args.nlim, refine=1)
-
     probs = [W.headline(i, n=args.n, nrhs=args.nrhs, nlam=args.nlam) for i in range(args.nprob)]
     ms = [p.m for p in probs]
+    tune = None
+    if args.nlim == "auto":
+        P.set_options(refine=1)
+        nlim, tune_ms = P.autotune_nlim(int(round(float(np.mean(ms)))), args.n, groups=256, nrhs=args.nrhs)
+        tune = {str(k): round(v, 1) for k, v in tune_ms.items()}
+    else:
+        nlim = int(args.nlim)
+    P.set_options(n_lim=nlim, refine=1)
     ns = [p.n for p in probs]
     lams = [l for p in probs for l in p.lams]
     col = torch.tensor(np.concatenate([p.col for p in probs]), device=dev)
@@ -216,7 +224,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "headline n=2^14, m=n+U{0..n/4}, envelope generators, 8 lambdas x 4 rhs",
                    "problems": args.nprob, "solves_per_step": nsolve, "n": args.n, "m_range": [min(ms), max(ms)],
-                   "N": st["N"], "depth": st["depth"], "leaf_nodes": st["leaf_nodes"], "n_lim": args.nlim, "refine": 1},
+                   "N": st["N"], "depth": st["depth"], "leaf_nodes": st["leaf_nodes"], "n_lim": nlim, "n_lim_autotune_ms": tune, "refine": 1},
         "n_log2n_sq_rate": round(value * args.n * math.log2(args.n) ** 2, 1),
         "plain_solves_per_s": round(plain, 4) if plain else None,
         "batched_over_plain": round(value / plain, 2) if plain else None,

@@ -130,6 +130,19 @@ int tikh_profile_units(double* units);
  */
 int tikh_fft_batched(void* data, int64_t items, int64_t nlines, int64_t len, int sign);
 
+/*
+ * Autotuner for the leaf cutoff N_lim of Alg. 2, which the paper calls
+ * machine-dependent (Sec. 6.2): times one batched forward solve of `groups`
+ * groups of min(nrhs, 4) right-hand sides of an m x n real problem (synthetic
+ * data generated on the device: generator with an exp(-|s|/32) envelope,
+ * uniform right-hand sides, lambda = 1e-2 sum_s |a_s|) for each N_lim in
+ * {64, 128, 192, 256}, keeps the fastest in the options and returns it in
+ * *best (host).  ms (host, may be NULL) receives the four times in
+ * milliseconds (-1 for a cutoff that does not apply).  Allocates and frees
+ * device memory; synchronizes.  groups <= 65535, 1 <= nrhs <= 4.
+ */
+int tikh_autotune_nlim(int64_t m, int64_t n, int64_t groups, int32_t nrhs, int32_t* best, double* ms);
+
 /* Library state.  tikh_init is optional (the first call initializes). */
 int tikh_init(void);
 int tikh_release(void);                              /* free workspace */

@@ -9,7 +9,7 @@ CPU fallback: importing this package raises if the library is missing.
 Paper: Turnes, Balcan, Romberg, "Superfast Tikhonov Regularization of Toeplitz
 Systems" (Sec. 2 eq. (tik)/(tiksol) with L = lambda I).
 """
-from ._lib import (TikhError, lib, library_path, set_options, get_options, get_stats, plan_info, fft_batched,
+from ._lib import (TikhError, lib, library_path, set_options, get_options, get_stats, plan_info, fft_batched, autotune_nlim,
                    profile_kernel, profile_read,
                    tikh_toeplitz_solve, tikh_toeplitz_solve_z, tikh_toeplitz_solve_normal,
                    tikh_toeplitz_solve_normal_z, tikh_toeplitz_solve_batched,
@@ -18,7 +18,7 @@ from ._lib import (TikhError, lib, library_path, set_options, get_options, get_s
                    backward, backward_batched)
 from .autograd import ToeplitzTikhonov, tikhonov_solve
 
-__all__ = ["TikhError", "lib", "library_path", "set_options", "get_options", "get_stats", "plan_info", "fft_batched", "profile_kernel", "profile_read",
+__all__ = ["TikhError", "lib", "library_path", "set_options", "get_options", "get_stats", "plan_info", "fft_batched", "autotune_nlim", "profile_kernel", "profile_read",
            "tikh_toeplitz_solve", "tikh_toeplitz_solve_z", "tikh_toeplitz_solve_normal",
            "tikh_toeplitz_solve_normal_z", "tikh_toeplitz_solve_batched",
            "tikh_toeplitz_solve_backward", "tikh_toeplitz_solve_backward_z",

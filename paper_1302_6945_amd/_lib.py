@@ -43,6 +43,8 @@ tikh_plan_info = _sig("tikh_plan_info", [_I64, _I64, ctypes.c_int32, ctypes.POIN
                                          ctypes.POINTER(ctypes.c_int64)])
 _sig("tikh_release", [])
 tikh_fft_batched = _sig("tikh_fft_batched", [_P, _I64, _I64, _I64, ctypes.c_int])
+tikh_autotune_nlim = _sig("tikh_autotune_nlim", [_I64, _I64, _I64, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                                 ctypes.POINTER(ctypes.c_double)])
 _sig("tikh_profile_kernel", [ctypes.c_char_p])
 _sig("tikh_profile_read", [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)])
 _sig("tikh_profile_units", [ctypes.POINTER(ctypes.c_double)])
@@ -161,6 +163,16 @@ def fft_batched(x, sign=-1):
     _stream()
     _check(tikh_fft_batched(_ptr(x), x.shape[0], x.shape[1], x.shape[2], int(sign)), "tikh_fft_batched")
     return x
+
+
+def autotune_nlim(m, n, groups=64, nrhs=4):
+    """Time one batched solve of an m x n synthetic problem for each leaf cutoff in
+    (64, 128, 192, 256), keep the fastest in the options; returns (best, {cutoff: ms})."""
+    _stream()
+    best = ctypes.c_int32()
+    ms = (ctypes.c_double * 4)()
+    _check(tikh_autotune_nlim(int(m), int(n), int(groups), int(nrhs), ctypes.byref(best), ms), "tikh_autotune_nlim")
+    return best.value, {c: ms[i] for i, c in enumerate((64, 128, 192, 256)) if ms[i] >= 0}
 
 
 def solve(col, row, b, lam):

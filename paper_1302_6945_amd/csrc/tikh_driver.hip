@@ -1122,6 +1122,80 @@ int tikh_fft_batched(void* data, int64_t items, int64_t nlines, int64_t len, int
     return hipGetLastError() == hipSuccess ? TIKH_OK : TIKH_EHIP;
 }
 
+int tikh_autotune_nlim(int64_t m, int64_t n, int64_t groups, int32_t nrhs, int32_t* best, double* ms) {
+    ensure_init();
+    if (m < 1 || n < 1 || groups < 1 || groups > 65535 || nrhs < 1 || nrhs > MAXNR || !best) return TIKH_EINVAL;
+    const int nr = group_size(nrhs);
+    // synthetic real problem: generator with an exp(-|s|/32) envelope about the main
+    // diagonal, uniform right-hand sides, lambda = 1e-2 sum |a_s| (so kappa <= 1e4)
+    double *col = nullptr, *row = nullptr, *bb = nullptr, *xx = nullptr;
+    const int64_t nx = groups * nr * n;
+    if (hipMalloc(&col, sizeof(double) * (m + n)) != hipSuccess) return TIKH_ENOMEM;
+    row = col + m;
+    if (hipMalloc(&bb, sizeof(double) * nr * m) != hipSuccess) { (void)hipFree(col); return TIKH_ENOMEM; }
+    if (hipMalloc(&xx, sizeof(double) * nx) != hipSuccess) { (void)hipFree(col); (void)hipFree(bb); return TIKH_ENOMEM; }
+    hipLaunchKernelGGL(k_synth, grid1(m, 1), dim3(256), 0, g.stream, col, m, 1ull, (int64_t)0, 32.0);
+    hipLaunchKernelGGL(k_synth, grid1(n, 1), dim3(256), 0, g.stream, row, n, 2ull, (int64_t)0, 32.0);
+    hipLaunchKernelGGL(k_synth, grid1(nr * m, 1), dim3(256), 0, g.stream, bb, nr * m, 3ull, (int64_t)0, 0.0);
+    std::vector<double> hc(m + n);
+    int rc = TIKH_OK;
+    if (hipMemcpyAsync(hc.data(), col, sizeof(double) * (m + n), hipMemcpyDeviceToHost, g.stream) != hipSuccess ||
+        hipStreamSynchronize(g.stream) != hipSuccess)
+        rc = TIKH_EHIP;
+    double asum = 0.0;
+    for (int64_t i = 0; i < m + n; ++i) asum += std::fabs(hc[i]) * (i == m ? 0.0 : 1.0);   // row[0] unused
+    std::vector<SolveDesc> sds;
+    for (int64_t gi = 0; gi < groups; ++gi)
+        for (int r = 0; r < nr; ++r) {
+            SolveDesc d{};
+            d.col = col; d.row = row; d.m = m; d.n = n; d.lam = 1e-2 * asum; d.cplx = 0; d.mode = 0;
+            d.rhs = bb + (int64_t)r * m;
+            d.x = xx + (gi * nr + r) * n;
+            d.orig = -1;
+            sds.push_back(d);
+        }
+    const tikh_opts saved = g.opts;
+    const int32_t cand[4] = {64, 128, 192, 256};
+    double best_ms = 0.0;
+    int32_t best_n = 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (rc == TIKH_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) rc = TIKH_EHIP;
+    for (int c = 0; c < 4 && rc == TIKH_OK; ++c) {
+        double t = -1.0;
+        int64_t NN, MM;
+        int pp;
+        if (opt_extend(m + n - 1, cand[c], &NN, &MM, &pp) && NN <= ((int64_t)1 << 19)) {
+            g.opts.n_lim = cand[c];
+            std::vector<SolveDesc> w = sds;
+            rc = run_solves(w, nr, nullptr);                      // warm-up (workspace, tables)
+            if (rc) break;
+            w = sds;
+            (void)hipEventRecord(e0, g.stream);
+            rc = run_solves(w, nr, nullptr);
+            if (rc) break;
+            (void)hipEventRecord(e1, g.stream);
+            if (hipEventSynchronize(e1) != hipSuccess) { rc = TIKH_EHIP; break; }
+            float f = 0.f;
+            (void)hipEventElapsedTime(&f, e0, e1);
+            t = f;
+            if (best_n == 0 || t < best_ms) { best_ms = t; best_n = cand[c]; }
+        }
+        if (ms) ms[c] = t;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(g.stream);
+    (void)hipFree(col);
+    (void)hipFree(bb);
+    (void)hipFree(xx);
+    g.opts = saved;
+    if (rc) return rc;
+    if (best_n == 0) return TIKH_EINVAL;
+    g.opts.n_lim = best_n;
+    *best = best_n;
+    return TIKH_OK;
+}
+
 int tikh_release(void) {
     if (g.ws) { hipStreamSynchronize(g.stream); hipFree(g.ws); g.ws = nullptr; g.ws_size = 0; }
     for (auto& kv : g.tw) (void)hipFree(kv.second);

@@ -629,6 +629,16 @@ __device__ __forceinline__ double hash_unit(uint64_t x) {
     return (double)(x >> 11) * (2.0 / 9007199254740992.0) - 1.0;
 }
 
+// Synthetic real data for timing runs: out[i] = u_i e^{-|i - center| / decay}
+// (decay <= 0: no envelope), u_i uniform in [-1, 1) from a hash of (seed, i).
+__global__ void k_synth(double* __restrict__ out, int64_t count, uint64_t seed, int64_t center, double decay) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+        double v = hash_unit(seed * 0x9E3779B97F4A7C15ull + (uint64_t)i);
+        if (decay > 0.0) v *= exp(-fabs((double)(i - center)) / decay);
+        out[i] = v;
+    }
+}
+
 // First column of the k-circulant extension (eq. (circexp)) per group:
 // c_T[r] = a_{r-(n+k-1)} for r >= k; r < k are the arbitrary entries a_{-n-k+1..-n}.
 __global__ void k_build_ct(const SolveDesc* __restrict__ sd, int nr, const double* __restrict__ rms,

@@ -276,3 +276,21 @@ def test_batched_rhs_groups(P, nrhs, cplx):
                 assert relerr(x[off:off + n], oracle.solve(col, row, b, lam)) <= TOL
                 off += n
     assert off == len(x)
+
+
+def test_autotune_nlim(P):
+    """The leaf-cutoff autotuner times the candidates on synthetic data, keeps the
+    fastest in the options, and solves stay correct under the chosen cutoff."""
+    try:
+        best, ms = P.autotune_nlim(384, 256, groups=8, nrhs=2)
+        assert best in (64, 128, 192, 256)
+        assert best in ms and all(v > 0 for v in ms.values())
+        assert ms[best] == min(ms.values())
+        assert P.get_options()["n_lim"] == best
+        pr = W.config0()
+        x = P.solve(dev(pr.col), dev(pr.row), dev(pr.b[0]), pr.lams[0]).cpu().numpy()
+        assert relerr(x, oracle.solve(pr.col, pr.row, pr.b[0], pr.lams[0])) <= TOL
+    finally:
+        P.set_options(n_lim=256)
+    with pytest.raises(P.TikhError):
+        P.autotune_nlim(384, 256, groups=0)
