@@ -1350,11 +1350,13 @@ __global__ __launch_bounds__(256) void k_prod_direct(const double2* __restrict__
     const double2* L = BL + g * l_stride;
     const double2* R = BR + g * r_stride;
     double2* O = out + g * o_stride;
-    // LDS staging: the B0 block of the left factor [16][ls] (entry i*4 + l), then
-    // one column j of the right factor at a time, rows 0..3 of length rs with
-    // PD_PAD zeros on both sides
+    // LDS staging: the B0 block of the left factor [16][ls] (entry i*4 + l), then the
+    // rows 0..3 of the right factor, zero-padded by PD_PAD on both sides: all columns
+    // at once when they fit (every (column, row, block) item in one pass over the
+    // threads), else one column at a time
     const int ls = dl + 1, rs = drm + 1 + 2 * PD_PAD;
     const bool staged = dl >= 0 && drm >= 0 && 16 * ls + 4 * rs <= PD_LDS;
+    const bool all_cols = staged && 16 * ls + 4 * C * rs <= PD_LDS;
     double2* shL = sh;
     double2* shR = sh + 16 * max(ls, 0);
     if (staged) {
@@ -1365,74 +1367,97 @@ __global__ __launch_bounds__(256) void k_prod_direct(const double2* __restrict__
         }
     }
     double cmx[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int j = 0; j < C; ++j) {
+    // one item: four consecutive output coefficients k0..k0+3 of entry (i, j); rj = the
+    // staged column j of the right factor (rows 0..3, stride rs)
+    auto item = [&](int j, int i, int k0, const double2* rj) {
         const int doj = sdout[j];
-        if (doj < 0) continue;
         const int dr = sdr[j];
+        double2 acc[4] = {c2(0.0, 0.0), c2(0.0, 0.0), c2(0.0, 0.0), c2(0.0, 0.0)};
         if (staged) {
-            __syncthreads();                         // previous column's readers are done
-            for (int w = threadIdx.x; w < 4 * rs; w += blockDim.x) {
-                const int l = w / rs, t = w - l * rs - PD_PAD;
-                shR[w] = (t >= 0 && t <= dr) ? cscale(R[(int64_t)(l * C + j) * rcp1 + t], ssr[j]) : c2(0.0, 0.0);
-            }
-            __syncthreads();
-        }
-        const int nblk = (doj + 4) / 4;              // blocks of four coefficients
-        for (int w = threadIdx.x; w < 4 * nblk; w += blockDim.x) {
-            const int i = w & 3;
-            const int k0 = (w >> 2) * 4;
-            double2 acc[4] = {c2(0.0, 0.0), c2(0.0, 0.0), c2(0.0, 0.0), c2(0.0, 0.0)};
-            if (staged) {
-                if (dr >= 0) {
-                    for (int l = 0; l < 4; ++l) {
-                        const int dla = sdl[l];
-                        if (dla < 0) continue;
-                        const int t0 = max(0, k0 - dr), t1 = min(dla, k0 + 3);
-                        if (t0 > t1) continue;
-                        const double2* lp = shL + (i * 4 + l) * ls;
-                        const double2* rp = shR + l * rs + PD_PAD + k0;   // rp[u - t] = R[k0 + u - t]
-                        // window win[u] = R[k0 + u - t], starting at t = t1, t decreasing
-                        double2 win[4];
+            if (dr >= 0) {
+                for (int l = 0; l < 4; ++l) {
+                    const int dla = sdl[l];
+                    if (dla < 0) continue;
+                    const int t0 = max(0, k0 - dr), t1 = min(dla, k0 + 3);
+                    if (t0 > t1) continue;
+                    const double2* lp = shL + (i * 4 + l) * ls;
+                    const double2* rp = rj + l * rs + PD_PAD + k0;   // rp[u - t] = R[k0 + u - t]
+                    // window win[u] = R[k0 + u - t], starting at t = t1, t decreasing
+                    double2 win[4];
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) win[u] = rp[u - t1];
-                        for (int t = t1; t >= t0; --t) {
-                            const double2 lv = lp[t];
+                    for (int u = 0; u < 4; ++u) win[u] = rp[u - t1];
+                    for (int t = t1; t >= t0; --t) {
+                        const double2 lv = lp[t];
 #pragma unroll
-                            for (int u = 0; u < 4; ++u) acc[u] = cfma(lv, win[u], acc[u]);
-                            if (t > t0) {
+                        for (int u = 0; u < 4; ++u) acc[u] = cfma(lv, win[u], acc[u]);
+                        if (t > t0) {
 #pragma unroll
-                                for (int u = 0; u < 3; ++u) win[u] = win[u + 1];
-                                win[3] = rp[4 - t];
-                            }
+                            for (int u = 0; u < 3; ++u) win[u] = win[u + 1];
+                            win[3] = rp[4 - t];
                         }
                     }
                 }
-            } else {
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int k = k0 + u;
-                    for (int l = 0; l < 4; ++l) {
-                        const int dla = sdl[l];
-                        if (dla < 0 || dr < 0) continue;
-                        const int t0 = max(0, k - dr), t1 = min(k, dla);
-                        const double2* lp = L + (int64_t)(i * C + l) * lcp1;
-                        const double2* rp = R + (int64_t)(l * C + j) * rcp1;
-                        double2 part = c2(0.0, 0.0);
-                        for (int t = t0; t <= t1; ++t) part = cfma(lp[t], rp[k - t], part);
-                        acc[u] = cfma(part, c2(ssl[l] * ssr[j], 0.0), acc[u]);
-                    }
-                }
             }
+        } else {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int k = k0 + u;
-                if (k > doj) break;
-                double2 v = acc[u];
-                if (j >= 4 && k <= sdl[j]) v = cadd(v, L[(int64_t)(i * C + j) * lcp1 + k]);
-                O[(int64_t)(i * C + j) * ocp1 + k] = v;
-#pragma unroll
-                for (int c = 0; c < 4; ++c) if (c == j) cmx[c] = fmax(cmx[c], cabs2(v));
+                for (int l = 0; l < 4; ++l) {
+                    const int dla = sdl[l];
+                    if (dla < 0 || dr < 0) continue;
+                    const int t0 = max(0, k - dr), t1 = min(k, dla);
+                    const double2* lp = L + (int64_t)(i * C + l) * lcp1;
+                    const double2* rp = R + (int64_t)(l * C + j) * rcp1;
+                    double2 part = c2(0.0, 0.0);
+                    for (int t = t0; t <= t1; ++t) part = cfma(lp[t], rp[k - t], part);
+                    acc[u] = cfma(part, c2(ssl[l] * ssr[j], 0.0), acc[u]);
+                }
             }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = k0 + u;
+            if (k > doj) break;
+            double2 v = acc[u];
+            if (j >= 4 && k <= sdl[j]) v = cadd(v, L[(int64_t)(i * C + j) * lcp1 + k]);
+            O[(int64_t)(i * C + j) * ocp1 + k] = v;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) if (c == j) cmx[c] = fmax(cmx[c], cabs2(v));
+        }
+    };
+    auto stage_col = [&](int j, double2* dst) {
+        const int dr = sdr[j];
+        for (int w = threadIdx.x; w < 4 * rs; w += blockDim.x) {
+            const int l = w / rs, t = w - l * rs - PD_PAD;
+            dst[w] = (t >= 0 && t <= dr) ? cscale(R[(int64_t)(l * C + j) * rcp1 + t], ssr[j]) : c2(0.0, 0.0);
+        }
+    };
+    if (all_cols) {
+        for (int j = 0; j < C; ++j) stage_col(j, shR + j * 4 * rs);
+        __syncthreads();
+        // items of all columns: column j has 4 * nblk_j items (nblk_j = blocks of 4 coefficients)
+        int nit = 0;
+        for (int j = 0; j < C; ++j) nit += sdout[j] < 0 ? 0 : 4 * ((sdout[j] + 4) / 4);
+        for (int w = threadIdx.x; w < nit; w += blockDim.x) {
+            int j = 0, rem = w;
+            for (; j < C; ++j) {
+                const int nj = sdout[j] < 0 ? 0 : 4 * ((sdout[j] + 4) / 4);
+                if (rem < nj) break;
+                rem -= nj;
+            }
+            item(j, rem & 3, (rem >> 2) * 4, shR + j * 4 * rs);
+        }
+    } else {
+        for (int j = 0; j < C; ++j) {
+            const int doj = sdout[j];
+            if (doj < 0) continue;
+            if (staged) {
+                __syncthreads();                     // previous column's readers are done
+                stage_col(j, shR);
+                __syncthreads();
+            }
+            const int nblk = (doj + 4) / 4;
+            for (int w = threadIdx.x; w < 4 * nblk; w += blockDim.x) item(j, w & 3, (w >> 2) * 4, shR);
         }
     }
 #pragma unroll
