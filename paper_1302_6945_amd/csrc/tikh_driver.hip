@@ -605,13 +605,13 @@ static int run_eval_chunk(const Plan& pl, const Layout& L, const Bufs& b, int64_
     const int64_t nleaves = (int64_t)1 << (pl.p - d);
     const int64_t t0 = ridx << (pl.p - d);
     if (L.nr == 1)
-        LAUNCH("eval_apply", k_eval_apply<1>, grid1(nleaves * pl.K, G), dim3(256), b.phi, L.sphi, b.V, L.sV, Lc, L1, oR,
+        LAUNCH("eval_apply", k_eval_apply<1>, grid1(nleaves * pl.K / 2, G), dim3(256), b.phi, L.sphi, b.V, L.sV, Lc, L1, oR,
                d, t0, nleaves, pl.N, pl.M, pl.p, pl.K);
     else if (L.nr == 2)
-        LAUNCH("eval_apply", k_eval_apply<2>, grid1(nleaves * pl.K, G), dim3(256), b.phi, L.sphi, b.V, L.sV, Lc, L1, oR,
+        LAUNCH("eval_apply", k_eval_apply<2>, grid1(nleaves * pl.K / 2, G), dim3(256), b.phi, L.sphi, b.V, L.sV, Lc, L1, oR,
                d, t0, nleaves, pl.N, pl.M, pl.p, pl.K);
     else
-        LAUNCH("eval_apply", k_eval_apply<4>, grid1(nleaves * pl.K, G), dim3(256), b.phi, L.sphi, b.V, L.sV, Lc, L1, oR,
+        LAUNCH("eval_apply", k_eval_apply<4>, grid1(nleaves * pl.K / 2, G), dim3(256), b.phi, L.sphi, b.V, L.sV, Lc, L1, oR,
                d, t0, nleaves, pl.N, pl.M, pl.p, pl.K);
     return TIKH_OK;
 }

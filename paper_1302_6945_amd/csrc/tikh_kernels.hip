@@ -1165,39 +1165,49 @@ __global__ __launch_bounds__(256) void k_leaf_build(const BuildArgs a) {
 // The right subtree (depth d, coset offset oR) spans leaves [t0, t0 + 2^{p-d}).
 // V holds each line in four-step order: value j at (j % L1) * (L / L1) + j / L1.
 template <int NR>
-__global__ void k_eval_apply(double2* __restrict__ phi, int64_t phi_stride, const double2* __restrict__ V,
-                             int64_t v_stride, int64_t L, int64_t L1, int64_t oR, int d, int64_t t0, int64_t nleaves,
-                             int64_t N, int64_t M, int p, int K) {
+__global__ __launch_bounds__(256) void k_eval_apply(double2* __restrict__ phi, int64_t phi_stride,
+                                                    const double2* __restrict__ V, int64_t v_stride, int64_t L,
+                                                    int64_t L1, int64_t oR, int d, int64_t t0, int64_t nleaves,
+                                                    int64_t N, int64_t M, int p, int K) {
     constexpr int C = 4 + NR;
     const int64_t g = blockIdx.y;
     const int64_t nq = 2 * N;
-    const int64_t cnt = nleaves * K;
+    // one thread per node: its F and G conditions (adjacent in tree order) share B_L(sigma)
+    const int nodes = (int)(nleaves * K / 2), hk = K / 2, hm = (int)(M / 2);
+    const int L2 = (int)(L / L1), iL1 = (int)L1;
+    const float inv_hk = 1.0f / (float)hk, inv_hm = 1.0f / (float)hm, inv_L1 = 1.0f / (float)L1;
     double2* ph = phi + g * phi_stride;
     const double2* Vs = V + g * v_stride;
-    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < cnt; u += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t q = t0 * K + u;
-        const int64_t t = q / K, h = q - t * K;
-        const int64_t c = h / M, jhi = (h - c * M) >> 1;
-        const int64_t ot = 2 * (int64_t)bitrev((int)t, p);
-        const int64_t jlo = (ot - oR) >> (d + 1);
-        const int64_t jn = jlo + (jhi << (p - d));
-        const int64_t j = (jn % L1) * (L / L1) + jn / L1;
-        double2 f[C];
+    for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < nodes; u += gridDim.x * blockDim.x) {
+        const int tl = fdiv(u, inv_hk, hk), hn = u - tl * hk;          // leaf within the subtree, node within the leaf
+        const int c = fdiv(hn, inv_hm, hm), jhi = hn - c * hm;          // coset, node within the coset
+        const int64_t t = t0 + tl;
+        const int64_t q = t * K + 2 * (int64_t)hn;                     // its F condition; q + 1 is G
+        const int ot = 2 * bitrev((int)t, p);
+        const int jlo = (int)((ot - oR) >> (d + 1));
+        const int jn = jlo + (jhi << (p - d));
+        const int a1 = fdiv(jn, inv_L1, iL1);
+        const int64_t j = (int64_t)(jn - a1 * iL1) * L2 + a1;         // four-step position of node jn
+        double2 f0[C], f1[C];
 #pragma unroll
-        for (int col = 0; col < C; ++col) f[col] = ph[col * nq + q];
-        double2 o[C];
+        for (int col = 0; col < C; ++col) { f0[col] = ph[col * nq + q]; f1[col] = ph[col * nq + q + 1]; }
+        double2 o0[C], o1[C];
 #pragma unroll
-        for (int col = 0; col < C; ++col) o[col] = col < 4 ? c2(0.0, 0.0) : f[col];
+        for (int col = 0; col < C; ++col) {
+            o0[col] = col < 4 ? c2(0.0, 0.0) : f0[col];
+            o1[col] = col < 4 ? c2(0.0, 0.0) : f1[col];
+        }
 #pragma unroll
         for (int row = 0; row < 4; ++row) {
 #pragma unroll
             for (int col = 0; col < C; ++col) {
-                double2 E = Vs[(int64_t)((row * C + col) * 2 + c) * L + j];
-                o[col] = cfma(f[row], E, o[col]);
+                const double2 E = Vs[(int64_t)((row * C + col) * 2 + c) * L + j];
+                o0[col] = cfma(f0[row], E, o0[col]);
+                o1[col] = cfma(f1[row], E, o1[col]);
             }
         }
 #pragma unroll
-        for (int col = 0; col < C; ++col) ph[col * nq + q] = o[col];
+        for (int col = 0; col < C; ++col) { ph[col * nq + q] = o0[col]; ph[col * nq + q + 1] = o1[col]; }
     }
 }
 
