@@ -126,7 +126,8 @@ int tikh_profile_units(double* units);
  *     X_k = sum_j x_j exp(sign * 2 pi i j k / len),   sign = -1 or +1,
  * unnormalized.  len must factor into 2, 3 and 5 and be at most 4096^2 (lines
  * longer than 4096 take two passes plus a reordering through the library
- * workspace); items <= 65535.  Asynchronous on the library stream.
+ * workspace); items <= 65535 and nlines * len < 2^31.  Asynchronous on the
+ * library stream.
  */
 int tikh_fft_batched(void* data, int64_t items, int64_t nlines, int64_t len, int sign);
 

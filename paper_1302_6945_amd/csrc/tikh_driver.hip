@@ -1104,7 +1104,8 @@ int tikh_plan_info(int64_t m, int64_t n, int32_t n_lim, int64_t* N, int64_t* M, 
 int tikh_fft_batched(void* data, int64_t items, int64_t nlines, int64_t len, int sign) {
     ensure_init();
     if (!data || items < 1 || items > 65535 || nlines < 1 || len < 1 || (sign != 1 && sign != -1)) return TIKH_EINVAL;
-    if (!smooth5(len) || len > (int64_t)FFT_LDS_MAX * FFT_LDS_MAX || nlines > ((int64_t)1 << 40) / len)
+    // one item's lines are addressed with 32-bit offsets
+    if (!smooth5(len) || len > (int64_t)FFT_LDS_MAX * FFT_LDS_MAX || nlines > (((int64_t)1 << 31) - 1) / len)
         return TIKH_EINVAL;
     if (len > FFT_LDS_MAX && fft_split(len) == 0) return TIKH_EINVAL;
     const double2* tw = twiddles(len);

@@ -60,7 +60,7 @@ __device__ __forceinline__ int64_t mod_fast(int64_t x, int64_t n, double invn) {
 }
 
 // e^{sign * 2 pi i idx / Q} for 0 <= idx < Q
-__device__ __forceinline__ double2 twd(const double2* __restrict__ tw, int64_t idx, int sign) {
+__device__ __forceinline__ double2 twd(const double2* __restrict__ tw, int idx, int sign) {
     double2 t = tw[idx];
     return sign > 0 ? t : cconj(t);
 }
@@ -76,8 +76,8 @@ __device__ __forceinline__ double2 twq(const double2* __restrict__ tw, int64_t Q
 // e^{2 pi i x / M} (0 <= x < M) from a two-level table
 // t = [e^{2 pi i j / M}, j < 2^bits | e^{2 pi i j 2^bits / M}, j <= (M - 1) >> bits]:
 // both parts are small, so scattered indices stay in cache
-__device__ __forceinline__ double2 tw2(const double2* __restrict__ t, int bits, int64_t x) {
-    return cmul(t[((int64_t)1 << bits) + (x >> bits)], t[x & (((int64_t)1 << bits) - 1)]);
+__device__ __forceinline__ double2 tw2(const double2* __restrict__ t, int bits, int x) {
+    return cmul(t[(1 << bits) + (x >> bits)], t[x & ((1 << bits) - 1)]);
 }
 
 __device__ __forceinline__ double2 load_elem(const void* p, int64_t i, int cplx) {
@@ -263,11 +263,11 @@ template <int R>
 __device__ __forceinline__ void stage_twiddle(double2* v, const double2* __restrict__ ltw, int idx, int sign) {
     if (R <= 5) {
 #pragma unroll
-        for (int r = 1; r < R; ++r) v[r] = cmul(v[r], twd(ltw, (int64_t)r * idx, sign));
+        for (int r = 1; r < R; ++r) v[r] = cmul(v[r], twd(ltw, r * idx, sign));
     } else {
         double2 w[R];
 #pragma unroll
-        for (int h = 1; h < R; h *= 2) w[h] = twd(ltw, (int64_t)h * idx, sign);
+        for (int h = 1; h < R; h *= 2) w[h] = twd(ltw, h * idx, sign);
 #pragma unroll
         for (int r = 3; r < R; ++r) {
             const int h = r >= 8 ? 8 : (r >= 4 ? 4 : 2);
@@ -397,11 +397,14 @@ struct FftArgs {
 // src[lsrc + i] folded over i = off + t*fold_L (off = in*line_stride + k*es,
 // i <= llim) and twisted by w^{loc*i}.  Fused store: element k goes to
 // dst[dbase + k*es] (scaled by dst_scale) if k*es <= dlim.
+// Offsets are 32-bit, relative to the line's group (every per-group region
+// holds fewer than 2^31 elements).
 struct FftLineInfo {
-    int64_t lsrc, llim, loc;
+    int lsrc, llim;
+    int64_t loc;
     double lsc;
     double2 lstep;                   // fused load 2: w^{loc fold_L}
-    int64_t dbase, dlim;
+    int dbase, dlim;
     int dcol;
 };
 
@@ -412,8 +415,8 @@ __device__ __forceinline__ void fft_line_info(const FftArgs& a, int64_t s, int64
         const int e = a.load_mode == 1 ? a.elist[o] : (int)(o >> 1);
         const int col = e % a.C;
         li.lsc = col < 4 ? pow2_inv_scale(mt.colmax_bits[col]) : 1.0;
-        li.lsrc = s * a.src_stride + (int64_t)e * a.src_cp1 + (a.load_mode == 1 ? inoff : 0);
-        li.llim = a.load_mode == 1 ? (int64_t)mt.deg[col] - inoff : (int64_t)mt.deg[col];
+        li.lsrc = (int)((int64_t)e * a.src_cp1 + (a.load_mode == 1 ? inoff : 0));
+        li.llim = (int)(a.load_mode == 1 ? (int64_t)mt.deg[col] - inoff : (int64_t)mt.deg[col]);
         li.loc = a.load_mode == 2 ? a.fold_o + (o & 1) : 0;
         if (a.load_mode == 2)
             li.lstep = tw2(a.ftw, a.fbits, mod_fast(li.loc * a.fold_L, a.fold_N, 1.0 / (double)a.fold_N));
@@ -422,8 +425,8 @@ __device__ __forceinline__ void fft_line_info(const FftArgs& a, int64_t s, int64
         const int e = a.dst_elist[o];
         const int col = e % a.C;
         li.dcol = col;
-        li.dbase = s * a.dst_stride + (int64_t)e * a.dst_cp1 + inoff;
-        li.dlim = min((int64_t)a.dst_meta[s].deg[col], a.dst_cp1 - 1) - inoff;
+        li.dbase = (int)((int64_t)e * a.dst_cp1 + inoff);
+        li.dlim = (int)(min((int64_t)a.dst_meta[s].deg[col], a.dst_cp1 - 1) - inoff);
     }
 }
 
@@ -433,9 +436,10 @@ __device__ __forceinline__ void fft_line_info(const FftArgs& a, int64_t s, int64
 // issue them together) and the remaining terms.
 struct FoldTerm {
     double2 acc, w;
-    int64_t off;
+    int off;
 };
-__device__ __forceinline__ FoldTerm fft_fold_first(const FftArgs& a, const FftLineInfo& li, int64_t off) {
+__device__ __forceinline__ FoldTerm fft_fold_first(const FftArgs& a, const double2* __restrict__ srcg,
+                                                   const FftLineInfo& li, int off) {
     FoldTerm f;
     f.off = off;
     f.acc = c2(0.0, 0.0);
@@ -443,16 +447,18 @@ __device__ __forceinline__ FoldTerm fft_fold_first(const FftArgs& a, const FftLi
     if (off <= li.llim) {
         const double invN = 1.0 / (double)a.fold_N;
         f.w = tw2(a.ftw, a.fbits, mod_fast(li.loc * off, a.fold_N, invN));
-        f.acc = cmul(a.src[li.lsrc + off], f.w);
+        f.acc = cmul(srcg[li.lsrc + off], f.w);
     }
     return f;
 }
-__device__ __forceinline__ double2 fft_fold_rest(const FftArgs& a, const FftLineInfo& li, FoldTerm f) {
-    if (f.off + a.fold_L <= li.llim) {
+__device__ __forceinline__ double2 fft_fold_rest(const FftArgs& a, const double2* __restrict__ srcg,
+                                                 const FftLineInfo& li, FoldTerm f) {
+    const int fl = (int)a.fold_L;
+    if (f.off + fl <= li.llim) {
         const double2 wstep = li.lstep;
-        for (int64_t i = f.off + a.fold_L; i <= li.llim; i += a.fold_L) {
+        for (int i = f.off + fl; i <= li.llim; i += fl) {
             f.w = cmul(f.w, wstep);
-            f.acc = cfma(a.src[li.lsrc + i], f.w, f.acc);
+            f.acc = cfma(srcg[li.lsrc + i], f.w, f.acc);
         }
     }
     return cscale(f.acc, li.lsc);
@@ -467,17 +473,20 @@ __device__ __forceinline__ double2 fft_fold_rest(const FftArgs& a, const FftLine
 template <int CAP>
 __global__ __launch_bounds__(FFT_THREADS, CAP <= 2048 ? 4 : 1) void k_fft(const FftArgs a) {
     __shared__ double2 sm[CAP + CAP / 16];
-    __shared__ int64_t sh_base[64];
+    __shared__ int sh_base[64];
     __shared__ int sh_in[64];
     __shared__ FftLineInfo sh_li[64];
     const int L = a.pl.L;
     const int64_t l0 = (int64_t)blockIdx.x * a.lpw;
     const int nl = (int)min((int64_t)a.lpw, a.nlines - l0);
     const int64_t s = blockIdx.y;
+    // per-group base pointers; offsets below are 32-bit
     double2* base = a.data + s * a.solve_stride;
+    const double2* srcg = a.load_mode ? a.src + s * a.src_stride : nullptr;
+    double2* dstg = a.store_mode ? a.dst + s * a.dst_stride : nullptr;
     if ((int)threadIdx.x < nl) {
         const int64_t l = l0 + threadIdx.x, o = l / a.lines_inner, in = l - o * a.lines_inner;
-        sh_base[threadIdx.x] = o * a.outer_stride + in * a.line_stride;
+        sh_base[threadIdx.x] = (int)(o * a.outer_stride + in * a.line_stride);
         sh_in[threadIdx.x] = (int)in;
         if (a.load_mode || a.store_mode) fft_line_info(a, s, o, in, sh_li[threadIdx.x]);
     }
@@ -487,29 +496,30 @@ __global__ __launch_bounds__(FFT_THREADS, CAP <= 2048 ? 4 : 1) void k_fft(const 
     const bool dload = (a.load_mode != 2) && nst > 0, dstore = nst > 0;
     const int tot = nl * L;
     const float invL = 1.0f / (float)L, invnl = 1.0f / (float)nl;
-    const int64_t es = a.elem_stride;
+    const int es = (int)a.elem_stride;
+    const int lstr = (int)a.line_stride;
     double cmx[4] = {0.0, 0.0, 0.0, 0.0};
     auto ld = [&](int g, int k) -> double2 {
         if (a.load_mode == 1) {
             const FftLineInfo& li = sh_li[g];
-            const int64_t off = (int64_t)k * es;
-            return off <= li.llim ? cscale(a.src[li.lsrc + off], li.lsc) : c2(0.0, 0.0);
+            const int off = k * es;
+            return off <= li.llim ? cscale(srcg[li.lsrc + off], li.lsc) : c2(0.0, 0.0);
         }
-        return base[sh_base[g] + (int64_t)k * es];
+        return base[sh_base[g] + k * es];
     };
     auto st = [&](int g, int k, double2 v) {
         // k * in < post_L: k < L and in < post_L / L for both four-step passes
         if (a.post_L) {
-            const double2 t = tw2(a.ptw, a.pbits, (int64_t)k * sh_in[g]);
+            const double2 t = tw2(a.ptw, a.pbits, k * sh_in[g]);
             v = cmul(v, a.sign > 0 ? t : cconj(t));
         }
         if (a.scale != 1.0) v = cscale(v, a.scale);
         if (a.store_mode) {
             const FftLineInfo& li = sh_li[g];
-            const int64_t off = (int64_t)k * es;
+            const int off = k * es;
             if (off <= li.dlim) {
                 v = cscale(v, a.dst_scale);
-                a.dst[li.dbase + off] = v;
+                dstg[li.dbase + off] = v;
                 const int col = li.dcol;
                 if (col < 4) {
                     const double m2 = cabs2(v);
@@ -518,7 +528,7 @@ __global__ __launch_bounds__(FFT_THREADS, CAP <= 2048 ? 4 : 1) void k_fft(const 
                 }
             }
         } else {
-            base[sh_base[g] + (int64_t)k * es] = v;
+            base[sh_base[g] + k * es] = v;
         }
     };
     if (!dload) {
@@ -534,14 +544,14 @@ __global__ __launch_bounds__(FFT_THREADS, CAP <= 2048 ? 4 : 1) void k_fft(const 
                 if (!linefast) { g = fdiv(i, invL, L); k = i - g * L; } else { k = fdiv(i, invnl, nl); g = i - k * nl; }
                 gg[u] = g; kk[u] = k;
                 if (a.load_mode == 2)
-                    f[u] = fft_fold_first(a, sh_li[g], (int64_t)sh_in[g] * a.line_stride + (int64_t)k * es);
+                    f[u] = fft_fold_first(a, srcg, sh_li[g], sh_in[g] * lstr + k * es);
                 else
                     f[u].acc = ld(g, k);
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (i0 + u * FFT_THREADS < tot) {
-                    const double2 v = a.load_mode == 2 ? fft_fold_rest(a, sh_li[gg[u]], f[u]) : f[u].acc;
+                    const double2 v = a.load_mode == 2 ? fft_fold_rest(a, srcg, sh_li[gg[u]], f[u]) : f[u].acc;
                     if (nst == 0) st(gg[u], kk[u], v);
                     else sm[lds_ix(gg[u] * L + kk[u])] = v;
                 }
