@@ -399,6 +399,8 @@ struct EList {
     int row0[MAXC];
     int vcols[4 * MAXNR];
     int xout[MAXNR];
+    int b0[16];            // the B0 block, i * C + t
+    int row0b0[4];         // row 0 of the B0 block
 };
 static EList make_elist(int nr) {
     EList e{};
@@ -408,6 +410,9 @@ static EList make_elist(int nr) {
     for (int i = 0; i < 4; ++i)
         for (int j = 0; j < nr; ++j) e.vcols[i * nr + j] = i * C + 4 + j;
     for (int j = 0; j < nr; ++j) e.xout[j] = 4 + j;
+    for (int i = 0; i < 4; ++i)
+        for (int t = 0; t < 4; ++t) e.b0[i * 4 + t] = i * C + t;
+    for (int t = 0; t < 4; ++t) e.row0b0[t] = t;
     return e;
 }
 
@@ -637,8 +642,10 @@ static int run_product_chunk(const Plan& pl, const Layout& L, const Bufs& b, int
     // the root forms row 0 only: the solution columns, or every column when deferred
     // conditions are still to be processed against it
     const bool full_root = root && defer_on();
-    const int nL = root ? C : 4 * C, nR = root && !full_root ? 4 * nr : 4 * C, nO = root ? (full_root ? C : nr) : 4 * C;
-    const int* eL = b.elist + (root ? offsetof(EList, row0) : offsetof(EList, all)) / sizeof(int);
+    // only the left factor's B0 block is transformed: its V block is added to the
+    // coefficients of the product by the inverse transform's store
+    const int nL = root ? 4 : 16, nR = root && !full_root ? 4 * nr : 4 * C, nO = root ? (full_root ? C : nr) : 4 * C;
+    const int* eL = b.elist + (root ? offsetof(EList, row0b0) : offsetof(EList, b0)) / sizeof(int);
     const int* eR = b.elist + (root && !full_root ? offsetof(EList, vcols) : offsetof(EList, all)) / sizeof(int);
     const int* eO = b.elist + (root ? (full_root ? offsetof(EList, row0) : offsetof(EList, xout)) : offsetof(EList, all)) /
                     sizeof(int);
@@ -665,6 +672,7 @@ static int run_product_chunk(const Plan& pl, const Layout& L, const Bufs& b, int
     FftArgs fo{};
     fo.store_mode = 1; fo.dst = dst; fo.dst_stride = dstride; fo.dst_cp1 = dcap + 1; fo.dst_meta = dmeta;
     fo.dst_elist = eO; fo.C = C; fo.dst_scale = 1.0 / (double)P;
+    fo.add_src = b.slotS[dc]; fo.add_stride = L.sslot[dc]; fo.add_cp1 = cp1; fo.add_meta = b.metaS[dc];
     rc = fft_lines(b.FL, G, L.sF, nO, P, +1, tw, pl.Q, b.scr, L.sscr, FFT_INV_T, &fo);
     if (rc) return rc;
     return TIKH_OK;

@@ -389,6 +389,11 @@ struct FftArgs {
     SlotMeta* dst_meta;
     const int* dst_elist;
     double dst_scale;
+    // fused store, columns 4..C-1: add the same entry of this basis (the left factor's
+    // V block, which enters the product unchanged), offsets up to its degree
+    const double2* add_src;
+    int64_t add_stride, add_cp1;
+    const SlotMeta* add_meta;
 };
 
 // Per-line descriptors of the fused loads and stores, computed once per
@@ -406,6 +411,7 @@ struct FftLineInfo {
     double2 lstep;                   // fused load 2: w^{loc fold_L}
     int dbase, dlim;
     int dcol;
+    int abase, alim;
 };
 
 __device__ __forceinline__ void fft_line_info(const FftArgs& a, int64_t s, int64_t o, int64_t in, FftLineInfo& li) {
@@ -427,6 +433,12 @@ __device__ __forceinline__ void fft_line_info(const FftArgs& a, int64_t s, int64
         li.dcol = col;
         li.dbase = (int)((int64_t)e * a.dst_cp1 + inoff);
         li.dlim = (int)(min((int64_t)a.dst_meta[s].deg[col], a.dst_cp1 - 1) - inoff);
+        li.alim = -1;
+        li.abase = 0;
+        if (a.add_src && col >= 4) {
+            li.abase = (int)((int64_t)e * a.add_cp1 + inoff);
+            li.alim = (int)((int64_t)a.add_meta[s].deg[col] - inoff);
+        }
     }
 }
 
@@ -484,6 +496,7 @@ __global__ __launch_bounds__(FFT_THREADS, CAP <= 2048 ? 4 : 1) void k_fft(const 
     double2* base = a.data + s * a.solve_stride;
     const double2* srcg = a.load_mode ? a.src + s * a.src_stride : nullptr;
     double2* dstg = a.store_mode ? a.dst + s * a.dst_stride : nullptr;
+    const double2* addg = a.add_src ? a.add_src + s * a.add_stride : nullptr;
     if ((int)threadIdx.x < nl) {
         const int64_t l = l0 + threadIdx.x, o = l / a.lines_inner, in = l - o * a.lines_inner;
         sh_base[threadIdx.x] = (int)(o * a.outer_stride + in * a.line_stride);
@@ -519,6 +532,7 @@ __global__ __launch_bounds__(FFT_THREADS, CAP <= 2048 ? 4 : 1) void k_fft(const 
             const int off = k * es;
             if (off <= li.dlim) {
                 v = cscale(v, a.dst_scale);
+                if (off <= li.alim) v = cadd(v, addg[li.abase + off]);
                 dstg[li.dbase + off] = v;
                 const int col = li.dcol;
                 if (col < 4) {
@@ -1504,10 +1518,15 @@ __global__ __launch_bounds__(256) void k_prod_direct(const double2* __restrict__
 // frequency, and the inverse transform writes the truncated, 1/P-scaled
 // entries into the destination slot (store mode 1).
 
-// Pointwise block product per frequency.  Full mode: FL and FR hold all 4C
-// entries (row-major, C columns); output all 4C entries.  Root mode: FL holds
-// row 0 (C entries), FR the columns 4..C-1 of rows 0..3 (4 NR entries, row-major);
-// output the NR solution polynomials (row 0, columns 4..C-1).
+// Pointwise block product per frequency, B0_L times the rows 0..3 of B_R (the
+// left factor's V block is added to the coefficients by the inverse
+// transform's store).  Full mode: FL holds the 16 entries of B0_L (i*4 + t),
+// FR all 4C entries of B_R (row-major, C columns); output all 4C entries
+// (i*C + j) in place over FL.  Root mode 1: FL holds row 0 of B0_L (4 entries),
+// FR the columns 4..C-1 of rows 0..3 (4 NR entries, row-major); output the NR
+// solution polynomials.  Root mode 2: FL row 0 of B0_L, FR all 4C entries,
+// output row 0 of every column.  Each thread reads all its inputs before it
+// writes, so the outputs may overlay FL.
 template <int NR>
 __global__ __launch_bounds__(64) void k_prod_mul(const double2* FL, const double2* __restrict__ FR,
                            double2* FO, int64_t f_stride, int64_t P, int root) {
@@ -1518,50 +1537,52 @@ __global__ __launch_bounds__(64) void k_prod_mul(const double2* FL, const double
     double2* O = FO + g * f_stride;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < P; k += (int64_t)gridDim.x * blockDim.x) {
         if (root == 2) {
-            // row 0 of every column: FL = row 0 (C entries), FR = all 4C entries
-            double2 l[C];
+            double2 l[4];
 #pragma unroll
-            for (int j = 0; j < C; ++j) l[j] = L[j * P + k];
+            for (int t = 0; t < 4; ++t) l[t] = L[t * P + k];
+            double2 o[C];
 #pragma unroll
             for (int j = 0; j < C; ++j) {
-                double2 acc = (j >= 4) ? l[j] : c2(0.0, 0.0);
+                double2 acc = c2(0.0, 0.0);
 #pragma unroll
                 for (int t = 0; t < 4; ++t) acc = cfma(l[t], R[(t * C + j) * P + k], acc);
-                O[j * P + k] = acc;
+                o[j] = acc;
             }
-        } else if (root) {
-            double2 l[C], r[4][NR];
 #pragma unroll
-            for (int j = 0; j < C; ++j) l[j] = L[j * P + k];
+            for (int j = 0; j < C; ++j) O[j * P + k] = o[j];
+        } else if (root) {
+            double2 l[4], r[4][NR];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) l[t] = L[t * P + k];
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
                 for (int j = 0; j < NR; ++j) r[i][j] = R[(i * NR + j) * P + k];
 #pragma unroll
             for (int j = 0; j < NR; ++j) {
-                double2 acc = l[4 + j];
+                double2 acc = c2(0.0, 0.0);
 #pragma unroll
                 for (int t = 0; t < 4; ++t) acc = cfma(l[t], r[t][j], acc);
                 O[j * P + k] = acc;
             }
         } else {
-            // the right factor stays in registers; the left factor streams row by row
-            // (row i of the output overwrites only row i of the left factor, already read)
-            double2 r[4][C];
+            double2 l[4][4];
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < C; ++j) r[i][j] = R[(i * C + j) * P + k];
+                for (int t = 0; t < 4; ++t) l[i][t] = L[(i * 4 + t) * P + k];
+            double2 r[4][C];
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int j = 0; j < C; ++j) r[t][j] = R[(t * C + j) * P + k];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                double2 l[C];
-#pragma unroll
-                for (int j = 0; j < C; ++j) l[j] = L[(i * C + j) * P + k];
 #pragma unroll
                 for (int j = 0; j < C; ++j) {
-                    double2 acc = (j >= 4) ? l[j] : c2(0.0, 0.0);
+                    double2 acc = c2(0.0, 0.0);
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) acc = cfma(l[t], r[t][j], acc);
+                    for (int t = 0; t < 4; ++t) acc = cfma(l[i][t], r[t][j], acc);
                     O[(i * C + j) * P + k] = acc;
                 }
             }
