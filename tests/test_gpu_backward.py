@@ -126,3 +126,40 @@ def test_backward_batched_matches_single(P):
                 assert rel(g_b[co:co + m].cpu().numpy(), gb.cpu().numpy()) <= 1e-12
                 assert abs(float(g_lam[k]) - float(gl)) <= 1e-12 * max(1, abs(float(gl)))
                 xo += n; co += m; ro += n; k += 1
+
+
+def test_complex_full_size_gradient_central_differences(P):
+    """Differentiation workload at full size (complex T, n = 2^15, m = n + n/8,
+    lambda = 0.02, loss 0.5 ||x - x_true||^2): central differences of the GPU forward
+    solve, h = 1e-6, along each gradient block's own direction (generator column,
+    generator row, b, lambda) and 16 random unit directions over all of them.
+    Measured at this size the difference converges quadratically to the gradient
+    (relative gap 1e-4, 1e-6, 1e-8 at h = 1e-5, 1e-6, 1e-7), so 1e-5 bounds it."""
+    pr = W.config3()
+    col, row, b, lam, xt = pr.col, pr.row, pr.b[0], pr.lams[0], pr.x_true
+    m, n = len(col), len(row)
+
+    def loss(c, r, bb, l):
+        x = P.solve(dev(c), dev(r), dev(bb), l).cpu().numpy()
+        return 0.5 * np.sum(np.abs(x - xt) ** 2)
+
+    x = P.solve(dev(col), dev(row), dev(b), lam)
+    g_col, g_row, g_b, g_lam = P.backward(dev(col), dev(row), dev(b), lam, x, x - dev(xt))
+    g_col, g_row, g_b, g_lam = g_col.cpu().numpy(), g_row.cpu().numpy(), g_b.cpu().numpy(), float(g_lam)
+    zc, zr, zb = np.zeros_like(col), np.zeros_like(row), np.zeros_like(b)
+    dirs = [(g_col / np.linalg.norm(g_col), zr, zb, 0.0), (zc, g_row / np.linalg.norm(g_row), zb, 0.0),
+            (zc, zr, g_b / np.linalg.norm(g_b), 0.0), (zc, zr, zb, 1.0)]
+    rng = np.random.default_rng(2024)
+    cn = lambda k: rng.standard_normal(k) + 1j * rng.standard_normal(k)
+    for _ in range(16):
+        dc, dr, db, dl = cn(m), cn(n), cn(m), rng.standard_normal()
+        dr[0] = 0
+        nrm = np.sqrt(np.sum(np.abs(dc) ** 2) + np.sum(np.abs(dr) ** 2) + np.sum(np.abs(db) ** 2) + dl ** 2)
+        dirs.append((dc / nrm, dr / nrm, db / nrm, dl / nrm))
+    hstep = 1e-6
+    for i, (dc, dr, db, dl) in enumerate(dirs):
+        fd = (loss(col + hstep * dc, row + hstep * dr, b + hstep * db, lam + hstep * dl)
+              - loss(col - hstep * dc, row - hstep * dr, b - hstep * db, lam - hstep * dl)) / (2 * hstep)
+        an = (np.sum((np.conj(g_col) * dc).real) + np.sum((np.conj(g_row) * dr).real)
+              + np.sum((np.conj(g_b) * db).real) + g_lam * dl)
+        assert abs(fd - an) <= 1e-5 * max(abs(an), 1.0), (i, fd, an)

@@ -294,3 +294,24 @@ def test_autotune_nlim(P):
         P.set_options(n_lim=256)
     with pytest.raises(P.TikhError):
         P.autotune_nlim(384, 256, groups=0)
+
+
+def _banded_normal_ld(h, n, v, lam):
+    """(T^H T + lam^2 I) v in long double for T = full convolution with taps h (m = n + len(h) - 1)."""
+    hl = np.asarray(h, np.longdouble); vl = np.asarray(v, np.longdouble)
+    tv = np.convolve(hl, vl)                                  # T v, length n + len(h) - 1
+    thtv = np.convolve(tv, hl[::-1])[len(h) - 1:len(h) - 1 + n]
+    return thtv + np.longdouble(lam) ** 2 * vl
+
+
+def test_deblurring_full_size_known_solution(P):
+    """The plain method at scale (1-D deblurring, n = 2^16, m = n + 192, Gaussian PSF
+    with 193 taps, lambda = 1e-2, kappa <= 1 + 1/lambda^2 = 1e4): normal form with a
+    right-hand side formed in long double from the known piecewise-constant x."""
+    pr = W.config1()
+    h = pr.col[:193]
+    assert np.all(pr.col[193:] == 0) and np.all(pr.row[1:] == 0)
+    lam = pr.lams[0]
+    y = _banded_normal_ld(h, pr.n, pr.x_true, lam).astype(np.float64)
+    x = P.solve_normal(dev(pr.col), dev(pr.row), dev(y), lam).cpu().numpy()
+    assert relerr(x, pr.x_true) <= TOL, relerr(x, pr.x_true)
