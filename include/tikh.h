@@ -74,7 +74,9 @@ typedef struct {
     int32_t n_lim;        /* max conditions per leaf (64..256, multiple of 64); default 256 */
     int32_t refine;       /* refinement steps for every solve (0..4); default 1 */
     int32_t refine_max;   /* most refinement steps for a solve above the error target (0..4); default 3 */
-    int32_t reserved0;
+    int32_t leaf_wave_groups; /* groups per call from which each group's leaf steps run in one
+                             wavefront rather than one wavefront per 64 conditions (>= 1;
+                             default 1536); either way the results are the same */
     double refine_tol;    /* target relative error of the adaptive steps (> 0, finite); default 1e-10 */
     double defer_tol;     /* difficult points (Sec. 5): a chosen condition whose pivot entry is below
                              defer_tol times its largest entry among columns 1..4 is set aside and

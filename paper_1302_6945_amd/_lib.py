@@ -20,7 +20,7 @@ _D = ctypes.c_double
 
 class _Opts(ctypes.Structure):
     _fields_ = [("n_lim", ctypes.c_int32), ("refine", ctypes.c_int32), ("refine_max", ctypes.c_int32),
-                ("reserved0", ctypes.c_int32), ("refine_tol", ctypes.c_double), ("defer_tol", ctypes.c_double),
+                ("leaf_wave_groups", ctypes.c_int32), ("refine_tol", ctypes.c_double), ("defer_tol", ctypes.c_double),
                 ("reserved", ctypes.c_int32 * 2)]
 
 
@@ -84,7 +84,8 @@ def _stream():
     lib.tikh_set_stream(ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
 
 
-def set_options(n_lim=None, refine=None, refine_max=None, refine_tol=None, defer_tol=None):
+def set_options(n_lim=None, refine=None, refine_max=None, refine_tol=None, defer_tol=None,
+                leaf_wave_groups=None):
     """Leaf cutoff, refinement steps for every solve, most refinement steps for a solve whose
     estimated error is above the target (see tikh_opts in include/tikh.h)."""
     o = _Opts()
@@ -99,6 +100,8 @@ def set_options(n_lim=None, refine=None, refine_max=None, refine_tol=None, defer
         o.refine_tol = float(refine_tol)
     if defer_tol is not None:
         o.defer_tol = float(defer_tol)
+    if leaf_wave_groups is not None:
+        o.leaf_wave_groups = int(leaf_wave_groups)
     _check(lib.tikh_set_options(ctypes.byref(o)), "tikh_set_options")
 
 
@@ -106,7 +109,7 @@ def get_options():
     o = _Opts()
     _check(lib.tikh_get_options(ctypes.byref(o)), "tikh_get_options")
     return dict(n_lim=o.n_lim, refine=o.refine, refine_max=o.refine_max, refine_tol=o.refine_tol,
-                defer_tol=o.defer_tol)
+                defer_tol=o.defer_tol, leaf_wave_groups=o.leaf_wave_groups)
 
 
 def plan_info(m, n, n_lim=256):

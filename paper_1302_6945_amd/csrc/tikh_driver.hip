@@ -119,6 +119,7 @@ static void ensure_init() {
     g.opts.n_lim = 256;
     g.opts.refine = 1;
     g.opts.refine_max = 3;
+    g.opts.leaf_wave_groups = 1536;
     g.opts.refine_tol = 1e-10;
     g.opts.defer_tol = 0.0;
     if (hipMalloc((void**)&g.dneed, sizeof(int)) != hipSuccess) g.dneed = nullptr;
@@ -257,7 +258,7 @@ static double2* twiddles(int64_t Q) {
     }
     double2* d = nullptr;
     if (hipMalloc(&d, sizeof(double2) * Q) != hipSuccess) return nullptr;
-    if (hipMemcpy(d, h.data(), sizeof(double2) * Q, hipMemcpyHostToDevice) != hipSuccess) { hipFree(d); return nullptr; }
+    if (hipMemcpy(d, h.data(), sizeof(double2) * Q, hipMemcpyHostToDevice) != hipSuccess) { (void)hipFree(d); return nullptr; }
     g.tw[Q] = d;
     return d;
 }
@@ -560,7 +561,14 @@ static int fft_lines(double2* data, int64_t S, int64_t sstride, int64_t nlines, 
 template <int NR>
 static void launch_leaf(const Plan& pl, const LeafArgs& la, const BuildArgs& ba, int64_t G, int slots) {
     const int waves = (pl.K + 63) / 64;           // one wavefront per 64 conditions (K <= 256)
-    LAUNCH("leaf_loop", k_leaf_loop<NR>, dim3((unsigned)G), dim3(64 * waves), la);
+    if (G >= g.opts.leaf_wave_groups && waves > 1) {
+        // large batches: one wavefront per group does the per-step common work once
+        if (waves == 2) LAUNCH("leaf_loop", (k_leaf_loop_sw<2, NR>), dim3((unsigned)G), dim3(64), la);
+        else if (waves == 3) LAUNCH("leaf_loop", (k_leaf_loop_sw<3, NR>), dim3((unsigned)G), dim3(64), la);
+        else LAUNCH("leaf_loop", (k_leaf_loop_sw<4, NR>), dim3((unsigned)G), dim3(64), la);
+    } else {
+        LAUNCH("leaf_loop", k_leaf_loop<NR>, dim3((unsigned)G), dim3(64 * waves), la);
+    }
     if (slots <= 1) LAUNCH("leaf_build", (k_leaf_build<1, NR>), dim3((unsigned)G), dim3(256), ba);
     else if (slots <= 2) LAUNCH("leaf_build", (k_leaf_build<2, NR>), dim3((unsigned)G), dim3(256), ba);
     else if (slots <= 3) LAUNCH("leaf_build", (k_leaf_build<3, NR>), dim3((unsigned)G), dim3(256), ba);
@@ -1206,7 +1214,7 @@ int tikh_autotune_nlim(int64_t m, int64_t n, int64_t groups, int32_t nrhs, int32
 }
 
 int tikh_release(void) {
-    if (g.ws) { hipStreamSynchronize(g.stream); hipFree(g.ws); g.ws = nullptr; g.ws_size = 0; }
+    if (g.ws) { (void)hipStreamSynchronize(g.stream); (void)hipFree(g.ws); g.ws = nullptr; g.ws_size = 0; }
     for (auto& kv : g.tw) (void)hipFree(kv.second);
     g.tw.clear();
     for (auto& kv : g.tw2) (void)hipFree(kv.second);
@@ -1221,7 +1229,7 @@ int tikh_set_options(const tikh_opts* o) {
     if (!o) return TIKH_EINVAL;
     if (o->n_lim < 64 || o->n_lim > LEAF_MAX || o->refine < 0 || o->refine > 4 || o->refine_max < 0 ||
         o->refine_max > 4 || !(o->refine_tol > 0.0) || !std::isfinite(o->refine_tol) || !(o->defer_tol >= 0.0) ||
-        !(o->defer_tol < 1.0))
+        !(o->defer_tol < 1.0) || o->leaf_wave_groups < 1)
         return TIKH_EINVAL;
     g.opts = *o;
     return TIKH_OK;

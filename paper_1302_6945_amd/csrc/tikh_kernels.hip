@@ -1040,6 +1040,163 @@ __global__ __launch_bounds__(256) void k_leaf_loop(const LeafArgs a) {
     }
 }
 
+// Single-wavefront variant for large batches: one wave per group holds R
+// conditions per lane, so the per-step work that is the same for every
+// condition (candidate reduction, division, multipliers) is done once per
+// group instead of once per wave; the steps are the same as above.
+template <int R, int NR>
+__global__ __launch_bounds__(64) void k_leaf_loop_sw(const LeafArgs a) {
+    constexpr int C = 4 + NR;
+    const int64_t g = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int K = a.K;
+    const int64_t nq = 2 * a.N;
+    const int64_t q0 = (int64_t)a.leaf * K;
+    double2* ph = a.phi + g * a.phi_stride;
+    LeafRec* rec = a.rec + g * a.rec_stride;
+    double2 r[R][C];
+    double2 sg[R];
+    bool alive[R], passive[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const int h = lane + 64 * i;
+        alive[i] = h < K;
+        passive[i] = false;
+#pragma unroll
+        for (int c = 0; c < C; ++c) r[i][c] = alive[i] ? ph[c * nq + q0 + h] : c2(0.0, 0.0);
+        sg[i] = alive[i] ? cond_node(q0 + h, a.N, a.M, a.p, K, a.tw, a.Q) : c2(0.0, 0.0);
+    }
+    int dl[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) dl[c] = a.st[g].delta[c];
+    int info = 0;
+    for (int step = 0; step < K; ++step) {
+        unsigned long long best = 0ull;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            if (!alive[i]) continue;
+            double a2[4];
+            double amax = 0.0;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) { a2[c] = cabs2(r[i][c]); amax = fmax(amax, a2[c]); }
+            const double thr = TIKH_ZTOL2 * amax;
+            int kd = INT_MAX, piv = -1;
+            double pm = -1.0;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                if (a2[c] > thr && a2[c] > 0.0 && (dl[c] < kd || (dl[c] == kd && a2[c] > pm))) {
+                    kd = dl[c]; piv = c; pm = a2[c];
+                }
+            }
+            if (piv >= 0) {
+                const unsigned long long k = cand_key(kd, pm, piv, i * 64 + lane);
+                best = k > best ? k : best;
+            }
+        }
+        const unsigned long long wk = wave_max_u64(best);
+        if (wk == 0ull) { info = 1; break; }      // no admissible pivot: breakdown
+        const int idx = 255 - (int)(wk & 255ull);
+        const int piv = (int)((wk >> 8) & 3ull);
+        const int wl = idx & 63, si = idx >> 6;
+        double2 rc[C];
+        double2 sc = c2(0.0, 0.0);
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            if (i == si) {
+#pragma unroll
+                for (int c = 0; c < C; ++c) rc[c] = c2(readlane_d(r[i][c].x, wl), readlane_d(r[i][c].y, wl));
+                sc = c2(readlane_d(sg[i].x, wl), readlane_d(sg[i].y, wl));
+            }
+        }
+        double2 rp = rc[0];
+#pragma unroll
+        for (int c = 1; c < 4; ++c) if (c == piv) rp = rc[c];
+        if (a.defer_tol2 > 0.0) {
+            double amax = 0.0;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) amax = fmax(amax, cabs2(rc[c]));
+            if (cabs2(rp) < a.defer_tol2 * amax) {
+                // difficult point: set aside for the end of the solve; no step is taken
+#pragma unroll
+                for (int i = 0; i < R; ++i)
+                    if (i == si && lane == wl) { alive[i] = false; passive[i] = true; }
+                if (lane == 0) rec[step].piv = -1;
+                continue;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i) if (i == si && lane == wl) alive[i] = false;
+        // -1 / r_pi
+        const double den = 1.0 / cabs2(rp);
+        const double2 inv = c2(-rp.x * den, rp.y * den);
+        double2 mu[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) mu[c] = (c == piv) ? c2(0.0, 0.0) : cmul(rc[c], inv);
+        if (lane == 0) {
+            LeafRec& o = rec[step];
+#pragma unroll
+            for (int c = 0; c < C; ++c) o.mu[c] = mu[c];
+            o.sig = sc;
+            o.piv = piv;
+            o.q = (int)(q0 + idx);
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            if (!alive[i] && !passive[i]) continue;
+            double2 rpv;
+            switch (piv) {
+                case 0: rpv = r[i][0]; break;
+                case 1: rpv = r[i][1]; break;
+                case 2: rpv = r[i][2]; break;
+                default: rpv = r[i][3]; break;
+            }
+            // mu[piv] = 0 leaves the pivot column unchanged here
+#pragma unroll
+            for (int c = 0; c < C; ++c) r[i][c] = cfma(mu[c], rpv, r[i][c]);
+            const double2 np = cmul(rpv, csub(sg[i], sc));
+            switch (piv) {
+                case 0: r[i][0] = np; break;
+                case 1: r[i][1] = np; break;
+                case 2: r[i][2] = np; break;
+                default: r[i][3] = np; break;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) if (c == piv) dl[c] += 1;
+    }
+    if (a.defer_tol2 > 0.0) {
+        // append the deferred conditions of this leaf with their current residual rows
+        __shared__ int sh_nd;
+        if (lane == 0) sh_nd = 0;
+        __syncthreads();
+        const int nd0 = a.st[g].ndef;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            if (passive[i]) {
+                const int pos = nd0 + atomicAdd(&sh_nd, 1);
+                if (pos < a.dl.cap) {
+                    const int64_t e = g * a.dl.cap + pos;
+                    a.dl.q[e] = (int32_t)(q0 + lane + 64 * i);
+                    a.dl.node[e] = sg[i];
+#pragma unroll
+                    for (int c = 0; c < C; ++c) a.dl.res[e * C + c] = r[i][c];
+                }
+            }
+        }
+        __syncthreads();
+        if (lane == 0) {
+            const int nd = nd0 + sh_nd;
+            a.st[g].ndef = min(nd, a.dl.cap);
+            if (nd > a.dl.cap) info |= 4;
+        }
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) a.st[g].delta[c] = dl[c];
+        if (info) a.st[g].info |= info;
+    }
+}
+
 // Basis of one leaf from its step records: B = E_1 E_2 ... E_K with the
 // elementary factors of eq. (spbasis).  One wavefront per row of [B0 | V]
 // (4 waves), coefficient k of each polynomial on lane k%64, slot k/64; the

@@ -93,3 +93,5 @@ def test_invalid_arguments_rejected_on_host():
     assert P.lib.tikh_set_options(ctypes.byref(o)) == -1
     o = P._lib._Opts(n_lim=256, refine=1, refine_max=3, refine_tol=0.0)
     assert P.lib.tikh_set_options(ctypes.byref(o)) == -1
+    o = P._lib._Opts(n_lim=256, refine=1, refine_max=3, refine_tol=1e-10, leaf_wave_groups=0)
+    assert P.lib.tikh_set_options(ctypes.byref(o)) == -1

@@ -180,6 +180,32 @@ def test_difficult_points_deferred(P, defer_tol, nlim):
     assert deferred > 0
 
 
+@pytest.mark.parametrize("nlim", [128, 192, 256])
+@pytest.mark.parametrize("defer_tol", [0.0, 1e-3])
+def test_leaf_single_wavefront_parity(P, nlim, defer_tol):
+    """The leaf steps (Alg. 1, leaf case) run either with one wavefront per 64
+    conditions or, for large batches, with one wavefront per group holding
+    several conditions per lane.  Forcing each path on the same batch, both
+    must match the oracle and each other."""
+    pr = W.headline(0, n=512, nrhs=2, nlam=4)
+    args = ([pr.m], [pr.n], dev(pr.col), dev(pr.row), list(pr.lams), 2, dev(np.concatenate(pr.b)))
+    ref = [oracle.solve(pr.col, pr.row, b, lam) for lam in pr.lams for b in pr.b]
+    xs = []
+    for wg in (1, 1 << 30):
+        P.set_options(n_lim=nlim, defer_tol=defer_tol, leaf_wave_groups=wg)
+        try:
+            x, info = P.solve_batched(*args)
+            torch.cuda.synchronize()
+        finally:
+            P.set_options(n_lim=256, defer_tol=0.0, leaf_wave_groups=1536)
+        x = x.cpu().numpy()
+        assert (info.cpu().numpy() == 0).all(), (wg, nlim, defer_tol)
+        for i, xr in enumerate(ref):
+            assert relerr(x[i * pr.n:(i + 1) * pr.n], xr) <= TOL, (wg, nlim, defer_tol, i)
+        xs.append(x)
+    assert relerr(xs[0], xs[1]) <= 1e-12
+
+
 def test_difficult_points_capacity(P):
     """More deferred conditions than a solve holds is reported (info bit 4),
     not silently dropped."""
