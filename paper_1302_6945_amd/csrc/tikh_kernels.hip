@@ -1040,13 +1040,37 @@ __global__ __launch_bounds__(256) void k_leaf_loop(const LeafArgs a) {
     }
 }
 
-// Single-wavefront variant for large batches: one wave per group holds R
-// conditions per lane, so the per-step work that is the same for every
-// condition (candidate reduction, division, multipliers) is done once per
-// group instead of once per wave; the steps are the same as above.
+// Position of the k-th set bit (k = 0, 1, ...) of m; k < popcount(m).
+__device__ __forceinline__ int nth_set_bit(unsigned long long m, int k) {
+    unsigned w = (unsigned)m;
+    int pos = 0;
+    int c = __popc(w);
+    if (k >= c) { k -= c; pos = 32; w = (unsigned)(m >> 32); }
+    c = __popc(w & 0xFFFFu); if (k >= c) { k -= c; pos += 16; w >>= 16; }
+    c = __popc(w & 0xFFu);   if (k >= c) { k -= c; pos += 8;  w >>= 8; }
+    c = __popc(w & 0xFu);    if (k >= c) { k -= c; pos += 4;  w >>= 4; }
+    c = __popc(w & 0x3u);    if (k >= c) { k -= c; pos += 2;  w >>= 2; }
+    if (k >= (int)(w & 1u)) pos += 1;
+    return pos;
+}
+__device__ __forceinline__ double bperm_d(int addr, double v) {
+    const int lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(v));
+    const int hi = __builtin_amdgcn_ds_bpermute(addr, __double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
+// Single-wavefront variant for large batches: one wave per group holds up to R
+// conditions per lane (slots), so the per-step work that is the same for every
+// condition (candidate reduction, division, multipliers) is done once per group
+// rather than once per wave.  A chosen condition leaves a hole; whenever the
+// conditions still held fit in fewer slots they are packed to the front in
+// (slot, lane) order by lane permutes, so that the per-condition work of a step
+// covers ceil(held / 64) slots rather than R.  Each condition keeps its index
+// within the leaf, which breaks ties between candidates as above.
 template <int R, int NR>
 __global__ __launch_bounds__(64) void k_leaf_loop_sw(const LeafArgs a) {
     constexpr int C = 4 + NR;
+    constexpr int PASSIVE = 0x100;           // deferred: updated, never chosen
     const int64_t g = blockIdx.x;
     const int lane = threadIdx.x;
     const int K = a.K;
@@ -1056,16 +1080,18 @@ __global__ __launch_bounds__(64) void k_leaf_loop_sw(const LeafArgs a) {
     LeafRec* rec = a.rec + g * a.rec_stride;
     double2 r[R][C];
     double2 sg[R];
-    bool alive[R], passive[R];
+    int hid[R];                              // condition index within the leaf (| PASSIVE); -1 = empty
 #pragma unroll
     for (int i = 0; i < R; ++i) {
         const int h = lane + 64 * i;
-        alive[i] = h < K;
-        passive[i] = false;
+        const bool in = h < K;
+        hid[i] = in ? h : -1;
 #pragma unroll
-        for (int c = 0; c < C; ++c) r[i][c] = alive[i] ? ph[c * nq + q0 + h] : c2(0.0, 0.0);
-        sg[i] = alive[i] ? cond_node(q0 + h, a.N, a.M, a.p, K, a.tw, a.Q) : c2(0.0, 0.0);
+        for (int c = 0; c < C; ++c) r[i][c] = in ? ph[c * nq + q0 + h] : c2(0.0, 0.0);
+        sg[i] = in ? cond_node(q0 + h, a.N, a.M, a.p, K, a.tw, a.Q) : c2(0.0, 0.0);
     }
+    int held = K;                            // conditions held (chosen ones leave)
+    int ns = (K + 63) / 64;                  // slots in use
     int dl[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) dl[c] = a.st[g].delta[c];
@@ -1074,7 +1100,8 @@ __global__ __launch_bounds__(64) void k_leaf_loop_sw(const LeafArgs a) {
         unsigned long long best = 0ull;
 #pragma unroll
         for (int i = 0; i < R; ++i) {
-            if (!alive[i]) continue;
+            if (i >= ns) break;
+            if (hid[i] < 0 || (hid[i] & PASSIVE)) continue;
             double a2[4];
             double amax = 0.0;
 #pragma unroll
@@ -1089,7 +1116,7 @@ __global__ __launch_bounds__(64) void k_leaf_loop_sw(const LeafArgs a) {
                 }
             }
             if (piv >= 0) {
-                const unsigned long long k = cand_key(kd, pm, piv, i * 64 + lane);
+                const unsigned long long k = cand_key(kd, pm, piv, hid[i]);
                 best = k > best ? k : best;
             }
         }
@@ -1097,7 +1124,14 @@ __global__ __launch_bounds__(64) void k_leaf_loop_sw(const LeafArgs a) {
         if (wk == 0ull) { info = 1; break; }      // no admissible pivot: breakdown
         const int idx = 255 - (int)(wk & 255ull);
         const int piv = (int)((wk >> 8) & 3ull);
-        const int wl = idx & 63, si = idx >> 6;
+        // slot and lane holding the chosen condition
+        int si = 0, wl = 0;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            if (i >= ns) break;
+            const unsigned long long m = __ballot(hid[i] == idx);
+            if (m) { si = i; wl = (int)__builtin_ctzll(m); }
+        }
         double2 rc[C];
         double2 sc = c2(0.0, 0.0);
 #pragma unroll
@@ -1119,13 +1153,14 @@ __global__ __launch_bounds__(64) void k_leaf_loop_sw(const LeafArgs a) {
                 // difficult point: set aside for the end of the solve; no step is taken
 #pragma unroll
                 for (int i = 0; i < R; ++i)
-                    if (i == si && lane == wl) { alive[i] = false; passive[i] = true; }
+                    if (i == si && lane == wl) hid[i] |= PASSIVE;
                 if (lane == 0) rec[step].piv = -1;
                 continue;
             }
         }
 #pragma unroll
-        for (int i = 0; i < R; ++i) if (i == si && lane == wl) alive[i] = false;
+        for (int i = 0; i < R; ++i) if (i == si && lane == wl) hid[i] = -1;
+        held -= 1;
         // -1 / r_pi
         const double den = 1.0 / cabs2(rp);
         const double2 inv = c2(-rp.x * den, rp.y * den);
@@ -1142,7 +1177,8 @@ __global__ __launch_bounds__(64) void k_leaf_loop_sw(const LeafArgs a) {
         }
 #pragma unroll
         for (int i = 0; i < R; ++i) {
-            if (!alive[i] && !passive[i]) continue;
+            if (i >= ns) break;
+            if (hid[i] < 0) continue;
             double2 rpv;
             switch (piv) {
                 case 0: rpv = r[i][0]; break;
@@ -1163,6 +1199,58 @@ __global__ __launch_bounds__(64) void k_leaf_loop_sw(const LeafArgs a) {
         }
 #pragma unroll
         for (int c = 0; c < 4; ++c) if (c == piv) dl[c] += 1;
+        const int nsn = (held + 63) / 64;
+        if (nsn < ns) {
+            // pack: destination position p = 64 j + lane takes the p-th held condition in
+            // (slot, lane) order, which sits at a position >= p, so slot j is rewritten only
+            // after every read of it
+            unsigned long long m[R];
+            int pre[R + 1];
+            pre[0] = 0;
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                m[i] = i < ns ? __ballot(hid[i] >= 0) : 0ull;
+                pre[i + 1] = pre[i] + __popcll(m[i]);
+            }
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                if (j >= nsn) break;
+                const int p = 64 * j + lane;
+                int ssl = j;
+#pragma unroll
+                for (int i = j + 1; i < R; ++i) if (i < ns && p >= pre[i]) ssl = i;
+                unsigned long long ms = m[j];
+#pragma unroll
+                for (int i = j + 1; i < R; ++i) if (ssl == i) ms = m[i];
+                const bool valid = p < held;
+                const int addr = valid ? 4 * nth_set_bit(ms, p - pre[ssl]) : 4 * lane;
+                double2 tr[C];
+                double2 ts = c2(0.0, 0.0);
+                int th = -1;
+#pragma unroll
+                for (int c = 0; c < C; ++c) tr[c] = c2(0.0, 0.0);
+#pragma unroll
+                for (int i = j; i < R; ++i) {
+                    if (i >= ns) break;
+                    const bool take = valid && ssl == i;
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        const double x = bperm_d(addr, r[i][c].x), y = bperm_d(addr, r[i][c].y);
+                        if (take) tr[c] = c2(x, y);
+                    }
+                    const double x = bperm_d(addr, sg[i].x), y = bperm_d(addr, sg[i].y);
+                    const int hh = __builtin_amdgcn_ds_bpermute(addr, hid[i]);
+                    if (take) { ts = c2(x, y); th = hh; }
+                }
+#pragma unroll
+                for (int c = 0; c < C; ++c) r[j][c] = tr[c];
+                sg[j] = ts;
+                hid[j] = th;
+            }
+#pragma unroll
+            for (int j = 0; j < R; ++j) if (j >= nsn) hid[j] = -1;
+            ns = nsn;
+        }
     }
     if (a.defer_tol2 > 0.0) {
         // append the deferred conditions of this leaf with their current residual rows
@@ -1172,11 +1260,11 @@ __global__ __launch_bounds__(64) void k_leaf_loop_sw(const LeafArgs a) {
         const int nd0 = a.st[g].ndef;
 #pragma unroll
         for (int i = 0; i < R; ++i) {
-            if (passive[i]) {
+            if (hid[i] >= 0 && (hid[i] & PASSIVE)) {
                 const int pos = nd0 + atomicAdd(&sh_nd, 1);
                 if (pos < a.dl.cap) {
                     const int64_t e = g * a.dl.cap + pos;
-                    a.dl.q[e] = (int32_t)(q0 + lane + 64 * i);
+                    a.dl.q[e] = (int32_t)(q0 + (hid[i] & 0xFF));
                     a.dl.node[e] = sg[i];
 #pragma unroll
                     for (int c = 0; c < C; ++c) a.dl.res[e * C + c] = r[i][c];

@@ -1,6 +1,8 @@
 """GPU adjoint (backward) through the C ABI, against the CPU oracle's
 hand-derived gradients (dense FP64), against central finite differences of the
 GPU forward solve, and through torch.autograd."""
+import os
+
 import numpy as np
 import pytest
 
@@ -10,13 +12,16 @@ pytestmark = pytest.mark.gpu
 import oracle
 import workloads as W
 
+LEAF_WAVE_GROUPS = int(os.environ.get("TIKH_TEST_LEAF_WAVE_GROUPS", "1536"))
+
 
 @pytest.fixture(scope="module")
 def P():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     import paper_1302_6945_amd as P
-    P.set_options(n_lim=256, refine=1)
+    # the leaf-step variant can be forced for the whole module (1: one wavefront per group)
+    P.set_options(n_lim=256, refine=1, leaf_wave_groups=LEAF_WAVE_GROUPS)
     return P
 
 

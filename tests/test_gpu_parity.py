@@ -7,6 +7,8 @@ full-size problems are checked through the optimality condition
 T^H (b - T x) = lambda^2 x, which holds at any size.  Tolerance: relative
 2-norm error <= 1e-9 against the oracle (the accuracy target for problems
 whose regularized normal matrix has condition number <= 1e6)."""
+import os
+
 import numpy as np
 import pytest
 
@@ -18,6 +20,7 @@ import oracle
 import workloads as W
 
 TOL = 1e-9
+LEAF_WAVE_GROUPS = int(os.environ.get("TIKH_TEST_LEAF_WAVE_GROUPS", "1536"))
 
 
 @pytest.fixture(scope="module")
@@ -25,7 +28,8 @@ def P():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     import paper_1302_6945_amd as P
-    P.set_options(n_lim=256, refine=1)
+    # the leaf-step variant can be forced for the whole module (1: one wavefront per group)
+    P.set_options(n_lim=256, refine=1, leaf_wave_groups=LEAF_WAVE_GROUPS)
     yield P
     P.set_options(n_lim=256, refine=1)
 
@@ -197,7 +201,7 @@ def test_leaf_single_wavefront_parity(P, nlim, defer_tol):
             x, info = P.solve_batched(*args)
             torch.cuda.synchronize()
         finally:
-            P.set_options(n_lim=256, defer_tol=0.0, leaf_wave_groups=1536)
+            P.set_options(n_lim=256, defer_tol=0.0, leaf_wave_groups=LEAF_WAVE_GROUPS)
         x = x.cpu().numpy()
         assert (info.cpu().numpy() == 0).all(), (wg, nlim, defer_tol)
         for i, xr in enumerate(ref):
