@@ -106,13 +106,14 @@ static void prof_print_detail() {
         fprintf(stderr, "[tikh prof] %-70s %10.3f ms %8lld launches\n", e.second.c_str(), e.first,
                 (long long)kprof.detail[e.second].second);
 }
-#define LAUNCH(kname, kern, grid, block, ...)                                              \
+#define LAUNCH_SH(kname, kern, grid, block, shmem, ...)                                     \
     do {                                                                                 \
         prof_begin(kname);                                                               \
-        hipLaunchKernelGGL(kern, grid, block, 0, g.stream, __VA_ARGS__);                 \
+        hipLaunchKernelGGL(kern, grid, block, shmem, g.stream, __VA_ARGS__);             \
         prof_end(kname);                                                                 \
         g.launches++;                                                                    \
     } while (0)
+#define LAUNCH(kname, kern, grid, block, ...) LAUNCH_SH(kname, kern, grid, block, 0, __VA_ARGS__)
 
 static void ensure_init() {
     if (g.init) return;
@@ -569,11 +570,22 @@ static void launch_leaf(const Plan& pl, const LeafArgs& la, const BuildArgs& ba,
     } else {
         LAUNCH("leaf_loop", k_leaf_loop<NR>, dim3((unsigned)G), dim3(64 * waves), la);
     }
-    if (slots <= 1) LAUNCH("leaf_build", (k_leaf_build<1, NR>), dim3((unsigned)G), dim3(256), ba);
-    else if (slots <= 2) LAUNCH("leaf_build", (k_leaf_build<2, NR>), dim3((unsigned)G), dim3(256), ba);
-    else if (slots <= 3) LAUNCH("leaf_build", (k_leaf_build<3, NR>), dim3((unsigned)G), dim3(256), ba);
-    else if (slots <= 4) LAUNCH("leaf_build", (k_leaf_build<4, NR>), dim3((unsigned)G), dim3(256), ba);
-    else LAUNCH("leaf_build", (k_leaf_build<5, NR>), dim3((unsigned)G), dim3(256), ba);
+    // the basis is built with one slot of 64 coefficients per polynomial (the pivot rule keeps
+    // the column degrees near K/4); a group with a column degree of 64 or more is flagged and
+    // built by a second launch with `slots` slots that skips every other group
+    const size_t shm = sizeof(LeafRec) * (size_t)pl.K;
+    BuildArgs b1 = ba;
+    b1.narrow = slots > 1;
+    b1.wide_pass = 0;
+    LAUNCH_SH("leaf_build", (k_leaf_build<1, NR>), dim3((unsigned)G), dim3(256), shm, b1);
+    if (slots <= 1) return;
+    BuildArgs b2 = ba;
+    b2.narrow = 0;
+    b2.wide_pass = 1;
+    if (slots <= 2) LAUNCH_SH("leaf_build", (k_leaf_build<2, NR>), dim3((unsigned)G), dim3(256), shm, b2);
+    else if (slots <= 3) LAUNCH_SH("leaf_build", (k_leaf_build<3, NR>), dim3((unsigned)G), dim3(256), shm, b2);
+    else if (slots <= 4) LAUNCH_SH("leaf_build", (k_leaf_build<4, NR>), dim3((unsigned)G), dim3(256), shm, b2);
+    else LAUNCH_SH("leaf_build", (k_leaf_build<5, NR>), dim3((unsigned)G), dim3(256), shm, b2);
 }
 
 static int run_leaf(const Plan& pl, const Layout& L, const Bufs& b, int64_t G, int t, double2* dst, int64_t dstride,

@@ -1298,6 +1298,9 @@ struct BuildArgs {
     int64_t cap;
     SlotMeta* meta;        // [g]
     int K;
+    // narrow pass (one slot of 64 coefficients): a group whose basis needs more is only
+    // flagged; the wide pass then builds the flagged groups alone
+    int narrow, wide_pass;
 };
 
 template <int S>
@@ -1312,14 +1315,31 @@ __global__ __launch_bounds__(256) void k_leaf_build(const BuildArgs a) {
     const int64_t g = blockIdx.x;
     const int row = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    __shared__ LeafRec lrec[LEAF_MAX];
+    if (a.wide_pass && a.st[g].wide == 0) return;    // built by the narrow pass
+    extern __shared__ double2 lds_dyn[];             // K records
+    LeafRec* lrec = (LeafRec*)lds_dyn;
     {
         const double2* src = (const double2*)(a.rec + g * a.rec_stride);
-        double2* dstp = (double2*)lrec;
+        double2* dstp = lds_dyn;
         const int nv = a.K * (int)(sizeof(LeafRec) / sizeof(double2));
         for (int i = threadIdx.x; i < nv; i += 256) dstp[i] = src[i];
     }
     __syncthreads();
+    if (a.narrow) {
+        // every column degree is at most the largest number of steps pivoting on one column
+        __shared__ int npiv[4];
+        if (threadIdx.x < 4) npiv[threadIdx.x] = 0;
+        __syncthreads();
+        for (int i = threadIdx.x; i < a.K; i += 256) {
+            const int pv = lrec[i].piv;
+            if (pv >= 0) atomicAdd(&npiv[pv], 1);
+        }
+        __syncthreads();
+        const bool wide = max(max(npiv[0], npiv[1]), max(npiv[2], npiv[3])) > 64 * S - 1;
+        __syncthreads();
+        if (threadIdx.x == 0) ((SolveState*)a.st)[g].wide = wide ? 1 : 0;
+        if (wide) return;
+    }
     double2 P[C][S];
 #pragma unroll
     for (int c = 0; c < C; ++c)
