@@ -698,20 +698,24 @@ static int run_product_chunk(const Plan& pl, const Layout& L, const Bufs& b, int
     return TIKH_OK;
 }
 
+// direct evaluation in two passes: groups that fit the narrow LDS budget, then the flagged rest
+template <int NR>
+static void launch_eval_direct(const Plan& pl, const Layout& L, const Bufs& b, int64_t G, int d, int64_t t0,
+                               int64_t nleaves, const double2* tw) {
+    LAUNCH("eval_direct", (k_eval_direct<NR, ED_LDS_NARROW, 1>), dim3((unsigned)G), dim3(256), b.phi, L.sphi,
+           b.slotS[d], L.sslot[d], pl.cap[d] + 1, b.metaS[d], t0, nleaves, pl.N, pl.M, pl.p, pl.K, tw, pl.Q, b.st);
+    LAUNCH("eval_direct", (k_eval_direct<NR, ED_LDS, 2>), dim3((unsigned)G), dim3(256), b.phi, L.sphi,
+           b.slotS[d], L.sslot[d], pl.cap[d] + 1, b.metaS[d], t0, nleaves, pl.N, pl.M, pl.p, pl.K, tw, pl.Q, b.st);
+}
+
 static int run_eval(const Plan& pl, const Layout& L, const Bufs& b, int64_t G, int d, int64_t idx, const double2* tw) {
     if (d == pl.p || ((2 * pl.N) >> d) <= DIRECT_MAX_COND) {
         const int64_t ridx = idx + 1;
         const int64_t nleaves = (int64_t)1 << (pl.p - d);
         const int64_t t0 = ridx << (pl.p - d);
-        if (L.nr == 1)
-            LAUNCH("eval_direct", k_eval_direct<1>, dim3((unsigned)G), dim3(256), b.phi, L.sphi, b.slotS[d], L.sslot[d],
-                   pl.cap[d] + 1, b.metaS[d], t0, nleaves, pl.N, pl.M, pl.p, pl.K, tw, pl.Q);
-        else if (L.nr == 2)
-            LAUNCH("eval_direct", k_eval_direct<2>, dim3((unsigned)G), dim3(256), b.phi, L.sphi, b.slotS[d], L.sslot[d],
-                   pl.cap[d] + 1, b.metaS[d], t0, nleaves, pl.N, pl.M, pl.p, pl.K, tw, pl.Q);
-        else
-            LAUNCH("eval_direct", k_eval_direct<4>, dim3((unsigned)G), dim3(256), b.phi, L.sphi, b.slotS[d], L.sslot[d],
-                   pl.cap[d] + 1, b.metaS[d], t0, nleaves, pl.N, pl.M, pl.p, pl.K, tw, pl.Q);
+        if (L.nr == 1) launch_eval_direct<1>(pl, L, b, G, d, t0, nleaves, tw);
+        else if (L.nr == 2) launch_eval_direct<2>(pl, L, b, G, d, t0, nleaves, tw);
+        else launch_eval_direct<4>(pl, L, b, G, d, t0, nleaves, tw);
         return TIKH_OK;
     }
     // the scratch pool is split for this level: as many groups per launch as fit
@@ -745,8 +749,13 @@ static int run_product(const Plan& pl, const Layout& L, const Bufs& b, int64_t G
                    b.slotT[dc], L.sT, pl.cap[dc] + 1, b.metaT[dc], pl.K, lo, mid, hi);
     }
     if (dp > 0 && dc == pl.p) {
-        LAUNCH("prod_direct", k_prod_direct, dim3((unsigned)G), dim3(256), b.slotS[dc], L.sslot[dc], pl.cap[dc] + 1,
-               b.metaS[dc], b.slotT[dc], L.sT, pl.cap[dc] + 1, b.metaT[dc], dst, dstride, dcap + 1, dmeta, b.st, L.C);
+        // two passes: groups whose factors fit the narrow LDS budget, then the flagged rest
+        LAUNCH("prod_direct", (k_prod_direct<PD_LDS_NARROW, 1>), dim3((unsigned)G), dim3(256), b.slotS[dc], L.sslot[dc],
+               pl.cap[dc] + 1, b.metaS[dc], b.slotT[dc], L.sT, pl.cap[dc] + 1, b.metaT[dc], dst, dstride, dcap + 1,
+               dmeta, b.st, L.C);
+        LAUNCH("prod_direct", (k_prod_direct<PD_LDS, 2>), dim3((unsigned)G), dim3(256), b.slotS[dc], L.sslot[dc],
+               pl.cap[dc] + 1, b.metaS[dc], b.slotT[dc], L.sT, pl.cap[dc] + 1, b.metaT[dc], dst, dstride, dcap + 1,
+               dmeta, b.st, L.C);
         return TIKH_OK;
     }
     // the scratch pool is split for this level: FL and FR hold the largest

@@ -46,7 +46,7 @@ struct SolveState {
     int32_t delta[4];  // tau-degrees of basis columns 1..4 (column 5 stays 0)
     int32_t info;      // 0 ok; or of 1 breakdown, 2 degree bound, 3 non-finite, 4 too many deferred conditions
     int32_t ndef;      // deferred (difficult) conditions of the current solve
-    int32_t wide;      // the current leaf basis has a column degree >= 64 (built by the wide pass)
+    int32_t wide;      // set by the narrow pass of a two-pass kernel: this group is left to the wide pass
     double e0;         // relative size of the first refinement correction (error estimate of the first solve)
 };
 

@@ -1507,19 +1507,26 @@ __global__ __launch_bounds__(256) void k_eval_apply(double2* __restrict__ phi, i
 // residual rows are staged in LDS; each thread evaluates one (node, column)
 // item as four independent Horner chains (rows 0..3).  Groups whose degrees
 // exceed the LDS budget evaluate from global memory, one node per thread.
-constexpr int ED_LDS = 4608;       // complex elements of LDS staging
+// Two passes: the narrow pass (MODE 1, a smaller LDS budget, so more workgroups
+// per CU) handles the groups that fit it and flags the others (SolveState::wide);
+// the wide pass (MODE 2) handles only the flagged groups, with the larger budget
+// and the global-memory path.  MODE 0 handles every group in one pass.
+constexpr int ED_LDS = 4608;       // complex elements of LDS staging (wide pass)
+constexpr int ED_LDS_NARROW = 2496;
 
-template <int NR>
+template <int NR, int LDSN, int MODE>
 __global__ __launch_bounds__(256) void k_eval_direct(double2* __restrict__ phi, int64_t phi_stride,
                                                      const double2* __restrict__ B, int64_t b_stride, int64_t cp1,
                                                      const SlotMeta* __restrict__ meta, int64_t t0, int64_t nleaves,
                                                      int64_t N, int64_t M, int p, int K,
-                                                     const double2* __restrict__ tw, int64_t Q) {
+                                                     const double2* __restrict__ tw, int64_t Q,
+                                                     SolveState* __restrict__ st) {
     constexpr int C = 4 + NR;
-    __shared__ double2 sh[ED_LDS];
+    __shared__ double2 sh[LDSN];
     __shared__ int sdeg[C];
     __shared__ double ssc[C];
     const int64_t g = blockIdx.x;
+    if (MODE == 2 && st[g].wide == 0) return;
     if (threadIdx.x < C) {
         const SlotMeta& mt = meta[g];
         sdeg[threadIdx.x] = mt.deg[threadIdx.x];
@@ -1535,7 +1542,11 @@ __global__ __launch_bounds__(256) void k_eval_direct(double2* __restrict__ phi, 
 #pragma unroll
     for (int c = 0; c < C; ++c) dmax = max(dmax, sdeg[c]);
     const int bs = dmax + 1;                         // coefficient stride of an entry in LDS
-    const bool staged = 4 * C * max(bs, 0) + 2 * C * nodes <= ED_LDS;
+    const bool staged = 4 * C * max(bs, 0) + 2 * C * nodes <= LDSN;
+    if (MODE == 1) {
+        if (threadIdx.x == 0) st[g].wide = staged ? 0 : 1;
+        if (!staged) return;
+    }
     if (staged) {
         double2* shB = sh;                           // [4C][bs], entry row*C + col
         double2* shF = sh + 4 * C * bs;              // [C][2*nodes] residual rows of the subtree
@@ -1571,6 +1582,7 @@ __global__ __launch_bounds__(256) void k_eval_direct(double2* __restrict__ phi, 
         }
         return;
     }
+    if constexpr (MODE != 1) {
     for (int u = threadIdx.x; u < nodes; u += blockDim.x) {
         const int64_t q = qb + 2 * u;
         const double2 z = cond_node(q, N, M, p, K, tw, Q);
@@ -1597,6 +1609,7 @@ __global__ __launch_bounds__(256) void k_eval_direct(double2* __restrict__ phi, 
 #pragma unroll
         for (int c = 0; c < C; ++c) { ph[c * nq + q] = o0[c]; ph[c * nq + q + 1] = o1[c]; }
     }
+    }
 }
 
 // Small subtrees: direct block product [[B0L, VL],[0,I]] [[B0R, VR],[0,I]]
@@ -1607,21 +1620,26 @@ __global__ __launch_bounds__(256) void k_eval_direct(double2* __restrict__ phi, 
 // staged in LDS; each thread forms four consecutive output coefficients of
 // one entry from a sliding window of right-factor coefficients.  Groups whose
 // degrees exceed the LDS budget read the factors from global memory instead.
-constexpr int PD_LDS = 4096;       // complex elements of LDS staging
+// Two passes as for the direct evaluation: the narrow pass takes the groups whose
+// factors fit its budget with every column staged at once.
+constexpr int PD_LDS = 4096;       // complex elements of LDS staging (wide pass)
+constexpr int PD_LDS_NARROW = 2496;
 constexpr int PD_PAD = 3;          // zero padding on each side of a right-factor entry
 
+template <int LDSN, int MODE>
 __global__ __launch_bounds__(256) void k_prod_direct(const double2* __restrict__ BL, int64_t l_stride, int64_t lcp1,
                                                      const SlotMeta* __restrict__ mL,
                                                      const double2* __restrict__ BR, int64_t r_stride, int64_t rcp1,
                                                      const SlotMeta* __restrict__ mR,
                                                      double2* __restrict__ out, int64_t o_stride, int64_t ocp1,
                                                      SlotMeta* __restrict__ mO, SolveState* __restrict__ st, int C) {
-    __shared__ double2 sh[PD_LDS];
-    __shared__ double red[4][256];
+    __shared__ double2 sh[LDSN];
+    __shared__ double red[4][4];
     __shared__ int sdl[MAXC], sdr[MAXC], sdout[MAXC];
     __shared__ double ssl[MAXC], ssr[MAXC];
     __shared__ int sbad;
     const int64_t g = blockIdx.x;
+    if (MODE == 2 && st[g].wide == 0) return;
     if (threadIdx.x == 0) {
         const SlotMeta a = mL[g], b = mR[g];
         int dl = -1;
@@ -1654,8 +1672,12 @@ __global__ __launch_bounds__(256) void k_prod_direct(const double2* __restrict__
     // at once when they fit (every (column, row, block) item in one pass over the
     // threads), else one column at a time
     const int ls = dl + 1, rs = drm + 1 + 2 * PD_PAD;
-    const bool staged = dl >= 0 && drm >= 0 && 16 * ls + 4 * rs <= PD_LDS;
-    const bool all_cols = staged && 16 * ls + 4 * C * rs <= PD_LDS;
+    const bool staged = dl >= 0 && drm >= 0 && 16 * ls + 4 * rs <= LDSN;
+    const bool all_cols = staged && 16 * ls + 4 * C * rs <= LDSN;
+    if (MODE == 1) {
+        if (threadIdx.x == 0) st[g].wide = all_cols ? 0 : 1;
+        if (!all_cols) return;
+    }
     double2* shL = sh;
     double2* shR = sh + 16 * max(ls, 0);
     if (staged) {
@@ -1672,7 +1694,7 @@ __global__ __launch_bounds__(256) void k_prod_direct(const double2* __restrict__
         const int doj = sdout[j];
         const int dr = sdr[j];
         double2 acc[4] = {c2(0.0, 0.0), c2(0.0, 0.0), c2(0.0, 0.0), c2(0.0, 0.0)};
-        if (staged) {
+        if (MODE == 1 || staged) {
             if (dr >= 0) {
                 for (int l = 0; l < 4; ++l) {
                     const int dla = sdl[l];
@@ -1731,7 +1753,7 @@ __global__ __launch_bounds__(256) void k_prod_direct(const double2* __restrict__
             dst[w] = (t >= 0 && t <= dr) ? cscale(R[(int64_t)(l * C + j) * rcp1 + t], ssr[j]) : c2(0.0, 0.0);
         }
     };
-    if (all_cols) {
+    if (MODE == 1 || all_cols) {
         for (int j = 0; j < C; ++j) stage_col(j, shR + j * 4 * rs);
         __syncthreads();
         // items of all columns: column j has 4 * nblk_j items (nblk_j = blocks of 4 coefficients)
@@ -1760,18 +1782,17 @@ __global__ __launch_bounds__(256) void k_prod_direct(const double2* __restrict__
         }
     }
 #pragma unroll
-    for (int c = 0; c < 4; ++c) red[c][threadIdx.x] = cmx[c];
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o)
-#pragma unroll
-            for (int c = 0; c < 4; ++c) red[c][threadIdx.x] = fmax(red[c][threadIdx.x], red[c][threadIdx.x + o]);
-        __syncthreads();
+    for (int c = 0; c < 4; ++c) {
+        const double mx = wave_max_d(cmx[c]);
+        if ((threadIdx.x & 63) == 0) red[c][threadIdx.x >> 6] = mx;
     }
+    __syncthreads();
     if (threadIdx.x == 0) {
         SlotMeta m;
         for (int j = 0; j < MAXC; ++j) m.deg[j] = sdout[j];
-        for (int c = 0; c < 4; ++c) m.colmax_bits[c] = (unsigned long long)__double_as_longlong(sqrt(red[c][0]));
+        for (int c = 0; c < 4; ++c)
+            m.colmax_bits[c] = (unsigned long long)__double_as_longlong(
+                sqrt(fmax(fmax(red[c][0], red[c][1]), fmax(red[c][2], red[c][3]))));
         mO[g] = m;
         if (sbad) atomicOr(&st[g].info, 2);
     }
