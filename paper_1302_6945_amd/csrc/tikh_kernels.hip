@@ -1101,7 +1101,9 @@ __global__ __launch_bounds__(64) void k_leaf_loop_sw(const LeafArgs a) {
 #pragma unroll
         for (int i = 0; i < R; ++i) {
             if (i >= ns) break;
-            if (hid[i] < 0 || (hid[i] & PASSIVE)) continue;
+            // every lane scores its slot (empty and chosen rows are zero or finite); only
+            // held, active conditions enter the reduction
+            const bool act = hid[i] >= 0 && !(hid[i] & PASSIVE);
             double a2[4];
             double amax = 0.0;
 #pragma unroll
@@ -1115,10 +1117,8 @@ __global__ __launch_bounds__(64) void k_leaf_loop_sw(const LeafArgs a) {
                     kd = dl[c]; piv = c; pm = a2[c];
                 }
             }
-            if (piv >= 0) {
-                const unsigned long long k = cand_key(kd, pm, piv, hid[i]);
-                best = k > best ? k : best;
-            }
+            const unsigned long long k = (act && piv >= 0) ? cand_key(kd, pm, piv, hid[i] & 0xFF) : 0ull;
+            best = k > best ? k : best;
         }
         const unsigned long long wk = wave_max_u64(best);
         if (wk == 0ull) { info = 1; break; }      // no admissible pivot: breakdown
@@ -1178,7 +1178,7 @@ __global__ __launch_bounds__(64) void k_leaf_loop_sw(const LeafArgs a) {
 #pragma unroll
         for (int i = 0; i < R; ++i) {
             if (i >= ns) break;
-            if (hid[i] < 0) continue;
+            // empty lanes are updated too: their rows stay finite and are never read
             double2 rpv;
             switch (piv) {
                 case 0: rpv = r[i][0]; break;
