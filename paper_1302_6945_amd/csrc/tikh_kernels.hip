@@ -924,7 +924,9 @@ __global__ __launch_bounds__(256) void k_leaf_loop(const LeafArgs a) {
     for (int step = 0; step < K; ++step) {
         const int par = step & 1;
         unsigned long long key = 0ull;
-        if (alive) {
+        {
+            // every lane scores its row (absent and chosen rows are zero or finite); only
+            // active conditions enter the reduction
             double a2[4];
             double amax = 0.0;
 #pragma unroll
@@ -938,7 +940,7 @@ __global__ __launch_bounds__(256) void k_leaf_loop(const LeafArgs a) {
                     kd = dl[c]; piv = c; pm = a2[c];
                 }
             }
-            if (piv >= 0) key = cand_key(kd, pm, piv, h);
+            key = (alive && piv >= 0) ? cand_key(kd, pm, piv, h) : 0ull;
         }
         const unsigned long long wk = wave_max_u64(key);
         if (wk != 0ull && h == 255 - (int)(wk & 255ull)) {
@@ -988,7 +990,8 @@ __global__ __launch_bounds__(256) void k_leaf_loop(const LeafArgs a) {
             o.piv = piv;
             o.q = (int)(q0 + idx);
         }
-        if (alive || passive) {
+        {
+            // every lane is updated: rows of absent and chosen conditions are never read
             double2 rpv;
             switch (piv) {
                 case 0: rpv = r[0]; break;
