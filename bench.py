@@ -41,9 +41,9 @@ def source_digest(root):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(root, kernel, args):
+def measured_traffic(root, kernel, args, nlim):
     """HBM bytes per launch of `kernel` from the committed counter summary, when it was taken on
-    the current sources and at this workload; None otherwise."""
+    the current sources, at this workload and leaf cutoff; None otherwise."""
     path = os.path.join(root, "profiles", "%s_hbm_traffic_headline_n16384.md" % kernel)
     if not os.path.exists(path):
         return None
@@ -54,7 +54,7 @@ def measured_traffic(root, kernel, args):
                 rec = json.loads(line.split(":", 1)[1])
     if not rec or rec.get("source_digest") != source_digest(root):
         return None
-    if rec.get("nprob") != args.nprob or rec.get("n") != args.n:
+    if rec.get("nprob") != args.nprob or rec.get("n") != args.n or rec.get("n_lim") != nlim:
         return None
     return rec.get("bytes_per_launch")
 
@@ -206,7 +206,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    traffic = measured_traffic(ROOT, roofline["kernel"], args)
+    traffic = measured_traffic(ROOT, roofline["kernel"], args, nlim)
     if traffic is not None:
         roofline["traffic"] = traffic
 
