@@ -41,6 +41,13 @@ def source_digest(root):
     return h.hexdigest()[:16]
 
 
+def pick_nlim(tune_ms, tol=0.02):
+    """Leaf cutoff from the autotuner's timings: the largest one within `tol` of the fastest
+    (the timings of 256 groups carry about 1% noise; a larger cutoff means fewer tree levels)."""
+    best = min(tune_ms.values())
+    return max(int(k) for k, v in tune_ms.items() if v <= (1.0 + tol) * best)
+
+
 def measured_traffic(root, kernel, args, nlim):
     """HBM bytes per launch of `kernel` from the committed counter summary, when it was taken on
     the current sources, at this workload and leaf cutoff; None otherwise."""
@@ -98,7 +105,8 @@ def main():
     tune = None
     if args.nlim == "auto":
         P.set_options(refine=1)
-        nlim, tune_ms = P.autotune_nlim(int(round(float(np.mean(ms)))), args.n, groups=256, nrhs=args.nrhs)
+        _, tune_ms = P.autotune_nlim(int(round(float(np.mean(ms)))), args.n, groups=256, nrhs=args.nrhs)
+        nlim = pick_nlim(tune_ms)
         tune = {str(k): round(v, 1) for k, v in tune_ms.items()}
     else:
         nlim = int(args.nlim)
