@@ -345,3 +345,39 @@ def test_deblurring_full_size_known_solution(P):
     y = _banded_normal_ld(h, pr.n, pr.x_true, lam).astype(np.float64)
     x = P.solve_normal(dev(pr.col), dev(pr.row), dev(y), lam).cpu().numpy()
     assert relerr(x, pr.x_true) <= TOL, relerr(x, pr.x_true)
+
+
+def test_headline_batch_full_config_sampled(P):
+    """The benchmark's launch configuration: 256 problems of the headline shape
+    (n = 2^14, m = n + U{0..n/4}) x 8 lambdas x 4 right-hand sides in one
+    batched call, i.e. 2048 groups in one chunk, which takes the one-wavefront-
+    per-group leaf steps.  32 generated problems are used 8 times each, every
+    copy with its lambda path scaled by its own factor so that no two groups
+    hold the same data.  Sampled solves across the batch must agree with the
+    single-problem path (whose accuracy at this size is pinned by the
+    known-solution tests above) to the parity tolerance."""
+    base = [W.headline(i, n=2 ** 14, nrhs=4, nlam=8) for i in range(32)]
+    probs = []
+    for c in range(8):
+        for p in base:
+            probs.append((p, [lam * (1.0 + 0.01 * c) for lam in p.lams]))
+    ms = [p.m for p, _ in probs]
+    ns = [p.n for p, _ in probs]
+    lams = [l for _, ls in probs for l in ls]
+    col = dev(np.concatenate([p.col for p, _ in probs]))
+    row = dev(np.concatenate([p.row for p, _ in probs]))
+    bb = dev(np.concatenate([np.concatenate(p.b) for p, _ in probs]))
+    P.set_options(n_lim=256, refine=1, leaf_wave_groups=1536)
+    try:
+        x, info = P.solve_batched(ms, ns, col, row, lams, 4, bb)
+        torch.cuda.synchronize()
+    finally:
+        P.set_options(leaf_wave_groups=LEAF_WAVE_GROUPS)
+    assert (info.cpu().numpy() == 0).all()
+    x = x.cpu().numpy()
+    n = 2 ** 14
+    for (ip, j, r) in [(0, 0, 0), (77, 7, 3), (150, 3, 1), (255, 5, 2), (200, 0, 2)]:
+        p, ls = probs[ip]
+        off = ((ip * 8 + j) * 4 + r) * n
+        xs = P.solve(dev(p.col), dev(p.row), dev(p.b[r]), ls[j]).cpu().numpy()
+        assert relerr(x[off:off + n], xs) <= TOL, (ip, j, r, relerr(x[off:off + n], xs))
