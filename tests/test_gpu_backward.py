@@ -168,3 +168,52 @@ def test_complex_full_size_gradient_central_differences(P):
         an = (np.sum((np.conj(g_col) * dc).real) + np.sum((np.conj(g_row) * dr).real)
               + np.sum((np.conj(g_b) * db).real) + g_lam * dl)
         assert abs(fd - an) <= 1e-5 * max(abs(an), 1.0), (i, fd, an)
+
+
+def test_backward_batch_full_config_sampled(P):
+    """The benchmark's launch configuration for the adjoint: 256 headline-shaped
+    problems (n = 2^14) x 8 lambdas x 4 right-hand sides, forward and backward
+    in one batched call each (2048 groups in one chunk).  32 generated problems
+    are used 8 times, each copy with its own scaled lambda path.  For sampled
+    solves every gradient block (generator column and row, b, lambda) must
+    agree with the single-problem backward fed the same x and upstream gradient,
+    whose accuracy is pinned against the oracle and central differences above."""
+    base = [W.headline(i, n=2 ** 14, nrhs=4, nlam=8) for i in range(32)]
+    probs = []
+    for c in range(8):
+        for p in base:
+            probs.append((p, [lam * (1.0 + 0.01 * c) for lam in p.lams]))
+    n = 2 ** 14
+    ms = [p.m for p, _ in probs]
+    ns = [n] * len(probs)
+    lams = [l for _, ls in probs for l in ls]
+    col = dev(np.concatenate([p.col for p, _ in probs]))
+    row = dev(np.concatenate([p.row for p, _ in probs]))
+    bb = dev(np.concatenate([np.concatenate(p.b) for p, _ in probs]))
+    xt = dev(np.concatenate([np.tile(p.x_true, 32) for p, _ in probs]))
+    P.set_options(n_lim=256, refine=1, leaf_wave_groups=1536)
+    try:
+        x, info = P.solve_batched(ms, ns, col, row, lams, 4, bb)
+        gx = x - xt
+        g_col, g_row, g_b, g_lam, binfo = P.backward_batched(ms, ns, col, row, lams, 4, bb, x, gx)
+        torch.cuda.synchronize()
+    finally:
+        P.set_options(leaf_wave_groups=LEAF_WAVE_GROUPS)
+    assert (info.cpu().numpy() == 0).all() and (binfo.cpu().numpy() == 0).all()
+    x, gx = x.cpu().numpy(), gx.cpu().numpy()
+    g_col, g_row, g_b, g_lam = g_col.cpu().numpy(), g_row.cpu().numpy(), g_b.cpu().numpy(), g_lam.cpu().numpy()
+    tol = 1e-9
+    colsum = np.concatenate([[0], np.cumsum(ms)])
+    for (ip, j, r) in [(0, 0, 0), (77, 7, 3), (150, 3, 1), (255, 5, 2)]:
+        p, ls = probs[ip]
+        m = p.m
+        k = (ip * 8 + j) * 4 + r
+        xs = x[k * n:(k + 1) * n]
+        gs = gx[k * n:(k + 1) * n]
+        oc = colsum[ip] * 32 + (j * 4 + r) * m
+        sc, sr, sb, sl = P.backward(dev(p.col), dev(p.row), dev(p.b[r]), ls[j], dev(xs), dev(gs))
+        sc, sr, sb = sc.cpu().numpy(), sr.cpu().numpy(), sb.cpu().numpy()
+        assert np.linalg.norm(g_col[oc:oc + m] - sc) <= tol * np.linalg.norm(sc), (ip, j, r, "col")
+        assert np.linalg.norm(g_row[k * n:(k + 1) * n] - sr) <= tol * np.linalg.norm(sr), (ip, j, r, "row")
+        assert np.linalg.norm(g_b[oc:oc + m] - sb) <= tol * np.linalg.norm(sb), (ip, j, r, "b")
+        assert abs(g_lam[k] - float(sl)) <= tol * max(1.0, abs(float(sl))), (ip, j, r, "lambda")
