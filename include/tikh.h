@@ -146,9 +146,31 @@ int tikh_fft_batched(void* data, int64_t items, int64_t nlines, int64_t len, int
  */
 int tikh_autotune_nlim(int64_t m, int64_t n, int64_t groups, int32_t nrhs, int32_t* best, double* ms);
 
+/*
+ * Workspace.  By default the library keeps one device buffer for all calls and
+ * grows it (one hipMalloc) when a call needs more, splitting a batch into equal
+ * chunks that fit 85% of free device memory.  A caller with its own allocator
+ * can hand the library a buffer instead:
+ *  - tikh_workspace_bytes (host only, no device work): the bytes with which a
+ *    batched solve or backward of these shapes (nprob problems of m[p] x n[p],
+ *    host arrays; nlam lambdas; nrhs right-hand sides) runs every group in one
+ *    chunk; *bytes is a host pointer.  TIKH_EINVAL for shapes the solves
+ *    reject.
+ *  - tikh_set_workspace(ptr, bytes): use this device buffer (256-byte aligned,
+ *    caller-owned, not touched by the caller until it is replaced) for every
+ *    later call; the library frees its own buffer.  Batches are split into
+ *    chunks that fit `bytes`; a call in which not even one group fits returns
+ *    TIKH_ENOMEM.  tikh_set_workspace(NULL, 0) returns to the library's own
+ *    buffer.  Synchronizes the library stream.  Twiddle tables (one per
+ *    transform size, at most a few MB) are still allocated by the library.
+ */
+int tikh_workspace_bytes(int64_t nprob, const int64_t* m, const int64_t* n, int64_t nlam, int64_t nrhs,
+                         size_t* bytes);
+int tikh_set_workspace(void* ptr, size_t bytes);
+
 /* Library state.  tikh_init is optional (the first call initializes). */
 int tikh_init(void);
-int tikh_release(void);                              /* free workspace */
+int tikh_release(void);                              /* free the library's workspace and tables */
 int tikh_set_stream(void* hip_stream);               /* hipStream_t; NULL = null stream */
 int tikh_set_options(const tikh_opts* opts);         /* host pointer */
 int tikh_get_options(tikh_opts* opts);               /* host pointer */

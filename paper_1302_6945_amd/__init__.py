@@ -15,10 +15,10 @@ from ._lib import (TikhError, lib, library_path, set_options, get_options, get_s
                    tikh_toeplitz_solve_normal_z, tikh_toeplitz_solve_batched,
                    tikh_toeplitz_solve_backward, tikh_toeplitz_solve_backward_z,
                    tikh_toeplitz_solve_backward_batched, solve, solve_normal, solve_batched,
-                   backward, backward_batched)
+                   backward, backward_batched, workspace_bytes, set_workspace)
 from .autograd import ToeplitzTikhonov, tikhonov_solve
 
-__all__ = ["TikhError", "lib", "library_path", "set_options", "get_options", "get_stats", "plan_info", "fft_batched", "autotune_nlim", "profile_kernel", "profile_read",
+__all__ = ["workspace_bytes", "set_workspace", "TikhError", "lib", "library_path", "set_options", "get_options", "get_stats", "plan_info", "fft_batched", "autotune_nlim", "profile_kernel", "profile_read",
            "tikh_toeplitz_solve", "tikh_toeplitz_solve_z", "tikh_toeplitz_solve_normal",
            "tikh_toeplitz_solve_normal_z", "tikh_toeplitz_solve_batched",
            "tikh_toeplitz_solve_backward", "tikh_toeplitz_solve_backward_z",

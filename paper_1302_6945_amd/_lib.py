@@ -42,6 +42,8 @@ tikh_plan_info = _sig("tikh_plan_info", [_I64, _I64, ctypes.c_int32, ctypes.POIN
                                          ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
                                          ctypes.POINTER(ctypes.c_int64)])
 _sig("tikh_release", [])
+tikh_workspace_bytes = _sig("tikh_workspace_bytes", [_I64, _P, _P, _I64, _I64, ctypes.POINTER(ctypes.c_size_t)])
+tikh_set_workspace = _sig("tikh_set_workspace", [_P, ctypes.c_size_t])
 tikh_fft_batched = _sig("tikh_fft_batched", [_P, _I64, _I64, _I64, ctypes.c_int])
 tikh_autotune_nlim = _sig("tikh_autotune_nlim", [_I64, _I64, _I64, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                                  ctypes.POINTER(ctypes.c_double)])
@@ -205,6 +207,33 @@ def solve_normal(col, row, y, lam):
 def _i64(vals):
     arr = (ctypes.c_int64 * len(vals))(*[int(v) for v in vals])
     return arr
+
+
+def workspace_bytes(ms, ns, nlam, nrhs):
+    """Bytes of workspace with which a batched solve or backward of these shapes runs in
+    one chunk (tikh_workspace_bytes; host only)."""
+    out = ctypes.c_size_t()
+    _check(tikh_workspace_bytes(len(ms), _i64(ms), _i64(ns), int(nlam), int(nrhs), ctypes.byref(out)),
+           "tikh_workspace_bytes")
+    return out.value
+
+
+_workspace_ref = None
+
+
+def set_workspace(buf=None):
+    """Hand the library a caller-owned device buffer (a CUDA tensor, kept referenced here
+    until replaced) as its workspace, or None to return to the library's own."""
+    global _workspace_ref
+    if buf is None:
+        _check(tikh_set_workspace(None, 0), "tikh_set_workspace")
+        _workspace_ref = None
+        return
+    if not buf.is_cuda or not buf.is_contiguous():
+        raise ValueError("workspace must be a contiguous device tensor")
+    _check(tikh_set_workspace(ctypes.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size()),
+           "tikh_set_workspace")
+    _workspace_ref = buf
 
 
 def solve_batched(ms, ns, col, row, lambdas, nrhs, b, complex_data=False, info=None, x=None):

@@ -37,6 +37,7 @@ struct Ctx {
     tikh_stats stats{};
     char* ws = nullptr;
     size_t ws_size = 0;
+    bool ws_ext = false;                 // ws is the caller's buffer (tikh_set_workspace)
     std::map<int64_t, double2*> tw;      // twiddle tables by size Q
     std::map<int64_t, double2*> tw2;     // two-level twiddle tables by size
     int64_t launches = 0;
@@ -382,6 +383,7 @@ static Bufs shift_bufs(const Bufs& b, const Layout& L, const Plan& pl, int64_t c
 
 static int ensure_ws(size_t bytes) {
     if (bytes <= g.ws_size) return TIKH_OK;
+    if (g.ws_ext) return TIKH_ENOMEM;                // the caller's buffer is too small
     if (g.ws) { (void)hipStreamSynchronize(g.stream); (void)hipFree(g.ws); g.ws = nullptr; g.ws_size = 0; }
     if (hipMalloc(&g.ws, bytes) != hipSuccess) { g.ws = nullptr; return TIKH_ENOMEM; }
     g.ws_size = bytes;
@@ -418,11 +420,18 @@ static EList make_elist(int nr) {
     return e;
 }
 
+// fixed part of a chunk's workspace beyond its per-group, per-solve and merge-scratch
+// terms (small buffers and the 256-byte alignment of every carved buffer)
+static const size_t WS_FIXED = 64 * 1024 + 256 * 128;
+
+static size_t chunk_bytes(const Layout& L, int64_t G, int64_t CH) {
+    return (size_t)G * L.group_bytes + (size_t)(G * L.nr) * L.solve_bytes + (size_t)CH * L.temp_bytes + WS_FIXED;
+}
+
 static int carve_bufs(const Plan& pl, const Layout& L, int64_t G, int64_t CH, Bufs* b) {
     const int nr = L.nr;
     const int64_t S = G * nr;
-    size_t need = (size_t)G * L.group_bytes + (size_t)S * L.solve_bytes + (size_t)CH * L.temp_bytes + 64 * 1024 +
-                  256 * 128;
+    size_t need = chunk_bytes(L, G, CH);
     int rc = ensure_ws(need);
     if (rc) return rc;
     char* p = g.ws;
@@ -1022,9 +1031,14 @@ static int run_solves(std::vector<SolveDesc>& sds, int nr, int32_t* info) {
         buckets[N].push_back(gi);
         shapes[N] = {M, p};
     }
-    size_t freeb = 0, totb = 0;
-    (void)hipMemGetInfo(&freeb, &totb);
-    size_t budget = std::max<size_t>((size_t)1 << 30, (size_t)((double)(freeb + g.ws_size) * 0.85));
+    size_t budget;
+    if (g.ws_ext) {
+        budget = g.ws_size > WS_FIXED ? g.ws_size - WS_FIXED : 0;
+    } else {
+        size_t freeb = 0, totb = 0;
+        (void)hipMemGetInfo(&freeb, &totb);
+        budget = std::max<size_t>((size_t)1 << 30, (size_t)((double)(freeb + g.ws_size) * 0.85)) - WS_FIXED;
+    }
     for (auto& kv : buckets) {
         Plan pl;
         if (!make_plan(kv.first, shapes[kv.first].first, shapes[kv.first].second, &pl)) return TIKH_EINVAL;
@@ -1037,7 +1051,9 @@ static int run_solves(std::vector<SolveDesc>& sds, int nr, int32_t* info) {
         // budget; smaller levels fit more), the rest held per group
         int64_t mchunk = std::max<int64_t>(1, std::min<int64_t>(128, (int64_t)(budget / 4 / L.temp_bytes)));
         const size_t per_group = L.group_bytes + (size_t)nr * L.solve_bytes;
-        int64_t chunk = std::max<int64_t>(1, (int64_t)((budget - (size_t)mchunk * L.temp_bytes) / per_group));
+        const size_t fixed = (size_t)mchunk * L.temp_bytes;
+        // at least one group per chunk: if even that does not fit, the workspace reports it
+        int64_t chunk = std::max<int64_t>(1, budget > fixed ? (int64_t)((budget - fixed) / per_group) : 0);
         chunk = std::min<int64_t>(chunk, 65535);
         // equal chunks: a small remainder chunk would repeat the whole serial recursion
         // for a handful of groups
@@ -1234,8 +1250,55 @@ int tikh_autotune_nlim(int64_t m, int64_t n, int64_t groups, int32_t nrhs, int32
     return TIKH_OK;
 }
 
+int tikh_workspace_bytes(int64_t nprob, const int64_t* m, const int64_t* n, int64_t nlam, int64_t nrhs,
+                         size_t* bytes) {
+    if (nprob < 0 || nlam < 1 || nrhs < 1 || !bytes || (nprob > 0 && (!m || !n))) return TIKH_EINVAL;
+    const int nr = group_size(nrhs);
+    const int64_t gpp = nlam * ((nrhs + nr - 1) / nr);  // groups per problem
+    const int32_t nlim = g.init ? g.opts.n_lim : 256;
+    struct Bucket { int64_t M; int p; int64_t G = 0, mmax = 1, nmax = 1; };
+    std::map<int64_t, Bucket> buckets;
+    for (int64_t q = 0; q < nprob; ++q) {
+        if (m[q] < 1 || n[q] < 1 || m[q] + n[q] > ((int64_t)1 << 30)) return TIKH_EINVAL;
+        int64_t N, M;
+        int p;
+        if (!opt_extend(m[q] + n[q] - 1, nlim, &N, &M, &p)) return TIKH_EINVAL;
+        if (N > ((int64_t)1 << 19)) return TIKH_EINVAL;
+        Bucket& bk = buckets[N];
+        bk.M = M; bk.p = p;
+        bk.G += gpp;
+        bk.mmax = std::max(bk.mmax, m[q]);
+        bk.nmax = std::max(bk.nmax, n[q]);
+    }
+    size_t most = 0;
+    for (auto& kv : buckets) {
+        Plan pl;
+        if (!make_plan(kv.first, kv.second.M, kv.second.p, &pl)) return TIKH_EINVAL;
+        Layout L;
+        make_layout(pl, nr, kv.second.mmax, kv.second.nmax, &L);
+        most = std::max(most, chunk_bytes(L, kv.second.G, std::min<int64_t>(kv.second.G, 128)));
+    }
+    *bytes = most;
+    return TIKH_OK;
+}
+
+int tikh_set_workspace(void* ptr, size_t bytes) {
+    ensure_init();
+    if ((ptr && bytes == 0) || ((uintptr_t)ptr & 255)) return TIKH_EINVAL;
+    HIPCHK(hipStreamSynchronize(g.stream));
+    if (g.ws && !g.ws_ext) (void)hipFree(g.ws);
+    g.ws = (char*)ptr;
+    g.ws_size = ptr ? bytes : 0;
+    g.ws_ext = ptr != nullptr;
+    return TIKH_OK;
+}
+
 int tikh_release(void) {
-    if (g.ws) { (void)hipStreamSynchronize(g.stream); (void)hipFree(g.ws); g.ws = nullptr; g.ws_size = 0; }
+    if (g.ws) {
+        (void)hipStreamSynchronize(g.stream);
+        if (!g.ws_ext) (void)hipFree(g.ws);
+        g.ws = nullptr; g.ws_size = 0; g.ws_ext = false;
+    }
     for (auto& kv : g.tw) (void)hipFree(kv.second);
     g.tw.clear();
     for (auto& kv : g.tw2) (void)hipFree(kv.second);

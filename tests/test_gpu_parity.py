@@ -381,3 +381,51 @@ def test_headline_batch_full_config_sampled(P):
         off = ((ip * 8 + j) * 4 + r) * n
         xs = P.solve(dev(p.col), dev(p.row), dev(p.b[r]), ls[j]).cpu().numpy()
         assert relerr(x[off:off + n], xs) <= TOL, (ip, j, r, relerr(x[off:off + n], xs))
+
+
+def test_caller_workspace(P):
+    """A caller-owned workspace (tikh_workspace_bytes / tikh_set_workspace): with
+    the queried size the batch runs in one chunk, as with the library's own
+    buffer, and gives its results bit for bit; with a third of it the batch runs
+    in several chunks, whose product transforms are sized by each chunk's own
+    degrees, so the results agree to rounding.  The backward too.  A buffer too
+    small for one group is reported, and NULL returns to the library's own."""
+    rng = np.random.default_rng(77)
+    shapes = [(300, 211), (260, 230), (290, 199)]
+    nlam, nrhs = 2, 4
+    cols, rows, bs, lams = [], [], [], []
+    for (m, n) in shapes:
+        col, row, _ = W.random_problem(rng, m, n, L=12.0)
+        cols.append(col); rows.append(row)
+        bs.extend(rng.standard_normal(m) for _ in range(nrhs))
+        lams.extend([0.3, 0.05])
+    ms = [s[0] for s in shapes]; ns = [s[1] for s in shapes]
+    args = (ms, ns, dev(np.concatenate(cols)), dev(np.concatenate(rows)), lams, nrhs, dev(np.concatenate(bs)))
+
+    def run():
+        x, info = P.solve_batched(*args)
+        gx = x * 0.5
+        gc, gr, gb, gl, binfo = P.backward_batched(*args, x, gx)
+        torch.cuda.synchronize()
+        assert (info.cpu().numpy() == 0).all() and (binfo.cpu().numpy() == 0).all()
+        return [t.cpu().numpy() for t in (x, gc, gr, gb, gl)]
+
+    ref = run()
+    nbytes = P.workspace_bytes(ms, ns, nlam, nrhs)
+    buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    try:
+        P.set_workspace(buf)
+        for a, b in zip(run(), ref):
+            assert np.array_equal(a, b)
+        P.set_workspace(buf[:nbytes // 3])
+        for a, b in zip(run(), ref):
+            assert relerr(a, b) <= 1e-12
+        P.set_workspace(buf[:1 << 16])
+        with pytest.raises(P.TikhError):
+            P.solve_batched(*args)
+    finally:
+        P.set_workspace(None)
+    for a, b in zip(run(), ref):
+        assert np.array_equal(a, b)
+    x = ref[0]
+    assert relerr(x[:211], oracle.solve(cols[0], rows[0], bs[0], lams[0])) <= TOL
