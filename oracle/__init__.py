@@ -3,10 +3,12 @@
 TEST INFRASTRUCTURE ONLY: imported by tests/, __graft_entry__.smoke() and the
 cpu_baseline leg of bench.py, never by the product package.  See
 oracle/tikh_oracle.c for what it computes (dense Householder QR of the stacked
-system [T; lambda I], the plain definition of eq. (tiksol) with L = lambda I).
+system [T; lambda I], the plain definition of eq. (tiksol) with L = lambda I;
+band_solve is the same least-squares problem by a banded QR, for generators of
+finite support at sizes the dense QR cannot reach).
 """
 from .oracle import (build, solve, solve_normal, gradients, T_apply, TH_apply,
-                     dense_T, normal_residual)
+                     dense_T, normal_residual, band_solve)
 
 __all__ = ["build", "solve", "solve_normal", "gradients", "T_apply", "TH_apply",
-           "dense_T", "normal_residual"]
+           "dense_T", "normal_residual", "band_solve"]

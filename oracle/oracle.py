@@ -17,10 +17,10 @@ _lib = None
 
 
 def build(force=False):
-    """Compile the C oracle with gcc (plain -O2, OpenMP)."""
+    """Compile the C oracle with gcc (-O3 for loop vectorization, OpenMP; no target-specific flags)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -39,6 +39,10 @@ def _load():
         lib.tikh_oracle_gradients.argtypes = [I64, I64, P, P, P, ctypes.c_double, P, P, P, P, P,
                                               ctypes.POINTER(ctypes.c_double), ctypes.c_int]
         lib.tikh_oracle_gradients.restype = ctypes.c_int
+        lib.tikh_oracle_band_solve.argtypes = [I64, I64, P, P, I64, P, P, ctypes.c_double, P]
+        lib.tikh_oracle_band_solve.restype = ctypes.c_int
+        lib.tikh_oracle_band_solve_real.argtypes = [I64, I64, P, P, I64, P, P, ctypes.c_double, P]
+        lib.tikh_oracle_band_solve_real.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -78,6 +82,33 @@ def solve_normal(col, row, y, lam, nthreads=1):
     if st != 0:
         raise RuntimeError("oracle QR failed with status %d" % st)
     return x
+
+
+def band_solve(col, row, rhs, lam, normal=False):
+    """Least-squares solutions by banded QR (Givens rotations; exact for generators of finite support).
+
+    rhs: one vector or a list of vectors sharing (T, lam): right-hand sides b (m entries), or with
+    normal=True normal-form data y (n entries, x = (T^H T + lam^2 I)^{-1} y).  Returns an array
+    [len(rhs)][n] (or [n] for a single vector).  Real data runs the real-arithmetic variant."""
+    single = np.ndim(rhs[0]) == 0
+    vecs = [rhs] if single else list(rhs)
+    m, n = len(col), len(row)
+    real = not (np.iscomplexobj(col) or np.iscomplexobj(row) or any(np.iscomplexobj(v) for v in vecs))
+    dt = np.float64 if real else np.complex128
+    colc = np.ascontiguousarray(np.asarray(col, dtype=dt))
+    rowc = np.ascontiguousarray(np.asarray(row, dtype=dt))
+    if normal:
+        assert all(len(v) == n for v in vecs)
+        top, bot = None, np.ascontiguousarray(np.stack([np.asarray(v, dtype=dt) / float(lam) for v in vecs]))
+    else:
+        assert all(len(v) == m for v in vecs)
+        top, bot = np.ascontiguousarray(np.stack([np.asarray(v, dtype=dt) for v in vecs])), None
+    x = np.zeros((len(vecs), n), dt)
+    fn = _load().tikh_oracle_band_solve_real if real else _load().tikh_oracle_band_solve
+    st = fn(m, n, _p(colc), _p(rowc), len(vecs), _p(top), _p(bot), float(lam), _p(x))
+    if st != 0:
+        raise RuntimeError("oracle banded QR failed with status %d" % st)
+    return x[0] if single else x
 
 
 def T_apply(col, row, v):

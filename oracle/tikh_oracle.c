@@ -16,7 +16,9 @@
  * obtained as the least-squares solution of the stacked system
  *     [ T        ]     [ b ]
  *     [ lambda I ] x ~ [ d ]
- * by dense Householder QR followed by back-substitution.  With d = 0 this is
+ * by dense Householder QR followed by back-substitution (and, for generators of
+ * finite support at sizes where the dense matrix is out of reach, by a banded
+ * QR of the same stacked system, tikh_oracle_band_solve).  With d = 0 this is
  * eq. (tiksol).  With b = 0 and d = y / lambda the normal equations of the
  * stacked system read (T^H T + lambda^2 I) x = y, the "normal-form" problem
  * the paper's experiments solve (Sec. 7.1, systems (G_T + G_L) x = y).
@@ -142,28 +144,42 @@ int tikh_oracle_qr_solve(int64_t m, int64_t n, const double* col_, const double*
     return status;
 }
 
-/* y = T v (m entries), direct O(mn) sum from the definition T = [a_{i-j}]. */
+/* Band limits of the generator: a_s = 0 for s > wl and for s < -wu. */
+static void gen_band(int64_t m, int64_t n, const cplx* col, const cplx* row, int64_t* wl, int64_t* wu) {
+    *wl = 0; *wu = 0;
+    for (int64_t s = 0; s < m; ++s) if (col[s].re != 0.0 || col[s].im != 0.0) *wl = s;
+    for (int64_t s = 1; s < n; ++s) if (row[s].re != 0.0 || row[s].im != 0.0) *wu = s;
+}
+
+/* y = T v (m entries), the sum of the definition T = [a_{i-j}] over the
+ * generator's support (the terms left out are exact zeros). */
 void tikh_oracle_T_apply(int64_t m, int64_t n, const double* col_, const double* row_,
                          const double* v_, double* y_)
 {
     const cplx* col = (const cplx*)col_; const cplx* row = (const cplx*)row_;
     const cplx* v = (const cplx*)v_; cplx* y = (cplx*)y_;
+    int64_t wl, wu;
+    gen_band(m, n, col, row, &wl, &wu);
     for (int64_t i = 0; i < m; ++i) {
         cplx s = {0, 0};
-        for (int64_t j = 0; j < n; ++j) s = cadd(s, cmul(gen(col, row, i - j), v[j]));
+        int64_t j0 = i - wl > 0 ? i - wl : 0, j1 = i + wu < n - 1 ? i + wu : n - 1;
+        for (int64_t j = j0; j <= j1; ++j) s = cadd(s, cmul(gen(col, row, i - j), v[j]));
         y[i] = s;
     }
 }
 
-/* y = T^H v (n entries), direct O(mn). */
+/* y = T^H v (n entries), likewise over the support. */
 void tikh_oracle_TH_apply(int64_t m, int64_t n, const double* col_, const double* row_,
                           const double* v_, double* y_)
 {
     const cplx* col = (const cplx*)col_; const cplx* row = (const cplx*)row_;
     const cplx* v = (const cplx*)v_; cplx* y = (cplx*)y_;
+    int64_t wl, wu;
+    gen_band(m, n, col, row, &wl, &wu);
     for (int64_t j = 0; j < n; ++j) {
         cplx s = {0, 0};
-        for (int64_t i = 0; i < m; ++i) s = cadd(s, cconjmul(gen(col, row, i - j), v[i]));
+        int64_t i0 = j - wu > 0 ? j - wu : 0, i1 = j + wl < m - 1 ? j + wl : m - 1;
+        for (int64_t i = i0; i <= i1; ++i) s = cadd(s, cconjmul(gen(col, row, i - j), v[i]));
         y[j] = s;
     }
 }
@@ -218,4 +234,197 @@ int tikh_oracle_gradients(int64_t m, int64_t n, const double* col_, const double
     }
     free(d); free(w); free(Tx); free(r);
     return st;
+}
+
+/*
+ * Banded QR least squares (exact for generators of finite support, at any n).
+ *
+ * When a_s = 0 for s > wl and for s < -wu, the stacked matrix [T; lambda I]
+ * has at most wl + wu + 1 nonzeros per row, and its QR factor R is upper
+ * triangular with bandwidth bw = wl + wu.  The least-squares solution of
+ * [T; lambda I] x ~ [top; bot] (the same problem as tikh_oracle_qr_solve) is
+ * formed by absorbing the rows one at a time into R with Givens rotations
+ * (the row-by-row orthogonal factorization of sparse least-squares problems):
+ * a row meeting an empty row k of R becomes that row; otherwise a rotation
+ * between R row k and the incoming row zeroes the incoming entry k.  The
+ * rotations are applied to the right-hand sides as well, so R x = Q^H c is
+ * left to back-substitution.  Rows are taken in the order of their leading
+ * column (the rows of T, then the row lambda e_j of column j), which keeps
+ * every incoming row inside the window [k, k + bw] of the row of R it meets.
+ * Row order does not change the least-squares solution.
+ *
+ * top: nrhs right-hand sides of m entries ([nrhs][m], or NULL = 0);
+ * bot: nrhs of n entries ([nrhs][n], or NULL = 0); x: [nrhs][n].
+ * All complex interleaved.  Returns 0, -1 on allocation failure, -2 if R is
+ * singular (not possible for lambda > 0).
+ */
+int tikh_oracle_band_solve(int64_t m, int64_t n, const double* col_, const double* row_, int64_t nrhs,
+                           const double* top_, const double* bot_, double lambda, double* x_)
+{
+    const cplx* col = (const cplx*)col_;
+    const cplx* row = (const cplx*)row_;
+    const cplx* top = (const cplx*)top_;
+    const cplx* bot = (const cplx*)bot_;
+    cplx* x = (cplx*)x_;
+    int64_t wl, wu;
+    gen_band(m, n, col, row, &wl, &wu);
+    const int64_t bw = wl + wu, W = bw + 1;
+    cplx* R = (cplx*)calloc((size_t)n * (size_t)W, sizeof(cplx));   /* R[k][t] = entry (k, k+t) */
+    cplx* d = (cplx*)calloc((size_t)n * (size_t)nrhs, sizeof(cplx)); /* d[k][r] = (Q^H c)_k */
+    char* have = (char*)calloc((size_t)n, 1);
+    cplx* v = (cplx*)calloc((size_t)(n + W + 1), sizeof(cplx));      /* incoming row, by column */
+    cplx* cv = (cplx*)calloc((size_t)nrhs, sizeof(cplx));
+    if (!R || !d || !have || !v || !cv) { free(R); free(d); free(have); free(v); free(cv); return -1; }
+
+    /* rows in order of leading column: T rows i with max(0, i - wl) = j, then lambda e_j */
+    for (int64_t j = 0; j < n; ++j) {
+        int64_t i0 = (j == 0) ? 0 : j + wl, i1 = j + wl;
+        for (int64_t ii = i0; ii <= i1 + 1; ++ii) {
+            int64_t lo, hi;
+            if (ii <= i1) {                              /* row ii of T */
+                if (ii >= m) continue;
+                lo = ii - wl < 0 ? 0 : ii - wl;
+                hi = ii + wu < n - 1 ? ii + wu : n - 1;
+                for (int64_t c = lo; c <= hi; ++c) v[c] = gen(col, row, ii - c);
+                for (int64_t r = 0; r < nrhs; ++r) {
+                    if (top) cv[r] = top[r * m + ii]; else { cv[r].re = 0; cv[r].im = 0; }
+                }
+            } else {                                     /* row lambda e_j */
+                lo = hi = j;
+                v[j].re = lambda; v[j].im = 0.0;
+                for (int64_t r = 0; r < nrhs; ++r) {
+                    if (bot) cv[r] = bot[r * n + j]; else { cv[r].re = 0; cv[r].im = 0; }
+                }
+            }
+            for (int64_t k = lo; k <= hi; ++k) {
+                cplx b = v[k];
+                if (b.re == 0.0 && b.im == 0.0) continue;
+                cplx* Rk = R + (size_t)k * W;
+                cplx* dk = d + (size_t)k * nrhs;
+                if (!have[k]) {                          /* the row becomes row k of R */
+                    for (int64_t t = 0; t < W && k + t < n; ++t) { Rk[t] = v[k + t]; v[k + t].re = 0; v[k + t].im = 0; }
+                    for (int64_t r = 0; r < nrhs; ++r) dk[r] = cv[r];
+                    have[k] = 1;
+                    break;
+                }
+                /* rotation [c s; -conj(s) c] with c real: [R_kk; b] -> [rho; 0] */
+                cplx a = Rk[0];
+                double aa = sqrt(cabs2(a)), bb = sqrt(cabs2(b));
+                double nrm = hypot(aa, bb);
+                double c;
+                cplx s;
+                if (aa == 0.0) { c = 0.0; s.re = b.re / bb; s.im = -b.im / bb; }
+                else {
+                    c = aa / nrm;
+                    cplx ph = {a.re / aa, a.im / aa};
+                    cplx cb = {b.re / nrm, -b.im / nrm};
+                    s = cmul(ph, cb);
+                }
+                cplx sc = {s.re, -s.im};                 /* conj(s) */
+                for (int64_t t = 0; t < W && k + t < n; ++t) {
+                    cplx rt = Rk[t], vt = v[k + t];
+                    Rk[t] = cadd(cscale(rt, c), cmul(s, vt));
+                    v[k + t] = csub(cscale(vt, c), cmul(sc, rt));
+                }
+                v[k].re = 0.0; v[k].im = 0.0;
+                for (int64_t r = 0; r < nrhs; ++r) {
+                    cplx rt = dk[r], vt = cv[r];
+                    dk[r] = cadd(cscale(rt, c), cmul(s, vt));
+                    cv[r] = csub(cscale(vt, c), cmul(sc, rt));
+                }
+                if (k + bw > hi) hi = k + bw < n - 1 ? k + bw : n - 1;
+            }
+        }
+    }
+    /* back-substitution R x = d */
+    int status = 0;
+    for (int64_t r = 0; r < nrhs; ++r) {
+        cplx* xr = x + (size_t)r * n;
+        for (int64_t k = n - 1; k >= 0; --k) {
+            const cplx* Rk = R + (size_t)k * W;
+            cplx s = d[(size_t)k * nrhs + r];
+            for (int64_t t = 1; t < W && k + t < n; ++t) s = csub(s, cmul(Rk[t], xr[k + t]));
+            if (!have[k] || (Rk[0].re == 0.0 && Rk[0].im == 0.0)) { status = -2; xr[k].re = 0; xr[k].im = 0; continue; }
+            xr[k] = cdiv(s, Rk[0]);
+        }
+    }
+    free(R); free(d); free(have); free(v); free(cv);
+    return status;
+}
+
+/*
+ * The same banded QR for real data (all generator entries and right-hand sides
+ * real): real rotations [c s; -s c], real R.  Arrays are plain doubles:
+ * col[m], row[n], top[nrhs][m] (or NULL), bot[nrhs][n] (or NULL), x[nrhs][n].
+ */
+int tikh_oracle_band_solve_real(int64_t m, int64_t n, const double* col, const double* row, int64_t nrhs,
+                                const double* top, const double* bot, double lambda, double* x)
+{
+    int64_t wl = 0, wu = 0;
+    for (int64_t s = 0; s < m; ++s) if (col[s] != 0.0) wl = s;
+    for (int64_t s = 1; s < n; ++s) if (row[s] != 0.0) wu = s;
+    const int64_t bw = wl + wu, W = bw + 1;
+    double* R = (double*)calloc((size_t)n * (size_t)W, sizeof(double));
+    double* d = (double*)calloc((size_t)n * (size_t)nrhs, sizeof(double));
+    char* have = (char*)calloc((size_t)n, 1);
+    double* v = (double*)calloc((size_t)(n + W + 1), sizeof(double));
+    double* cv = (double*)calloc((size_t)nrhs, sizeof(double));
+    if (!R || !d || !have || !v || !cv) { free(R); free(d); free(have); free(v); free(cv); return -1; }
+    for (int64_t j = 0; j < n; ++j) {
+        int64_t i0 = (j == 0) ? 0 : j + wl, i1 = j + wl;
+        for (int64_t ii = i0; ii <= i1 + 1; ++ii) {
+            int64_t lo, hi;
+            if (ii <= i1) {
+                if (ii >= m) continue;
+                lo = ii - wl < 0 ? 0 : ii - wl;
+                hi = ii + wu < n - 1 ? ii + wu : n - 1;
+                for (int64_t c = lo; c <= hi; ++c) v[c] = (ii - c >= 0) ? col[ii - c] : row[c - ii];
+                for (int64_t r = 0; r < nrhs; ++r) cv[r] = top ? top[r * m + ii] : 0.0;
+            } else {
+                lo = hi = j;
+                v[j] = lambda;
+                for (int64_t r = 0; r < nrhs; ++r) cv[r] = bot ? bot[r * n + j] : 0.0;
+            }
+            for (int64_t k = lo; k <= hi; ++k) {
+                double b = v[k];
+                if (b == 0.0) continue;
+                double* Rk = R + (size_t)k * W;
+                double* dk = d + (size_t)k * nrhs;
+                if (!have[k]) {
+                    for (int64_t t = 0; t < W && k + t < n; ++t) { Rk[t] = v[k + t]; v[k + t] = 0.0; }
+                    for (int64_t r = 0; r < nrhs; ++r) dk[r] = cv[r];
+                    have[k] = 1;
+                    break;
+                }
+                double a = Rk[0], nrm = hypot(a, b);
+                double c = a / nrm, s = b / nrm;
+                const int64_t tmax = (k + W <= n) ? W : n - k;
+                for (int64_t t = 0; t < tmax; ++t) {
+                    double rt = Rk[t], vt = v[k + t];
+                    Rk[t] = c * rt + s * vt;
+                    v[k + t] = c * vt - s * rt;
+                }
+                v[k] = 0.0;
+                for (int64_t r = 0; r < nrhs; ++r) {
+                    double rt = dk[r], vt = cv[r];
+                    dk[r] = c * rt + s * vt;
+                    cv[r] = c * vt - s * rt;
+                }
+                if (k + bw > hi) hi = k + bw < n - 1 ? k + bw : n - 1;
+            }
+        }
+    }
+    int status = 0;
+    for (int64_t r = 0; r < nrhs; ++r) {
+        double* xr = x + (size_t)r * n;
+        for (int64_t k = n - 1; k >= 0; --k) {
+            const double* Rk = R + (size_t)k * W;
+            double s = d[(size_t)k * nrhs + r];
+            for (int64_t t = 1; t < W && k + t < n; ++t) s -= Rk[t] * xr[k + t];
+            if (!have[k] || Rk[0] == 0.0) { status = -2; xr[k] = 0.0; continue; }
+            xr[k] = s / Rk[0];
+        }
+    }
+    free(R); free(d); free(have); free(v); free(cv);
+    return status;
 }

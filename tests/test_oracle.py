@@ -180,3 +180,78 @@ def test_gradients_central_differences(cplx):
     # dx/dlambda = -2 lambda A^{-1} x
     dxdl = (oracle.solve(col, row, b, lam + h) - oracle.solve(col, row, b, lam - h)) / (2 * h)
     np.testing.assert_allclose(dxdl, -2 * lam * oracle.solve_normal(col, row, x, lam), rtol=1e-6, atol=1e-8)
+
+
+# ---- banded QR (exact for generators of finite support, used at full sizes) ----
+
+def _banded_problem(rng, m, n, wl, wu, cplx):
+    col = rng.standard_normal(m) + (1j * rng.standard_normal(m) if cplx else 0)
+    row = rng.standard_normal(n) + (1j * rng.standard_normal(n) if cplx else 0)
+    col[wl + 1:] = 0
+    row[wu + 1:] = 0
+    row[0] = col[0]
+    return col, row
+
+
+@pytest.mark.parametrize("m,n,wl,wu,cplx", [(40, 30, 5, 3, False), (30, 40, 2, 7, True), (50, 50, 0, 0, False),
+                                            (60, 20, 10, 0, True), (25, 60, 0, 9, False), (7, 5, 6, 4, True),
+                                            (1, 1, 0, 0, False), (90, 64, 89, 63, True)])
+def test_band_qr_against_lstsq(m, n, wl, wu, cplx):
+    """Banded QR against numpy's least squares of the stacked system, several right-hand
+    sides sharing one factorization, both entries (b, and normal-form y)."""
+    rng = np.random.default_rng(m * 1000 + n * 10 + wl)
+    col, row = _banded_problem(rng, m, n, wl, wu, cplx)
+    lam = 0.3
+    T = oracle.dense_T(col, row)
+    A = np.vstack([T, lam * np.eye(n)])
+    bs = [rng.standard_normal(m) + (1j * rng.standard_normal(m) if cplx else 0) for _ in range(3)]
+    xb = oracle.band_solve(col, row, bs, lam)
+    for r in range(3):
+        xe = np.linalg.lstsq(A, np.concatenate([bs[r], np.zeros(n)]), rcond=None)[0]
+        np.testing.assert_allclose(xb[r], xe, rtol=1e-11, atol=1e-12)
+    ys = [rng.standard_normal(n) + (1j * rng.standard_normal(n) if cplx else 0) for _ in range(2)]
+    xn = oracle.band_solve(col, row, ys, lam, normal=True)
+    for r in range(2):
+        np.testing.assert_allclose((T.conj().T @ T + lam ** 2 * np.eye(n)) @ xn[r], ys[r], rtol=1e-11, atol=1e-11)
+
+
+@pytest.mark.parametrize("n,L,cplx", [(600, 6.0, False), (1500, 4.0, True), (2000, 10.0, False)])
+def test_band_qr_against_dense_qr(n, L, cplx):
+    """Banded QR against the dense Householder QR at n <= 2000 on envelope generators
+    cut at 40 L (the inputs of the full-size workloads), tall and square."""
+    rng = np.random.default_rng(n)
+    m = n + n // 8
+    col, row = W.envelope_generator(rng, m, n, L, cplx=cplx)
+    b = rng.standard_normal(m) + (1j * rng.standard_normal(m) if cplx else 0)
+    lam = 0.05
+    xd = oracle.solve(col, row, b, lam, nthreads=8)
+    xb = oracle.band_solve(col, row, [b], lam)[0]
+    assert np.linalg.norm(xb - xd) / np.linalg.norm(xd) < 1e-11
+
+
+def test_band_qr_closed_forms():
+    """T = c I (bandwidth 0): x = conj(c) b / (|c|^2 + lam^2); T = 0: x = 0; the scaling law
+    x(alpha T, alpha lam) = x(T, lam) / alpha on a banded operator."""
+    n = 300
+    rng = np.random.default_rng(9)
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    c, lam = 1.5 - 0.5j, 0.8
+    col = np.zeros(n, complex); col[0] = c; row = np.zeros(n, complex); row[0] = c
+    np.testing.assert_allclose(oracle.band_solve(col, row, [b], lam)[0], np.conj(c) * b / (abs(c) ** 2 + lam ** 2),
+                               rtol=1e-14)
+    assert np.abs(oracle.band_solve(np.zeros(n + 5), np.zeros(n), [b.real[:1].repeat(n + 5)], lam)[0]).max() == 0.0
+    col, row = _banded_problem(rng, n + 20, n, 12, 5, True)
+    b2 = rng.standard_normal(n + 20)
+    x1 = oracle.band_solve(col, row, [b2], 0.4)[0]
+    x2 = oracle.band_solve(3.7 * col, 3.7 * row, [b2], 3.7 * 0.4)[0]
+    np.testing.assert_allclose(x2, x1 / 3.7, rtol=1e-12)
+
+
+def test_band_qr_mutation_fails():
+    """A plausible slip (the conjugate generator, i.e. T^T instead of T) must fail the pin."""
+    rng = np.random.default_rng(17)
+    col, row = _banded_problem(rng, 30, 24, 4, 3, True)
+    b = rng.standard_normal(30) + 1j * rng.standard_normal(30)
+    xe = oracle.solve(col, row, b, 0.5)
+    xbad = oracle.band_solve(np.conj(col), np.conj(row), [b], 0.5)[0]
+    assert np.linalg.norm(xbad - xe) / np.linalg.norm(xe) > 1e-3
