@@ -8,7 +8,9 @@ band_solve is the same least-squares problem by a banded QR, for generators of
 finite support at sizes the dense QR cannot reach).
 """
 from .oracle import (build, solve, solve_normal, gradients, T_apply, TH_apply,
-                     dense_T, normal_residual, band_solve)
+                     dense_T, normal_residual, normal_residual_fft, band_solve,
+                     band_gradients)
 
 __all__ = ["build", "solve", "solve_normal", "gradients", "T_apply", "TH_apply",
-           "dense_T", "normal_residual", "band_solve"]
+           "dense_T", "normal_residual", "normal_residual_fft", "band_solve",
+           "band_gradients"]

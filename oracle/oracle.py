@@ -43,6 +43,7 @@ def _load():
         lib.tikh_oracle_band_solve.restype = ctypes.c_int
         lib.tikh_oracle_band_solve_real.argtypes = [I64, I64, P, P, I64, P, P, ctypes.c_double, P]
         lib.tikh_oracle_band_solve_real.restype = ctypes.c_int
+        lib.tikh_oracle_lag_sums.argtypes = [I64, I64, P, P, P, P, P, P]
         _lib = lib
     return _lib
 
@@ -111,6 +112,24 @@ def band_solve(col, row, rhs, lam, normal=False):
     return x[0] if single else x
 
 
+def band_gradients(col, row, b, lam, x, gx, lag_sums=True):
+    """Gradients of a loss through x = solve(col, row, b, lam) (eq. (tiksol)) with the banded QR:
+    w = (T^H T + lam^2 I)^{-1} gx, g_b = T w, g_lam = -2 lam Re<w, x>, and (optionally, O(mn))
+    the lag sums of (b - T x) w^H - (T w) x^H.  x is the forward solution the gradient is taken at."""
+    col, row, b, x, gx = _c(col), _c(row), _c(b), _c(x), _c(gx)
+    m, n = len(col), len(row)
+    w = _c(band_solve(col, row, [gx], lam, normal=True)[0])
+    Tw = T_apply(col, row, w)
+    out = dict(w=w, g_b=Tw, g_lam=float(-2.0 * lam * np.vdot(w, x).real))
+    if lag_sums:
+        r = b - T_apply(col, row, x)
+        gcol = np.zeros(m, np.complex128)
+        grow = np.zeros(n, np.complex128)
+        _load().tikh_oracle_lag_sums(m, n, _p(r), _p(w), _p(Tw), _p(x), _p(gcol), _p(grow))
+        out.update(g_col=gcol, g_row=grow)
+    return out
+
+
 def T_apply(col, row, v):
     col, row, v = _c(col), _c(row), _c(v)
     m, n = len(col), len(row)
@@ -152,6 +171,29 @@ def dense_T(col, row):
         for j in range(n):
             T[i, j] = col[i - j] if i >= j else row[j - i]
     return T
+
+
+def normal_residual_fft(col, row, b, lam, x):
+    """The same relative residual with the products T v and T^H v formed by numpy FFT
+    convolutions of the generator (for full sizes)."""
+    col, row, b, x = _c(col), _c(row), _c(b), _c(x)
+    m, n = len(col), len(row)
+    g = np.concatenate([row[1:][::-1], col])              # a_{-(n-1)} .. a_{m-1}
+    L = 1
+    while L < len(g) + max(m, n):
+        L *= 2
+    G = np.fft.fft(g, L)
+    GH = np.fft.fft(np.conj(g[::-1]), L)                   # conj(a_{m-1}) .. conj(a_{-(n-1)})
+
+    def T(v):
+        return np.fft.ifft(G * np.fft.fft(v, L))[n - 1:n - 1 + m]
+
+    def TH(v):
+        return np.fft.ifft(GH * np.fft.fft(v, L))[m - 1:m - 1 + n]
+
+    r = TH(b - T(x)) - float(lam) ** 2 * x
+    scale = np.linalg.norm(TH(b)) + float(lam) ** 2 * np.linalg.norm(x)
+    return float(np.linalg.norm(r) / scale)
 
 
 def normal_residual(col, row, b, lam, x):

@@ -428,3 +428,26 @@ int tikh_oracle_band_solve_real(int64_t m, int64_t n, const double* col, const d
     free(R); free(d); free(have); free(v); free(cv);
     return status;
 }
+
+/*
+ * Generator gradient of the adjoint (derived from eq. (tiksol)): the lag sums
+ *     g_col[s] = sum_{i-j=s} G_ij (s = 0..m-1),  g_row[s] = sum_{j-i=s} G_ij (s = 1..n-1),
+ * of G = r w^H - (T w) x^H, written out term by term (O(mn)).  Inputs r, Tw
+ * (m entries) and w, x (n entries); g_row[0] = 0.  Complex interleaved.
+ */
+void tikh_oracle_lag_sums(int64_t m, int64_t n, const double* r_, const double* w_, const double* Tw_,
+                          const double* x_, double* gcol_, double* grow_)
+{
+    const cplx* r = (const cplx*)r_; const cplx* w = (const cplx*)w_;
+    const cplx* Tw = (const cplx*)Tw_; const cplx* x = (const cplx*)x_;
+    cplx* gcol = (cplx*)gcol_; cplx* grow = (cplx*)grow_;
+    for (int64_t i = 0; i < m; ++i) { gcol[i].re = 0; gcol[i].im = 0; }
+    for (int64_t j = 0; j < n; ++j) { grow[j].re = 0; grow[j].im = 0; }
+    for (int64_t i = 0; i < m; ++i) {
+        for (int64_t j = 0; j < n; ++j) {
+            cplx g = csub(cconjmul(w[j], r[i]), cconjmul(x[j], Tw[i]));   /* r_i conj(w_j) - (Tw)_i conj(x_j) */
+            int64_t s = i - j;
+            if (s >= 0) gcol[s] = cadd(gcol[s], g); else grow[-s] = cadd(grow[-s], g);
+        }
+    }
+}

@@ -255,3 +255,34 @@ def test_band_qr_mutation_fails():
     xe = oracle.solve(col, row, b, 0.5)
     xbad = oracle.band_solve(np.conj(col), np.conj(row), [b], 0.5)[0]
     assert np.linalg.norm(xbad - xe) / np.linalg.norm(xe) > 1e-3
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_band_gradients_against_dense(cplx):
+    """The banded adjoint (w by banded QR, g_b = T w, g_lam, lag sums) against the dense
+    oracle's gradients, which central differences pin above."""
+    rng = np.random.default_rng(31 + cplx)
+    m, n = 70, 52
+    col, row = _banded_problem(rng, m, n, 9, 4, cplx)
+    b = rng.standard_normal(m) + (1j * rng.standard_normal(m) if cplx else 0)
+    gx = rng.standard_normal(n) + (1j * rng.standard_normal(n) if cplx else 0)
+    lam = 0.35
+    ref = oracle.gradients(col, row, b, lam, gx)
+    got = oracle.band_gradients(col, row, b, lam, ref["x"], gx)
+    for k in ("g_b", "g_col", "g_row"):
+        np.testing.assert_allclose(got[k], ref[k], rtol=1e-11, atol=1e-12)
+    assert abs(got["g_lam"] - ref["g_lam"]) <= 1e-11 * max(1.0, abs(ref["g_lam"]))
+
+
+def test_normal_residual_fft():
+    """FFT-formed optimality residual: equal to the direct one on a small problem, at
+    rounding level for the oracle's solution, and large for a perturbed solution."""
+    rng = np.random.default_rng(41)
+    col, row, b = W.random_problem(rng, 90, 70, cplx=True, L=10.0)
+    lam = 0.2
+    x = oracle.solve(col, row, b, lam)
+    r1 = oracle.normal_residual_fft(col, row, b, lam, x)
+    assert r1 < 1e-14
+    xp = x * (1 + 1e-6)
+    assert abs(oracle.normal_residual_fft(col, row, b, lam, xp) / oracle.normal_residual(col, row, b, lam, xp) - 1) < 1e-6
+    assert oracle.normal_residual_fft(col, row, b, lam, xp) > 1e-8
