@@ -13,12 +13,24 @@ batched forward solve of every (problem, lambda, rhs) triple plus one batched
 backward (adjoint solve + gradients w.r.t. generator, b and lambda).
 
 Prints ONE JSON line (rank 0).  `value` is whole-job fwd+bwd solves/s with the
-inputs resident in HBM; `roofline` reports the dominant kernel's live average
-launch duration (HIP events on the library stream) against its bound (the FFT
-against HBM bandwidth, the leaf steps against the FP64 vector peak) and, when a
-counter summary taken on the current sources is committed, its measured HBM
-bytes per launch; `cpu_baseline` times the CPU oracle (dense Householder QR) on a bounded
-sample and scales it by the oracle's flop count to the benchmark size.
+inputs resident in HBM.  `roofline` reports the dominant kernel against its
+bound with the method's algorithmic work (a derived count for the recursion of
+Alg. 1 on 5 x 5 bases: per merge of K conditions 280 K bytes and
+31 K log2(K/8) + 94 K log2(K/4) + 350 K flops, per leaf of K conditions 180 K
+bytes and 45 K^2 flops, setup 16 (m+n) + 160 N bytes and 20 N log2 N flops,
+times 2.05 for forward plus backward), credited in full to that kernel's
+launches, whose average duration is measured live with HIP events on the
+library stream; `step_roofline` is the same work over the whole step.
+`cpu_baseline` times the CPU oracle (banded QR of [T; lambda I], exact for the
+generators' finite support) on a bounded sample of the timed workload: every
+lambda and right-hand side of the problem with the narrowest generator, forward
+and adjoint.  The same oracle results gate the run (`parity`): the timed
+forward solves of that problem must match the oracle element by element to
+1e-9 (relative 2-norm), the batched backward in the timed launch configuration
+fed the oracle's solutions must match the oracle's gradients to 1e-9, and the
+optimality residual of eq. (tiksol) is checked on a stratified sample of timed
+solves across the batch.  If the gate fails, `value` is null and the exit
+status is 1.
 """
 import argparse
 import json
@@ -46,6 +58,142 @@ def pick_nlim(tune_ms, tol=0.02):
     (the timings of 256 groups carry about 1% noise; a larger cutoff means fewer tree levels)."""
     best = min(tune_ms.values())
     return max(int(k) for k, v in tune_ms.items() if v <= (1.0 + tol) * best)
+
+
+def method_work(m, n, N, p, M):
+    """Algorithmic (flops, HBM bytes) of one forward solve of the recursion on an m x n
+    problem with N nodes, 2^p leaves of 2M conditions (derived count, +-30%)."""
+    K_leaf = 2 * M
+    flops = (1 << p) * 45.0 * K_leaf ** 2 + 20.0 * N * math.log2(N)
+    nbytes = (1 << p) * 180.0 * K_leaf + 16.0 * (m + n) + 160.0 * N
+    for d in range(p):
+        K = (2 * N) >> d
+        flops += (1 << d) * (31.0 * K * math.log2(K / 8) + 94.0 * K * math.log2(K / 4) + 350.0 * K)
+        nbytes += (1 << d) * 280.0 * K
+    return flops, nbytes
+
+
+FWD_BWD = 2.05   # forward plus backward: one more solve and about 10 transforms of length ~2N
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def oracle_leg(probs, ip, nlam, nrhs, x_gpu, run_backward, cores):
+    """CPU oracle on the problem `ip` of the timed batch (all lambdas and right-hand sides):
+    banded QR forward solves and adjoint solves (upstream gradient x - x_true), one thread per
+    lambda; returns (cpu_baseline, parity).  x_gpu: the timed forward solutions (numpy).
+    run_backward(x_in) runs the batched backward in the timed launch configuration with forward
+    solutions x_in and upstream gradient x_in - x_true, and returns numpy (g_col, g_row, g_b, g_lam)."""
+    import numpy as np
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    pr = probs[ip]
+    m, n = pr.m, pr.n
+
+    def fwd_bwd(j):
+        t0 = time.perf_counter()
+        xs = oracle.band_solve(pr.col, pr.row, pr.b, pr.lams[j])
+        ws = oracle.band_solve(pr.col, pr.row, [xs[r] - pr.x_true for r in range(nrhs)], pr.lams[j], normal=True)
+        return xs, ws, time.perf_counter() - t0
+
+    threads = max(1, min(cores, nlam))
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        res = list(ex.map(fwd_bwd, range(nlam)))
+    wall = time.perf_counter() - t0
+    xref = [r[0] for r in res]
+    wref = [r[1] for r in res]
+    per_thread = [r[2] for r in res]
+
+    # cost model of the banded QR: (m + n) (bandwidth + 1)^2 per factorization
+    def band_cost(p_):
+        wl = int(np.max(np.nonzero(p_.col)[0])) if np.any(p_.col) else 0
+        wu = int(np.max(np.nonzero(p_.row[1:])[0]) + 1) if np.any(p_.row[1:]) else 0
+        return (p_.m + p_.n) * float(wl + wu + 1) ** 2
+    c_sample = band_cost(pr)
+    c_mean = float(np.mean([band_cost(q) for q in probs]))
+    nsol = nlam * nrhs
+    rate_sample = nsol / wall
+    cpu = {"value": rate_sample * c_sample / c_mean, "unit": "solves/s (fwd+bwd)", "cores": threads,
+           "kind": "oracle", "cpu_model": cpu_model(),
+           "sample": "banded QR of [T; lambda I] (Givens rows, exact for the generator's support) for the "
+                     "%d forward and %d adjoint solves of problem %d (m=%d, n=%d, envelope L=%.2f) of the timed "
+                     "batch, one thread per lambda: %.1f s wall on %d threads (%.1f s per lambda single-threaded, "
+                     "4 right-hand sides per factorization); value scaled to the batch's average problem by the "
+                     "banded-QR cost (m+n)(bandwidth+1)^2 (x%.1f)" % (nsol, nsol, ip, m, n, pr.meta["L"], wall,
+                                                                       threads, float(np.median(per_thread)),
+                                                                       c_mean / c_sample),
+           "sample_rate": round(rate_sample, 4), "single_thread_s_per_lambda": round(float(np.median(per_thread)), 2)}
+
+    # forward parity: timed solves of problem ip against the oracle, element by element
+    def rel(a, b):
+        return float(np.linalg.norm(np.asarray(a) - b) / max(np.linalg.norm(b), 1e-300))
+    base = sum(q.n * nlam * nrhs for q in probs[:ip])
+    fwd_err = []
+    for j in range(nlam):
+        for r in range(nrhs):
+            o = base + (j * nrhs + r) * n
+            fwd_err.append(rel(x_gpu[o:o + n], xref[j][r].real))
+
+    # backward parity: the batched backward (timed launch configuration) fed the oracle's
+    # solutions for problem ip, against the oracle's adjoint
+    x_in = x_gpu.copy()
+    for j in range(nlam):
+        for r in range(nrhs):
+            o = base + (j * nrhs + r) * n
+            x_in[o:o + n] = xref[j][r].real
+    g_col, g_row, g_b, g_lam = run_backward(x_in)
+    mbase = sum(q.m * nlam * nrhs for q in probs[:ip])
+    bwd_err = []
+    lag_checked = []
+    for j in range(nlam):
+        for r in range(nrhs):
+            k = ip * nlam * nrhs + j * nrhs + r
+            w = wref[j][r]
+            gb_ref = oracle.T_apply(pr.col, pr.row, w)
+            gl_ref = float(-2.0 * pr.lams[j] * np.vdot(w, xref[j][r]).real)
+            o = mbase + (j * nrhs + r) * m
+            bwd_err.append(rel(g_b[o:o + m], gb_ref.real))
+            bwd_err.append(abs(float(g_lam[k]) - gl_ref) / max(1.0, abs(gl_ref)))
+            if r == j % nrhs and j % 2 == 0:       # generator gradient for 4 of the solves (O(mn) each)
+                gc_ref, gr_ref = oracle.lag_sums(pr.col, pr.row, pr.b[r], xref[j][r], w)
+                ro = base + (j * nrhs + r) * n
+                bwd_err.append(rel(g_col[o:o + m], gc_ref.real))
+                bwd_err.append(rel(g_row[ro + 1:ro + n], gr_ref.real[1:]))
+                lag_checked.append([j, r])
+    parity = {"oracle": "banded QR", "problem": ip, "tol": 1e-9,
+              "fwd_solves_checked": len(fwd_err), "fwd_max_rel_err": max(fwd_err),
+              "bwd_checked": "g_b and g_lambda of all %d solves, generator gradient of (lambda, rhs) %s" %
+                             (nsol, lag_checked),
+              "bwd_max_rel_err": max(bwd_err)}
+    parity["ok"] = parity["fwd_max_rel_err"] <= 1e-9 and parity["bwd_max_rel_err"] <= 1e-9
+    return cpu, parity
+
+
+def residual_sample(probs, nlam, nrhs, x_gpu, count=64):
+    """Optimality residual ||T^H (b - T x) - lambda^2 x|| / (||T^H b|| + lambda^2 ||x||) of eq. (tiksol)
+    for a stratified sample of timed solves (every lambda, every right-hand side, problems spread
+    over the batch), with FFT products on the CPU."""
+    import numpy as np
+    import oracle
+    offs = np.concatenate([[0], np.cumsum([q.n * nlam * nrhs for q in probs])])
+    worst = 0.0
+    for i in range(count):
+        ip = (i * 37) % len(probs)
+        j, r = i % nlam, (i // nlam) % nrhs
+        pr = probs[ip]
+        o = offs[ip] + (j * nrhs + r) * pr.n
+        worst = max(worst, oracle.normal_residual_fft(pr.col, pr.row, pr.b[r], pr.lams[j], x_gpu[o:o + pr.n]))
+    return count, worst
 
 
 def measured_traffic(root, kernel, args, nlim):
@@ -79,8 +227,10 @@ def main():
                     help="leaf cutoff N_lim (Alg. 2), or 'auto': picked by the library's autotuner on 256 groups "
                          "of the workload's shape before the timed steps")
     ap.add_argument("--plain-solves", type=int, default=2)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-n", type=int, default=4096, help="size of the CPU-oracle sample (about 15 s on 16 cores)")
+    ap.add_argument("--no-oracle", "--no-cpu-baseline", dest="no_oracle", action="store_true",
+                    help="skip the CPU-oracle leg (cpu_baseline and the parity gate)")
+    ap.add_argument("--residual-sample", type=int, default=64,
+                    help="timed solves whose optimality residual is checked on the CPU")
     ap.add_argument("--kernel", default="auto", help="kernel for the roofline object: fft, leaf_loop or auto "
                                                      "(the one with the larger share of the step)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
@@ -140,6 +290,7 @@ def main():
     ms_per_step = ms_total / args.steps
     value = nsolve * args.steps / (ms_total / 1e3)
     info_max = int(max(info.max().item(), binfo.max().item()))
+    x_timed = x.cpu().numpy()
 
     # dominant kernels: live launch timing over one more step each (HIP events on the library stream)
     st = P.get_stats()
@@ -151,22 +302,42 @@ def main():
         k_ms, k_count, units = P.profile_read()
         rl[kern] = (k_ms, k_count, units)
     P.profile_kernel(None)
+    kernel_ms = {k: round(v[0], 1) for k, v in rl.items()}
+
+    # the method's algorithmic work per step, from each problem's plan
+    alg_flops = alg_bytes = 0.0
+    for p in probs:
+        N, M, depth, _ = P.plan_info(p.m, p.n, nlim)
+        f, b_ = method_work(p.m, p.n, N, depth, M)
+        alg_flops += f * FWD_BWD * args.nlam * args.nrhs
+        alg_bytes += b_ * FWD_BWD * args.nlam * args.nrhs
+    step_s = ms_per_step / 1e3
+    step_roofline = {"alg_bytes_per_step": alg_bytes, "alg_flops_per_step": alg_flops,
+                     "hbm_TBps": round(alg_bytes / step_s / 1e12, 3), "hbm_frac": round(alg_bytes / step_s / 8e12, 4),
+                     "fp64_TFLOPs": round(alg_flops / step_s / 1e12, 3),
+                     "fp64_frac": round(alg_flops / step_s / 78.6e12, 4),
+                     "ceiling_solves_per_s": round(nsolve / max(alg_bytes / 8e12, alg_flops / 78.6e12), 1)}
+
     main_kernel = args.kernel if args.kernel in ("fft", "leaf_loop") else max(("fft", "leaf_loop"),
                                                                                 key=lambda k: rl[k][0])
     k_ms, k_count, units = rl[main_kernel]
     avg_ms = k_ms / max(k_count, 1)
     if main_kernel == "fft":
-        achieved = units / (k_ms / 1e3) / 1e9 if k_ms > 0 else 0.0
+        per_launch = alg_bytes / max(k_count, 1)
+        achieved = per_launch / (avg_ms / 1e3) / 1e9 if k_ms > 0 else 0.0
         roofline = {"bound": "hbm", "kernel": "k_fft", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
                     "frac": round(achieved / 8000.0, 4), "traffic": None, "avg_launch_ms": round(avg_ms, 4),
-                    "launches_per_step": k_count, "bytes_per_launch": round(units / max(k_count, 1))}
+                    "launches_per_step": k_count, "alg_bytes_per_launch": round(per_launch),
+                    "alg_bytes_note": "every algorithmic byte of the step credited to k_fft's launches",
+                    "pass_bytes_per_launch": round(units / max(k_count, 1)),
+                    "pass_bytes_note": "one read and one write of every transformed element per pass"}
     else:
-        achieved = units / (k_ms / 1e3) / 1e12 if k_ms > 0 else 0.0
+        per_launch = alg_flops / max(k_count, 1)
+        achieved = per_launch / (avg_ms / 1e3) / 1e12 if k_ms > 0 else 0.0
         roofline = {"bound": "alu", "kernel": "k_leaf_loop", "achieved": round(achieved, 3), "peak": 78.6,
                     "unit": "TFLOP/s", "frac": round(achieved / 78.6, 5), "traffic": None,
                     "avg_launch_ms": round(avg_ms, 4), "launches_per_step": k_count,
-                    "flops_per_launch": round(units / max(k_count, 1))}
-    kernel_ms = {k: round(v[0], 1) for k, v in rl.items()}
+                    "alg_flops_per_launch": round(per_launch), "pass_flops_per_launch": round(units / max(k_count, 1))}
 
     # plain method: single-problem C-ABI calls, one solve + one backward per call
     plain = None
@@ -187,24 +358,28 @@ def main():
         torch.cuda.synchronize()
         plain = args.plain_solves / (time.perf_counter() - t0)
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
+    cpu = parity = None
+    if not args.no_oracle:
         cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
         cores = max(1, min(cores, 16))
-        pc = W.headline(0, n=args.cpu_n, nrhs=1, nlam=1)
-        t0 = time.perf_counter()
-        g = oracle.gradients(pc.col, pc.row, pc.b[0], pc.lams[0], pc.x_true, nthreads=cores)
-        dt = time.perf_counter() - t0
-        # dense QR of the stacked (m+n) x n system: ~2 (m+n) n^2 - 2n^3/3 flops, done twice (x and w)
-        def qr_flops(m, n):
-            return 2.0 * (m + n) * n * n - 2.0 * n ** 3 / 3.0
-        m_avg = float(np.mean(ms))
-        scale = qr_flops(m_avg, args.n) / qr_flops(pc.m, pc.n)
-        cpu = {"value": 1.0 / (dt * scale), "unit": "solves/s (fwd+bwd)", "cores": cores, "kind": "oracle",
-               "sample": "one fwd+bwd (dense Householder QR for x and for the adjoint w, plus direct O(mn) "
-                         "gradient sums) at n=%d, m=%d took %.2f s on %d threads; scaled by the QR flop "
-                         "ratio %.1f to n=%d, m=%.0f" % (pc.n, pc.m, dt, cores, scale, args.n, m_avg)}
+        ip = min(range(args.nprob), key=lambda i: probs[i].meta["L"])
+
+        def run_backward(x_in):
+            xi = torch.tensor(x_in, device=dev)
+            g_col, g_row, g_b, g_lam, binf = P.backward_batched(ms, ns, col, row, lams, args.nrhs, bb, xi, xi - xt)
+            torch.cuda.synchronize()
+            assert int(binf.max().item()) == 0
+            return g_col.cpu().numpy(), g_row.cpu().numpy(), g_b.cpu().numpy(), g_lam.cpu().numpy()
+
+        cpu, parity = oracle_leg(probs, ip, args.nlam, args.nrhs, x_timed, run_backward, cores)
+        if args.residual_sample > 0:
+            cnt, worst = residual_sample(probs, args.nlam, args.nrhs, x_timed, args.residual_sample)
+            parity["residual_solves_checked"] = cnt
+            parity["residual_max"] = worst
+            parity["residual_tol"] = 1e-11
+            parity["ok"] = parity["ok"] and worst <= 1e-11
+        parity["info_max"] = info_max
+        parity["ok"] = parity["ok"] and info_max == 0
 
     if args.copy_calib_mib > 0:
         src = torch.ones(args.copy_calib_mib * 2 ** 20 // 8, dtype=torch.float64, device=dev)
@@ -217,10 +392,14 @@ def main():
     traffic = measured_traffic(ROOT, roofline["kernel"], args, nlim)
     if traffic is not None:
         roofline["traffic"] = traffic
+        if main_kernel == "fft":
+            roofline["traffic_over_alg"] = round(traffic / roofline["alg_bytes_per_launch"], 3)
+            roofline["traffic_over_pass"] = round(traffic / max(roofline["pass_bytes_per_launch"], 1), 3)
 
+    ok = parity is None or parity["ok"]
     out = {
         "metric": "batched regularized solves/s (fwd+bwd) at n=2^14 vs plain, rel err <= 1e-9",
-        "value": round(value, 3),
+        "value": round(value, 3) if ok else None,
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -233,16 +412,23 @@ def main():
         "data": "synthetic",
         "config": {"workload": "headline n=2^14, m=n+U{0..n/4}, envelope generators, 8 lambdas x 4 rhs",
                    "problems": args.nprob, "solves_per_step": nsolve, "n": args.n, "m_range": [min(ms), max(ms)],
-                   "N": st["N"], "depth": st["depth"], "leaf_nodes": st["leaf_nodes"], "n_lim": nlim, "n_lim_autotune_ms": tune, "refine": 1},
+                   "N": st["N"], "depth": st["depth"], "leaf_nodes": st["leaf_nodes"], "n_lim": nlim,
+                   "n_lim_autotune_ms": tune, "refine": 1},
         "n_log2n_sq_rate": round(value * args.n * math.log2(args.n) ** 2, 1),
         "plain_solves_per_s": round(plain, 4) if plain else None,
         "batched_over_plain": round(value / plain, 2) if plain else None,
         "info_max": info_max,
+        "parity": parity,
         "roofline": roofline,
+        "step_roofline": step_roofline,
         "kernel_ms_per_step": kernel_ms,
         "cpu_baseline": cpu,
     }
+    if not ok:
+        out["unmeasured_reason"] = "parity gate failed: no value is reported"
     print(json.dumps(out), flush=True)
+    if not ok:
+        sys.exit(1)
 
 
 if __name__ == "__main__":

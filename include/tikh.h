@@ -34,10 +34,13 @@
  *
  * Errors: every entry point returns TIKH_OK (0) or a negative TIKH_E* code;
  * tikh_strerror() describes it.  On error the outputs are undefined.  The
- * numerical status of each solve is reported in an info word: 0 = OK,
- * 1 = breakdown (no admissible pivot / final tau-degrees not {1,1,1,1,0}),
- * 2 = a basis degree exceeded its storage bound, 3 = non-finite values,
- * 4 = more deferred difficult conditions than a solve can hold (bits may combine).
+ * numerical status of each solve is reported in an info word of bits: 0 = OK,
+ * bit 1 = breakdown (no admissible pivot / final tau-degrees not {1,1,1,1,0}),
+ * bit 2 = a basis degree exceeded its storage bound, bit 4 = more deferred
+ * difficult conditions than a solve can hold, bit 8 = non-finite values in the
+ * solution (bits may combine).  Right-hand sides of one (problem, lambda) share
+ * a pivot sequence, so bits 1, 2 and 4 of a forward solve are those of its
+ * (problem, lambda); bit 8 is the solve's own.
  * Single-problem calls synchronize the stream and return TIKH_ENUMERIC when
  * info != 0.  Calls are not thread safe (one host thread per library state).
  */

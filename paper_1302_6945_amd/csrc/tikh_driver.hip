@@ -116,17 +116,20 @@ static void prof_print_detail() {
     } while (0)
 #define LAUNCH(kname, kern, grid, block, ...) LAUNCH_SH(kname, kern, grid, block, 0, __VA_ARGS__)
 
+// Options take their defaults once; the degree readback words are (re)allocated
+// until both exist, and a merge that finds either missing reports TIKH_ENOMEM.
 static void ensure_init() {
-    if (g.init) return;
-    g.opts.n_lim = 256;
-    g.opts.refine = 1;
-    g.opts.refine_max = 3;
-    g.opts.leaf_wave_groups = 1536;
-    g.opts.refine_tol = 1e-10;
-    g.opts.defer_tol = 0.0;
-    if (hipMalloc((void**)&g.dneed, sizeof(int)) != hipSuccess) g.dneed = nullptr;
-    if (hipHostMalloc((void**)&g.hneed, sizeof(int), hipHostMallocDefault) != hipSuccess) g.hneed = nullptr;
-    g.init = true;
+    if (!g.init) {
+        g.opts.n_lim = 256;
+        g.opts.refine = 1;
+        g.opts.refine_max = 3;
+        g.opts.leaf_wave_groups = 1536;
+        g.opts.refine_tol = 1e-10;
+        g.opts.defer_tol = 0.0;
+        g.init = true;
+    }
+    if (!g.dneed && hipMalloc((void**)&g.dneed, sizeof(int)) != hipSuccess) g.dneed = nullptr;
+    if (!g.hneed && hipHostMalloc((void**)&g.hneed, sizeof(int), hipHostMallocDefault) != hipSuccess) g.hneed = nullptr;
 }
 
 // ---------------------------------------------------------------- planning (Alg. 2)
@@ -658,6 +661,7 @@ static int run_product_chunk(const Plan& pl, const Layout& L, const Bufs& b, int
     int64_t P = pl.P[dp];
     {
         // size the transforms by the actual degrees of this chunk (host readback)
+        if (!g.dneed || !g.hneed) return TIKH_ENOMEM;
         hipLaunchKernelGGL(k_deg_need, dim3(1), dim3(256), 0, g.stream, b.metaS[dc], b.metaT[dc], (int)G, C, g.dneed);
         HIPCHK(hipMemcpyAsync(g.hneed, g.dneed, sizeof(int), hipMemcpyDeviceToHost, g.stream));
         HIPCHK(hipStreamSynchronize(g.stream));
@@ -959,6 +963,10 @@ static int run_chunk(const Plan& pl, int nr, const std::vector<SolveDesc>& sds, 
         }
     }
     if (!sds[0].backward) {
+        if (info) {
+            hipLaunchKernelGGL(k_clear_info, dim3((unsigned)((S + 255) / 256)), dim3(256), 0, g.stream, b.sd, S, info);
+            g.launches++;
+        }
         hipLaunchKernelGGL(k_store_x, grid1(nmax, S), dim3(256), 0, g.stream, b.sd, nr, b.xacc, L.sn, b.st, info);
         g.launches++;
     } else {

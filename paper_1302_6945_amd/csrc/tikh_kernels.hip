@@ -2091,7 +2091,7 @@ __global__ __launch_bounds__(256) void k_extract(const SolveDesc* __restrict__ s
     double ndx = 0.0, nx = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < d.n; i += (int64_t)gridDim.x * blockDim.x) {
         double2 v = (i <= dg && i < cp1) ? v1[i] : c2(0.0, 0.0);
-        if (!isfinite(v.x) || !isfinite(v.y)) atomicOr(&st[g].info, 3);
+        if (!isfinite(v.x) || !isfinite(v.y)) atomicOr(&st[g].info, 8);
         if (accumulate) {
             const double2 xn = cadd(xacc[s * x_stride + i], v);
             ndx += cabs2(v);
@@ -2111,17 +2111,33 @@ __global__ __launch_bounds__(256) void k_extract(const SolveDesc* __restrict__ s
     }
 }
 
+// info words of the chunk's solves are cleared before k_store_x ORs bits into them
+__global__ void k_clear_info(const SolveDesc* __restrict__ sd, int64_t S, int32_t* __restrict__ info) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < S && sd[s].rhs) info[sd[s].orig] = 0;
+}
+
+// Stores x and the solve's info word: the group's bits other than the non-finite
+// bit (the right-hand sides of a group share the pivot sequence), and the
+// non-finite bit (8) from this solve's own entries.
 __global__ void k_store_x(const SolveDesc* __restrict__ sd, int nr, const double2* __restrict__ xacc, int64_t x_stride,
                           const SolveState* __restrict__ st, int32_t* __restrict__ info) {
     const int64_t s = blockIdx.y;
     const SolveDesc d = sd[s];
     if (!d.rhs) return;                        // padding solve
+    bool bad = false;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < d.n; i += (int64_t)gridDim.x * blockDim.x) {
         double2 v = xacc[s * x_stride + i];
+        bad |= !isfinite(v.x) || !isfinite(v.y);
         if (d.cplx) ((double2*)d.x)[i] = v;
         else ((double*)d.x)[i] = v.x;
     }
-    if (info && blockIdx.x == 0 && threadIdx.x == 0) info[d.orig] = st[s / nr].info;
+    if (!info) return;
+    if (bad) atomicOr(&info[d.orig], 8);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const int32_t gi = st[s / nr].info & ~8;
+        if (gi) atomicOr(&info[d.orig], gi);
+    }
 }
 
 // ---------------------------------------------------------------- adjoint (backward)

@@ -19,3 +19,69 @@ def test_pick_nlim_prefers_larger_cutoff_on_near_ties():
     assert b.pick_nlim({64: 711.1, 128: 1259.9, 192: 590.3, 256: 600.0}) == 256
     assert b.pick_nlim({64: 500.0, 128: 700.0, 192: 590.3, 256: 620.0}) == 64
     assert b.pick_nlim({128: 100.0}) == 128
+
+
+def test_method_work_headline_plan():
+    """Algorithmic bytes of one forward solve at the headline plan (N = 36864, 2^9 leaves of
+    144 conditions): 9 merge levels of 280 x 2N bytes, 512 leaves of 180 x 144 bytes and the
+    setup's 16 (m + n) + 160 N bytes."""
+    b = _bench()
+    m, n = 18432, 16384
+    flops, nbytes = b.method_work(m, n, 36864, 9, 72)
+    expect = 9 * 280 * 73728 + 512 * 180 * 144 + 16 * (m + n) + 160 * 36864
+    assert abs(nbytes - expect) < 1.0
+    assert 1.2e9 < flops < 1.8e9
+
+
+def _layout(probs, nlam, nrhs, per_solve, key):
+    import numpy as np
+    out = []
+    for p in probs:
+        for j in range(nlam):
+            for r in range(nrhs):
+                out.append(np.asarray(per_solve[(id(p), j, r)][key]).real)
+    return np.concatenate(out)
+
+
+def test_oracle_leg_indexing_and_gate():
+    """The bench's oracle leg on a small batch whose 'timed' outputs come from the oracle
+    itself: the parity gate passes at rounding level; a wrong entry in the checked problem's
+    solutions fails it."""
+    import numpy as np
+    import oracle
+    import workloads as W
+    b = _bench()
+    nlam, nrhs = 2, 2
+    probs = [W.headline(i, n=48, nrhs=nrhs, nlam=nlam) for i in range(3)]
+    ref = {}
+    for p in probs:
+        for j in range(nlam):
+            xs = oracle.band_solve(p.col, p.row, p.b, p.lams[j])
+            for r in range(nrhs):
+                ref[(id(p), j, r)] = {"x": xs[r]}
+    x_gpu = _layout(probs, nlam, nrhs, ref, "x")
+
+    def run_backward(x_in):
+        xo = 0
+        gc, gr, gb, gl = [], [], [], []
+        for p in probs:
+            for j in range(nlam):
+                for r in range(nrhs):
+                    xi = x_in[xo:xo + p.n]
+                    g = oracle.band_gradients(p.col, p.row, p.b[r], p.lams[j], xi, xi - p.x_true)
+                    gc.append(g["g_col"].real); gr.append(g["g_row"].real); gb.append(g["g_b"].real)
+                    gl.append(g["g_lam"])
+                    xo += p.n
+        return np.concatenate(gc), np.concatenate(gr), np.concatenate(gb), np.array(gl)
+
+    ip = min(range(3), key=lambda i: probs[i].meta["L"])
+    cpu, parity = b.oracle_leg(probs, ip, nlam, nrhs, x_gpu, run_backward, cores=2)
+    assert parity["ok"] and parity["fwd_max_rel_err"] < 1e-13 and parity["bwd_max_rel_err"] < 1e-12
+    assert parity["fwd_solves_checked"] == nlam * nrhs and cpu["value"] > 0
+    cnt, worst = b.residual_sample(probs, nlam, nrhs, x_gpu, count=12)
+    assert cnt == 12 and worst < 1e-13
+    bad = x_gpu.copy()
+    off = sum(p.n * nlam * nrhs for p in probs[:ip]) + (1 * nrhs + 1) * probs[ip].n + 5
+    bad[off] += 1e-6 * np.abs(x_gpu).max()
+    _, parity2 = b.oracle_leg(probs, ip, nlam, nrhs, bad, run_backward, cores=2)
+    assert not parity2["ok"]

@@ -2,9 +2,11 @@
 
 Small and medium problems are compared element by element with the oracle
 (dense Householder QR of [T; lambda I]) at sizes the oracle finishes in
-seconds, spanning several leaves, several tree levels and ragged extensions;
-full-size problems are checked through the optimality condition
-T^H (b - T x) = lambda^2 x, which holds at any size.  Tolerance: relative
+seconds, spanning several leaves, several tree levels and ragged extensions.
+Full-size problems (generators of finite support) are compared element by
+element with the banded QR oracle, which solves the same least-squares problem
+exactly at any size, or with known solutions whose right-hand sides are formed
+in long double.  Tolerance: relative
 2-norm error <= 1e-9 against the oracle (the accuracy target for problems
 whose regularized normal matrix has condition number <= 1e6)."""
 import os
@@ -265,6 +267,63 @@ def test_headline_size_rhs_transform(P):
     assert relerr(x1, x2) <= TOL
 
 
+@pytest.mark.parametrize("n,cplx", [(1000, False), (4096, True), (2 ** 14, False)])
+def test_circulant_closed_form_gpu(P, n, cplx):
+    """Circulant T (m = n, a_{-j} = a_{n-j}): the Fourier-domain closed form
+    x = IDFT(conj(a^) b^ / (|a^|^2 + lambda^2)) holds at any size; lambda is set so
+    that the regularized normal matrix has condition number 1e6."""
+    rng = np.random.default_rng(n + 31 * cplx)
+    c = rng.standard_normal(n) + (1j * rng.standard_normal(n) if cplx else 0)
+    col = c.copy()
+    row = np.concatenate([[c[0]], c[1:][::-1]])
+    b = rng.standard_normal(n) + (1j * rng.standard_normal(n) if cplx else 0)
+    ah = np.fft.fft(c)
+    lam = float(np.abs(ah).max()) * 1e-3
+    xe = np.fft.ifft(np.conj(ah) * np.fft.fft(b) / (np.abs(ah) ** 2 + lam ** 2))
+    if not cplx:
+        xe = xe.real
+    x = P.solve(dev(col), dev(row), dev(b), lam).cpu().numpy()
+    assert relerr(x, xe) <= TOL, (n, cplx, relerr(x, xe))
+
+
+@pytest.mark.parametrize("m,n", [(500, 500), (700, 500), (300, 450)])
+def test_scaled_identity_and_zero_gpu(P, m, n):
+    """T = c [I; 0] (only a_0 = c nonzero): x = conj(c) b[:n] / (|c|^2 + lambda^2) (with
+    zeros past row m when m < n); T = 0: x = 0 from the least-squares entry and
+    x = y / lambda^2 from the normal form.  Generators with all but one entry zero, or
+    none, give residual columns that are exactly zero."""
+    rng = np.random.default_rng(m + 7 * n)
+    c = 1.5 - 0.5j
+    col = np.zeros(m, complex); col[0] = c
+    row = np.zeros(n, complex); row[0] = c
+    b = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+    lam = 0.8
+    xe = np.zeros(n, complex)
+    k = min(m, n)
+    xe[:k] = np.conj(c) * b[:k] / (abs(c) ** 2 + lam ** 2)
+    x = P.solve(dev(col), dev(row), dev(b), lam).cpu().numpy()
+    assert relerr(x, xe) <= TOL, relerr(x, xe)
+    z = np.zeros(m)
+    x0 = P.solve(dev(z), dev(np.zeros(n)), dev(b.real), lam).cpu().numpy()
+    assert np.abs(x0).max() == 0.0
+    y = rng.standard_normal(n)
+    xn = P.solve_normal(dev(z), dev(np.zeros(n)), dev(y), lam).cpu().numpy()
+    assert relerr(xn, y / lam ** 2) <= TOL
+
+
+def test_scaling_law_gpu(P):
+    """x(alpha T, alpha lambda, b) = x(T, lambda, b) / alpha, for a ragged tall problem
+    over three leaf levels, alpha a power of two and not."""
+    rng = np.random.default_rng(404)
+    col, row, b = W.random_problem(rng, 700, 611, cplx=True, L=15.0)
+    lam = 0.05
+    x1 = P.solve(dev(col), dev(row), dev(b), lam).cpu().numpy()
+    assert relerr(x1, oracle.solve(col, row, b, lam)) <= TOL
+    for alpha in (0.0625, 3.7, 1e3):
+        xa = P.solve(dev(alpha * col), dev(alpha * row), dev(b), alpha * lam).cpu().numpy()
+        assert relerr(alpha * xa, x1) <= TOL, (alpha, relerr(alpha * xa, x1))
+
+
 def test_invalid_lambda_and_sizes(P):
     c = dev(np.ones(4)); r = dev(np.ones(4)); b = dev(np.ones(4))
     for lam in (0.0, -1.0, float("nan"), float("inf")):
@@ -277,6 +336,16 @@ def test_nonfinite_input_reports_info(P):
     with pytest.raises(P.TikhError) as e:
         P.solve(dev(col), dev(np.ones(10)), dev(np.ones(20)), 0.5)
     assert e.value.code == -4
+    # a non-finite right-hand side leaves the pivots (columns 1..4) intact: only the
+    # non-finite bit (8) is set, for that solve alone
+    rng = np.random.default_rng(8)
+    col, row, _ = W.random_problem(rng, 40, 30, L=6.0)
+    b = rng.standard_normal((2, 40))
+    b[1, 5] = np.inf
+    x, info = P.solve_batched([40], [30], dev(col), dev(row), [0.3], 2, dev(b.ravel()))
+    torch.cuda.synchronize()
+    assert info.cpu().numpy().tolist() == [0, 8]
+    assert relerr(x[:30].cpu().numpy(), oracle.solve(col, row, b[0], 0.3)) <= TOL
 
 
 @pytest.mark.parametrize("nrhs,cplx", [(3, False), (4, True), (5, False)])
@@ -347,15 +416,25 @@ def test_deblurring_full_size_known_solution(P):
     assert relerr(x, pr.x_true) <= TOL, relerr(x, pr.x_true)
 
 
+def _band_oracle(col, row, rhs_by_lam, lams, normal=False):
+    """Banded-QR oracle solutions for several lambdas at once (one thread per lambda; the
+    C oracle releases the interpreter lock): returns [len(lams)][nrhs][n]."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=min(16, len(lams))) as ex:
+        futs = [ex.submit(oracle.band_solve, col, row, rhs, lam, normal) for rhs, lam in zip(rhs_by_lam, lams)]
+        return [f.result() for f in futs]
+
+
 def test_headline_batch_full_config_sampled(P):
     """The benchmark's launch configuration: 256 problems of the headline shape
     (n = 2^14, m = n + U{0..n/4}) x 8 lambdas x 4 right-hand sides in one
     batched call, i.e. 2048 groups in one chunk, which takes the one-wavefront-
     per-group leaf steps.  32 generated problems are used 8 times each, every
     copy with its lambda path scaled by its own factor so that no two groups
-    hold the same data.  Sampled solves across the batch must agree with the
-    single-problem path (whose accuracy at this size is pinned by the
-    known-solution tests above) to the parity tolerance."""
+    hold the same data.  Every solve of two copies of the generated problem
+    with the narrowest generator support (all 8 lambdas, kappa up to 1 + 1e6,
+    and all 4 right-hand sides) is compared element by element with the banded
+    QR oracle; sampled solves elsewhere in the batch with the single-problem path."""
     base = [W.headline(i, n=2 ** 14, nrhs=4, nlam=8) for i in range(32)]
     probs = []
     for c in range(8):
@@ -376,11 +455,31 @@ def test_headline_batch_full_config_sampled(P):
     assert (info.cpu().numpy() == 0).all()
     x = x.cpu().numpy()
     n = 2 ** 14
-    for (ip, j, r) in [(0, 0, 0), (77, 7, 3), (150, 3, 1), (255, 5, 2), (200, 0, 2)]:
+    inarrow = min(range(32), key=lambda i: base[i].meta["L"])
+    for ip in (inarrow, inarrow + 7 * 32):
+        p, ls = probs[ip]
+        ref = _band_oracle(p.col, p.row, [p.b] * 8, ls)
+        for j in range(8):
+            for r in range(4):
+                off = ((ip * 8 + j) * 4 + r) * n
+                e = relerr(x[off:off + n], ref[j][r])
+                assert e <= TOL, (ip, j, r, e)
+    for (ip, j, r) in [(0, 0, 0), (77, 7, 3), (150, 3, 1)]:
         p, ls = probs[ip]
         off = ((ip * 8 + j) * 4 + r) * n
         xs = P.solve(dev(p.col), dev(p.row), dev(p.b[r]), ls[j]).cpu().numpy()
         assert relerr(x[off:off + n], xs) <= TOL, (ip, j, r, relerr(x[off:off + n], xs))
+
+
+def test_deblurring_full_size_vs_band_oracle(P):
+    """The plain method at scale through the least-squares entry: 1-D deblurring at
+    n = 2^16, m = n + 192 (193-tap Gaussian PSF, lambda = 1e-2, b with noise), against
+    the banded QR oracle (exact for the PSF's finite support)."""
+    pr = W.config1()
+    lam = pr.lams[0]
+    x = P.solve(dev(pr.col), dev(pr.row), dev(pr.b[0]), lam).cpu().numpy()
+    xr = oracle.band_solve(pr.col, pr.row, [pr.b[0]], lam)[0]
+    assert relerr(x, xr) <= TOL, relerr(x, xr)
 
 
 def test_caller_workspace(P):
