@@ -112,7 +112,7 @@ def band_solve(col, row, rhs, lam, normal=False):
     return x[0] if single else x
 
 
-def band_gradients(col, row, b, lam, x, gx, lag_sums=True):
+def band_gradients(col, row, b, lam, x, gx, with_lag_sums=True):
     """Gradients of a loss through x = solve(col, row, b, lam) (eq. (tiksol)) with the banded QR:
     w = (T^H T + lam^2 I)^{-1} gx, g_b = T w, g_lam = -2 lam Re<w, x>, and (optionally, O(mn))
     the lag sums of (b - T x) w^H - (T w) x^H.  x is the forward solution the gradient is taken at."""
@@ -121,13 +121,38 @@ def band_gradients(col, row, b, lam, x, gx, lag_sums=True):
     w = _c(band_solve(col, row, [gx], lam, normal=True)[0])
     Tw = T_apply(col, row, w)
     out = dict(w=w, g_b=Tw, g_lam=float(-2.0 * lam * np.vdot(w, x).real))
-    if lag_sums:
-        r = b - T_apply(col, row, x)
-        gcol = np.zeros(m, np.complex128)
-        grow = np.zeros(n, np.complex128)
-        _load().tikh_oracle_lag_sums(m, n, _p(r), _p(w), _p(Tw), _p(x), _p(gcol), _p(grow))
+    if with_lag_sums:
+        gcol, grow = lag_sums(col, row, b, x, w)
         out.update(g_col=gcol, g_row=grow)
     return out
+
+
+def lag_sums(col, row, b, x, w):
+    """Generator gradient of the adjoint: lag sums of (b - T x) w^H - (T w) x^H written out (O(mn))."""
+    col, row, b, x, w = _c(col), _c(row), _c(b), _c(x), _c(w)
+    m, n = len(col), len(row)
+    r = b - T_apply(col, row, x)
+    Tw = T_apply(col, row, w)
+    gcol = np.zeros(m, np.complex128)
+    grow = np.zeros(n, np.complex128)
+    _load().tikh_oracle_lag_sums(m, n, _p(r), _p(w), _p(Tw), _p(x), _p(gcol), _p(grow))
+    return gcol, grow
+
+
+def gramian_solve(gram, lcol, lrow, y):
+    """Toeplitz-Gramian problem (Sec. 2, third case; Sec. 3.4): x = (G + L^H L)^{-1} y, where G is
+    the n x n Hermitian Toeplitz Gramian with first column gram (G[r][s] = gram[r-s] for r >= s,
+    conj(gram[s-r]) otherwise) and L the p x n Toeplitz regularizer (lcol[i] = l_i, lrow[j] = l_{-j}).
+    The matrix G + L^H L is formed densely and solved by LAPACK (numpy.linalg.solve)."""
+    gram, lcol, lrow, y = _c(gram), _c(lcol), _c(lrow), _c(y)
+    n = len(gram)
+    assert len(lrow) == n and len(y) == n
+    G = np.empty((n, n), np.complex128)
+    for r in range(n):
+        G[r, :r + 1] = gram[r::-1]
+        G[r, r + 1:] = np.conj(gram[1:n - r])
+    L = dense_T(lcol, lrow)
+    return np.linalg.solve(G + L.conj().T @ L, y)
 
 
 def T_apply(col, row, v):

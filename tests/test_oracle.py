@@ -286,3 +286,77 @@ def test_normal_residual_fft():
     xp = x * (1 + 1e-6)
     assert abs(oracle.normal_residual_fft(col, row, b, lam, xp) / oracle.normal_residual(col, row, b, lam, xp) - 1) < 1e-6
     assert oracle.normal_residual_fft(col, row, b, lam, xp) > 1e-8
+
+
+# ---- Toeplitz-Gramian problem (Sec. 2, third case; Sec. 3.4) ----
+
+def test_gramian_reduces_to_l2():
+    """T circulant (so that G = T^H T is Toeplitz) with L = lambda I (a p = n Toeplitz
+    regularizer) is the l2 problem's normal form: the Gramian oracle must equal the dense-QR
+    normal-form solve."""
+    rng = np.random.default_rng(51)
+    for (n, cplx) in [(20, False), (25, True), (9, True)]:
+        c = rng.standard_normal(n) + (1j * rng.standard_normal(n) if cplx else 0)
+        col = c.copy(); row = np.concatenate([[c[0]], c[1:][::-1]])
+        T = oracle.dense_T(col, row)
+        gram = (T.conj().T @ T)[:, 0]
+        lam = 0.6
+        lcol = np.zeros(n); lcol[0] = lam
+        lrow = np.zeros(n); lrow[0] = lam
+        y = rng.standard_normal(n) + (1j * rng.standard_normal(n) if cplx else 0)
+        np.testing.assert_allclose(oracle.gramian_solve(gram, lcol, lrow, y), oracle.solve_normal(col, row, y, lam),
+                                   rtol=1e-11, atol=1e-12)
+
+
+@pytest.mark.parametrize("n", [16, 63, 200])
+def test_gramian_circulant_closed_form(n):
+    """G and L circulant (Hermitian-symmetric first column c for G, first column d for L,
+    p = n): x = IDFT(y^ / (c^ + |d^|^2))."""
+    rng = np.random.default_rng(n + 5)
+    c = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    c = 0.5 * (c + np.conj(np.roll(c[::-1], 1)))          # c_{n-s} = conj(c_s): G Hermitian
+    ch = np.fft.fft(c).real
+    c[0] += 1.0 - ch.min()                                   # G positive definite
+    d = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    gram = c.copy()
+    lcol = d.copy(); lrow = np.concatenate([[d[0]], d[1:][::-1]])
+    y = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    xe = np.fft.ifft(np.fft.fft(y) / (np.fft.fft(c).real + np.abs(np.fft.fft(d)) ** 2))
+    np.testing.assert_allclose(oracle.gramian_solve(gram, lcol, lrow, y), xe, rtol=1e-10, atol=1e-11)
+
+
+def test_gramian_exact_rational():
+    """Integer data, exact rational elimination of (G + L^T L) x = y (G symmetric Toeplitz
+    with a dominant diagonal, L a 4 x 5 Toeplitz regularizer)."""
+    rng = np.random.default_rng(61)
+    n, p = 5, 4
+    gram = rng.integers(-3, 4, size=n); gram[0] = 12
+    G = [[int(gram[abs(r - s)]) for s in range(n)] for r in range(n)]
+    lcol = rng.integers(-3, 4, size=p); lrow = rng.integers(-3, 4, size=n); lrow[0] = lcol[0]
+    L = [[int(lcol[i - j]) if i >= j else int(lrow[j - i]) for j in range(n)] for i in range(p)]
+    A = [[Fraction(G[r][s] + sum(L[k][r] * L[k][s] for k in range(p))) for s in range(n)] for r in range(n)]
+    y = [Fraction(int(v)) for v in rng.integers(-5, 6, size=n)]
+    M = [row[:] + [y[i]] for i, row in enumerate(A)]
+    for c in range(n):
+        pv = next(r for r in range(c, n) if M[r][c] != 0)
+        M[c], M[pv] = M[pv], M[c]
+        for r in range(n):
+            if r != c and M[r][c] != 0:
+                f = M[r][c] / M[c][c]
+                M[r] = [M[r][k] - f * M[c][k] for k in range(n + 1)]
+    xe = np.array([float(M[i][n] / M[i][i]) for i in range(n)])
+    x = oracle.gramian_solve(gram, lcol, lrow, np.array([float(v) for v in y]))
+    np.testing.assert_allclose(x.real, xe, rtol=1e-12, atol=1e-13)
+    assert np.abs(x.imag).max() == 0.0
+
+
+def test_gramian_mutation_fails():
+    """A plausible slip (G built from conj(gram), i.e. G transposed) must change the answer."""
+    rng = np.random.default_rng(71)
+    n = 12
+    gram = rng.standard_normal(n) + 1j * rng.standard_normal(n); gram[0] = 8.0
+    lcol = rng.standard_normal(n); lrow = np.concatenate([[lcol[0]], rng.standard_normal(n - 1)])
+    y = rng.standard_normal(n)
+    x1 = oracle.gramian_solve(gram, lcol, lrow, y)
+    x2 = oracle.gramian_solve(np.conj(gram), lcol, lrow, y)
+    assert np.linalg.norm(x1 - x2) / np.linalg.norm(x1) > 1e-3

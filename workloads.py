@@ -226,3 +226,72 @@ def random_problem(rng, m, n, cplx=False, L=None):
     col, row = split_generator(a, m, n)
     b = rng.standard_normal(m) + (1j * rng.standard_normal(m) if cplx else 0.0)
     return col, row, b
+
+
+@dataclass
+class GramianProblem:
+    """Toeplitz-Gramian problem (G + L^H L) x = y: gram = first column of the n x n Hermitian
+    Toeplitz Gramian, (lcol, lrow) the p x n Toeplitz regularizer, ys right-hand sides."""
+    gram: np.ndarray
+    lcol: np.ndarray
+    lrow: np.ndarray
+    ys: List[np.ndarray]
+    x_true: Optional[np.ndarray] = None
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self):
+        return len(self.gram)
+
+    @property
+    def p(self):
+        return len(self.lcol)
+
+
+def nufft_problem(index=0, n=4096, K=4096, lreg=1e4):
+    """Reconstruction from non-uniform spectral samples (Sec. 7.4): x_true is a length-n sum of
+    three real sinusoids with frequencies in [0, 0.02]; K sample frequencies f_k are drawn from the
+    triangular distribution on [-1/2, 1/2) (mode 0); the Voronoi-cell widths of the sorted
+    frequencies (period 1), in units of the uniform spacing 1/K (so a uniform grid has unit
+    weights), weight the samples (regularized condition number about 1e7, as the paper reports
+    for its example); the weighted Gramian A^H W A with
+    A_{ks} = exp(-2 pi i f_k s) is Hermitian Toeplitz with first column g_d = sum_k w_k exp(2 pi i f_k d);
+    L is the scaled second difference (2 lreg on the diagonal, -lreg beside it, p = n); the
+    right-hand side is y = A^H W X for the exact samples X = A x_true."""
+    rng = rng_for(7, index)
+    fr = rng.uniform(0.0, 0.02, 3)
+    ph = rng.uniform(0.0, 2 * math.pi, 3)
+    amp = rng.standard_normal(3)
+    s = np.arange(n)
+    x = sum(a * np.cos(2 * math.pi * f * s + q) for a, f, q in zip(amp, fr, ph))
+    fk = np.sort(rng.triangular(-0.5, 0.0, 0.5, K))
+    fk[fk >= 0.5] -= 1.0
+    fk = np.sort(fk)
+    ext = np.concatenate([[fk[-1] - 1.0], fk, [fk[0] + 1.0]])
+    w = 0.5 * K * (ext[2:] - ext[:-2])
+    E = np.exp(-2j * math.pi * np.outer(fk, s))                 # A, K x n
+    X = E @ x
+    y = E.conj().T @ (w * X)
+    gram = np.exp(2j * math.pi * np.outer(s, fk)) @ w           # g_d, d = 0 .. n-1
+    lcol = np.zeros(n); lcol[0] = 2 * lreg; lcol[1] = -lreg
+    lrow = np.zeros(n); lrow[0] = 2 * lreg; lrow[1] = -lreg
+    return GramianProblem(gram, lcol, lrow, [y], x, dict(config="nufft", freqs=fr, K=K))
+
+
+def random_gramian(rng, n, p, cplx=True, L=None):
+    """Random Toeplitz-Gramian problem for parity sweeps: the Gramian of a random circulant
+    (so that it is Toeplitz and positive semidefinite) and a random p x n Toeplitz L."""
+    c = rng.standard_normal(n) + (1j * rng.standard_normal(n) if cplx else 0)
+    if L is not None:
+        c = c * np.exp(-np.minimum(np.arange(n), n - np.arange(n)) / L)
+    ch = np.fft.fft(c)
+    gram = np.fft.ifft(np.abs(ch) ** 2)                           # first column of C^H C
+    if not cplx:
+        gram = gram.real
+    s = np.arange(-(n - 1), p)
+    a = rng.standard_normal(len(s)) + (1j * rng.standard_normal(len(s)) if cplx else 0)
+    if L is not None:
+        a = a * np.exp(-np.abs(s) / L)
+    lcol, lrow = split_generator(0.3 * a, p, n)
+    y = rng.standard_normal(n) + (1j * rng.standard_normal(n) if cplx else 0)
+    return GramianProblem(gram, lcol, lrow, [y], None, dict(config="gramian"))
