@@ -221,6 +221,33 @@ int tikh_toeplitz_solve_batched(int64_t nprob, const int64_t* m, const int64_t* 
                                 int32_t* info, int complex_data);
 
 /*
+ * Toeplitz-Gramian problem (Sec. 2, third case; Sec. 3.4, eq. (gramblk) and
+ * (ex7)): x = (G + L^H L)^{-1} y, where G is an n x n Hermitian Toeplitz
+ * Gramian (for instance G = A^H W A of a non-uniform Fourier matrix, Sec. 7.4)
+ * given by its first column gram[s] = G[s][0] (G[r][s] = gram[r-s] for r >= s,
+ * conj(gram[s-r]) otherwise; gram[n-1] is the last entry), L is a p x n
+ * Toeplitz regularizer (lcol[i] = l_i, i < p; lrow[j] = l_{-j}, 0 < j < n;
+ * lrow[0] ignored), and y[n] is the right-hand side (T^H b of the underlying
+ * least-squares problem).  The same extension (circulant blocks of size N >=
+ * max(2n - 1, p + n - 1), Alg. 2), interpolation recursion and refinement as
+ * the l2 solves; G + L^H L must be nonsingular.  Device arrays as above;
+ * single-problem calls synchronize and return TIKH_ENUMERIC if info != 0.
+ */
+int tikh_gramian_solve(const double* gram, const double* lcol, const double* lrow, int64_t p, int64_t n,
+                       const double* y, double* x);
+int tikh_gramian_solve_z(const tikh_c64* gram, const tikh_c64* lcol, const tikh_c64* lrow, int64_t p, int64_t n,
+                         const tikh_c64* y, tikh_c64* x);
+/*
+ * Batched: nprob problems with host arrays p[nprob], n[nprob]; packed device
+ * buffers gram (sum n_q), lcol (sum p_q), lrow (sum n_q), y and x (for each
+ * problem q, nrhs vectors of n_q entries); info as for tikh_toeplitz_solve_batched.
+ * Asynchronous.
+ */
+int tikh_gramian_solve_batched(int64_t nprob, const int64_t* p, const int64_t* n, const void* gram,
+                               const void* lcol, const void* lrow, int64_t nrhs, const void* y, void* x,
+                               int32_t* info, int complex_data);
+
+/*
  * Adjoint (backward) of x = solve(col, row, b, lambda) for a scalar loss with
  * upstream gradient gx[n] = dL/dRe(x) + i dL/dIm(x) (real data: dL/dx).  x is
  * the forward solution.  Derived from eq. (tiksol): w = (T^H T + lambda^2 I)^{-1} gx

@@ -61,6 +61,10 @@ tikh_toeplitz_solve_normal = _sig("tikh_toeplitz_solve_normal", [_P, _P, _I64, _
 tikh_toeplitz_solve_normal_z = _sig("tikh_toeplitz_solve_normal_z", [_P, _P, _I64, _I64, _P, _D, _P])
 tikh_toeplitz_solve_batched = _sig("tikh_toeplitz_solve_batched",
                                    [_I64, _P, _P, _P, _P, _I64, _P, _I64, _P, _P, _P, ctypes.c_int])
+tikh_gramian_solve = _sig("tikh_gramian_solve", [_P, _P, _P, _I64, _I64, _P, _P])
+tikh_gramian_solve_z = _sig("tikh_gramian_solve_z", [_P, _P, _P, _I64, _I64, _P, _P])
+tikh_gramian_solve_batched = _sig("tikh_gramian_solve_batched",
+                                  [_I64, _P, _P, _P, _P, _P, _I64, _P, _P, _P, ctypes.c_int])
 tikh_toeplitz_solve_backward = _sig("tikh_toeplitz_solve_backward",
                                     [_P, _P, _I64, _I64, _P, _D, _P, _P, _P, _P, _P, _P])
 tikh_toeplitz_solve_backward_z = _sig("tikh_toeplitz_solve_backward_z",
@@ -255,6 +259,32 @@ def solve_batched(ms, ns, col, row, lambdas, nrhs, b, complex_data=False, info=N
     _check(tikh_toeplitz_solve_batched(nprob, _i64(ms), _i64(ns), _ptr(col), _ptr(row), nlam, lam_arr, int(nrhs),
                                        _ptr(b), _ptr(x), _ptr(info), 1 if complex_data else 0),
            "tikh_toeplitz_solve_batched")
+    return x, info
+
+
+def gramian_solve(gram, lcol, lrow, y):
+    """Toeplitz-Gramian problem x = (G + L^H L)^{-1} y (tikh_gramian_solve[_z]); G Hermitian
+    Toeplitz with first column gram, L Toeplitz (lcol, lrow).  Synchronizes."""
+    dt = _dtype_of(gram, lcol, lrow, y)
+    gram, lcol, lrow, y = (_dev(t.to(dt), dt) for t in (gram, lcol, lrow, y))
+    x = torch.empty_like(y)
+    fn = tikh_gramian_solve_z if dt == torch.complex128 else tikh_gramian_solve
+    _stream()
+    _check(fn(_ptr(gram), _ptr(lcol), _ptr(lrow), lcol.numel(), gram.numel(), _ptr(y), _ptr(x)), "tikh_gramian_solve")
+    return x
+
+
+def gramian_solve_batched(ps, ns, gram, lcol, lrow, nrhs, y, complex_data=False):
+    """Packed batched Toeplitz-Gramian solves (tikh_gramian_solve_batched); returns (x, info),
+    asynchronous on the current stream."""
+    dt = torch.complex128 if complex_data else torch.float64
+    gram, lcol, lrow, y = _dev(gram, dt), _dev(lcol, dt), _dev(lrow, dt), _dev(y, dt)
+    x = torch.empty_like(y)
+    info = torch.zeros(len(ps) * nrhs, dtype=torch.int32, device=y.device)
+    _stream()
+    _check(tikh_gramian_solve_batched(len(ps), _i64(ps), _i64(ns), _ptr(gram), _ptr(lcol), _ptr(lrow), int(nrhs),
+                                      _ptr(y), _ptr(x), _ptr(info), 1 if complex_data else 0),
+           "tikh_gramian_solve_batched")
     return x, info
 
 

@@ -43,6 +43,7 @@ struct Ctx {
     int64_t launches = 0;
     int* dneed = nullptr;                // device / pinned host word for degree readback
     int* hneed = nullptr;
+    std::map<int64_t, std::vector<double2>> htw, htw2;   // host copies of the tables, by size
 };
 static Ctx g;
 
@@ -118,16 +119,18 @@ static void prof_print_detail() {
 
 // Options take their defaults once; the degree readback words are (re)allocated
 // until both exist, and a merge that finds either missing reports TIKH_ENOMEM.
+static void init_opts() {
+    if (g.init) return;
+    g.opts.n_lim = 256;
+    g.opts.refine = 1;
+    g.opts.refine_max = 3;
+    g.opts.leaf_wave_groups = 1536;
+    g.opts.refine_tol = 1e-10;
+    g.opts.defer_tol = 0.0;
+    g.init = true;
+}
 static void ensure_init() {
-    if (!g.init) {
-        g.opts.n_lim = 256;
-        g.opts.refine = 1;
-        g.opts.refine_max = 3;
-        g.opts.leaf_wave_groups = 1536;
-        g.opts.refine_tol = 1e-10;
-        g.opts.defer_tol = 0.0;
-        g.init = true;
-    }
+    init_opts();
     if (!g.dneed && hipMalloc((void**)&g.dneed, sizeof(int)) != hipSuccess) g.dneed = nullptr;
     if (!g.hneed && hipHostMalloc((void**)&g.hneed, sizeof(int), hipHostMallocDefault) != hipSuccess) g.hneed = nullptr;
 }
@@ -227,11 +230,13 @@ static int tw2_bits(int64_t M) {
     while (((int64_t)1 << lg) < M) ++lg;
     return std::max(1, (lg + 1) / 2);
 }
-static double2* twiddles2(int64_t M, int* bits) {
-    *bits = tw2_bits(M);
-    auto it = g.tw2.find(M);
-    if (it != g.tw2.end()) return it->second;
-    const int64_t nlo = (int64_t)1 << *bits, nhi = ((M - 1) >> *bits) + 1;
+
+// Host tables (long double angles, rounded once), kept for the life of the library.
+static const std::vector<double2>& host_twiddles2(int64_t M) {
+    auto it = g.htw2.find(M);
+    if (it != g.htw2.end()) return it->second;
+    const int bits = tw2_bits(M);
+    const int64_t nlo = (int64_t)1 << bits, nhi = ((M - 1) >> bits) + 1;
     std::vector<double2> h(nlo + nhi);
     const long double pi2 = 6.283185307179586476925286766559005768L;
     for (int64_t j = 0; j < nlo; ++j) {
@@ -242,31 +247,35 @@ static double2* twiddles2(int64_t M, int* bits) {
         long double a = pi2 * (long double)(j * nlo) / (long double)M;
         h[nlo + j] = make_double2((double)cosl(a), (double)sinl(a));
     }
-    double2* d = nullptr;
-    if (hipMalloc(&d, sizeof(double2) * h.size()) != hipSuccess) return nullptr;
-    if (hipMemcpy(d, h.data(), sizeof(double2) * h.size(), hipMemcpyHostToDevice) != hipSuccess) {
-        (void)hipFree(d);
-        return nullptr;
-    }
-    g.tw2[M] = d;
-    return d;
+    return g.htw2[M] = std::move(h);
 }
-
-static double2* twiddles(int64_t Q) {
-    auto it = g.tw.find(Q);
-    if (it != g.tw.end()) return it->second;
+static const std::vector<double2>& host_twiddles(int64_t Q) {
+    auto it = g.htw.find(Q);
+    if (it != g.htw.end()) return it->second;
     std::vector<double2> h(Q);
     const long double pi2 = 6.283185307179586476925286766559005768L;
     for (int64_t q = 0; q < Q; ++q) {
         long double a = pi2 * (long double)q / (long double)Q;
         h[q] = make_double2((double)cosl(a), (double)sinl(a));
     }
-    double2* d = nullptr;
-    if (hipMalloc(&d, sizeof(double2) * Q) != hipSuccess) return nullptr;
-    if (hipMemcpy(d, h.data(), sizeof(double2) * Q, hipMemcpyHostToDevice) != hipSuccess) { (void)hipFree(d); return nullptr; }
-    g.tw[Q] = d;
-    return d;
+    return g.htw[Q] = std::move(h);
 }
+
+// A device copy of a host table, allocated once and kept.
+static double2* device_table(std::map<int64_t, double2*>& keep, int64_t key, const std::vector<double2>& h) {
+    const size_t bytes = sizeof(double2) * h.size();
+    auto it = keep.find(key);
+    if (it != keep.end()) return it->second;
+    double2* d = nullptr;
+    if (hipMalloc(&d, bytes) != hipSuccess) return nullptr;
+    if (hipMemcpy(d, h.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) { (void)hipFree(d); return nullptr; }
+    return keep[key] = d;
+}
+static double2* twiddles2(int64_t M, int* bits) {
+    *bits = tw2_bits(M);
+    return device_table(g.tw2, M, host_twiddles2(M));
+}
+static double2* twiddles(int64_t Q) { return device_table(g.tw, Q, host_twiddles(Q)); }
 
 // Adaptive refinement: the factor of the estimate cfac * e0 * ||dx|| / ||x||
 // of the error left after a step.
@@ -313,7 +322,7 @@ static void make_layout(const Plan& pl, int nr, int64_t mmax, int64_t nmax, Layo
     L->sF = fmax;
     L->sscr = std::max(L->sV, L->sF);
     size_t tot = 0;
-    tot += L->sN + L->sphi + L->srec;
+    tot += 2 * L->sN + L->sphi + L->srec;     // symbols of T (or L) and of the Gramian, residuals, step records
     // pending left children: one slot per depth; right-child results: one
     // shared slot (a right child's basis is consumed by the next product,
     // which reads it completely before it writes its own result).  Results
@@ -331,7 +340,7 @@ static void make_layout(const Plan& pl, int nr, int64_t mmax, int64_t nmax, Layo
         L->sT = std::max(L->sT, ((d & 1) ? L->tOff : 0) + sz);
     }
     tot += L->sT;
-    L->group_bytes = tot * sizeof(double2) + 2 * (pl.p + 1) * sizeof(SlotMeta) + sizeof(SolveState) + sizeof(double) +
+    L->group_bytes = tot * sizeof(double2) + 2 * (pl.p + 1) * sizeof(SlotMeta) + sizeof(SolveState) + 2 * sizeof(double) +
                      sizeof(int32_t) + sizeof(int2) + DEFER_CAP * (sizeof(int32_t) + (1 + L->C) * sizeof(double2)) + 256;
     L->solve_bytes = (size_t)(4 * L->sN + 4 * L->sn) * sizeof(double2) + sizeof(SolveDesc) + 2 * sizeof(double) + 64;
     L->temp_bytes = (size_t)(L->sV + 2 * L->sF + L->sscr) * sizeof(double2);
@@ -342,7 +351,9 @@ struct Bufs {
     SolveDesc* sd;                   // [G*nr]
     SolveState* st;                  // [G]
     double* rms;                     // [G]
+    double* rmsg;                    // [G] Gramian generator rms (Toeplitz-Gramian problem)
     double2* chat;                   // [G][N]
+    double2* cg;                     // [G][N] symbol of the extended Gramian
     double2 *bA, *bB, *bC, *bS;      // [G*nr][N]
     double2 *yv, *xacc, *t1, *t2;    // [G*nr][sn]
     double2* phi;                    // [G][C][2N]
@@ -369,8 +380,9 @@ struct Bufs {
 static Bufs shift_bufs(const Bufs& b, const Layout& L, const Plan& pl, int64_t c0) {
     Bufs o = b;
     const int64_t s0 = c0 * b.nr;
-    o.sd += s0; o.st += c0; o.rms += c0;
+    o.sd += s0; o.st += c0; o.rms += c0; o.rmsg += c0;
     o.chat += c0 * L.sN;
+    o.cg += c0 * L.sN;
     o.bA += s0 * L.sN; o.bB += s0 * L.sN; o.bC += s0 * L.sN; o.bS += s0 * L.sN;
     o.yv += s0 * L.sn; o.xacc += s0 * L.sn; o.t1 += s0 * L.sn; o.t2 += s0 * L.sn;
     o.phi += c0 * L.sphi;
@@ -443,6 +455,7 @@ static int carve_bufs(const Plan& pl, const Layout& L, int64_t G, int64_t CH, Bu
     b->sd = (SolveDesc*)carve(p, sizeof(SolveDesc) * S);
     b->st = (SolveState*)carve(p, sizeof(SolveState) * G);
     b->rms = (double*)carve(p, sizeof(double) * G);
+    b->rmsg = (double*)carve(p, sizeof(double) * G);
     b->elist = (int*)carve(p, sizeof(EList));
     b->dl.cap = DEFER_CAP;
     b->dl.C = L.C;
@@ -454,6 +467,7 @@ static int carve_bufs(const Plan& pl, const Layout& L, int64_t G, int64_t CH, Bu
     b->pairs = (int2*)carve(p, sizeof(int2) * G);
     auto cv = [&](int64_t per, int64_t cnt) { return (double2*)carve(p, sizeof(double2) * per * cnt); };
     b->chat = cv(L.sN, G);
+    b->cg = cv(L.sN, G);
     b->bA = cv(L.sN, S); b->bB = cv(L.sN, S); b->bC = cv(L.sN, S); b->bS = cv(L.sN, S);
     b->yv = cv(L.sn, S); b->xacc = cv(L.sn, S); b->t1 = cv(L.sn, S); b->t2 = cv(L.sn, S);
     b->phi = cv(L.sphi, G);
@@ -661,12 +675,14 @@ static int run_product_chunk(const Plan& pl, const Layout& L, const Bufs& b, int
     int64_t P = pl.P[dp];
     {
         // size the transforms by the actual degrees of this chunk (host readback)
-        if (!g.dneed || !g.hneed) return TIKH_ENOMEM;
-        hipLaunchKernelGGL(k_deg_need, dim3(1), dim3(256), 0, g.stream, b.metaS[dc], b.metaT[dc], (int)G, C, g.dneed);
-        HIPCHK(hipMemcpyAsync(g.hneed, g.dneed, sizeof(int), hipMemcpyDeviceToHost, g.stream));
+        int* dneed = g.dneed;
+        int* hneed = g.hneed;
+        if (!dneed || !hneed) return TIKH_ENOMEM;
+        hipLaunchKernelGGL(k_deg_need, dim3(1), dim3(256), 0, g.stream, b.metaS[dc], b.metaT[dc], (int)G, C, dneed);
+        HIPCHK(hipMemcpyAsync(hneed, dneed, sizeof(int), hipMemcpyDeviceToHost, g.stream));
         HIPCHK(hipStreamSynchronize(g.stream));
         g.launches += 1;
-        const int64_t need = std::max<int64_t>(1, (int64_t)*g.hneed);
+        const int64_t need = std::max<int64_t>(1, (int64_t)*hneed);
         if (need <= P) P = smallest_divisor_geq(pl.Q, need);
         if (P > pl.P[dp]) P = pl.P[dp];
     }
@@ -826,10 +842,10 @@ static int run_recursion(const Plan& pl, const Layout& L, const Bufs& b, int64_t
 
 // circulant products on length-N per-solve buffers (symbol from the group)
 static void circ_apply(const Plan& pl, const Layout& L, const Bufs& b, int64_t S, double2* buf, int mode,
-                       const double2* tw) {
+                       const double2* tw, const double2* symbol = nullptr) {
     fft_lines(buf, S, L.sN, 1, pl.N, +1, tw, pl.Q, b.bS, L.sN);
-    hipLaunchKernelGGL(k_mul_symbol, grid1(pl.N, S), dim3(256), 0, g.stream, b.sd, L.nr, b.chat, buf, pl.N, L.sN, mode,
-                       tw, pl.Q);
+    hipLaunchKernelGGL(k_mul_symbol, grid1(pl.N, S), dim3(256), 0, g.stream, b.sd, L.nr, symbol ? symbol : b.chat, buf,
+                       pl.N, L.sN, mode, tw, pl.Q);
     fft_lines(buf, S, L.sN, 1, pl.N, -1, tw, pl.Q, b.bS, L.sN);
     g.launches++;
 }
@@ -859,6 +875,15 @@ static int run_chunk(const Plan& pl, int nr, const std::vector<SolveDesc>& sds, 
     g.launches += 3;
     rc = fft_lines(b.chat, G, L.sN, 1, N, +1, tw, pl.Q, b.bS, L.sN);
     if (rc) return rc;
+    const bool gramian = sds[0].gramian != 0;
+    if (gramian) {
+        // Toeplitz-Gramian problem: the extended Gramian's symbol (Sec. 3.4)
+        hipLaunchKernelGGL(k_gram_rms, dim3((unsigned)G), dim3(256), 0, g.stream, b.sd, nr, b.rmsg);
+        hipLaunchKernelGGL(k_build_cg, grid1(N, G), dim3(256), 0, g.stream, b.sd, nr, b.rmsg, b.cg, N, L.sN);
+        g.launches += 2;
+        rc = fft_lines(b.cg, G, L.sN, 1, N, +1, tw, pl.Q, b.bS, L.sN);
+        if (rc) return rc;
+    }
     // right-hand side y = T^H b as the bottom n entries of C_k(T^H) [b; 0], per solve
     const bool normal = sds[0].mode == 1;
     if (!normal) {
@@ -897,7 +922,7 @@ static int run_chunk(const Plan& pl, int nr, const std::vector<SolveDesc>& sds, 
                 HIPCHK(hipMemcpyAsync(b.pairs, hp.data(), sizeof(int2) * hp.size(), hipMemcpyHostToDevice, g.stream));
                 HIPCHK(hipStreamSynchronize(g.stream));
                 hipLaunchKernelGGL(k_swap_groups, dim3(64, (unsigned)hp.size()), dim3(256), 0, g.stream, b.sd, b.st,
-                                   b.chat, L.sN, b.yv, b.xacc, L.sn, nr, b.pairs);
+                                   b.chat, L.sN, b.yv, b.xacc, L.sn, nr, b.pairs, gramian ? b.cg : nullptr);
                 g.launches++;
             }
             Ga = G2;
@@ -906,7 +931,16 @@ static int run_chunk(const Plan& pl, int nr, const std::vector<SolveDesc>& sds, 
         }
         const double2* rhs = b.yv;
         if (it > 0) {
-            // residual of the normal equations, r = y - (T^H T + lam^2) x (Sec. 7.2: iterative refinement)
+            // residual of the normal equations, r = y - (T^H T + lam^2) x (Sec. 7.2: iterative refinement);
+            // Toeplitz-Gramian problem: r = y - (L^H L + G) x, with G x (bC) from the Gramian's circulant
+            if (gramian) {
+                hipLaunchKernelGGL(k_load_pad, grid1(N, Sa), dim3(256), 0, g.stream, b.sd, 0, b.xacc, L.sn, 1, 0, 1.0,
+                                   b.bB, N, L.sN);
+                circ_apply(pl, L, b, Sa, b.bB, 0, tw, b.cg);
+                hipLaunchKernelGGL(k_take_tail, grid1(nmax, Sa), dim3(256), 0, g.stream, b.sd, b.bB, N, L.sN, 1, invN,
+                                   b.bC, L.sN);
+                g.launches += 2;
+            }
             hipLaunchKernelGGL(k_load_pad, grid1(N, Sa), dim3(256), 0, g.stream, b.sd, 0, b.xacc, L.sn, 1, 0, 1.0,
                                b.bB, N, L.sN);
             circ_apply(pl, L, b, Sa, b.bB, 0, tw);
@@ -918,7 +952,7 @@ static int run_chunk(const Plan& pl, int nr, const std::vector<SolveDesc>& sds, 
             hipLaunchKernelGGL(k_take_tail, grid1(nmax, Sa), dim3(256), 0, g.stream, b.sd, b.bB, N, L.sN, 1, invN,
                                b.t2, L.sn);
             hipLaunchKernelGGL(k_normal_residual, grid1(nmax, Sa), dim3(256), 0, g.stream, b.sd, b.yv, b.t2, b.xacc,
-                               b.t1, L.sn);
+                               b.t1, L.sn, gramian ? (const double2*)b.bC : (const double2*)nullptr, L.sN);
             hipLaunchKernelGGL(k_init_state, dim3((unsigned)((Ga + 63) / 64)), dim3(64), 0, g.stream, b.sd, nr, b.st,
                                (int)Ga, 1);
             hipLaunchKernelGGL(k_zero_d, grid1(2 * Sa, 1), dim3(256), 0, g.stream, b.nrm, 2 * Sa);
@@ -931,7 +965,7 @@ static int run_chunk(const Plan& pl, int nr, const std::vector<SolveDesc>& sds, 
         rc = fft_lines(b.bA, Sa, L.sN, 1, N, +1, tw, pl.Q, b.bS, L.sN);
         if (rc) return rc;
         hipLaunchKernelGGL(k_assemble, grid1(2 * N, Ga), dim3(256), 0, g.stream, b.sd, nr, b.chat, b.bA, L.sN, b.phi,
-                           L.sphi, N, pl.M, pl.p, pl.K, tw, pl.Q);
+                           L.sphi, N, pl.M, pl.p, pl.K, tw, pl.Q, (const double2*)b.cg);
         g.launches++;
         rc = run_recursion(pl, L, b, Ga, tw);
         if (rc) return rc;
@@ -1033,7 +1067,10 @@ static int run_solves(std::vector<SolveDesc>& sds, int nr, int32_t* info) {
         SolveDesc& d0 = sds[gi * nr];
         int64_t N, M;
         int p;
-        if (!opt_extend(d0.m + d0.n - 1, g.opts.n_lim, &N, &M, &p)) return TIKH_EINVAL;
+        // the circulant must hold T (m + n - 1 generator entries), or for the Toeplitz-Gramian
+        // problem both L (p + n - 1) and the Gramian (2n - 1)
+        const int64_t Nt = d0.gramian ? std::max(d0.m + d0.n - 1, 2 * d0.n - 1) : d0.m + d0.n - 1;
+        if (!opt_extend(Nt, g.opts.n_lim, &N, &M, &p)) return TIKH_EINVAL;
         if (N > ((int64_t)1 << 19)) return TIKH_EINVAL;   // tau-degrees must fit the 20-bit pivot key
         for (int r = 0; r < nr; ++r) sds[gi * nr + r].k = N - (d0.m + d0.n - 1);
         buckets[N].push_back(gi);
@@ -1362,23 +1399,20 @@ int tikh_toeplitz_solve_normal_z(const tikh_c64* col, const tikh_c64* row, int64
     return solve_single(col, row, m, n, y, lambda, x, 1, 1);
 }
 
-int tikh_toeplitz_solve_batched(int64_t nprob, const int64_t* m, const int64_t* n, const void* col, const void* row,
-                                int64_t nlam, const double* lambdas, int64_t nrhs, const void* b, void* x,
-                                int32_t* info, int complex_data) {
-    ensure_init();
-    if (nprob < 0 || nlam < 1 || nrhs < 1 || !m || !n || !lambdas) return TIKH_EINVAL;
-    if (nprob == 0) return TIKH_OK;
+// Solve descriptors of a batched call (group-major, the last group of each
+// (problem, lambda) padded with empty solves).
+static int batched_sds(int64_t nprob, const int64_t* m, const int64_t* n, const void* col, const void* row,
+                       int64_t nlam, const double* lambdas, int64_t nrhs, const void* b, void* x, int complex_data,
+                       std::vector<SolveDesc>& sds) {
     if (!col || !row || !b || !x) return TIKH_EINVAL;
     const size_t es = complex_data ? sizeof(double2) : sizeof(double);
     const int nr = group_size(nrhs);
-    std::vector<SolveDesc> sds;
     int64_t co = 0, ro = 0, bo = 0, xo = 0, si = 0;
     for (int64_t p = 0; p < nprob; ++p) {
         if (m[p] < 1 || n[p] < 1) return TIKH_EINVAL;
         for (int64_t l = 0; l < nlam; ++l) {
             double lam = lambdas[p * nlam + l];
             if (bad_lambda(lam)) return TIKH_EINVAL;
-            // the rhs of (p, l) in groups of nr; the last group is padded with empty solves
             for (int64_t r0 = 0; r0 < nrhs; r0 += nr) {
                 for (int64_t r = r0; r < r0 + nr; ++r) {
                     SolveDesc d{};
@@ -1398,7 +1432,88 @@ int tikh_toeplitz_solve_batched(int64_t nprob, const int64_t* m, const int64_t* 
         }
         co += m[p]; ro += n[p]; bo += nrhs * m[p]; xo += nlam * nrhs * n[p]; si += nlam * nrhs;
     }
-    return run_solves(sds, nr, info);
+    return TIKH_OK;
+}
+
+int tikh_toeplitz_solve_batched(int64_t nprob, const int64_t* m, const int64_t* n, const void* col, const void* row,
+                                int64_t nlam, const double* lambdas, int64_t nrhs, const void* b, void* x,
+                                int32_t* info, int complex_data) {
+    ensure_init();
+    if (nprob < 0 || nlam < 1 || nrhs < 1 || !m || !n || !lambdas) return TIKH_EINVAL;
+    if (nprob == 0) return TIKH_OK;
+    std::vector<SolveDesc> sds;
+    int rc = batched_sds(nprob, m, n, col, row, nlam, lambdas, nrhs, b, x, complex_data, sds);
+    if (rc) return rc;
+    return run_solves(sds, group_size(nrhs), info);
+}
+
+// Toeplitz-Gramian problem (Sec. 2 third case, Sec. 3.4): solve descriptors with the
+// regularizer L in col/row/m, the Gramian's first column in gram, normal-form y.
+static int gramian_sds(int64_t nprob, const int64_t* p, const int64_t* n, const void* gram, const void* lcol,
+                       const void* lrow, int64_t nrhs, const void* y, void* x, int complex_data,
+                       std::vector<SolveDesc>& sds) {
+    if (!gram || !lcol || !lrow || !y || !x) return TIKH_EINVAL;
+    const size_t es = complex_data ? sizeof(double2) : sizeof(double);
+    const int nr = group_size(nrhs);
+    int64_t go = 0, lo = 0, ro = 0, yo = 0, si = 0;
+    for (int64_t q = 0; q < nprob; ++q) {
+        if (p[q] < 1 || n[q] < 1) return TIKH_EINVAL;
+        for (int64_t r0 = 0; r0 < nrhs; r0 += nr) {
+            for (int64_t r = r0; r < r0 + nr; ++r) {
+                SolveDesc d{};
+                d.col = (const char*)lcol + es * lo;
+                d.row = (const char*)lrow + es * ro;
+                d.gram = (const char*)gram + es * go;
+                d.gramian = 1;
+                d.m = p[q]; d.n = n[q]; d.lam = 1.0; d.cplx = complex_data ? 1 : 0; d.mode = 1;
+                if (r < nrhs) {
+                    d.rhs = (const char*)y + es * (yo + r * n[q]);
+                    d.x = (char*)x + es * (yo + r * n[q]);
+                    d.orig = (int32_t)(si + r);
+                } else {
+                    d.orig = -1;
+                }
+                sds.push_back(d);
+            }
+        }
+        go += n[q]; lo += p[q]; ro += n[q]; yo += nrhs * n[q]; si += nrhs;
+    }
+    return TIKH_OK;
+}
+
+int tikh_gramian_solve_batched(int64_t nprob, const int64_t* p, const int64_t* n, const void* gram, const void* lcol,
+                               const void* lrow, int64_t nrhs, const void* y, void* x, int32_t* info,
+                               int complex_data) {
+    ensure_init();
+    if (nprob < 0 || nrhs < 1 || !p || !n) return TIKH_EINVAL;
+    if (nprob == 0) return TIKH_OK;
+    std::vector<SolveDesc> sds;
+    int rc = gramian_sds(nprob, p, n, gram, lcol, lrow, nrhs, y, x, complex_data, sds);
+    if (rc) return rc;
+    return run_solves(sds, group_size(nrhs), info);
+}
+
+static int gramian_single(const void* gram, const void* lcol, const void* lrow, int64_t p, int64_t n, const void* y,
+                          void* x, int cplx) {
+    ensure_init();
+    if (p < 1 || n < 1 || p + 2 * n > ((int64_t)1 << 30)) return TIKH_EINVAL;
+    std::vector<SolveDesc> sds;
+    int rc = gramian_sds(1, &p, &n, gram, lcol, lrow, 1, y, x, cplx, sds);
+    if (rc) return rc;
+    int32_t* dinfo = nullptr;
+    HIPCHK(hipMallocAsync((void**)&dinfo, sizeof(int32_t), g.stream));
+    HIPCHK(hipMemsetAsync(dinfo, 0, sizeof(int32_t), g.stream));
+    return sync_info(run_solves(sds, 1, dinfo), dinfo);
+}
+
+int tikh_gramian_solve(const double* gram, const double* lcol, const double* lrow, int64_t p, int64_t n,
+                       const double* y, double* x) {
+    return gramian_single(gram, lcol, lrow, p, n, y, x, 0);
+}
+
+int tikh_gramian_solve_z(const tikh_c64* gram, const tikh_c64* lcol, const tikh_c64* lrow, int64_t p, int64_t n,
+                         const tikh_c64* y, tikh_c64* x) {
+    return gramian_single(gram, lcol, lrow, p, n, y, x, 1);
 }
 
 static int backward_single(const void* col, const void* row, int64_t m, int64_t n, const void* b, double lambda,

@@ -39,6 +39,11 @@ struct SolveDesc {
     double* glam;      // dL/d lambda (scalar)
     int32_t backward;
     int32_t orig;      // index of this solve in the caller's info array (-1: padding solve)
+    // Toeplitz-Gramian problem (G + L^H L) x = y: col/row/m hold the regularizer L
+    // (p x n), gram the first column of the Hermitian Toeplitz Gramian G (n entries)
+    const void* gram;
+    int32_t gramian;
+    int32_t pad_;
 };
 
 // Per-group running state of the recursion.

@@ -682,6 +682,49 @@ __global__ void k_build_ct(const SolveDesc* __restrict__ sd, int nr, const doubl
     }
 }
 
+// Toeplitz-Gramian problem (Sec. 3.4): entry g_s of the Hermitian Toeplitz
+// Gramian, s = -(n-1) .. n-1 (g_{-s} = conj(g_s)).
+__device__ __forceinline__ double2 gram_coef(const SolveDesc& d, int64_t s) {
+    const double2 v = load_elem(d.gram, s >= 0 ? s : -s, d.cplx);
+    return s >= 0 ? v : cconj(v);
+}
+
+// Root-mean-square of the Gramian's 2n - 1 generator entries (scale of its
+// arbitrary extension entries).
+__global__ __launch_bounds__(256) void k_gram_rms(const SolveDesc* __restrict__ sd, int nr, double* __restrict__ rms) {
+    const SolveDesc d = sd[(int64_t)blockIdx.x * nr];
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < d.n; i += blockDim.x) acc += (i == 0 ? 1.0 : 2.0) * cabs2(gram_coef(d, i));
+    __shared__ double red[256];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) rms[blockIdx.x] = sqrt(red[0] / (double)(2 * d.n - 1));
+}
+
+// First column of the circulant extension of the Gramian G (n x n), eq. (gramblk):
+// c_G[N - n + s] = g_s for |s| < n, so that rows N-n.. N-1 and columns 0..n-1 of the
+// circulant hold G; the N - 2n + 1 entries r <= N - 2n are arbitrary.
+__global__ void k_build_cg(const SolveDesc* __restrict__ sd, int nr, const double* __restrict__ rms,
+                           double2* __restrict__ out, int64_t N, int64_t stride) {
+    const int64_t g = blockIdx.y;
+    const SolveDesc d = sd[g * nr];
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < N; r += (int64_t)gridDim.x * blockDim.x) {
+        double2 v;
+        if (r > N - 2 * d.n) {
+            v = gram_coef(d, r - (N - d.n));
+        } else {
+            double sc = rms[g] * 1.7320508075688772;
+            uint64_t key = ((uint64_t)d.n << 21) ^ ((uint64_t)r << 43) ^ 0x2545F4914F6CDD1Dull;
+            v = c2(sc * hash_unit(key), d.cplx ? sc * hash_unit(key ^ 0x5851F42D4C957F2Dull) : 0.0);
+        }
+        out[g * stride + r] = v;
+    }
+}
+
 // dst[i] = scale * src[off + i] for i < len, 0 for len <= i < N, per solve.
 // src is either a user array (per-solve pointer in SolveDesc: which = 0 rhs,
 // 1 x, 2 the forward solution xin of an adjoint solve; padding solves read 0)
@@ -734,16 +777,18 @@ __global__ void k_take_tail(const SolveDesc* __restrict__ sd, const double2* __r
         dst[s * dst_stride + i] = cscale(buf[s * stride + N - len + i], scale);
 }
 
-// Residual of the normal equations: r = y - (T^H T x) - lam^2 x  (all length n).
+// Residual of the normal equations: r = y - (T^H T x) - lam^2 x  (all length n);
+// for the Toeplitz-Gramian problem (gx != nullptr, T = L): r = y - L^H L x - G x.
 __global__ void k_normal_residual(const SolveDesc* __restrict__ sd, const double2* __restrict__ y,
                                   const double2* __restrict__ thtx, const double2* __restrict__ x,
-                                  double2* __restrict__ r, int64_t stride) {
+                                  double2* __restrict__ r, int64_t stride, const double2* __restrict__ gx,
+                                  int64_t gx_stride) {
     const int64_t s = blockIdx.y;
     const SolveDesc d = sd[s];
     const double l2 = d.lam * d.lam;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < d.n; i += (int64_t)gridDim.x * blockDim.x) {
-        double2 xv = x[s * stride + i];
-        r[s * stride + i] = csub(csub(y[s * stride + i], thtx[s * stride + i]), cscale(xv, l2));
+        const double2 reg = gx ? gx[s * gx_stride + i] : cscale(x[s * stride + i], l2);
+        r[s * stride + i] = csub(csub(y[s * stride + i], thtx[s * stride + i]), reg);
     }
 }
 
@@ -755,10 +800,12 @@ __global__ void k_normal_residual(const SolveDesc* __restrict__ sd, const double
 // The nr right-hand sides of a group give columns 4 .. 3+nr (one y^ each).
 // Tree order: leaf t (in-order) holds nodes nu = o_t + c + j*2^{p+1}, o_t = 2*bitrev_p(t),
 // c in {0,1}, j < M/2 (paired interleaving, Sec. 6.1); slot h = c*M + 2j + type.
+// Toeplitz-Gramian problem (eq. (ex7), sizes n, p, N-n, N-p, 1; T = L): the first
+// entry of F_nu is the symbol of the extended Gramian, cg(nu), in place of lam^2 w^{(N-n) nu}.
 __global__ void k_assemble(const SolveDesc* __restrict__ sd, int nr, const double2* __restrict__ chat,
                            const double2* __restrict__ yhat, int64_t vstride, double2* __restrict__ phi,
                            int64_t phi_stride, int64_t N, int64_t M, int p, int K,
-                           const double2* __restrict__ tw, int64_t Q) {
+                           const double2* __restrict__ tw, int64_t Q, const double2* __restrict__ cg) {
     const int64_t g = blockIdx.y;
     const SolveDesc d = sd[g * nr];
     const int64_t twN = Q / N;
@@ -775,7 +822,7 @@ __global__ void k_assemble(const SolveDesc* __restrict__ sd, int nr, const doubl
         if (type == 0) {
             double2 wmk = twq(tw, Q, ((N - d.n) * nu % N) * twN, +1);        // w^{(m+k-1) nu}
             double2 wk1 = twq(tw, Q, ((((d.k - 1) % N + N) % N) * nu % N) * twN, +1);
-            ph[0 * nq + q] = cscale(wmk, l2);
+            ph[0 * nq + q] = d.gramian ? cg[g * vstride + nu] : cscale(wmk, l2);
             ph[1 * nq + q] = cmul(wk1, cconj(ch));
             ph[2 * nq + q] = c2(1.0, 0.0);
             ph[3 * nq + q] = c2(0.0, 0.0);
@@ -2241,15 +2288,17 @@ __global__ void k_zero_d(double* __restrict__ p, int64_t n) {
 // descriptors, state, symbol, right-hand side and current solution.
 __global__ void k_swap_groups(SolveDesc* __restrict__ sd, SolveState* __restrict__ st, double2* __restrict__ chat,
                               int64_t sN, double2* __restrict__ yv, double2* __restrict__ xacc, int64_t sn, int nr,
-                              const int2* __restrict__ pairs) {
+                              const int2* __restrict__ pairs, double2* __restrict__ cg) {
     const int2 pr = pairs[blockIdx.y];
     const int64_t a = pr.x, b = pr.y;
-    const int64_t tot = sN + 2 * nr * sn;
+    const int64_t nsym = cg ? 2 * sN : sN;         // the Gramian's symbol too, when there is one
+    const int64_t tot = nsym + 2 * nr * sn;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
         double2 *pa, *pb;
         if (i < sN) { pa = chat + a * sN + i; pb = chat + b * sN + i; }
+        else if (i < nsym) { pa = cg + a * sN + (i - sN); pb = cg + b * sN + (i - sN); }
         else {
-            const int64_t j = i - sN, which = j / (nr * sn), rem = j - which * nr * sn;
+            const int64_t j = i - nsym, which = j / (nr * sn), rem = j - which * nr * sn;
             double2* base = which == 0 ? yv : xacc;
             pa = base + a * nr * sn + rem;
             pb = base + b * nr * sn + rem;
