@@ -61,7 +61,8 @@ enum {
     TIKH_EINVAL = -1,     /* invalid argument (sizes, non-positive or non-finite lambda, null pointer) */
     TIKH_ENOMEM = -2,     /* device allocation failed */
     TIKH_EHIP = -3,       /* a HIP runtime call failed */
-    TIKH_ENUMERIC = -4    /* a solve reported info != 0 (see above) */
+    TIKH_ENUMERIC = -4,   /* a solve reported info != 0 (see above) */
+    TIKH_ETOOBIG = -5     /* the allocation-free entry point's scratch buffer cannot hold the call */
 };
 
 /*
@@ -219,6 +220,28 @@ int tikh_toeplitz_solve_batched(int64_t nprob, const int64_t* m, const int64_t* 
                                 int64_t nlam, const double* lambdas,
                                 int64_t nrhs, const void* b, void* x,
                                 int32_t* info, int complex_data);
+
+/*
+ * Allocation-free variant of tikh_toeplitz_solve_batched, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments, packing, results
+ * (to rounding) and asynchrony, except that the call allocates nothing: the
+ * library's workspace, twiddle tables and readback word come from a static
+ * device buffer of 64 MiB per GPU (held until the process ends), and no
+ * timing events are created.  The batch is split into chunks that fit it;
+ * a call whose single group (or whose twiddle tables, given 640 N bytes + 1 MiB
+ * for N extended nodes) does not fit returns TIKH_ETOOBIG without touching the
+ * outputs (roughly: one right-hand side per group up to m + n ~ 2^14).  Every
+ * call on a GPU shares that GPU's buffer and overwrites what the previous call
+ * left there; calls that overlap on one GPU (several host threads, or several
+ * streams without ordering between the calls) race and must not be made.
+ * The per-merge transform sizing still synchronizes the library stream.
+ */
+int tikh_toeplitz_solve_batched_noalloc(int64_t nprob, const int64_t* m, const int64_t* n,
+                                        const void* col, const void* row,
+                                        int64_t nlam, const double* lambdas,
+                                        int64_t nrhs, const void* b, void* x,
+                                        int32_t* info, int complex_data);
 
 /*
  * Toeplitz-Gramian problem (Sec. 2, third case; Sec. 3.4, eq. (gramblk) and

@@ -13,6 +13,7 @@ from ._lib import (TikhError, lib, library_path, set_options, get_options, get_s
                    profile_kernel, profile_read,
                    tikh_toeplitz_solve, tikh_toeplitz_solve_z, tikh_toeplitz_solve_normal,
                    tikh_toeplitz_solve_normal_z, tikh_toeplitz_solve_batched,
+                   tikh_toeplitz_solve_batched_noalloc, solve_batched_noalloc,
                    tikh_gramian_solve, tikh_gramian_solve_z, tikh_gramian_solve_batched, gramian_solve,
                    gramian_solve_batched,
                    tikh_toeplitz_solve_backward, tikh_toeplitz_solve_backward_z,
@@ -23,6 +24,7 @@ from .autograd import ToeplitzTikhonov, tikhonov_solve
 __all__ = ["workspace_bytes", "set_workspace", "TikhError", "lib", "library_path", "set_options", "get_options", "get_stats", "plan_info", "fft_batched", "autotune_nlim", "profile_kernel", "profile_read",
            "tikh_toeplitz_solve", "tikh_toeplitz_solve_z", "tikh_toeplitz_solve_normal",
            "tikh_toeplitz_solve_normal_z", "tikh_toeplitz_solve_batched",
+           "tikh_toeplitz_solve_batched_noalloc", "solve_batched_noalloc",
            "tikh_gramian_solve", "tikh_gramian_solve_z", "tikh_gramian_solve_batched", "gramian_solve",
            "gramian_solve_batched",
            "tikh_toeplitz_solve_backward", "tikh_toeplitz_solve_backward_z",

@@ -61,6 +61,8 @@ tikh_toeplitz_solve_normal = _sig("tikh_toeplitz_solve_normal", [_P, _P, _I64, _
 tikh_toeplitz_solve_normal_z = _sig("tikh_toeplitz_solve_normal_z", [_P, _P, _I64, _I64, _P, _D, _P])
 tikh_toeplitz_solve_batched = _sig("tikh_toeplitz_solve_batched",
                                    [_I64, _P, _P, _P, _P, _I64, _P, _I64, _P, _P, _P, ctypes.c_int])
+tikh_toeplitz_solve_batched_noalloc = _sig("tikh_toeplitz_solve_batched_noalloc",
+                                           [_I64, _P, _P, _P, _P, _I64, _P, _I64, _P, _P, _P, ctypes.c_int])
 tikh_gramian_solve = _sig("tikh_gramian_solve", [_P, _P, _P, _I64, _I64, _P, _P])
 tikh_gramian_solve_z = _sig("tikh_gramian_solve_z", [_P, _P, _P, _I64, _I64, _P, _P])
 tikh_gramian_solve_batched = _sig("tikh_gramian_solve_batched",
@@ -259,6 +261,24 @@ def solve_batched(ms, ns, col, row, lambdas, nrhs, b, complex_data=False, info=N
     _check(tikh_toeplitz_solve_batched(nprob, _i64(ms), _i64(ns), _ptr(col), _ptr(row), nlam, lam_arr, int(nrhs),
                                        _ptr(b), _ptr(x), _ptr(info), 1 if complex_data else 0),
            "tikh_toeplitz_solve_batched")
+    return x, info
+
+
+def solve_batched_noalloc(ms, ns, col, row, lambdas, nrhs, b, x, info, complex_data=False):
+    """Allocation-free batched solve (tikh_toeplitz_solve_batched_noalloc): like solve_batched,
+    with the outputs x and info supplied by the caller; the library allocates nothing."""
+    dt = torch.complex128 if complex_data else torch.float64
+    nprob = len(ms)
+    nlam = len(lambdas) // max(nprob, 1)
+    assert nlam * nprob == len(lambdas)
+    col, row, b = _dev(col, dt), _dev(row, dt), _dev(b, dt)
+    assert x.dtype == dt and x.is_contiguous() and x.numel() == sum(nlam * nrhs * int(n) for n in ns)
+    assert info.dtype == torch.int32 and info.is_contiguous() and info.numel() == nprob * nlam * nrhs
+    lam_arr = (ctypes.c_double * len(lambdas))(*[float(v) for v in lambdas])
+    _stream()
+    _check(tikh_toeplitz_solve_batched_noalloc(nprob, _i64(ms), _i64(ns), _ptr(col), _ptr(row), nlam, lam_arr,
+                                               int(nrhs), _ptr(b), _ptr(x), _ptr(info), 1 if complex_data else 0),
+           "tikh_toeplitz_solve_batched_noalloc")
     return x, info
 
 

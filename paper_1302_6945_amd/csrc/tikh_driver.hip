@@ -43,6 +43,13 @@ struct Ctx {
     int64_t launches = 0;
     int* dneed = nullptr;                // device / pinned host word for degree readback
     int* hneed = nullptr;
+    // allocation-free calls: twiddle tables and the readback word live in an arena at
+    // the front of the device's static scratch buffer (re-filled by every such call)
+    bool noalloc = false;
+    char* arena = nullptr;
+    size_t arena_size = 0, arena_used = 0;
+    std::map<int64_t, double2*> ntw, ntw2;
+    int* ndneed = nullptr;
     std::map<int64_t, std::vector<double2>> htw, htw2;   // host copies of the tables, by size
 };
 static Ctx g;
@@ -66,14 +73,14 @@ static KProf kprof;
 
 static bool prof_on(const char* name) { return !kprof.name.empty() && kprof.name == name; }
 static void prof_begin(const char* name) {
-    if (!prof_on(name)) return;
+    if (!prof_on(name) || g.noalloc) return;     // allocation-free calls create no events
     if (kprof.used + 2 > kprof.pool.size()) {
         for (int i = 0; i < 256; ++i) { hipEvent_t e; if (hipEventCreate(&e) == hipSuccess) kprof.pool.push_back(e); }
     }
     if (kprof.used + 2 <= kprof.pool.size()) (void)hipEventRecord(kprof.pool[kprof.used], g.stream);
 }
 static void prof_end(const char* name) {
-    if (!prof_on(name)) return;
+    if (!prof_on(name) || g.noalloc) return;
     if (kprof.used + 2 <= kprof.pool.size()) {
         (void)hipEventRecord(kprof.pool[kprof.used + 1], g.stream);
         kprof.used += 2;
@@ -261,9 +268,21 @@ static const std::vector<double2>& host_twiddles(int64_t Q) {
     return g.htw[Q] = std::move(h);
 }
 
-// A device copy of a host table, allocated once and kept.
-static double2* device_table(std::map<int64_t, double2*>& keep, int64_t key, const std::vector<double2>& h) {
+// A device copy of a host table: in an allocation-free call carved from the arena
+// (and copied on the library stream), otherwise allocated once and kept.
+static double2* device_table(std::map<int64_t, double2*>& keep, std::map<int64_t, double2*>& per_call, int64_t key,
+                             const std::vector<double2>& h) {
     const size_t bytes = sizeof(double2) * h.size();
+    if (g.noalloc) {
+        auto it = per_call.find(key);
+        if (it != per_call.end()) return it->second;
+        const size_t off = (g.arena_used + 255) & ~(size_t)255;
+        if (off + bytes > g.arena_size) return nullptr;
+        double2* d = (double2*)(g.arena + off);
+        if (hipMemcpyAsync(d, h.data(), bytes, hipMemcpyHostToDevice, g.stream) != hipSuccess) return nullptr;
+        g.arena_used = off + bytes;
+        return per_call[key] = d;
+    }
     auto it = keep.find(key);
     if (it != keep.end()) return it->second;
     double2* d = nullptr;
@@ -273,9 +292,9 @@ static double2* device_table(std::map<int64_t, double2*>& keep, int64_t key, con
 }
 static double2* twiddles2(int64_t M, int* bits) {
     *bits = tw2_bits(M);
-    return device_table(g.tw2, M, host_twiddles2(M));
+    return device_table(g.tw2, g.ntw2, M, host_twiddles2(M));
 }
-static double2* twiddles(int64_t Q) { return device_table(g.tw, Q, host_twiddles(Q)); }
+static double2* twiddles(int64_t Q) { return device_table(g.tw, g.ntw, Q, host_twiddles(Q)); }
 
 // Adaptive refinement: the factor of the estimate cfac * e0 * ||dx|| / ||x||
 // of the error left after a step.
@@ -675,8 +694,9 @@ static int run_product_chunk(const Plan& pl, const Layout& L, const Bufs& b, int
     int64_t P = pl.P[dp];
     {
         // size the transforms by the actual degrees of this chunk (host readback)
-        int* dneed = g.dneed;
-        int* hneed = g.hneed;
+        int hword = 0;
+        int* dneed = g.noalloc ? g.ndneed : g.dneed;
+        int* hneed = g.noalloc ? &hword : g.hneed;
         if (!dneed || !hneed) return TIKH_ENOMEM;
         hipLaunchKernelGGL(k_deg_need, dim3(1), dim3(256), 0, g.stream, b.metaS[dc], b.metaT[dc], (int)G, C, dneed);
         HIPCHK(hipMemcpyAsync(hneed, dneed, sizeof(int), hipMemcpyDeviceToHost, g.stream));
@@ -1375,6 +1395,7 @@ const char* tikh_strerror(int code) {
         case TIKH_ENOMEM: return "device allocation failed";
         case TIKH_EHIP: return hipGetErrorString(last_hip_error);
         case TIKH_ENUMERIC: return "numerical breakdown reported by a solve (info != 0)";
+        case TIKH_ETOOBIG: return "the batch does not fit the allocation-free scratch buffer (64 MiB per device)";
         default: return "unknown error";
     }
 }
@@ -1445,6 +1466,82 @@ int tikh_toeplitz_solve_batched(int64_t nprob, const int64_t* m, const int64_t* 
     int rc = batched_sds(nprob, m, n, col, row, nlam, lambdas, nrhs, b, x, complex_data, sds);
     if (rc) return rc;
     return run_solves(sds, group_size(nrhs), info);
+}
+
+}  // extern "C"
+
+namespace tikh {
+
+// Allocation-free batched solves: every device buffer the library needs beyond
+// the caller's inputs and outputs comes from this file-scope array.  Each GPU
+// holds its own copy; its address on a device is looked up once with
+// hipGetSymbolAddress (the array's name is not a device address in host code).
+static const size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+static const int NOALLOC_MAX_DEVICES = 64;
+static void* scratch_ptr[NOALLOC_MAX_DEVICES];
+
+}  // namespace tikh
+
+extern "C" {
+
+int tikh_toeplitz_solve_batched_noalloc(int64_t nprob, const int64_t* m, const int64_t* n, const void* col,
+                                        const void* row, int64_t nlam, const double* lambdas, int64_t nrhs,
+                                        const void* b, void* x, int32_t* info, int complex_data) {
+    init_opts();
+    if (nprob < 0 || nlam < 1 || nrhs < 1 || !m || !n || !lambdas) return TIKH_EINVAL;
+    if (nprob == 0) return TIKH_OK;
+    std::vector<SolveDesc> sds;
+    int rc = batched_sds(nprob, m, n, col, row, nlam, lambdas, nrhs, b, x, complex_data, sds);
+    if (rc) return rc;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return TIKH_EINVAL;
+    if (!scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            last_hip_error = e != hipSuccess ? e : hipErrorInvalidSymbol;
+            return TIKH_EHIP;
+        }
+        scratch_ptr[dev] = ptr;
+    }
+    // arena for the twiddle tables: the Q = 8N table, the per-length tables of the transforms
+    // (lengths dividing 8N that the chunks' degrees select; 32N entries leave room for several
+    // product lengths per level) and the two-level tables, plus the readback word
+    int64_t Nmax = 1;
+    for (int64_t p = 0; p < nprob; ++p) {
+        int64_t N, M;
+        int pp;
+        if (!opt_extend(m[p] + n[p] - 1, g.opts.n_lim, &N, &M, &pp)) return TIKH_EINVAL;
+        Nmax = std::max(Nmax, N);
+    }
+    const size_t arena = ((sizeof(double2) * (size_t)(40 * Nmax + 65536) + 4096) + 255) & ~(size_t)255;
+    if (arena + WS_FIXED >= NOALLOC_SCRATCH_BYTES) return TIKH_ETOOBIG;
+    char* base = (char*)scratch_ptr[dev];
+    char* save_ws = g.ws;
+    const size_t save_size = g.ws_size;
+    const bool save_ext = g.ws_ext;
+    g.noalloc = true;
+    g.arena = base;
+    g.arena_size = arena;
+    g.arena_used = 256;
+    g.ndneed = (int*)base;
+    g.ntw.clear();
+    g.ntw2.clear();
+    g.ws = base + arena;
+    g.ws_size = NOALLOC_SCRATCH_BYTES - arena;
+    g.ws_ext = true;
+    rc = run_solves(sds, group_size(nrhs), info);
+    g.ws = save_ws;
+    g.ws_size = save_size;
+    g.ws_ext = save_ext;
+    g.noalloc = false;
+    g.arena = nullptr;
+    g.ndneed = nullptr;
+    g.ntw.clear();
+    g.ntw2.clear();
+    return rc == TIKH_ENOMEM ? TIKH_ETOOBIG : rc;
 }
 
 // Toeplitz-Gramian problem (Sec. 2 third case, Sec. 3.4): solve descriptors with the
