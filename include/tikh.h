@@ -67,7 +67,12 @@ enum {
 
 /*
  * Tunable options (Sec. 6.2: leaf cutoff N_lim; Sec. 7.2: iterative
- * refinement).  Every solve takes `refine` refinement steps; a solve whose
+ * refinement).  Product transform lengths (Alg. 1 step 4) follow the degrees
+ * of the bases being multiplied: the first recursion of a batch composition
+ * reads them back once per merge; later recursions and later calls with the
+ * same composition (sizes, extension, lambda, element type) reuse the recorded
+ * lengths without host synchronization, checked on the device, and a batch
+ * whose degrees outgrow a recorded length is run again with read-back sizing.  Every solve takes `refine` refinement steps; a solve whose
  * estimated relative error is still above `refine_tol` takes further steps,
  * up to `refine_max` in all (the estimate: e0 = ||dx_1|| / ||x|| of the
  * first step approximates the first solve's error and the factor by which
@@ -86,7 +91,10 @@ typedef struct {
                              defer_tol times its largest entry among columns 1..4 is set aside and
                              processed after the root, against the final basis (0 <= defer_tol < 1;
                              0 = off, the default; at most 64 per solve, else info bit 4) */
-    int32_t reserved[2];
+    int32_t record_short;  /* testing only (default 0): record product transform lengths half as long as
+                             the degrees need, so that the device check of recorded lengths fires and the
+                             chunk runs again with read-back sizing (results are unaffected) */
+    int32_t reserved;
 } tikh_opts;
 
 /* Per-solve statistics of the last call (host memory, filled by tikh_get_stats). */
@@ -99,6 +107,8 @@ typedef struct {
     int64_t launches;     /* kernel launches enqueued by the last call */
     int64_t refine_extra; /* refinement steps beyond `refine` taken by the last call, summed over solves */
     int64_t deferred;     /* difficult conditions deferred by the last call, summed over groups and steps */
+    int64_t host_syncs;   /* host synchronizations inside the last call (transform sizing read back per
+                             merge, refinement decisions, the check of recorded transform lengths) */
 } tikh_stats;
 
 /*

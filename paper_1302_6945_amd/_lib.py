@@ -21,13 +21,13 @@ _D = ctypes.c_double
 class _Opts(ctypes.Structure):
     _fields_ = [("n_lim", ctypes.c_int32), ("refine", ctypes.c_int32), ("refine_max", ctypes.c_int32),
                 ("leaf_wave_groups", ctypes.c_int32), ("refine_tol", ctypes.c_double), ("defer_tol", ctypes.c_double),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("record_short", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int64), ("k", ctypes.c_int64), ("depth", ctypes.c_int32),
                 ("leaf_nodes", ctypes.c_int32), ("solves", ctypes.c_int64), ("launches", ctypes.c_int64),
-                ("refine_extra", ctypes.c_int64), ("deferred", ctypes.c_int64)]
+                ("refine_extra", ctypes.c_int64), ("deferred", ctypes.c_int64), ("host_syncs", ctypes.c_int64)]
 
 
 def _sig(name, args, res=ctypes.c_int):
@@ -93,7 +93,7 @@ def _stream():
 
 
 def set_options(n_lim=None, refine=None, refine_max=None, refine_tol=None, defer_tol=None,
-                leaf_wave_groups=None):
+                leaf_wave_groups=None, record_short=None):
     """Leaf cutoff, refinement steps for every solve, most refinement steps for a solve whose
     estimated error is above the target (see tikh_opts in include/tikh.h)."""
     o = _Opts()
@@ -110,6 +110,8 @@ def set_options(n_lim=None, refine=None, refine_max=None, refine_tol=None, defer
         o.defer_tol = float(defer_tol)
     if leaf_wave_groups is not None:
         o.leaf_wave_groups = int(leaf_wave_groups)
+    if record_short is not None:
+        o.record_short = int(record_short)
     _check(lib.tikh_set_options(ctypes.byref(o)), "tikh_set_options")
 
 
@@ -145,7 +147,7 @@ def get_stats():
     s = _Stats()
     _check(lib.tikh_get_stats(ctypes.byref(s)), "tikh_get_stats")
     return dict(N=s.N, k=s.k, depth=s.depth, leaf_nodes=s.leaf_nodes, solves=s.solves, launches=s.launches,
-                refine_extra=s.refine_extra, deferred=s.deferred)
+                refine_extra=s.refine_extra, deferred=s.deferred, host_syncs=s.host_syncs)
 
 
 def _dev(t, dtype):

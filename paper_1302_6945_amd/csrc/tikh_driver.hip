@@ -51,6 +51,20 @@ struct Ctx {
     std::map<int64_t, double2*> ntw, ntw2;
     int* ndneed = nullptr;
     std::map<int64_t, std::vector<double2>> htw, htw2;   // host copies of the tables, by size
+    // Product transform lengths by merge (depth, index) for a batch composition: recorded
+    // from the degrees read back while a chunk's first recursion runs, then reused without
+    // host synchronization by its later recursions and by later calls with the same
+    // composition, and checked on the device (a product that would need a longer transform
+    // raises the chunk's overflow flag, and the chunk is run again with read-back sizing).
+    struct Sizes {
+        std::map<int64_t, int64_t> P;
+        bool complete = false;
+    };
+    std::map<uint64_t, Sizes> sizes;
+    Sizes* cur_sizes = nullptr;          // entry of the running chunk (nullptr: read back every merge)
+    bool replay = false;                 // the running recursion takes its lengths from cur_sizes
+    int* overflow = nullptr;             // device flag of the running chunk
+    int64_t syncs = 0;                   // host synchronizations of the last call
 };
 static Ctx g;
 
@@ -392,6 +406,7 @@ struct Bufs {
     double2* pool;                   // V, FL, FR and scr as one region (re-split per level)
     int64_t pool_elems;
     int* elist;                      // device entry lists
+    int* ovf;                        // product-length overflow flag of the chunk
 };
 
 // Group pointers advanced by c0 groups, solve pointers by c0*nr solves
@@ -476,6 +491,7 @@ static int carve_bufs(const Plan& pl, const Layout& L, int64_t G, int64_t CH, Bu
     b->rms = (double*)carve(p, sizeof(double) * G);
     b->rmsg = (double*)carve(p, sizeof(double) * G);
     b->elist = (int*)carve(p, sizeof(EList));
+    b->ovf = (int*)carve(p, sizeof(int));
     b->dl.cap = DEFER_CAP;
     b->dl.C = L.C;
     b->dl.q = (int32_t*)carve(p, sizeof(int32_t) * G * DEFER_CAP);
@@ -687,12 +703,20 @@ static int run_eval_chunk(const Plan& pl, const Layout& L, const Bufs& b, int64_
 }
 
 // B_parent = B_L B_R for the parent at depth dp (children at depth dp+1), one merge chunk.
-static int run_product_chunk(const Plan& pl, const Layout& L, const Bufs& b, int64_t G, int dp, double2* dst,
-                             int64_t dstride, SlotMeta* dmeta, int64_t dcap, const double2* tw) {
+static int run_product_chunk(const Plan& pl, const Layout& L, const Bufs& b, int64_t G, int dp, int64_t pidx,
+                             double2* dst, int64_t dstride, SlotMeta* dmeta, int64_t dcap, const double2* tw) {
     const int dc = dp + 1;
     const int C = L.C, nr = L.nr;
     int64_t P = pl.P[dp];
-    {
+    const int64_t site = ((int64_t)dp << 40) | pidx;
+    auto known = g.cur_sizes ? g.cur_sizes->P.find(site) : std::map<int64_t, int64_t>::iterator();
+    if (g.replay && g.cur_sizes && known != g.cur_sizes->P.end()) {
+        // recorded length: checked on the device against this chunk's degrees
+        P = known->second;
+        hipLaunchKernelGGL(k_deg_check, dim3(1), dim3(256), 0, g.stream, b.metaS[dc], b.metaT[dc], (int)G, C, (int)P,
+                           g.overflow);
+        g.launches += 1;
+    } else {
         // size the transforms by the actual degrees of this chunk (host readback)
         int hword = 0;
         int* dneed = g.noalloc ? g.ndneed : g.dneed;
@@ -702,9 +726,15 @@ static int run_product_chunk(const Plan& pl, const Layout& L, const Bufs& b, int
         HIPCHK(hipMemcpyAsync(hneed, dneed, sizeof(int), hipMemcpyDeviceToHost, g.stream));
         HIPCHK(hipStreamSynchronize(g.stream));
         g.launches += 1;
+        g.syncs += 1;
         const int64_t need = std::max<int64_t>(1, (int64_t)*hneed);
         if (need <= P) P = smallest_divisor_geq(pl.Q, need);
         if (P > pl.P[dp]) P = pl.P[dp];
+        if (g.cur_sizes) {
+            int64_t& rec = g.cur_sizes->P[site];
+            const int64_t keep = g.opts.record_short ? smallest_divisor_geq(pl.Q, std::max<int64_t>(1, need / 2)) : P;
+            rec = std::max(rec, std::min(keep, P));
+        }
     }
     const int64_t cp1 = pl.cap[dc] + 1;
     const bool root = (dp == 0);
@@ -817,8 +847,8 @@ static int run_product(const Plan& pl, const Layout& L, const Bufs& b, int64_t G
         Bufs bc = shift_bufs(b, L, pl, c0);
         bc.FL = b.pool;
         bc.FR = b.pool + ch * Ld.sF;
-        int rc = run_product_chunk(pl, Ld, bc, std::min(ch, G - c0), dp, dst + c0 * dstride, dstride, dmeta + c0,
-                                   dcap, tw);
+        int rc = run_product_chunk(pl, Ld, bc, std::min(ch, G - c0), dp, pidx, dst + c0 * dstride, dstride,
+                                   dmeta + c0, dcap, tw);
         if (rc) return rc;
     }
     return TIKH_OK;
@@ -870,8 +900,33 @@ static void circ_apply(const Plan& pl, const Layout& L, const Bufs& b, int64_t S
     g.launches++;
 }
 
+// Key of a chunk's composition for the recorded product lengths: the plan, the
+// right-hand sides per group, the deferral threshold and every group's operator
+// (sizes, extension, element type, entry, variant, lambda).
+static uint64_t sizes_key(const Plan& pl, int nr, const std::vector<SolveDesc>& sds) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&h](uint64_t v) {
+        for (int i = 0; i < 8; ++i) { h ^= (v >> (8 * i)) & 0xffu; h *= 1099511628211ull; }
+    };
+    auto bits = [](double v) { uint64_t u; memcpy(&u, &v, 8); return u; };
+    mix((uint64_t)pl.N); mix((uint64_t)pl.M); mix((uint64_t)pl.p); mix((uint64_t)nr); mix(sds.size());
+    mix(bits(g.opts.defer_tol));
+    for (size_t i = 0; i < sds.size(); i += (size_t)nr) {
+        const SolveDesc& d = sds[i];
+        mix((uint64_t)d.m); mix((uint64_t)d.n); mix((uint64_t)d.k); mix(bits(d.lam));
+        mix((uint64_t)(d.cplx | (d.mode << 1) | (d.gramian << 2) | (d.backward << 3)));
+    }
+    return h;
+}
+
+static const int TIKH_RESIZE = 100;   // internal: a recorded product length was too short
+
 // One chunk of groups sharing the plan (sds holds G*nr solves, group-major).
-static int run_chunk(const Plan& pl, int nr, const std::vector<SolveDesc>& sds, int32_t* info, int64_t merge_chunk) {
+// With use_sizes, product lengths recorded for this composition are reused (and the
+// first recursion records them if there are none yet); returns TIKH_RESIZE if the
+// device found a recorded length too short, after which the chunk must run again.
+static int run_chunk_once(const Plan& pl, int nr, const std::vector<SolveDesc>& sds, int32_t* info,
+                          int64_t merge_chunk, bool use_sizes) {
     const int64_t S = (int64_t)sds.size();
     const int64_t G = S / nr;
     int64_t mmax = 1, nmax = 1;
@@ -886,6 +941,12 @@ static int run_chunk(const Plan& pl, int nr, const std::vector<SolveDesc>& sds, 
     const EList el = make_elist(nr);
     HIPCHK(hipMemcpyAsync(b.sd, sds.data(), sizeof(SolveDesc) * S, hipMemcpyHostToDevice, g.stream));
     HIPCHK(hipMemcpyAsync(b.elist, &el, sizeof(EList), hipMemcpyHostToDevice, g.stream));
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, g.stream, b.ovf, (int64_t)1);
+    g.launches++;
+    if (g.sizes.size() > 4096) g.sizes.clear();   // bound the record over many compositions
+    g.cur_sizes = use_sizes ? &g.sizes[sizes_key(pl, nr, sds)] : nullptr;
+    g.overflow = b.ovf;
+    bool replayed = false;
     const int64_t N = pl.N;
     const double invN = 1.0 / (double)N;
     hipLaunchKernelGGL(k_init_state, dim3((unsigned)((G + 63) / 64)), dim3(64), 0, g.stream, b.sd, nr, b.st, (int)G, 0);
@@ -930,6 +991,7 @@ static int run_chunk(const Plan& pl, int nr, const std::vector<SolveDesc>& sds, 
             hflags.resize((size_t)Ga);
             HIPCHK(hipMemcpyAsync(hflags.data(), b.flags, sizeof(int32_t) * Ga, hipMemcpyDeviceToHost, g.stream));
             HIPCHK(hipStreamSynchronize(g.stream));
+            g.syncs += 1;
             std::vector<int64_t> want, holes;
             int64_t G2 = 0;
             for (int64_t gi = 0; gi < Ga; ++gi) G2 += hflags[gi] ? 1 : 0;
@@ -941,6 +1003,7 @@ static int run_chunk(const Plan& pl, int nr, const std::vector<SolveDesc>& sds, 
                 for (size_t i = 0; i < holes.size(); ++i) hp[i] = make_int2((int)holes[i], (int)want[i]);
                 HIPCHK(hipMemcpyAsync(b.pairs, hp.data(), sizeof(int2) * hp.size(), hipMemcpyHostToDevice, g.stream));
                 HIPCHK(hipStreamSynchronize(g.stream));
+                g.syncs += 1;
                 hipLaunchKernelGGL(k_swap_groups, dim3(64, (unsigned)hp.size()), dim3(256), 0, g.stream, b.sd, b.st,
                                    b.chat, L.sN, b.yv, b.xacc, L.sn, nr, b.pairs, gramian ? b.cg : nullptr);
                 g.launches++;
@@ -987,8 +1050,12 @@ static int run_chunk(const Plan& pl, int nr, const std::vector<SolveDesc>& sds, 
         hipLaunchKernelGGL(k_assemble, grid1(2 * N, Ga), dim3(256), 0, g.stream, b.sd, nr, b.chat, b.bA, L.sN, b.phi,
                            L.sphi, N, pl.M, pl.p, pl.K, tw, pl.Q, (const double2*)b.cg);
         g.launches++;
+        g.replay = g.cur_sizes && g.cur_sizes->complete;
+        replayed |= g.replay;
         rc = run_recursion(pl, L, b, Ga, tw);
+        g.replay = false;
         if (rc) return rc;
+        if (g.cur_sizes) g.cur_sizes->complete = true;   // every merge of the tree has been sized
         const int64_t xcp1 = pl.cap[0] + 1;
         if (defer_on()) {
             // deferred conditions, one step each on the final basis (Sec. 5)
@@ -1068,14 +1135,34 @@ static int run_chunk(const Plan& pl, int nr, const std::vector<SolveDesc>& sds, 
         g.launches += 14;
     }
     HIPCHK(hipGetLastError());
+    if (replayed) {
+        // one synchronization per chunk: were the recorded lengths long enough?
+        int hovf = 0;
+        HIPCHK(hipMemcpyAsync(&hovf, b.ovf, sizeof(int), hipMemcpyDeviceToHost, g.stream));
+        HIPCHK(hipStreamSynchronize(g.stream));
+        g.syncs += 1;
+        if (hovf) return TIKH_RESIZE;
+    }
     return TIKH_OK;
+}
+
+static int run_chunk(const Plan& pl, int nr, const std::vector<SolveDesc>& sds, int32_t* info, int64_t merge_chunk) {
+    int rc = run_chunk_once(pl, nr, sds, info, merge_chunk, true);
+    g.cur_sizes = nullptr;
+    if (rc == TIKH_RESIZE) {
+        g.sizes.erase(sizes_key(pl, nr, sds));
+        rc = run_chunk_once(pl, nr, sds, info, merge_chunk, false);
+        g.cur_sizes = nullptr;
+    }
+    return rc;
 }
 
 // Group solves by plan and run them in chunks that fit the workspace budget.
 // sds is group-major: solves g*nr .. g*nr + nr - 1 share the operator.
 static int run_solves(std::vector<SolveDesc>& sds, int nr, int32_t* info) {
-    ensure_init();
+    init_opts();                 // (allocation-free calls pass through here too)
     g.launches = 0;
+    g.syncs = 0;
     g.stats.refine_extra = 0;
     g.stats.deferred = 0;
     if (sds.empty()) return TIKH_OK;
@@ -1142,6 +1229,7 @@ static int run_solves(std::vector<SolveDesc>& sds, int nr, int32_t* info) {
     }
     g.stats.solves = (int64_t)sds.size();
     g.stats.launches = g.launches;
+    g.stats.host_syncs = g.syncs;
     return TIKH_OK;
 }
 
@@ -1368,6 +1456,7 @@ int tikh_release(void) {
     g.tw.clear();
     for (auto& kv : g.tw2) (void)hipFree(kv.second);
     g.tw2.clear();
+    g.sizes.clear();
     return TIKH_OK;
 }
 

@@ -1949,6 +1949,27 @@ __global__ __launch_bounds__(256) void k_deg_need(const SlotMeta* __restrict__ m
     if (threadIdx.x == 0) *need = red[0];
 }
 
+// Check of a recorded product length P against this chunk's degrees: raises *overflow
+// if a product needs more than P coefficients (the length would wrap it around).
+__global__ __launch_bounds__(256) void k_deg_check(const SlotMeta* __restrict__ mL, const SlotMeta* __restrict__ mR,
+                                                   int ngroup, int C, int P, int* __restrict__ overflow) {
+    bool bad = false;
+    for (int s = threadIdx.x; s < ngroup; s += 256) {
+        SlotMeta a = mL[s], b = mR[s];
+        int dl = -1, dr = -1, dv = -1;
+        for (int l = 0; l < 4; ++l) dl = max(dl, a.deg[l]);
+        for (int j = 0; j < C; ++j) dr = max(dr, b.deg[j]);
+        for (int j = 4; j < C; ++j) dv = max(dv, a.deg[j]);
+        bad |= max(dl + dr, dv) + 1 > P;
+    }
+    if (bad) atomicOr(overflow, 1);
+}
+
+__global__ void k_zero_i32(int* __restrict__ p, int64_t count) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
 // Degrees of the product: column j of B0L B0R has degree <= max_l degL(l) + degR(j);
 // V columns: max(max_l degL(l) + degR(j), degL(j)).  Resets the column maxima.
 __global__ void k_prod_meta(const SlotMeta* __restrict__ mL, const SlotMeta* __restrict__ mR,
