@@ -38,7 +38,10 @@
  * bit 1 = breakdown (no admissible pivot / final tau-degrees not {1,1,1,1,0}),
  * bit 2 = a basis degree exceeded its storage bound, bit 4 = more deferred
  * difficult conditions than a solve can hold, bit 8 = non-finite values in the
- * solution (bits may combine).  Right-hand sides of one (problem, lambda) share
+ * solution, bit 16 = after its last iterative refinement step the solve's
+ * error estimate (see tikh_opts) is still above 1e-4: the refinement diverged or
+ * barely converges, i.e. the recursion lost the solution (see fallback_nlim) or
+ * the regularized system is too ill-conditioned for it (bits may combine).  Right-hand sides of one (problem, lambda) share
  * a pivot sequence, so bits 1, 2 and 4 of a forward solve are those of its
  * (problem, lambda); bit 8 is the solve's own.
  * Single-problem calls synchronize the stream and return TIKH_ENUMERIC when
@@ -94,6 +97,16 @@ typedef struct {
     int32_t record_short;  /* testing only (default 0): record product transform lengths half as long as
                              the degrees need, so that the device check of recorded lengths fires and the
                              chunk runs again with read-back sizing (results are unaffected) */
+    int32_t streams;      /* streams on which chunks of different extended sizes (ragged batches) run side
+                             by side (1..16; default 16; 1 runs them one after another on the library stream) */
+    double merge_tol;     /* ragged batches: problems whose extended sizes N lie within a factor 1 + merge_tol
+                             of each other share the largest one's plan (a larger circulant extension k),
+                             so that they run in the same launches (0..4; default 0.25; 0 = one plan per N) */
+    int32_t fallback_nlim; /* a group whose solve failed (info bits 1, 2, 8 or 16: pivots so small that the
+                             basis lost the solution, Sec. 5's difficult points, or a breakdown) is solved
+                             again with this smaller leaf cutoff, i.e. another tree over the same conditions
+                             (64..256 and below n_lim, or 0 = off; default 64); its outputs and info are
+                             those of the second solve */
     int32_t reserved;
 } tikh_opts;
 
@@ -109,6 +122,7 @@ typedef struct {
     int64_t deferred;     /* difficult conditions deferred by the last call, summed over groups and steps */
     int64_t host_syncs;   /* host synchronizations inside the last call (transform sizing read back per
                              merge, refinement decisions, the check of recorded transform lengths) */
+    int64_t fallback_groups; /* groups of the last call solved again with the fallback leaf cutoff */
 } tikh_stats;
 
 /*

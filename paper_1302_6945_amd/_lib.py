@@ -21,13 +21,15 @@ _D = ctypes.c_double
 class _Opts(ctypes.Structure):
     _fields_ = [("n_lim", ctypes.c_int32), ("refine", ctypes.c_int32), ("refine_max", ctypes.c_int32),
                 ("leaf_wave_groups", ctypes.c_int32), ("refine_tol", ctypes.c_double), ("defer_tol", ctypes.c_double),
-                ("record_short", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("record_short", ctypes.c_int32), ("streams", ctypes.c_int32), ("merge_tol", ctypes.c_double),
+                ("fallback_nlim", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int64), ("k", ctypes.c_int64), ("depth", ctypes.c_int32),
                 ("leaf_nodes", ctypes.c_int32), ("solves", ctypes.c_int64), ("launches", ctypes.c_int64),
-                ("refine_extra", ctypes.c_int64), ("deferred", ctypes.c_int64), ("host_syncs", ctypes.c_int64)]
+                ("refine_extra", ctypes.c_int64), ("deferred", ctypes.c_int64), ("host_syncs", ctypes.c_int64),
+                ("fallback_groups", ctypes.c_int64)]
 
 
 def _sig(name, args, res=ctypes.c_int):
@@ -93,7 +95,7 @@ def _stream():
 
 
 def set_options(n_lim=None, refine=None, refine_max=None, refine_tol=None, defer_tol=None,
-                leaf_wave_groups=None, record_short=None):
+                leaf_wave_groups=None, record_short=None, streams=None, merge_tol=None, fallback_nlim=None):
     """Leaf cutoff, refinement steps for every solve, most refinement steps for a solve whose
     estimated error is above the target (see tikh_opts in include/tikh.h)."""
     o = _Opts()
@@ -112,6 +114,12 @@ def set_options(n_lim=None, refine=None, refine_max=None, refine_tol=None, defer
         o.leaf_wave_groups = int(leaf_wave_groups)
     if record_short is not None:
         o.record_short = int(record_short)
+    if streams is not None:
+        o.streams = int(streams)
+    if merge_tol is not None:
+        o.merge_tol = float(merge_tol)
+    if fallback_nlim is not None:
+        o.fallback_nlim = int(fallback_nlim)
     _check(lib.tikh_set_options(ctypes.byref(o)), "tikh_set_options")
 
 
@@ -119,7 +127,8 @@ def get_options():
     o = _Opts()
     _check(lib.tikh_get_options(ctypes.byref(o)), "tikh_get_options")
     return dict(n_lim=o.n_lim, refine=o.refine, refine_max=o.refine_max, refine_tol=o.refine_tol,
-                defer_tol=o.defer_tol, leaf_wave_groups=o.leaf_wave_groups)
+                defer_tol=o.defer_tol, leaf_wave_groups=o.leaf_wave_groups, record_short=o.record_short,
+                streams=o.streams, merge_tol=o.merge_tol, fallback_nlim=o.fallback_nlim)
 
 
 def plan_info(m, n, n_lim=256):
@@ -147,7 +156,8 @@ def get_stats():
     s = _Stats()
     _check(lib.tikh_get_stats(ctypes.byref(s)), "tikh_get_stats")
     return dict(N=s.N, k=s.k, depth=s.depth, leaf_nodes=s.leaf_nodes, solves=s.solves, launches=s.launches,
-                refine_extra=s.refine_extra, deferred=s.deferred, host_syncs=s.host_syncs)
+                refine_extra=s.refine_extra, deferred=s.deferred, host_syncs=s.host_syncs,
+                fallback_groups=s.fallback_groups)
 
 
 def _dev(t, dtype):

@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -65,6 +66,8 @@ struct Ctx {
     bool replay = false;                 // the running recursion takes its lengths from cur_sizes
     int* overflow = nullptr;             // device flag of the running chunk
     int64_t syncs = 0;                   // host synchronizations of the last call
+    std::vector<hipStream_t> pool;       // streams of chunks run side by side
+    std::vector<hipEvent_t> events;      // their fork and join events
 };
 static Ctx g;
 
@@ -146,6 +149,9 @@ static void init_opts() {
     g.opts.refine = 1;
     g.opts.refine_max = 3;
     g.opts.leaf_wave_groups = 1536;
+    g.opts.streams = 16;
+    g.opts.merge_tol = 0.25;
+    g.opts.fallback_nlim = 64;
     g.opts.refine_tol = 1e-10;
     g.opts.defer_tol = 0.0;
     g.init = true;
@@ -313,6 +319,11 @@ static double2* twiddles(int64_t Q) { return device_table(g.tw, g.ntw, Q, host_t
 // Adaptive refinement: the factor of the estimate cfac * e0 * ||dx|| / ||x||
 // of the error left after a step.
 static const double REFINE_CFAC = 1000.0;
+// Estimate above which a solve's refinement counts as failed after its last step (info bit 16):
+// far above the refinement target, so that slow but converging refinement is not flagged
+// (measured: an adjoint solve whose refinement contracted by 1e-2 per step ended with an
+// estimate of 1e-6 and an error of 1e-9), while a basis that lost the solution is.
+static const double REFINE_FAIL = 1e-4;
 
 // Deferred (difficult) conditions held per group and solve; more set info bit 4.
 static const int DEFER_CAP = 64;
@@ -477,13 +488,11 @@ static size_t chunk_bytes(const Layout& L, int64_t G, int64_t CH) {
     return (size_t)G * L.group_bytes + (size_t)(G * L.nr) * L.solve_bytes + (size_t)CH * L.temp_bytes + WS_FIXED;
 }
 
-static int carve_bufs(const Plan& pl, const Layout& L, int64_t G, int64_t CH, Bufs* b) {
+// Carves a chunk's buffers from the workspace region at base (chunk_bytes(L, G, CH) long).
+static int carve_bufs(const Plan& pl, const Layout& L, int64_t G, int64_t CH, char* base, Bufs* b) {
     const int nr = L.nr;
     const int64_t S = G * nr;
-    size_t need = chunk_bytes(L, G, CH);
-    int rc = ensure_ws(need);
-    if (rc) return rc;
-    char* p = g.ws;
+    char* p = base;
     b->nr = nr;
     b->chunk = CH;
     b->sd = (SolveDesc*)carve(p, sizeof(SolveDesc) * S);
@@ -518,7 +527,7 @@ static int carve_bufs(const Plan& pl, const Layout& L, int64_t G, int64_t CH, Bu
     b->FL = cv(L.sF, CH); b->FR = cv(L.sF, CH); b->scr = cv(L.sscr, CH);
     b->pool = b->V;
     b->pool_elems = (int64_t)((p - (char*)b->V) / sizeof(double2));
-    if ((size_t)(p - g.ws) > g.ws_size) return TIKH_ENOMEM;
+    if ((size_t)(p - base) > chunk_bytes(L, G, CH)) return TIKH_ENOMEM;
     return TIKH_OK;
 }
 
@@ -921,32 +930,159 @@ static uint64_t sizes_key(const Plan& pl, int nr, const std::vector<SolveDesc>& 
 
 static const int TIKH_RESIZE = 100;   // internal: a recorded product length was too short
 
-// One chunk of groups sharing the plan (sds holds G*nr solves, group-major).
-// With use_sizes, product lengths recorded for this composition are reused (and the
-// first recursion records them if there are none yet); returns TIKH_RESIZE if the
+// One chunk of groups sharing the plan (sds holds G*nr solves, group-major), run in
+// phases so that chunks of different plans can proceed side by side on their own
+// streams: chunk_begin, chunk_adapt until done, chunk_finish, chunk_check.  With
+// use_sizes, product lengths recorded for this composition are reused (the first
+// recursion records them if there are none yet); chunk_check returns TIKH_RESIZE if the
 // device found a recorded length too short, after which the chunk must run again.
-static int run_chunk_once(const Plan& pl, int nr, const std::vector<SolveDesc>& sds, int32_t* info,
-                          int64_t merge_chunk, bool use_sizes) {
-    const int64_t S = (int64_t)sds.size();
-    const int64_t G = S / nr;
-    int64_t mmax = 1, nmax = 1;
-    for (auto& d : sds) { mmax = std::max(mmax, d.m); nmax = std::max(nmax, d.n); }
+struct ChunkRun {
+    Plan pl;
+    int nr = 1;
+    std::vector<SolveDesc> sds;
+    int32_t* info = nullptr;
+    int64_t mchunk = 1;
+    bool use_sizes = true;
+    hipStream_t stream = nullptr;
+    char* base = nullptr;                // workspace region (chunk_bytes long)
     Layout L;
-    make_layout(pl, nr, mmax, nmax, &L);
     Bufs b;
-    int rc = carve_bufs(pl, L, G, std::min<int64_t>(G, merge_chunk), &b);
+    const double2* tw = nullptr;
+    int64_t S = 0, G = 0, Ga = 0, Sa = 0, mmax = 1, nmax = 1;
+    bool gramian = false, replayed = false, done = false;
+    int steps_min = 1, steps_max = 1, it = 0;
+    Ctx::Sizes* sizes = nullptr;
+    std::vector<SolveDesc> failed;       // descriptors of the groups whose solve failed
+};
+
+static void chunk_layout(ChunkRun& r) {
+    r.mmax = 1; r.nmax = 1;
+    for (auto& d : r.sds) { r.mmax = std::max(r.mmax, d.m); r.nmax = std::max(r.nmax, d.n); }
+    make_layout(r.pl, r.nr, r.mmax, r.nmax, &r.L);
+}
+static size_t chunk_run_bytes(const ChunkRun& r) {
+    const int64_t G = (int64_t)r.sds.size() / r.nr;
+    return chunk_bytes(r.L, G, std::min<int64_t>(G, r.mchunk));
+}
+// the chunk's stream and recorded lengths become the library's current ones
+static void chunk_enter(ChunkRun& r) {
+    g.stream = r.stream;
+    g.cur_sizes = r.sizes;
+    g.overflow = r.b.ovf;
+}
+
+// One solve of the chunk's current right-hand sides (it = 0: y; it > 0: the
+// refinement residual of the solutions so far) over its first Ga groups.
+static int chunk_step(ChunkRun& r, int it) {
+    const Plan& pl = r.pl;
+    const Layout& L = r.L;
+    const Bufs& b = r.b;
+    const double2* tw = r.tw;
+    const int nr = r.nr;
+    const int64_t Ga = r.Ga, Sa = r.Sa, mmax = r.mmax, nmax = r.nmax, N = pl.N;
+    const double invN = 1.0 / (double)N;
+    const bool gramian = r.gramian;
+    const int steps_max = r.steps_max;
+    int rc = TIKH_OK;
+    const double2* rhs = b.yv;
+    if (it > 0) {
+        // residual of the normal equations, r = y - (T^H T + lam^2) x (Sec. 7.2: iterative refinement);
+        // Toeplitz-Gramian problem: r = y - (L^H L + G) x, with G x (bC) from the Gramian's circulant
+        if (gramian) {
+            hipLaunchKernelGGL(k_load_pad, grid1(N, Sa), dim3(256), 0, g.stream, b.sd, 0, b.xacc, L.sn, 1, 0, 1.0,
+                               b.bB, N, L.sN);
+            circ_apply(pl, L, b, Sa, b.bB, 0, tw, b.cg);
+            hipLaunchKernelGGL(k_take_tail, grid1(nmax, Sa), dim3(256), 0, g.stream, b.sd, b.bB, N, L.sN, 1, invN,
+                               b.bC, L.sN);
+            g.launches += 2;
+        }
+        hipLaunchKernelGGL(k_load_pad, grid1(N, Sa), dim3(256), 0, g.stream, b.sd, 0, b.xacc, L.sn, 1, 0, 1.0,
+                           b.bB, N, L.sN);
+        circ_apply(pl, L, b, Sa, b.bB, 0, tw);
+        hipLaunchKernelGGL(k_take_tail, grid1(mmax, Sa), dim3(256), 0, g.stream, b.sd, b.bB, N, L.sN, 0, invN,
+                           b.t1, L.sn);
+        hipLaunchKernelGGL(k_load_pad, grid1(N, Sa), dim3(256), 0, g.stream, b.sd, 0, b.t1, L.sn, 0, 0, 1.0, b.bB,
+                           N, L.sN);
+        circ_apply(pl, L, b, Sa, b.bB, 1, tw);
+        hipLaunchKernelGGL(k_take_tail, grid1(nmax, Sa), dim3(256), 0, g.stream, b.sd, b.bB, N, L.sN, 1, invN,
+                           b.t2, L.sn);
+        hipLaunchKernelGGL(k_normal_residual, grid1(nmax, Sa), dim3(256), 0, g.stream, b.sd, b.yv, b.t2, b.xacc,
+                           b.t1, L.sn, gramian ? (const double2*)b.bC : (const double2*)nullptr, L.sN);
+        hipLaunchKernelGGL(k_init_state, dim3((unsigned)((Ga + 63) / 64)), dim3(64), 0, g.stream, b.sd, nr, b.st,
+                           (int)Ga, 1);
+        hipLaunchKernelGGL(k_zero_d, grid1(2 * Sa, 1), dim3(256), 0, g.stream, b.nrm, 2 * Sa);
+        g.launches += 7;
+        rhs = b.t1;
+    }
+    hipLaunchKernelGGL(k_load_pad, grid1(N, Sa), dim3(256), 0, g.stream, b.sd, 0, rhs, L.sn, 1, 0, 1.0, b.bA, N,
+                       L.sN);
+    g.launches++;
+    rc = fft_lines(b.bA, Sa, L.sN, 1, N, +1, tw, pl.Q, b.bS, L.sN);
     if (rc) return rc;
-    const double2* tw = twiddles(pl.Q);
-    if (!tw) return TIKH_ENOMEM;
+    hipLaunchKernelGGL(k_assemble, grid1(2 * N, Ga), dim3(256), 0, g.stream, b.sd, nr, b.chat, b.bA, L.sN, b.phi,
+                       L.sphi, N, pl.M, pl.p, pl.K, tw, pl.Q, (const double2*)b.cg);
+    g.launches++;
+    g.replay = g.cur_sizes && g.cur_sizes->complete;
+    r.replayed |= g.replay;
+    rc = run_recursion(pl, L, b, Ga, tw);
+    g.replay = false;
+    if (rc) return rc;
+    if (g.cur_sizes) g.cur_sizes->complete = true;   // every merge of the tree has been sized
+    const int64_t xcp1 = pl.cap[0] + 1;
+    if (defer_on()) {
+        // deferred conditions, one step each on the final basis (Sec. 5)
+        if (nr == 1)
+            LAUNCH("defer_complete", k_defer_complete<1>, dim3((unsigned)Ga), dim3(256), b.dl, b.st, b.slotT[0],
+                   L.sT, xcp1, b.metaT[0]);
+        else if (nr == 2)
+            LAUNCH("defer_complete", k_defer_complete<2>, dim3((unsigned)Ga), dim3(256), b.dl, b.st, b.slotT[0],
+                   L.sT, xcp1, b.metaT[0]);
+        else
+            LAUNCH("defer_complete", k_defer_complete<4>, dim3((unsigned)Ga), dim3(256), b.dl, b.st, b.slotT[0],
+                   L.sT, xcp1, b.metaT[0]);
+        // count them for the statistics
+        std::vector<SolveState> hst((size_t)Ga);
+        HIPCHK(hipMemcpyAsync(hst.data(), b.st, sizeof(SolveState) * Ga, hipMemcpyDeviceToHost, g.stream));
+        HIPCHK(hipStreamSynchronize(g.stream));
+        for (const SolveState& x : hst) g.stats.deferred += x.ndef;
+    }
+    hipLaunchKernelGGL(k_extract, grid1(nmax, Sa), dim3(256), 0, g.stream, b.sd, nr, b.st, b.slotT[0], L.sT,
+                       xcp1, b.metaT[0], b.xacc, L.sn, it > 0 ? 1 : 0, b.nrm);
+    g.launches++;
+    if (it > 0 && it + 1 < steps_max) {
+        hipLaunchKernelGGL(k_refine_decide, dim3((unsigned)((Ga + 63) / 64)), dim3(64), 0, g.stream, b.nrm, nr,
+                           b.st, (int)Ga, it == 1 ? 1 : 0, REFINE_CFAC, g.opts.refine_tol, b.flags);
+        g.launches++;
+    }
+    return TIKH_OK;
+}
+
+// Uploads the chunk, builds its symbols and right-hand sides and runs the steps every
+// group takes (the solve and `refine` refinement steps).  Device work goes to r.stream.
+static int chunk_begin(ChunkRun& r) {
+    const Plan& pl = r.pl;
+    const int nr = r.nr;
+    const std::vector<SolveDesc>& sds = r.sds;
+    r.S = (int64_t)sds.size();
+    r.G = r.S / nr;
+    const int64_t S = r.S, G = r.G;
+    int rc = carve_bufs(pl, r.L, G, std::min<int64_t>(G, r.mchunk), r.base, &r.b);
+    if (rc) return rc;
+    const Layout& L = r.L;
+    Bufs& b = r.b;
+    r.tw = twiddles(pl.Q);
+    if (!r.tw) return TIKH_ENOMEM;
+    const double2* tw = r.tw;
+    const int64_t mmax = r.mmax, nmax = r.nmax;
     const EList el = make_elist(nr);
     HIPCHK(hipMemcpyAsync(b.sd, sds.data(), sizeof(SolveDesc) * S, hipMemcpyHostToDevice, g.stream));
     HIPCHK(hipMemcpyAsync(b.elist, &el, sizeof(EList), hipMemcpyHostToDevice, g.stream));
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, g.stream, b.ovf, (int64_t)1);
     g.launches++;
     if (g.sizes.size() > 4096) g.sizes.clear();   // bound the record over many compositions
-    g.cur_sizes = use_sizes ? &g.sizes[sizes_key(pl, nr, sds)] : nullptr;
+    r.sizes = r.use_sizes ? &g.sizes[sizes_key(pl, nr, sds)] : nullptr;
+    g.cur_sizes = r.sizes;
     g.overflow = b.ovf;
-    bool replayed = false;
     const int64_t N = pl.N;
     const double invN = 1.0 / (double)N;
     hipLaunchKernelGGL(k_init_state, dim3((unsigned)((G + 63) / 64)), dim3(64), 0, g.stream, b.sd, nr, b.st, (int)G, 0);
@@ -978,111 +1114,85 @@ static int run_chunk_once(const Plan& pl, int nr, const std::vector<SolveDesc>& 
                            0, 1.0, b.yv, nmax, L.sn);
     }
     g.launches += 2;
+    r.gramian = gramian;
     // Refinement: `refine` steps for every group, then up to `refine_max` steps in
-    // all for the groups whose estimated error is still above refine_tol; those
-    // groups are first exchanged into a prefix [0, Ga) of the chunk.
-    const int steps_min = 1 + std::max(0, std::min(4, (int)g.opts.refine));
-    const int steps_max = g.opts.refine > 0 ? std::max(steps_min, 1 + std::min(4, (int)g.opts.refine_max)) : steps_min;
-    int64_t Ga = G, Sa = S;
-    std::vector<int32_t> hflags;
-    for (int it = 0; it < steps_max; ++it) {
-        if (it >= steps_min) {
-            // groups still above the tolerance after the last step
-            hflags.resize((size_t)Ga);
-            HIPCHK(hipMemcpyAsync(hflags.data(), b.flags, sizeof(int32_t) * Ga, hipMemcpyDeviceToHost, g.stream));
-            HIPCHK(hipStreamSynchronize(g.stream));
-            g.syncs += 1;
-            std::vector<int64_t> want, holes;
-            int64_t G2 = 0;
-            for (int64_t gi = 0; gi < Ga; ++gi) G2 += hflags[gi] ? 1 : 0;
-            if (G2 == 0) break;
-            for (int64_t gi = 0; gi < G2; ++gi) if (!hflags[gi]) holes.push_back(gi);
-            for (int64_t gi = G2; gi < Ga; ++gi) if (hflags[gi]) want.push_back(gi);
-            if (!holes.empty()) {
-                std::vector<int2> hp(holes.size());
-                for (size_t i = 0; i < holes.size(); ++i) hp[i] = make_int2((int)holes[i], (int)want[i]);
-                HIPCHK(hipMemcpyAsync(b.pairs, hp.data(), sizeof(int2) * hp.size(), hipMemcpyHostToDevice, g.stream));
-                HIPCHK(hipStreamSynchronize(g.stream));
-                g.syncs += 1;
-                hipLaunchKernelGGL(k_swap_groups, dim3(64, (unsigned)hp.size()), dim3(256), 0, g.stream, b.sd, b.st,
-                                   b.chat, L.sN, b.yv, b.xacc, L.sn, nr, b.pairs, gramian ? b.cg : nullptr);
-                g.launches++;
-            }
-            Ga = G2;
-            Sa = G2 * nr;
-            g.stats.refine_extra += Sa;
-        }
-        const double2* rhs = b.yv;
-        if (it > 0) {
-            // residual of the normal equations, r = y - (T^H T + lam^2) x (Sec. 7.2: iterative refinement);
-            // Toeplitz-Gramian problem: r = y - (L^H L + G) x, with G x (bC) from the Gramian's circulant
-            if (gramian) {
-                hipLaunchKernelGGL(k_load_pad, grid1(N, Sa), dim3(256), 0, g.stream, b.sd, 0, b.xacc, L.sn, 1, 0, 1.0,
-                                   b.bB, N, L.sN);
-                circ_apply(pl, L, b, Sa, b.bB, 0, tw, b.cg);
-                hipLaunchKernelGGL(k_take_tail, grid1(nmax, Sa), dim3(256), 0, g.stream, b.sd, b.bB, N, L.sN, 1, invN,
-                                   b.bC, L.sN);
-                g.launches += 2;
-            }
-            hipLaunchKernelGGL(k_load_pad, grid1(N, Sa), dim3(256), 0, g.stream, b.sd, 0, b.xacc, L.sn, 1, 0, 1.0,
-                               b.bB, N, L.sN);
-            circ_apply(pl, L, b, Sa, b.bB, 0, tw);
-            hipLaunchKernelGGL(k_take_tail, grid1(mmax, Sa), dim3(256), 0, g.stream, b.sd, b.bB, N, L.sN, 0, invN,
-                               b.t1, L.sn);
-            hipLaunchKernelGGL(k_load_pad, grid1(N, Sa), dim3(256), 0, g.stream, b.sd, 0, b.t1, L.sn, 0, 0, 1.0, b.bB,
-                               N, L.sN);
-            circ_apply(pl, L, b, Sa, b.bB, 1, tw);
-            hipLaunchKernelGGL(k_take_tail, grid1(nmax, Sa), dim3(256), 0, g.stream, b.sd, b.bB, N, L.sN, 1, invN,
-                               b.t2, L.sn);
-            hipLaunchKernelGGL(k_normal_residual, grid1(nmax, Sa), dim3(256), 0, g.stream, b.sd, b.yv, b.t2, b.xacc,
-                               b.t1, L.sn, gramian ? (const double2*)b.bC : (const double2*)nullptr, L.sN);
-            hipLaunchKernelGGL(k_init_state, dim3((unsigned)((Ga + 63) / 64)), dim3(64), 0, g.stream, b.sd, nr, b.st,
-                               (int)Ga, 1);
-            hipLaunchKernelGGL(k_zero_d, grid1(2 * Sa, 1), dim3(256), 0, g.stream, b.nrm, 2 * Sa);
-            g.launches += 7;
-            rhs = b.t1;
-        }
-        hipLaunchKernelGGL(k_load_pad, grid1(N, Sa), dim3(256), 0, g.stream, b.sd, 0, rhs, L.sn, 1, 0, 1.0, b.bA, N,
-                           L.sN);
-        g.launches++;
-        rc = fft_lines(b.bA, Sa, L.sN, 1, N, +1, tw, pl.Q, b.bS, L.sN);
+    // all for the groups whose estimated error is still above refine_tol (chunk_adapt).
+    r.steps_min = 1 + std::max(0, std::min(4, (int)g.opts.refine));
+    r.steps_max = g.opts.refine > 0 ? std::max(r.steps_min, 1 + std::min(4, (int)g.opts.refine_max)) : r.steps_min;
+    r.Ga = G;
+    r.Sa = S;
+    for (r.it = 0; r.it < r.steps_min; ++r.it) {
+        rc = chunk_step(r, r.it);
         if (rc) return rc;
-        hipLaunchKernelGGL(k_assemble, grid1(2 * N, Ga), dim3(256), 0, g.stream, b.sd, nr, b.chat, b.bA, L.sN, b.phi,
-                           L.sphi, N, pl.M, pl.p, pl.K, tw, pl.Q, (const double2*)b.cg);
-        g.launches++;
-        g.replay = g.cur_sizes && g.cur_sizes->complete;
-        replayed |= g.replay;
-        rc = run_recursion(pl, L, b, Ga, tw);
-        g.replay = false;
-        if (rc) return rc;
-        if (g.cur_sizes) g.cur_sizes->complete = true;   // every merge of the tree has been sized
-        const int64_t xcp1 = pl.cap[0] + 1;
-        if (defer_on()) {
-            // deferred conditions, one step each on the final basis (Sec. 5)
-            if (nr == 1)
-                LAUNCH("defer_complete", k_defer_complete<1>, dim3((unsigned)Ga), dim3(256), b.dl, b.st, b.slotT[0],
-                       L.sT, xcp1, b.metaT[0]);
-            else if (nr == 2)
-                LAUNCH("defer_complete", k_defer_complete<2>, dim3((unsigned)Ga), dim3(256), b.dl, b.st, b.slotT[0],
-                       L.sT, xcp1, b.metaT[0]);
-            else
-                LAUNCH("defer_complete", k_defer_complete<4>, dim3((unsigned)Ga), dim3(256), b.dl, b.st, b.slotT[0],
-                       L.sT, xcp1, b.metaT[0]);
-            // count them for the statistics
-            std::vector<SolveState> hst((size_t)Ga);
-            HIPCHK(hipMemcpyAsync(hst.data(), b.st, sizeof(SolveState) * Ga, hipMemcpyDeviceToHost, g.stream));
-            HIPCHK(hipStreamSynchronize(g.stream));
-            for (const SolveState& x : hst) g.stats.deferred += x.ndef;
-        }
-        hipLaunchKernelGGL(k_extract, grid1(nmax, Sa), dim3(256), 0, g.stream, b.sd, nr, b.st, b.slotT[0], L.sT,
-                           xcp1, b.metaT[0], b.xacc, L.sn, it > 0 ? 1 : 0, b.nrm);
-        g.launches++;
-        if (it > 0 && it + 1 < steps_max) {
-            hipLaunchKernelGGL(k_refine_decide, dim3((unsigned)((Ga + 63) / 64)), dim3(64), 0, g.stream, b.nrm, nr,
-                               b.st, (int)Ga, it == 1 ? 1 : 0, REFINE_CFAC, g.opts.refine_tol, b.flags);
+    }
+    return TIKH_OK;
+}
+
+// One adaptive refinement step: the groups whose estimated error is still above
+// refine_tol are exchanged into a prefix [0, Ga) and take another step (one host
+// synchronization for the decisions).  Sets r.done when no group needs one.
+static int chunk_adapt(ChunkRun& r) {
+    if (r.done) return TIKH_OK;
+    if (r.it >= r.steps_max) {
+        if (r.it > 1) {
+            // the groups that took the last step: did their refinement fail (estimate above 1e-4)?
+            hipLaunchKernelGGL(k_refine_decide, dim3((unsigned)((r.Ga + 63) / 64)), dim3(64), 0, g.stream, r.b.nrm,
+                               r.nr, r.b.st, (int)r.Ga, r.it == 2 ? 1 : 0, REFINE_CFAC, REFINE_FAIL,
+                               (int32_t*)nullptr);
             g.launches++;
         }
+        r.done = true;
+        return TIKH_OK;
     }
+    Bufs& b = r.b;
+    const Layout& L = r.L;
+    const int nr = r.nr;
+    const bool gramian = r.gramian;
+    int64_t& Ga = r.Ga;
+    std::vector<int32_t> hflags;
+    {
+        // groups still above the tolerance after the last step
+        hflags.resize((size_t)Ga);
+        HIPCHK(hipMemcpyAsync(hflags.data(), b.flags, sizeof(int32_t) * Ga, hipMemcpyDeviceToHost, g.stream));
+        HIPCHK(hipStreamSynchronize(g.stream));
+        g.syncs += 1;
+        std::vector<int64_t> want, holes;
+        int64_t G2 = 0;
+        for (int64_t gi = 0; gi < Ga; ++gi) G2 += hflags[gi] ? 1 : 0;
+        if (G2 == 0) { r.done = true; return TIKH_OK; }
+        for (int64_t gi = 0; gi < G2; ++gi) if (!hflags[gi]) holes.push_back(gi);
+        for (int64_t gi = G2; gi < Ga; ++gi) if (hflags[gi]) want.push_back(gi);
+        if (!holes.empty()) {
+            std::vector<int2> hp(holes.size());
+            for (size_t i = 0; i < holes.size(); ++i) hp[i] = make_int2((int)holes[i], (int)want[i]);
+            HIPCHK(hipMemcpyAsync(b.pairs, hp.data(), sizeof(int2) * hp.size(), hipMemcpyHostToDevice, g.stream));
+            HIPCHK(hipStreamSynchronize(g.stream));
+            g.syncs += 1;
+            hipLaunchKernelGGL(k_swap_groups, dim3(64, (unsigned)hp.size()), dim3(256), 0, g.stream, b.sd, b.st,
+                               b.chat, L.sN, b.yv, b.xacc, L.sn, nr, b.pairs, gramian ? b.cg : nullptr);
+            g.launches++;
+        }
+        Ga = G2;
+        r.Sa = G2 * nr;
+        g.stats.refine_extra += r.Sa;
+    }
+    int rc = chunk_step(r, r.it);
+    r.it++;
+    return rc;
+}
+
+// Results: x and info (forward), or the gradients of the adjoint.
+static int chunk_finish(ChunkRun& r) {
+    const Plan& pl = r.pl;
+    const Layout& L = r.L;
+    const Bufs& b = r.b;
+    const double2* tw = r.tw;
+    const int nr = r.nr;
+    const int64_t S = r.S, mmax = r.mmax, nmax = r.nmax, N = pl.N;
+    const double invN = 1.0 / (double)N;
+    const std::vector<SolveDesc>& sds = r.sds;
+    int32_t* info = r.info;
+    int rc = TIKH_OK;
     if (!sds[0].backward) {
         if (info) {
             hipLaunchKernelGGL(k_clear_info, dim3((unsigned)((S + 255) / 256)), dim3(256), 0, g.stream, b.sd, S, info);
@@ -1135,36 +1245,200 @@ static int run_chunk_once(const Plan& pl, int nr, const std::vector<SolveDesc>& 
         g.launches += 14;
     }
     HIPCHK(hipGetLastError());
-    if (replayed) {
-        // one synchronization per chunk: were the recorded lengths long enough?
-        int hovf = 0;
-        HIPCHK(hipMemcpyAsync(&hovf, b.ovf, sizeof(int), hipMemcpyDeviceToHost, g.stream));
-        HIPCHK(hipStreamSynchronize(g.stream));
-        g.syncs += 1;
-        if (hovf) return TIKH_RESIZE;
+    return rc;
+}
+
+// After the chunk's stream has drained: were the recorded lengths long enough?
+static int chunk_check(ChunkRun& r) {
+    if (!r.replayed) return TIKH_OK;
+    int hovf = 0;
+    HIPCHK(hipMemcpyAsync(&hovf, r.b.ovf, sizeof(int), hipMemcpyDeviceToHost, r.stream));
+    HIPCHK(hipStreamSynchronize(r.stream));
+    g.syncs += 1;
+    return hovf ? TIKH_RESIZE : TIKH_OK;
+}
+
+// Info bits of a failed solve (breakdown, degree bound, non-finite, refinement failure):
+// such groups are solved again with the fallback leaf cutoff.
+static const int32_t FAIL_BITS = 1 | 2 | 8 | 16;
+
+// After the chunk's stream has drained: the descriptors (in their final order after the
+// refinement's exchanges) of the groups whose solve failed.
+static int chunk_failed(ChunkRun& r) {
+    r.failed.clear();
+    std::vector<SolveState> st((size_t)r.G);
+    std::vector<SolveDesc> sd((size_t)r.S);
+    HIPCHK(hipMemcpyAsync(st.data(), r.b.st, sizeof(SolveState) * r.G, hipMemcpyDeviceToHost, r.stream));
+    HIPCHK(hipMemcpyAsync(sd.data(), r.b.sd, sizeof(SolveDesc) * r.S, hipMemcpyDeviceToHost, r.stream));
+    HIPCHK(hipStreamSynchronize(r.stream));
+    g.syncs += 1;
+    for (int64_t gi = 0; gi < r.G; ++gi)
+        if (st[gi].info & FAIL_BITS)
+            for (int q = 0; q < r.nr; ++q) r.failed.push_back(sd[gi * r.nr + q]);
+    return TIKH_OK;
+}
+
+// A chunk on its own: phases in order on the library stream; a chunk whose recorded
+// lengths were too short runs again with read-back sizing.
+static int run_chunk(ChunkRun& spec) {
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        ChunkRun r;
+        r.pl = spec.pl; r.nr = spec.nr; r.sds = spec.sds; r.info = spec.info; r.mchunk = spec.mchunk;
+        r.use_sizes = attempt == 0;
+        r.stream = g.stream;
+        chunk_layout(r);
+        int rc = ensure_ws(chunk_run_bytes(r));
+        if (rc) return rc;
+        r.base = g.ws;
+        rc = chunk_begin(r);
+        while (rc == TIKH_OK && !r.done) rc = chunk_adapt(r);
+        if (rc == TIKH_OK) rc = chunk_finish(r);
+        if (rc == TIKH_OK) rc = chunk_check(r);
+        if (rc == TIKH_OK && g.opts.fallback_nlim > 0) rc = chunk_failed(r);
+        g.cur_sizes = nullptr;
+        spec.failed.swap(r.failed);
+        if (rc != TIKH_RESIZE) return rc;
+        g.sizes.erase(sizes_key(spec.pl, spec.nr, spec.sds));
+    }
+    return TIKH_EHIP;
+}
+
+// Chunks of different plans (ragged batches) side by side: each wave of chunks that fits
+// the workspace gets disjoint workspace regions and its own streams (default priority,
+// ordered after the library stream's earlier work by an event and joined back by events),
+// and the phases are interleaved over the wave, so one chunk's host synchronizations
+// (transform sizing read back on a first call, adaptive refinement decisions) leave the
+// other chunks' queued work running.  Chunks whose recorded lengths were too short run
+// again afterwards, one at a time.
+static int run_concurrent(std::vector<std::unique_ptr<ChunkRun>>& runs, size_t budget) {
+    const int nstreams = std::max(1, std::min((int)g.opts.streams, 16));
+    while ((int)g.pool.size() < nstreams) {
+        hipStream_t st;
+        HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        g.pool.push_back(st);
+    }
+    while (g.events.size() < (size_t)nstreams + 1) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        g.events.push_back(e);
+    }
+    const hipStream_t user = g.stream;
+    std::vector<ChunkRun*> rerun;
+    size_t i0 = 0;
+    int rc = TIKH_OK;
+    while (i0 < runs.size() && rc == TIKH_OK) {
+        // the next wave: consecutive chunks while they fit the budget and the stream pool
+        size_t i1 = i0, total = 0;
+        while (i1 < runs.size() && (int)(i1 - i0) < nstreams) {
+            const size_t bytes = (chunk_run_bytes(*runs[i1]) + 255) & ~(size_t)255;
+            if (i1 > i0 && total + bytes > budget) break;
+            total += bytes;
+            ++i1;
+        }
+        rc = ensure_ws(total);
+        if (rc) break;
+        HIPCHK(hipEventRecord(g.events[nstreams], user));
+        size_t off = 0;
+        for (size_t i = i0; i < i1; ++i) {
+            ChunkRun& r = *runs[i];
+            r.stream = g.pool[i - i0];
+            r.base = g.ws + off;
+            off += (chunk_run_bytes(r) + 255) & ~(size_t)255;
+            HIPCHK(hipStreamWaitEvent(r.stream, g.events[nstreams], 0));
+        }
+        for (size_t i = i0; i < i1 && rc == TIKH_OK; ++i) { chunk_enter(*runs[i]); rc = chunk_begin(*runs[i]); }
+        for (bool more = true; more && rc == TIKH_OK;) {
+            more = false;
+            for (size_t i = i0; i < i1 && rc == TIKH_OK; ++i) {
+                ChunkRun& r = *runs[i];
+                if (r.done) continue;
+                chunk_enter(r);
+                rc = chunk_adapt(r);
+                more |= !r.done;
+            }
+        }
+        for (size_t i = i0; i < i1 && rc == TIKH_OK; ++i) { chunk_enter(*runs[i]); rc = chunk_finish(*runs[i]); }
+        for (size_t i = i0; i < i1 && rc == TIKH_OK; ++i) {
+            chunk_enter(*runs[i]);
+            int c = chunk_check(*runs[i]);
+            if (c == TIKH_OK && g.opts.fallback_nlim > 0) c = chunk_failed(*runs[i]);
+            if (c == TIKH_RESIZE) rerun.push_back(runs[i].get());
+            else rc = c;
+        }
+        // join the wave back into the library stream
+        for (size_t i = i0; i < i1; ++i) {
+            (void)hipEventRecord(g.events[i - i0], runs[i]->stream);
+            (void)hipStreamWaitEvent(user, g.events[i - i0], 0);
+        }
+        g.stream = user;
+        g.cur_sizes = nullptr;
+        i0 = i1;
+    }
+    g.stream = user;
+    g.cur_sizes = nullptr;
+    if (rc) return rc;
+    for (ChunkRun* r : rerun) {
+        g.sizes.erase(sizes_key(r->pl, r->nr, r->sds));
+        rc = run_chunk(*r);
+        if (rc) return rc;
     }
     return TIKH_OK;
 }
 
-static int run_chunk(const Plan& pl, int nr, const std::vector<SolveDesc>& sds, int32_t* info, int64_t merge_chunk) {
-    int rc = run_chunk_once(pl, nr, sds, info, merge_chunk, true);
-    g.cur_sizes = nullptr;
-    if (rc == TIKH_RESIZE) {
-        g.sizes.erase(sizes_key(pl, nr, sds));
-        rc = run_chunk_once(pl, nr, sds, info, merge_chunk, false);
-        g.cur_sizes = nullptr;
+// Ragged batches: extended sizes within a factor 1 + merge_tol of the smallest of a run
+// share the largest one's plan (a larger extension k, Sec. 3.1), so fewer, fuller
+// launches walk fewer trees.  Maps every N (ascending keys) to the N it runs at.
+static std::map<int64_t, int64_t> merged_sizes(const std::vector<int64_t>& Ns) {
+    std::map<int64_t, int64_t> to;
+    size_t i = 0;
+    while (i < Ns.size()) {
+        size_t j = i;
+        while (j + 1 < Ns.size() && g.opts.merge_tol > 0.0 &&
+               (double)Ns[j + 1] <= (1.0 + g.opts.merge_tol) * (double)Ns[i])
+            ++j;
+        for (size_t u = i; u <= j; ++u) to[Ns[u]] = Ns[j];
+        i = j + 1;
     }
-    return rc;
+    return to;
 }
 
 // Group solves by plan and run them in chunks that fit the workspace budget.
 // sds is group-major: solves g*nr .. g*nr + nr - 1 share the operator.
+static int run_solves_core(std::vector<SolveDesc>& sds, int nr, int32_t* info,
+                           std::vector<SolveDesc>* failed);
+
+// Groups whose solve failed (FAIL_BITS: the recursion met pivots so small that its
+// basis lost the solution, Sec. 5 "difficult points", or broke down) are solved again
+// with the smaller leaf cutoff fallback_nlim: a different tree over the same
+// conditions, whose leaves hold fewer of them.  Their outputs and info are overwritten.
 static int run_solves(std::vector<SolveDesc>& sds, int nr, int32_t* info) {
     init_opts();                 // (allocation-free calls pass through here too)
     g.launches = 0;
     g.syncs = 0;
     g.stats.refine_extra = 0;
     g.stats.deferred = 0;
+    g.stats.fallback_groups = 0;
+    std::vector<SolveDesc> failed;
+    const bool fb = g.opts.fallback_nlim > 0 && g.opts.fallback_nlim < g.opts.n_lim;
+    int rc = run_solves_core(sds, nr, info, fb ? &failed : nullptr);
+    if (rc || failed.empty()) return rc;
+    g.stats.fallback_groups = (int64_t)failed.size() / nr;
+    const int32_t keep = g.opts.n_lim;
+    g.opts.n_lim = g.opts.fallback_nlim;
+    const tikh_stats st = g.stats;
+    rc = run_solves_core(failed, nr, info, nullptr);
+    g.opts.n_lim = keep;
+    // the statistics describe the main solve (plan, shapes), with the fallback's counts added
+    const int64_t launches = g.stats.launches, syncs = g.stats.host_syncs, extra = g.stats.refine_extra;
+    g.stats = st;
+    g.stats.launches = launches;
+    g.stats.host_syncs = syncs;
+    g.stats.refine_extra += extra;
+    return rc;
+}
+
+static int run_solves_core(std::vector<SolveDesc>& sds, int nr, int32_t* info,
+                           std::vector<SolveDesc>* failed) {
     if (sds.empty()) return TIKH_OK;
     if (nr != 1 && nr != 2 && nr != 4) return TIKH_EINVAL;
     const int64_t G = (int64_t)sds.size() / nr;
@@ -1183,6 +1457,21 @@ static int run_solves(std::vector<SolveDesc>& sds, int nr, int32_t* info) {
         buckets[N].push_back(gi);
         shapes[N] = {M, p};
     }
+    {
+        std::vector<int64_t> Ns;
+        for (auto& kv : buckets) Ns.push_back(kv.first);
+        const std::map<int64_t, int64_t> to = merged_sizes(Ns);
+        std::map<int64_t, std::vector<int64_t>> merged;
+        for (auto& kv : buckets) {
+            const int64_t Nt = to.at(kv.first);
+            for (int64_t gi : kv.second) {
+                SolveDesc& d0 = sds[gi * nr];
+                for (int r = 0; r < nr; ++r) sds[gi * nr + r].k = Nt - (d0.m + d0.n - 1);
+                merged[Nt].push_back(gi);
+            }
+        }
+        buckets.swap(merged);
+    }
     size_t budget;
     if (g.ws_ext) {
         budget = g.ws_size > WS_FIXED ? g.ws_size - WS_FIXED : 0;
@@ -1191,6 +1480,7 @@ static int run_solves(std::vector<SolveDesc>& sds, int nr, int32_t* info) {
         (void)hipMemGetInfo(&freeb, &totb);
         budget = std::max<size_t>((size_t)1 << 30, (size_t)((double)(freeb + g.ws_size) * 0.85)) - WS_FIXED;
     }
+    std::vector<std::unique_ptr<ChunkRun>> runs;
     for (auto& kv : buckets) {
         Plan pl;
         if (!make_plan(kv.first, shapes[kv.first].first, shapes[kv.first].second, &pl)) return TIKH_EINVAL;
@@ -1215,18 +1505,30 @@ static int run_solves(std::vector<SolveDesc>& sds, int nr, int32_t* info) {
         }
         for (size_t c0 = 0; c0 < idx.size(); c0 += (size_t)chunk) {
             size_t c1 = std::min(idx.size(), c0 + (size_t)chunk);
-            std::vector<SolveDesc> part;
-            part.reserve((c1 - c0) * nr);
+            auto r = std::make_unique<ChunkRun>();
+            r->pl = pl; r->nr = nr; r->info = info; r->mchunk = mchunk;
+            r->sds.reserve((c1 - c0) * nr);
             for (size_t u = c0; u < c1; ++u)
-                for (int r = 0; r < nr; ++r) part.push_back(sds[idx[u] * nr + r]);
-            int rc = run_chunk(pl, nr, part, info, mchunk);
-            if (rc) return rc;
+                for (int q = 0; q < nr; ++q) r->sds.push_back(sds[idx[u] * nr + q]);
+            chunk_layout(*r);
+            runs.push_back(std::move(r));
             g.stats.N = pl.N;
-            g.stats.k = part[0].k;
+            g.stats.k = runs.back()->sds[0].k;
             g.stats.depth = pl.p;
             g.stats.leaf_nodes = (int32_t)pl.M;
         }
     }
+    int rc = (runs.size() > 1 && !g.noalloc && g.opts.streams > 1) ? run_concurrent(runs, budget + WS_FIXED)
+                                                                    : TIKH_OK;
+    if (runs.size() <= 1 || g.noalloc || g.opts.streams <= 1) {
+        for (auto& r : runs) {
+            rc = run_chunk(*r);
+            if (rc) break;
+        }
+    }
+    if (rc) return rc;
+    if (failed)
+        for (auto& r : runs) failed->insert(failed->end(), r->failed.begin(), r->failed.end());
     g.stats.solves = (int64_t)sds.size();
     g.stats.launches = g.launches;
     g.stats.host_syncs = g.syncs;
@@ -1408,7 +1710,8 @@ int tikh_workspace_bytes(int64_t nprob, const int64_t* m, const int64_t* n, int6
     if (nprob < 0 || nlam < 1 || nrhs < 1 || !bytes || (nprob > 0 && (!m || !n))) return TIKH_EINVAL;
     const int nr = group_size(nrhs);
     const int64_t gpp = nlam * ((nrhs + nr - 1) / nr);  // groups per problem
-    const int32_t nlim = g.init ? g.opts.n_lim : 256;
+    init_opts();
+    const int32_t nlim = g.opts.n_lim;
     struct Bucket { int64_t M; int p; int64_t G = 0, mmax = 1, nmax = 1; };
     std::map<int64_t, Bucket> buckets;
     for (int64_t q = 0; q < nprob; ++q) {
@@ -1423,15 +1726,31 @@ int tikh_workspace_bytes(int64_t nprob, const int64_t* m, const int64_t* n, int6
         bk.mmax = std::max(bk.mmax, m[q]);
         bk.nmax = std::max(bk.nmax, n[q]);
     }
-    size_t most = 0;
+    init_opts();
+    std::vector<int64_t> Ns;
+    for (auto& kv : buckets) Ns.push_back(kv.first);
+    const std::map<int64_t, int64_t> to = merged_sizes(Ns);
+    std::map<int64_t, Bucket> merged;
     for (auto& kv : buckets) {
+        Bucket& bk = merged[to.at(kv.first)];
+        const Bucket& src = buckets[to.at(kv.first)];
+        bk.M = src.M; bk.p = src.p;
+        bk.G += kv.second.G;
+        bk.mmax = std::max(bk.mmax, kv.second.mmax);
+        bk.nmax = std::max(bk.nmax, kv.second.nmax);
+    }
+    // every bucket in one chunk; with several streams all of them side by side
+    size_t most = 0, sum = 0;
+    for (auto& kv : merged) {
         Plan pl;
         if (!make_plan(kv.first, kv.second.M, kv.second.p, &pl)) return TIKH_EINVAL;
         Layout L;
         make_layout(pl, nr, kv.second.mmax, kv.second.nmax, &L);
-        most = std::max(most, chunk_bytes(L, kv.second.G, std::min<int64_t>(kv.second.G, 128)));
+        const size_t b = chunk_bytes(L, kv.second.G, std::min<int64_t>(kv.second.G, 128));
+        most = std::max(most, b);
+        sum += (b + 255) & ~(size_t)255;
     }
-    *bytes = most;
+    *bytes = (merged.size() > 1 && g.opts.streams > 1 && merged.size() <= (size_t)g.opts.streams) ? sum : most;
     return TIKH_OK;
 }
 
@@ -1457,6 +1776,10 @@ int tikh_release(void) {
     for (auto& kv : g.tw2) (void)hipFree(kv.second);
     g.tw2.clear();
     g.sizes.clear();
+    for (hipStream_t st : g.pool) (void)hipStreamDestroy(st);
+    g.pool.clear();
+    for (hipEvent_t e : g.events) (void)hipEventDestroy(e);
+    g.events.clear();
     return TIKH_OK;
 }
 
@@ -1467,7 +1790,9 @@ int tikh_set_options(const tikh_opts* o) {
     if (!o) return TIKH_EINVAL;
     if (o->n_lim < 64 || o->n_lim > LEAF_MAX || o->refine < 0 || o->refine > 4 || o->refine_max < 0 ||
         o->refine_max > 4 || !(o->refine_tol > 0.0) || !std::isfinite(o->refine_tol) || !(o->defer_tol >= 0.0) ||
-        !(o->defer_tol < 1.0) || o->leaf_wave_groups < 1)
+        !(o->defer_tol < 1.0) || o->leaf_wave_groups < 1 || o->streams < 1 || o->streams > 16 ||
+        !(o->merge_tol >= 0.0) || !(o->merge_tol <= 4.0) ||
+        (o->fallback_nlim != 0 && (o->fallback_nlim < 64 || o->fallback_nlim > LEAF_MAX)))
         return TIKH_EINVAL;
     g.opts = *o;
     return TIKH_OK;

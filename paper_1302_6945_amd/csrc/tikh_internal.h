@@ -49,7 +49,8 @@ struct SolveDesc {
 // Per-group running state of the recursion.
 struct SolveState {
     int32_t delta[4];  // tau-degrees of basis columns 1..4 (column 5 stays 0)
-    int32_t info;      // 0 ok; or of bits 1 breakdown, 2 degree bound, 4 too many deferred conditions, 8 non-finite
+    int32_t info;      // 0 ok; or of bits 1 breakdown, 2 degree bound, 4 too many deferred conditions, 8 non-finite,
+                       // 16 refinement estimate above its target after the last step
     int32_t ndef;      // deferred (difficult) conditions of the current solve
     int32_t wide;      // set by the narrow pass of a two-pass kernel: this group is left to the wide pass
     double e0;         // relative size of the first refinement correction (error estimate of the first solve)

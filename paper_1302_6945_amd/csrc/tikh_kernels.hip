@@ -895,7 +895,7 @@ struct LeafArgs {
     DeferList dl;
 };
 
-#define TIKH_ZTOL2 1e-22   // (1e-11)^2: relative size below which a residual entry counts as zero
+#define TIKH_ZTOL2 1e-18   // (1e-9)^2: relative size below which a residual entry counts as zero
 
 // ---- cross-lane helpers (DPP, wave64)
 template <int CTRL, int RM = 0xF>
@@ -2285,6 +2285,9 @@ __global__ __launch_bounds__(256) void k_grad_lambda(const SolveDesc* __restrict
 // estimated as cfac * e0 * rel (refinement contracts the error by a factor
 // of about the first solve's relative error).  flags[g] = 1 asks for one
 // more step.
+// flags == nullptr: after the last step, a group whose estimate is still above tol
+// (here the caller passes a failure threshold, far above the refinement target) gets
+// info bit 16: its refinement diverged or converges too slowly to be trusted.
 __global__ void k_refine_decide(const double* __restrict__ nrm, int nr, SolveState* __restrict__ st, int ngroup,
                                 int first, double cfac, double tol, int32_t* __restrict__ flags) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -2292,12 +2295,15 @@ __global__ void k_refine_decide(const double* __restrict__ nrm, int nr, SolveSta
     double rel = 0.0;
     for (int r = 0; r < nr; ++r) {
         const double dx2 = nrm[2 * ((int64_t)g * nr + r)], x2 = nrm[2 * ((int64_t)g * nr + r) + 1];
+        if (!isfinite(dx2) || !isfinite(x2)) continue;   // a non-finite solve reports itself (bit 8)
         if (x2 > 0.0) rel = fmax(rel, sqrt(dx2 / x2));
         else if (dx2 > 0.0) rel = INFINITY;
     }
     if (first) st[g].e0 = rel;
     const double est = cfac * st[g].e0 * rel;
-    flags[g] = (est > tol || !(est == est)) && st[g].info == 0 ? 1 : 0;
+    const bool above = est > tol || !(est == est);
+    if (flags) flags[g] = above && st[g].info == 0 ? 1 : 0;
+    else if (above) st[g].info |= 16;
 }
 
 __global__ void k_zero_d(double* __restrict__ p, int64_t n) {

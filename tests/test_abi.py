@@ -99,16 +99,23 @@ def test_invalid_arguments_rejected_on_host():
 
 def test_workspace_query_on_host():
     """tikh_workspace_bytes is host arithmetic: positive, growing with the batch,
-    one bucket per transform size (the larger bucket sets the size), and it
+    one bucket per transform size (with several streams the buckets run side by side
+    and their sizes add up; with one stream the larger bucket sets the size), and it
     rejects the shapes the solves reject."""
     _ensure_built()
     import paper_1302_6945_amd as P
     one = P.workspace_bytes([300], [211], 2, 4)
     two = P.workspace_bytes([300, 300], [211, 211], 2, 4)
     assert 0 < one < two < 2 * one + (1 << 20)
-    # a second problem of another transform size adds a bucket; the size is the larger bucket's
-    mixed = P.workspace_bytes([300, 40], [211, 30], 2, 4)
-    assert mixed == max(one, P.workspace_bytes([40], [30], 2, 4))
+    # a second problem of another transform size adds a bucket
+    small = P.workspace_bytes([40], [30], 2, 4)
+    up = lambda v: (v + 255) // 256 * 256
+    assert P.workspace_bytes([300, 40], [211, 30], 2, 4) == up(one) + up(small)
+    P.set_options(streams=1)
+    try:
+        assert P.workspace_bytes([300, 40], [211, 30], 2, 4) == max(one, small)
+    finally:
+        P.set_options(streams=16)
     assert P.workspace_bytes([], [], 1, 1) == 0
     for bad in (([0], [5], 1, 1), ([5], [5], 0, 1), ([5], [5], 1, 0)):
         with pytest.raises(P.TikhError):

@@ -528,3 +528,58 @@ def test_caller_workspace(P):
         assert np.array_equal(a, b)
     x = ref[0]
     assert relerr(x[:211], oracle.solve(cols[0], rows[0], bs[0], lams[0])) <= TOL
+
+
+def test_headline_problems_with_tight_extension(P):
+    """Headline-shaped problems whose extension k = N - (m + n - 1) lies in 43..89 (4 of the
+    256 benchmark problems).  With a zero threshold of 1e-11 their leaves pivoted the
+    gamma_1 column on rounding noise (a residual entry that is zero in exact arithmetic)
+    and the basis lost the solution; with 1e-9 they solve like the rest, with no fallback
+    solve, and match known solutions (normal form, right-hand side formed in long double)
+    at the ends of the lambda path."""
+    picks = [35, 54, 94, 249]
+    probs = [W.headline(i) for i in picks]
+    for p in probs:
+        assert 40 <= P.plan_info(p.m, p.n, 256)[3] <= 90
+    args = ([p.m for p in probs], [p.n for p in probs], dev(np.concatenate([p.col for p in probs])),
+            dev(np.concatenate([p.row for p in probs])), [l for p in probs for l in p.lams], 4,
+            dev(np.concatenate([np.concatenate(p.b) for p in probs])))
+    P.set_options(n_lim=256, refine=1)
+    x, info = P.solve_batched(*args)
+    torch.cuda.synchronize()
+    assert (info.cpu().numpy() == 0).all()
+    assert P.get_stats()["fallback_groups"] == 0
+    x = x.cpu().numpy()
+    off = 0
+    for p in probs:
+        for j, lam in enumerate(p.lams):
+            for r in range(4):
+                res = oracle.normal_residual_fft(p.col, p.row, p.b[r], lam, x[off:off + p.n])
+                assert res <= 1e-11, (j, r, res)
+                off += p.n
+    for p in probs[:2]:
+        for j in (0, 7):
+            lam = p.lams[j]
+            y = (_ld_TH(p.col, p.row, _ld_T(p.col, p.row, p.x_true)) + np.longdouble(lam) ** 2 * p.x_true).astype(
+                np.float64)
+            xs = P.solve_normal(dev(p.col), dev(p.row), dev(y), lam).cpu().numpy()
+            assert relerr(xs, p.x_true) <= TOL, (j, relerr(xs, p.x_true))
+
+
+def test_fallback_leaf_cutoff(P):
+    """A group whose solve failed is solved again with the fallback leaf cutoff.  Forced
+    here with non-finite data (info bit 8 persists: the second solve fails too, and the
+    outputs are those of the second solve) and, for a solvable problem, by counting: no
+    group of a sound batch takes the fallback."""
+    rng = np.random.default_rng(91)
+    col, row, _ = W.random_problem(rng, 300, 250, L=8.0)
+    b = rng.standard_normal((2, 300))
+    b[0, 7] = np.nan
+    x, info = P.solve_batched([300], [250], dev(col), dev(row), [0.2, 0.7], 2, dev(b.ravel()))
+    torch.cuda.synchronize()
+    st = P.get_stats()
+    assert info.cpu().numpy().tolist() == [8, 0, 8, 0]
+    assert st["fallback_groups"] == 2
+    x = x.cpu().numpy()
+    assert relerr(x[250:500], oracle.solve(col, row, b[1], 0.2)) <= TOL
+    assert relerr(x[750:1000], oracle.solve(col, row, b[1], 0.7)) <= TOL
