@@ -196,6 +196,91 @@ def residual_sample(probs, nlam, nrhs, x_gpu, count=64):
     return count, worst
 
 
+def config2_leg(P, torch, W, steps, with_oracle):
+    """The batching workload at full size: 1024 problems with n log-uniform in [2^9, 2^14],
+    m = n + U{0..n/4}, 8 absolute lambdas 1e-4..1, 4 right-hand sides (32768 solves), forward and
+    backward batched (ragged: chunks of different extended sizes side by side on several streams),
+    against the plain one-problem-per-call method measured on one problem per octave of n and
+    scaled by the octave counts.  With the oracle: sampled solves of the narrowest-band problem of
+    two octaves against the oracle at every lambda with kappa <= 1e6 (1e-9)."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    probs = [W.config2(i) for i in range(1024)]
+    ms = [p.m for p in probs]
+    ns = [p.n for p in probs]
+    lams = [l for p in probs for l in p.lams]
+    col = torch.tensor(np.concatenate([p.col for p in probs]), device=dev)
+    row = torch.tensor(np.concatenate([p.row for p in probs]), device=dev)
+    bb = torch.tensor(np.concatenate([np.concatenate(p.b) for p in probs]), device=dev)
+    xt = torch.tensor(np.concatenate([np.tile(p.x_true, 32) for p in probs]), device=dev)
+
+    def step():
+        x, info = P.solve_batched(ms, ns, col, row, lams, 4, bb)
+        g = P.backward_batched(ms, ns, col, row, lams, 4, bb, x, x - xt)
+        return x, info, g[4]
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        x, info, binfo = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    nsol = 1024 * 8 * 4
+    info = info.cpu().numpy()
+    binfo = binfo.cpu().numpy()
+    # plain method: one problem per octave of n, one fwd+bwd per call, scaled by the octave counts
+    octs = [min(13, max(9, int(np.floor(np.log2(n))))) for n in ns]
+    plain_s = 0.0
+    plain_detail = {}
+    for o in range(9, 14):
+        idx = [i for i in range(1024) if octs[i] == o]
+        if not idx:
+            continue
+        p0 = probs[idx[0]]
+        c0, r0, b0 = (torch.tensor(a, device=dev) for a in (p0.col, p0.row, p0.b[0]))
+        x0t = torch.tensor(p0.x_true, device=dev)
+        x0 = P.solve(c0, r0, b0, p0.lams[4])
+        P.backward(c0, r0, b0, p0.lams[4], x0, x0 - x0t)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        x0 = P.solve(c0, r0, b0, p0.lams[4])
+        P.backward(c0, r0, b0, p0.lams[4], x0, x0 - x0t)
+        torch.cuda.synchronize()
+        per = time.perf_counter() - t1
+        plain_detail[str(2 ** o)] = round(per, 4)
+        plain_s += per * len(idx) * 32
+    out = {"workload": "1024 problems, n log-uniform 2^9..2^14, m = n + U{0..n/4}, 8 lambdas 1e-4..1 x 4 rhs",
+           "solves_per_step": nsol, "value": round(nsol / dt, 2), "unit": "solves/s (fwd+bwd)",
+           "ms_per_step": round(dt * 1e3, 1), "steps": steps,
+           "plain_solves_per_s": round(nsol / plain_s, 4), "batched_over_plain": round(plain_s / dt, 1),
+           "plain_s_per_solve_by_octave": plain_detail,
+           "flagged_fwd": int(((info & 16) != 0).sum()), "flagged_bwd": int(((binfo & 16) != 0).sum()),
+           "other_info": int(((info | binfo) & ~16).max())}
+    if with_oracle:
+        import oracle
+        xh = x.cpu().numpy()
+        xoff = np.concatenate([[0], np.cumsum([p.n * 32 for p in probs])])
+        worst, checked = 0.0, 0
+        for lo in (9, 11):
+            cand = [i for i in range(1024) if 2 ** lo <= probs[i].n < 2 ** (lo + 1)]
+            ip = min(cand, key=lambda i: probs[i].meta["L"] * (probs[i].m + probs[i].n))
+            p = probs[ip]
+            smax = W.norm2_estimate(p.col, p.row, iters=60)
+            for j, lam in enumerate(p.lams):
+                if 1.0 + (smax / lam) ** 2 > 1e6:
+                    continue
+                xr = (oracle.band_solve(p.col, p.row, p.b, lam) if p.n > 1100 else
+                      np.array([oracle.solve(p.col, p.row, b, lam) for b in p.b]))
+                for r in range(4):
+                    o = xoff[ip] + (j * 4 + r) * p.n
+                    e = float(np.linalg.norm(xh[o:o + p.n] - xr[r].real) / np.linalg.norm(xr[r]))
+                    worst = max(worst, e)
+                    checked += 1
+        out["parity"] = {"solves_checked": checked, "max_rel_err": worst, "tol": 1e-9, "ok": worst <= 1e-9}
+    return out
+
+
 def measured_traffic(root, kernel, args, nlim):
     """HBM bytes per launch of `kernel` from the committed counter summary, when it was taken on
     the current sources, at this workload and leaf cutoff; None otherwise."""
@@ -233,6 +318,9 @@ def main():
                     help="timed solves whose optimality residual is checked on the CPU")
     ap.add_argument("--kernel", default="auto", help="kernel for the roofline object: fft, leaf_loop or auto "
                                                      "(the one with the larger share of the step)")
+    ap.add_argument("--config2-steps", type=int, default=2,
+                    help="timed steps of the 1024-problem ragged batching workload reported beside the headline "
+                         "(0 = skip)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="after the run, negate a float64 buffer of this many MiB into another three times "
                          "(a plain streaming kernel of known traffic that calibrates the HBM byte counters)")
@@ -391,6 +479,11 @@ def main():
         parity["info_max"] = info_max
         parity["ok"] = parity["ok"] and info_max == 0
 
+    cfg2 = None
+    if args.config2_steps > 0:
+        cfg2 = config2_leg(P, torch, W, args.config2_steps, not args.no_oracle)
+        P.set_options(n_lim=nlim, refine=1)
+
     if args.copy_calib_mib > 0:
         src = torch.ones(args.copy_calib_mib * 2 ** 20 // 8, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
@@ -406,6 +499,9 @@ def main():
             roofline["traffic_over_alg"] = round(traffic / roofline["alg_bytes_per_launch"], 3)
             roofline["traffic_over_pass"] = round(traffic / max(roofline["pass_bytes_per_launch"], 1), 3)
 
+    if parity is not None and cfg2 is not None and "parity" in cfg2:
+        parity["config2_ok"] = cfg2["parity"]["ok"] and cfg2["other_info"] == 0
+        parity["ok"] = parity["ok"] and parity["config2_ok"]
     ok = parity is None or parity["ok"]
     out = {
         "metric": "batched regularized solves/s (fwd+bwd) at n=2^14 vs plain, rel err <= 1e-9",
@@ -434,6 +530,7 @@ def main():
         "step_roofline": step_roofline,
         "kernel_ms_per_step": kernel_ms,
         "cpu_baseline": cpu,
+        "config2": cfg2,
     }
     if not ok:
         out["unmeasured_reason"] = "parity gate failed: no value is reported"

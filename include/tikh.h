@@ -106,7 +106,9 @@ typedef struct {
                              basis lost the solution, Sec. 5's difficult points, or a breakdown) is solved
                              again with this smaller leaf cutoff, i.e. another tree over the same conditions
                              (64..256 and below n_lim, or 0 = off; default 64); its outputs and info are
-                             those of the second solve */
+                             those of the second solve.  Not for a group whose conditioning bound
+                             1 + (sum_s |a_s| / lambda)^2 exceeds 1e8 (the failure may then be the
+                             conditioning itself, which another tree does not cure): its flags stand */
     int32_t reserved;
 } tikh_opts;
 

@@ -384,7 +384,7 @@ static void make_layout(const Plan& pl, int nr, int64_t mmax, int64_t nmax, Layo
         L->sT = std::max(L->sT, ((d & 1) ? L->tOff : 0) + sz);
     }
     tot += L->sT;
-    L->group_bytes = tot * sizeof(double2) + 2 * (pl.p + 1) * sizeof(SlotMeta) + sizeof(SolveState) + 2 * sizeof(double) +
+    L->group_bytes = tot * sizeof(double2) + 2 * (pl.p + 1) * sizeof(SlotMeta) + sizeof(SolveState) + 3 * sizeof(double) +
                      sizeof(int32_t) + sizeof(int2) + DEFER_CAP * (sizeof(int32_t) + (1 + L->C) * sizeof(double2)) + 256;
     L->solve_bytes = (size_t)(4 * L->sN + 4 * L->sn) * sizeof(double2) + sizeof(SolveDesc) + 2 * sizeof(double) + 64;
     L->temp_bytes = (size_t)(L->sV + 2 * L->sF + L->sscr) * sizeof(double2);
@@ -395,6 +395,7 @@ struct Bufs {
     SolveDesc* sd;                   // [G*nr]
     SolveState* st;                  // [G]
     double* rms;                     // [G]
+    double* asum;                    // [G] sum of the generator's magnitudes (a bound on ||T||_2)
     double* rmsg;                    // [G] Gramian generator rms (Toeplitz-Gramian problem)
     double2* chat;                   // [G][N]
     double2* cg;                     // [G][N] symbol of the extended Gramian
@@ -425,7 +426,7 @@ struct Bufs {
 static Bufs shift_bufs(const Bufs& b, const Layout& L, const Plan& pl, int64_t c0) {
     Bufs o = b;
     const int64_t s0 = c0 * b.nr;
-    o.sd += s0; o.st += c0; o.rms += c0; o.rmsg += c0;
+    o.sd += s0; o.st += c0; o.rms += c0; o.rmsg += c0; o.asum += c0;
     o.chat += c0 * L.sN;
     o.cg += c0 * L.sN;
     o.bA += s0 * L.sN; o.bB += s0 * L.sN; o.bC += s0 * L.sN; o.bS += s0 * L.sN;
@@ -498,6 +499,7 @@ static int carve_bufs(const Plan& pl, const Layout& L, int64_t G, int64_t CH, ch
     b->sd = (SolveDesc*)carve(p, sizeof(SolveDesc) * S);
     b->st = (SolveState*)carve(p, sizeof(SolveState) * G);
     b->rms = (double*)carve(p, sizeof(double) * G);
+    b->asum = (double*)carve(p, sizeof(double) * G);
     b->rmsg = (double*)carve(p, sizeof(double) * G);
     b->elist = (int*)carve(p, sizeof(EList));
     b->ovf = (int*)carve(p, sizeof(int));
@@ -1087,7 +1089,7 @@ static int chunk_begin(ChunkRun& r) {
     const double invN = 1.0 / (double)N;
     hipLaunchKernelGGL(k_init_state, dim3((unsigned)((G + 63) / 64)), dim3(64), 0, g.stream, b.sd, nr, b.st, (int)G, 0);
     // extension (eq. (circexp)) and its symbol c^ = F c_T (eq. (circdiag)), per group
-    hipLaunchKernelGGL(k_gen_rms, dim3((unsigned)G), dim3(256), 0, g.stream, b.sd, nr, b.rms);
+    hipLaunchKernelGGL(k_gen_rms, dim3((unsigned)G), dim3(256), 0, g.stream, b.sd, nr, b.rms, b.asum);
     hipLaunchKernelGGL(k_build_ct, grid1(N, G), dim3(256), 0, g.stream, b.sd, nr, b.rms, b.chat, N, L.sN);
     g.launches += 3;
     rc = fft_lines(b.chat, G, L.sN, 1, N, +1, tw, pl.Q, b.bS, L.sN);
@@ -1169,7 +1171,7 @@ static int chunk_adapt(ChunkRun& r) {
             HIPCHK(hipStreamSynchronize(g.stream));
             g.syncs += 1;
             hipLaunchKernelGGL(k_swap_groups, dim3(64, (unsigned)hp.size()), dim3(256), 0, g.stream, b.sd, b.st,
-                               b.chat, L.sN, b.yv, b.xacc, L.sn, nr, b.pairs, gramian ? b.cg : nullptr);
+                               b.chat, L.sN, b.yv, b.xacc, L.sn, nr, b.pairs, gramian ? b.cg : nullptr, b.asum);
             g.launches++;
         }
         Ga = G2;
@@ -1262,19 +1264,32 @@ static int chunk_check(ChunkRun& r) {
 // such groups are solved again with the fallback leaf cutoff.
 static const int32_t FAIL_BITS = 1 | 2 | 8 | 16;
 
+// Condition number below which (by the bound 1 + (sum_s |a_s| / lambda)^2 >= kappa) a failed
+// solve is solved again with the fallback leaf cutoff; above it the failure may be the
+// conditioning itself, which another tree does not cure, and the flag stands.
+static const double FALLBACK_KAPPA = 1e8;
+
 // After the chunk's stream has drained: the descriptors (in their final order after the
-// refinement's exchanges) of the groups whose solve failed.
+// refinement's exchanges) of the groups whose solve failed and whose conditioning bound
+// is below FALLBACK_KAPPA.
 static int chunk_failed(ChunkRun& r) {
     r.failed.clear();
     std::vector<SolveState> st((size_t)r.G);
     std::vector<SolveDesc> sd((size_t)r.S);
+    std::vector<double> asum((size_t)r.G);
     HIPCHK(hipMemcpyAsync(st.data(), r.b.st, sizeof(SolveState) * r.G, hipMemcpyDeviceToHost, r.stream));
     HIPCHK(hipMemcpyAsync(sd.data(), r.b.sd, sizeof(SolveDesc) * r.S, hipMemcpyDeviceToHost, r.stream));
+    HIPCHK(hipMemcpyAsync(asum.data(), r.b.asum, sizeof(double) * r.G, hipMemcpyDeviceToHost, r.stream));
     HIPCHK(hipStreamSynchronize(r.stream));
     g.syncs += 1;
-    for (int64_t gi = 0; gi < r.G; ++gi)
-        if (st[gi].info & FAIL_BITS)
-            for (int q = 0; q < r.nr; ++q) r.failed.push_back(sd[gi * r.nr + q]);
+    for (int64_t gi = 0; gi < r.G; ++gi) {
+        if (!(st[gi].info & FAIL_BITS)) continue;
+        const SolveDesc& d = sd[gi * r.nr];
+        // (the Gramian problem has no such bound at hand: always solved again)
+        const double kb = 1.0 + (asum[gi] / d.lam) * (asum[gi] / d.lam);
+        if (!d.gramian && !(kb <= FALLBACK_KAPPA)) continue;
+        for (int q = 0; q < r.nr; ++q) r.failed.push_back(sd[gi * r.nr + q]);
+    }
     return TIKH_OK;
 }
 

@@ -629,19 +629,29 @@ __global__ void k_copy(const double2* __restrict__ src, double2* __restrict__ ds
 
 // Root-mean-square of the generator (scale of the arbitrary extension
 // entries, Sec. 6.2: chosen "similar in value" to the known coefficients).
-__global__ __launch_bounds__(256) void k_gen_rms(const SolveDesc* __restrict__ sd, int nr, double* __restrict__ rms) {
+// Also the sum of the generator's magnitudes, sum_s |a_s| >= ||T||_2 (asum, may be null).
+__global__ __launch_bounds__(256) void k_gen_rms(const SolveDesc* __restrict__ sd, int nr, double* __restrict__ rms,
+                                                 double* __restrict__ asum) {
     const SolveDesc d = sd[(int64_t)blockIdx.x * nr];
-    double acc = 0.0;
+    double acc = 0.0, acc1 = 0.0;
     const int64_t cnt = d.m + d.n - 1;
-    for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x) acc += cabs2(gen_coef(d, i - (d.n - 1)));
-    __shared__ double red[256];
+    for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+        const double a2 = cabs2(gen_coef(d, i - (d.n - 1)));
+        acc += a2;
+        acc1 += sqrt(a2);
+    }
+    __shared__ double red[256], red1[256];
     red[threadIdx.x] = acc;
+    red1[threadIdx.x] = acc1;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        if ((int)threadIdx.x < o) { red[threadIdx.x] += red[threadIdx.x + o]; red1[threadIdx.x] += red1[threadIdx.x + o]; }
         __syncthreads();
     }
-    if (threadIdx.x == 0) rms[blockIdx.x] = sqrt(red[0] / (double)cnt);
+    if (threadIdx.x == 0) {
+        rms[blockIdx.x] = sqrt(red[0] / (double)cnt);
+        if (asum) asum[blockIdx.x] = red1[0];
+    }
 }
 
 __device__ __forceinline__ double hash_unit(uint64_t x) {
@@ -2315,7 +2325,7 @@ __global__ void k_zero_d(double* __restrict__ p, int64_t n) {
 // descriptors, state, symbol, right-hand side and current solution.
 __global__ void k_swap_groups(SolveDesc* __restrict__ sd, SolveState* __restrict__ st, double2* __restrict__ chat,
                               int64_t sN, double2* __restrict__ yv, double2* __restrict__ xacc, int64_t sn, int nr,
-                              const int2* __restrict__ pairs, double2* __restrict__ cg) {
+                              const int2* __restrict__ pairs, double2* __restrict__ cg, double* __restrict__ asum) {
     const int2 pr = pairs[blockIdx.y];
     const int64_t a = pr.x, b = pr.y;
     const int64_t nsym = cg ? 2 * sN : sN;         // the Gramian's symbol too, when there is one
@@ -2343,6 +2353,9 @@ __global__ void k_swap_groups(SolveDesc* __restrict__ sd, SolveState* __restrict
         const SolveState t = st[a];
         st[a] = st[b];
         st[b] = t;
+        const double u = asum[a];
+        asum[a] = asum[b];
+        asum[b] = u;
     }
 }
 
