@@ -318,6 +318,17 @@ def main():
                     help="timed solves whose optimality residual is checked on the CPU")
     ap.add_argument("--kernel", default="auto", help="kernel for the roofline object: fft, leaf_loop or auto "
                                                      "(the one with the larger share of the step)")
+    ap.add_argument("--kernel-times", type=int, default=1,
+                    help="time the dominant kernels with HIP events over one extra step each (0 = skip, e.g. under "
+                         "a profiler)")
+    ap.add_argument("--streams", type=int, default=0,
+                    help="streams the library runs chunks on side by side (0 = library default; 1 = one stream, "
+                         "e.g. for counter collection, which serializes dispatches)")
+    ap.add_argument("--chunk-groups", type=int, default=-1,
+                    help="most groups per chunk (chunks of one call run side by side on the streams); "
+                         "-1 = library default")
+    ap.add_argument("--leaf-wave-groups", type=int, default=0,
+                    help="groups per chunk from which leaf steps run one wavefront per group (0 = library default)")
     ap.add_argument("--config2-steps", type=int, default=2,
                     help="timed steps of the 1024-problem ragged batching workload reported beside the headline "
                          "(0 = skip)")
@@ -349,6 +360,12 @@ def main():
     else:
         nlim = int(args.nlim)
     P.set_options(n_lim=nlim, refine=1)
+    if args.streams:
+        P.set_options(streams=args.streams)
+    if args.chunk_groups >= 0:
+        P.set_options(chunk_groups=args.chunk_groups)
+    if args.leaf_wave_groups > 0:
+        P.set_options(leaf_wave_groups=args.leaf_wave_groups)
     ns = [p.n for p in probs]
     lams = [l for p in probs for l in p.lams]
     col = torch.tensor(np.concatenate([p.col for p in probs]), device=dev)
@@ -390,6 +407,9 @@ def main():
     st = P.get_stats()
     rl = {}
     for kern in ("fft", "leaf_loop", "leaf_build"):
+        if not args.kernel_times:
+            rl[kern] = (0.0, 0, 0.0)
+            continue
         P.profile_kernel(kern)
         step()
         torch.cuda.synchronize()

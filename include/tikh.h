@@ -109,7 +109,9 @@ typedef struct {
                              those of the second solve.  Not for a group whose conditioning bound
                              1 + (sum_s |a_s| / lambda)^2 exceeds 1e8 (the failure may then be the
                              conditioning itself, which another tree does not cure): its flags stand */
-    int32_t reserved;
+    int32_t chunk_groups; /* most groups (recursions run in the same launches) per chunk, 0 = as many as the
+                             workspace holds (the default); with streams > 1 the chunks of a call run side by
+                             side, so that one chunk's serial leaf steps overlap another's transforms */
 } tikh_opts;
 
 /* Per-solve statistics of the last call (host memory, filled by tikh_get_stats). */

@@ -22,7 +22,7 @@ class _Opts(ctypes.Structure):
     _fields_ = [("n_lim", ctypes.c_int32), ("refine", ctypes.c_int32), ("refine_max", ctypes.c_int32),
                 ("leaf_wave_groups", ctypes.c_int32), ("refine_tol", ctypes.c_double), ("defer_tol", ctypes.c_double),
                 ("record_short", ctypes.c_int32), ("streams", ctypes.c_int32), ("merge_tol", ctypes.c_double),
-                ("fallback_nlim", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("fallback_nlim", ctypes.c_int32), ("chunk_groups", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -95,7 +95,8 @@ def _stream():
 
 
 def set_options(n_lim=None, refine=None, refine_max=None, refine_tol=None, defer_tol=None,
-                leaf_wave_groups=None, record_short=None, streams=None, merge_tol=None, fallback_nlim=None):
+                leaf_wave_groups=None, record_short=None, streams=None, merge_tol=None, fallback_nlim=None,
+                chunk_groups=None):
     """Leaf cutoff, refinement steps for every solve, most refinement steps for a solve whose
     estimated error is above the target (see tikh_opts in include/tikh.h)."""
     o = _Opts()
@@ -120,6 +121,8 @@ def set_options(n_lim=None, refine=None, refine_max=None, refine_tol=None, defer
         o.merge_tol = float(merge_tol)
     if fallback_nlim is not None:
         o.fallback_nlim = int(fallback_nlim)
+    if chunk_groups is not None:
+        o.chunk_groups = int(chunk_groups)
     _check(lib.tikh_set_options(ctypes.byref(o)), "tikh_set_options")
 
 
@@ -128,7 +131,8 @@ def get_options():
     _check(lib.tikh_get_options(ctypes.byref(o)), "tikh_get_options")
     return dict(n_lim=o.n_lim, refine=o.refine, refine_max=o.refine_max, refine_tol=o.refine_tol,
                 defer_tol=o.defer_tol, leaf_wave_groups=o.leaf_wave_groups, record_short=o.record_short,
-                streams=o.streams, merge_tol=o.merge_tol, fallback_nlim=o.fallback_nlim)
+                streams=o.streams, merge_tol=o.merge_tol, fallback_nlim=o.fallback_nlim,
+                chunk_groups=o.chunk_groups)
 
 
 def plan_info(m, n, n_lim=256):

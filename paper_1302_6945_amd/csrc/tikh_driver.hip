@@ -1512,6 +1512,7 @@ static int run_solves_core(std::vector<SolveDesc>& sds, int nr, int32_t* info,
         // at least one group per chunk: if even that does not fit, the workspace reports it
         int64_t chunk = std::max<int64_t>(1, budget > fixed ? (int64_t)((budget - fixed) / per_group) : 0);
         chunk = std::min<int64_t>(chunk, 65535);
+        if (g.opts.chunk_groups > 0) chunk = std::min<int64_t>(chunk, g.opts.chunk_groups);
         // equal chunks: a small remainder chunk would repeat the whole serial recursion
         // for a handful of groups
         {
@@ -1754,18 +1755,27 @@ int tikh_workspace_bytes(int64_t nprob, const int64_t* m, const int64_t* n, int6
         bk.mmax = std::max(bk.mmax, kv.second.mmax);
         bk.nmax = std::max(bk.nmax, kv.second.nmax);
     }
-    // every bucket in one chunk; with several streams all of them side by side
-    size_t most = 0, sum = 0;
+    // every bucket in one chunk, or in equal chunks of at most chunk_groups groups; with
+    // several streams up to `streams` chunks side by side (the largest ones bound the sum)
+    std::vector<size_t> sizes;
     for (auto& kv : merged) {
         Plan pl;
         if (!make_plan(kv.first, kv.second.M, kv.second.p, &pl)) return TIKH_EINVAL;
         Layout L;
         make_layout(pl, nr, kv.second.mmax, kv.second.nmax, &L);
-        const size_t b = chunk_bytes(L, kv.second.G, std::min<int64_t>(kv.second.G, 128));
-        most = std::max(most, b);
-        sum += (b + 255) & ~(size_t)255;
+        const int64_t G = kv.second.G;
+        const int64_t cg = g.opts.chunk_groups > 0 ? std::min<int64_t>(G, g.opts.chunk_groups) : G;
+        const int64_t nch = (G + cg - 1) / cg, cs = (G + nch - 1) / nch;
+        for (int64_t c0 = 0; c0 < G; c0 += cs) {
+            const int64_t gc = std::min(cs, G - c0);
+            sizes.push_back((chunk_bytes(L, gc, std::min<int64_t>(gc, 128)) + 255) & ~(size_t)255);
+        }
     }
-    *bytes = (merged.size() > 1 && g.opts.streams > 1 && merged.size() <= (size_t)g.opts.streams) ? sum : most;
+    std::sort(sizes.begin(), sizes.end(), std::greater<size_t>());
+    size_t total = 0;
+    const size_t side = g.opts.streams > 1 ? std::min(sizes.size(), (size_t)g.opts.streams) : 1;
+    for (size_t i = 0; i < side && i < sizes.size(); ++i) total += sizes[i];
+    *bytes = total;
     return TIKH_OK;
 }
 
@@ -1807,7 +1817,7 @@ int tikh_set_options(const tikh_opts* o) {
         o->refine_max > 4 || !(o->refine_tol > 0.0) || !std::isfinite(o->refine_tol) || !(o->defer_tol >= 0.0) ||
         !(o->defer_tol < 1.0) || o->leaf_wave_groups < 1 || o->streams < 1 || o->streams > 16 ||
         !(o->merge_tol >= 0.0) || !(o->merge_tol <= 4.0) ||
-        (o->fallback_nlim != 0 && (o->fallback_nlim < 64 || o->fallback_nlim > LEAF_MAX)))
+        (o->fallback_nlim != 0 && (o->fallback_nlim < 64 || o->fallback_nlim > LEAF_MAX)) || o->chunk_groups < 0)
         return TIKH_EINVAL;
     g.opts = *o;
     return TIKH_OK;

@@ -116,6 +116,14 @@ def test_workspace_query_on_host():
         assert P.workspace_bytes([300, 40], [211, 30], 2, 4) == max(one, small)
     finally:
         P.set_options(streams=16)
+    # chunks of at most chunk_groups groups run side by side: four one-group chunks need four
+    # one-group workspaces (2 problems x 2 lambdas, one group each)
+    P.set_options(chunk_groups=1)
+    try:
+        per = P.workspace_bytes([300], [211], 1, 4)
+        assert P.workspace_bytes([300, 300], [211, 211], 2, 4) == 4 * up(per)
+    finally:
+        P.set_options(chunk_groups=0)
     assert P.workspace_bytes([], [], 1, 1) == 0
     for bad in (([0], [5], 1, 1), ([5], [5], 0, 1), ([5], [5], 1, 0)):
         with pytest.raises(P.TikhError):

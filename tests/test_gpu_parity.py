@@ -125,6 +125,37 @@ def test_batched_ragged(P):
     assert off == len(x)
 
 
+@pytest.mark.parametrize("chunk_groups", [1, 5])
+def test_chunked_batch_side_by_side(P, chunk_groups):
+    """A batch split into chunks of at most chunk_groups groups (equal chunks, run side by
+    side on several streams) gives the oracle's solutions, as the one-chunk batch does."""
+    rng = np.random.default_rng(7)
+    m, n, nlam, nrhs = 260, 200, 3, 4
+    probs = [W.random_problem(rng, m, n, L=12.0)[:2] for _ in range(4)]
+    B = [[rng.standard_normal(m) for _ in range(nrhs)] for _ in probs]
+    lams = [0.05 * (4 ** j) for j in range(nlam)]
+    args = ([m] * 4, [n] * 4, dev(np.concatenate([c for c, _ in probs])), dev(np.concatenate([r for _, r in probs])),
+            lams * 4, nrhs, dev(np.concatenate([np.concatenate(b) for b in B])))
+    x1, i1 = P.solve_batched(*args)
+    P.set_options(chunk_groups=chunk_groups)
+    try:
+        x2, i2 = P.solve_batched(*args)
+        torch.cuda.synchronize()
+    finally:
+        P.set_options(chunk_groups=0)
+    assert (i1.cpu().numpy() == 0).all() and (i2.cpu().numpy() == 0).all()
+    x1, x2 = x1.cpu().numpy(), x2.cpu().numpy()
+    off = 0
+    for (col, row), bs in zip(probs, B):
+        for lam in lams:
+            for b in bs:
+                ref = oracle.solve(col, row, b, lam)
+                assert relerr(x2[off:off + n], ref) <= TOL
+                assert relerr(x2[off:off + n], x1[off:off + n]) <= TOL
+                off += n
+    assert off == len(x2)
+
+
 def test_adaptive_refinement_batched(P):
     """Groups whose estimated error is still above the target after the
     mandatory refinement step take more steps, after being exchanged to the
