@@ -41,7 +41,11 @@
  * solution, bit 16 = after its last iterative refinement step the solve's
  * error estimate (see tikh_opts) is still above 1e-4: the refinement diverged or
  * barely converges, i.e. the recursion lost the solution (see fallback_nlim) or
- * the regularized system is too ill-conditioned for it (bits may combine).  Right-hand sides of one (problem, lambda) share
+ * the regularized system is too ill-conditioned for it, bit 32 = (prepared
+ * batches only) a recorded product transform length was too short for the
+ * call's basis degrees, the results are not valid and the batch must be
+ * prepared again, bit 64 = (prepared batches only) the solve's lambda was not
+ * positive and finite: it was solved with lambda = 1 (bits may combine).  Right-hand sides of one (problem, lambda) share
  * a pivot sequence, so bits 1, 2 and 4 of a forward solve are those of its
  * (problem, lambda); bit 8 is the solve's own.
  * Single-problem calls synchronize the stream and return TIKH_ENUMERIC when
@@ -332,6 +336,45 @@ int tikh_toeplitz_solve_backward_batched(int64_t nprob, const int64_t* m, const 
                                          const void* gx, void* g_col, void* g_row,
                                          void* g_b, double* g_lambda,
                                          int32_t* info, int complex_data);
+
+/*
+ * Prepared batches (Alg. 1 run as a fixed launch schedule; for callers that replay the
+ * same batch many times, e.g. a training step captured into a graph).  A prepare call
+ * takes the arguments of tikh_toeplitz_solve_batched (or of the batched backward) with
+ * one difference: `lambdas` is a DEVICE array [nprob * nlam] that every run reads, so
+ * the caller may change the values between runs (or inside a captured graph).  It
+ * plans the batch, allocates the batch's own workspace (tikh_prepared_workspace), uploads
+ * the descriptors and runs the batch once, synchronously, recording the product
+ * transform lengths for degrees 1/8 + 8 above the ones met (outputs and info of that
+ * run are valid).  The pointer arguments (col, row, b, x, gx, outputs, info, lambdas)
+ * are kept: they must stay valid and in place for the handle's lifetime.
+ *
+ * tikh_prepared_run enqueues the batch on the library stream (tikh_set_stream) with
+ * kernel launches and stream/event ordering only: no host synchronization, no
+ * allocation, no copy from host memory, so the call may be captured into a hipGraph.
+ * Every solve takes `refine` refinement steps (the adaptive steps, the fallback
+ * re-solve and the deferral of difficult points are not available: info bits stand as
+ * set; defer_tol > 0 at prepare time gives TIKH_EINVAL).  The options in force at
+ * prepare time apply to every run.  A lambda that is not positive and finite gives
+ * info bit 64 for its solves.  Degrees beyond the recorded lengths give info bit 32.
+ * Runs of one handle must not overlap; handles are independent of each other and of
+ * the other entry points, except that tikh_release invalidates every handle (its runs
+ * return TIKH_EINVAL; tikh_prepared_free still frees it).
+ */
+typedef struct tikh_prepared tikh_prepared;
+int tikh_prepare_batched(int64_t nprob, const int64_t* m, const int64_t* n,
+                         const void* col, const void* row, int64_t nlam,
+                         const double* lambdas /* device */, int64_t nrhs, const void* b,
+                         void* x, int32_t* info, int complex_data, tikh_prepared** handle);
+int tikh_prepare_backward_batched(int64_t nprob, const int64_t* m, const int64_t* n,
+                                  const void* col, const void* row, int64_t nlam,
+                                  const double* lambdas /* device */, int64_t nrhs,
+                                  const void* b, const void* x, const void* gx,
+                                  void* g_col, void* g_row, void* g_b, double* g_lambda,
+                                  int32_t* info, int complex_data, tikh_prepared** handle);
+int tikh_prepared_run(tikh_prepared* handle);
+int tikh_prepared_workspace(const tikh_prepared* handle, size_t* bytes);  /* host pointer */
+int tikh_prepared_free(tikh_prepared* handle);   /* synchronizes the device; NULL is a no-op */
 
 #ifdef __cplusplus
 }

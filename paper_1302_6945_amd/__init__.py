@@ -18,7 +18,9 @@ from ._lib import (TikhError, lib, library_path, set_options, get_options, get_s
                    gramian_solve_batched,
                    tikh_toeplitz_solve_backward, tikh_toeplitz_solve_backward_z,
                    tikh_toeplitz_solve_backward_batched, solve, solve_normal, solve_batched,
-                   backward, backward_batched, workspace_bytes, set_workspace)
+                   backward, backward_batched, workspace_bytes, set_workspace,
+                   PreparedBatch, prepare_batched, prepare_backward_batched,
+                   tikh_prepare_batched, tikh_prepare_backward_batched, tikh_prepared_run, tikh_prepared_free)
 from .autograd import ToeplitzTikhonov, tikhonov_solve
 
 __all__ = ["workspace_bytes", "set_workspace", "TikhError", "lib", "library_path", "set_options", "get_options", "get_stats", "plan_info", "fft_batched", "autotune_nlim", "profile_kernel", "profile_read",
@@ -29,4 +31,6 @@ __all__ = ["workspace_bytes", "set_workspace", "TikhError", "lib", "library_path
            "gramian_solve_batched",
            "tikh_toeplitz_solve_backward", "tikh_toeplitz_solve_backward_z",
            "tikh_toeplitz_solve_backward_batched", "solve", "solve_normal", "solve_batched",
-           "backward", "backward_batched", "ToeplitzTikhonov", "tikhonov_solve"]
+           "backward", "backward_batched", "ToeplitzTikhonov", "tikhonov_solve",
+           "PreparedBatch", "prepare_batched", "prepare_backward_batched", "tikh_prepare_batched",
+           "tikh_prepare_backward_batched", "tikh_prepared_run", "tikh_prepared_free"]

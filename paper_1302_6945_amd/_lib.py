@@ -76,6 +76,14 @@ tikh_toeplitz_solve_backward_z = _sig("tikh_toeplitz_solve_backward_z",
 tikh_toeplitz_solve_backward_batched = _sig("tikh_toeplitz_solve_backward_batched",
                                             [_I64, _P, _P, _P, _P, _I64, _P, _I64, _P, _P, _P, _P, _P, _P, _P,
                                              _P, ctypes.c_int])
+tikh_prepare_batched = _sig("tikh_prepare_batched", [_I64, _P, _P, _P, _P, _I64, _P, _I64, _P, _P, _P, ctypes.c_int,
+                                                     ctypes.POINTER(ctypes.c_void_p)])
+tikh_prepare_backward_batched = _sig("tikh_prepare_backward_batched",
+                                     [_I64, _P, _P, _P, _P, _I64, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P,
+                                      ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)])
+tikh_prepared_run = _sig("tikh_prepared_run", [_P])
+tikh_prepared_workspace = _sig("tikh_prepared_workspace", [_P, ctypes.POINTER(ctypes.c_size_t)])
+tikh_prepared_free = _sig("tikh_prepared_free", [_P])
 
 
 class TikhError(RuntimeError):
@@ -359,3 +367,96 @@ def backward_batched(ms, ns, col, row, lambdas, nrhs, b, x, gx, complex_data=Fal
                                                 _ptr(g_b), _ptr(g_lam), _ptr(info), 1 if complex_data else 0),
            "tikh_toeplitz_solve_backward_batched")
     return g_col, g_row, g_b, g_lam, info
+
+
+class PreparedBatch:
+    """A prepared batch (tikh_prepare_batched / tikh_prepare_backward_batched): the batch's
+    plan, workspace and recorded transform lengths are fixed once; run() enqueues it on the
+    current stream with kernel launches only, so it can be captured into a CUDA/HIP graph
+    (torch.cuda.graph).  The lambdas are read from the device tensor `lam` at every run.
+    The tensors passed in are kept referenced for the handle's lifetime; the outputs are
+    the attributes x/info (forward) or g_col/g_row/g_b/g_lam/info (backward)."""
+
+    def __init__(self, handle, keep, outputs):
+        self._h = handle
+        self._keep = keep
+        for k, v in outputs.items():
+            setattr(self, k, v)
+
+    def run(self):
+        if self._h is None:
+            raise TikhError(-1, "tikh_prepared_run (freed handle)")
+        _stream()
+        _check(tikh_prepared_run(self._h), "tikh_prepared_run")
+
+    def workspace_bytes(self):
+        out = ctypes.c_size_t()
+        _check(tikh_prepared_workspace(self._h, ctypes.byref(out)), "tikh_prepared_workspace")
+        return out.value
+
+    def free(self):
+        if self._h is not None:
+            tikh_prepared_free(self._h)
+            self._h = None
+            self._keep = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def _lam_dev(lam, nvals):
+    if not isinstance(lam, torch.Tensor) or not lam.is_cuda or lam.dtype != torch.float64 or not lam.is_contiguous():
+        raise TypeError("expected a contiguous float64 HIP device tensor of lambdas")
+    if lam.numel() != nvals:
+        raise ValueError("expected %d lambdas, got %d" % (nvals, lam.numel()))
+    return lam
+
+
+def prepare_batched(ms, ns, col, row, lam, nrhs, b, complex_data=False):
+    """Prepared forward batch: like solve_batched, with the lambdas in the device tensor
+    `lam` [nprob*nlam].  Runs the batch once (synchronously); returns a PreparedBatch whose
+    x/info hold the results of every run."""
+    dt = torch.complex128 if complex_data else torch.float64
+    nprob = len(ms)
+    nlam = lam.numel() // max(nprob, 1)
+    lam = _lam_dev(lam, nprob * nlam)
+    col, row, b = _dev(col, dt), _dev(row, dt), _dev(b, dt)
+    x = torch.empty(sum(nlam * nrhs * int(n) for n in ns), dtype=dt, device=col.device)
+    info = torch.zeros(nprob * nlam * nrhs, dtype=torch.int32, device=col.device)
+    h = ctypes.c_void_p()
+    mm, nn = _i64(ms), _i64(ns)
+    _stream()
+    _check(tikh_prepare_batched(nprob, mm, nn, _ptr(col), _ptr(row), nlam, _ptr(lam), int(nrhs), _ptr(b), _ptr(x),
+                                _ptr(info), 1 if complex_data else 0, ctypes.byref(h)), "tikh_prepare_batched")
+    return PreparedBatch(h, (col, row, b, lam, mm, nn), dict(x=x, info=info))
+
+
+def prepare_backward_batched(ms, ns, col, row, lam, nrhs, b, x, gx, complex_data=False):
+    """Prepared backward batch: like backward_batched, with the lambdas in the device tensor
+    `lam`; x and gx are read at every run (the caller updates them in place)."""
+    dt = torch.complex128 if complex_data else torch.float64
+    nprob = len(ms)
+    nlam = lam.numel() // max(nprob, 1)
+    lam = _lam_dev(lam, nprob * nlam)
+    col, row, b = _dev(col, dt), _dev(row, dt), _dev(b, dt)
+    for t in (x, gx):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dt or not t.is_contiguous():
+            raise TypeError("x and gx must be contiguous device tensors of the batch's dtype (kept in place)")
+    nsol = nprob * nlam * nrhs
+    g_col = torch.empty(sum(nlam * nrhs * int(m) for m in ms), dtype=dt, device=col.device)
+    g_row = torch.empty(sum(nlam * nrhs * int(n) for n in ns), dtype=dt, device=col.device)
+    g_b = torch.empty(sum(nlam * nrhs * int(m) for m in ms), dtype=dt, device=col.device)
+    g_lam = torch.empty(nsol, dtype=torch.float64, device=col.device)
+    info = torch.zeros(nsol, dtype=torch.int32, device=col.device)
+    h = ctypes.c_void_p()
+    mm, nn = _i64(ms), _i64(ns)
+    _stream()
+    _check(tikh_prepare_backward_batched(nprob, mm, nn, _ptr(col), _ptr(row), nlam, _ptr(lam), int(nrhs), _ptr(b),
+                                         _ptr(x), _ptr(gx), _ptr(g_col), _ptr(g_row), _ptr(g_b), _ptr(g_lam),
+                                         _ptr(info), 1 if complex_data else 0, ctypes.byref(h)),
+           "tikh_prepare_backward_batched")
+    return PreparedBatch(h, (col, row, b, lam, x, gx, mm, nn), dict(g_col=g_col, g_row=g_row, g_b=g_b, g_lam=g_lam,
+                                                                   info=info))

@@ -65,6 +65,8 @@ struct Ctx {
     Sizes* cur_sizes = nullptr;          // entry of the running chunk (nullptr: read back every merge)
     bool replay = false;                 // the running recursion takes its lengths from cur_sizes
     int* overflow = nullptr;             // device flag of the running chunk
+    bool headroom = false;               // record lengths for degrees 1/8 + 8 above the ones read back
+    int64_t generation = 0;              // counts tikh_release calls (prepared batches hold tables of one)
     int64_t syncs = 0;                   // host synchronizations of the last call
     std::vector<hipStream_t> pool;       // streams of chunks run side by side
     std::vector<hipEvent_t> events;      // their fork and join events
@@ -743,8 +745,10 @@ static int run_product_chunk(const Plan& pl, const Layout& L, const Bufs& b, int
         if (P > pl.P[dp]) P = pl.P[dp];
         if (g.cur_sizes) {
             int64_t& rec = g.cur_sizes->P[site];
-            const int64_t keep = g.opts.record_short ? smallest_divisor_geq(pl.Q, std::max<int64_t>(1, need / 2)) : P;
-            rec = std::max(rec, std::min(keep, P));
+            int64_t keep = g.opts.record_short ? smallest_divisor_geq(pl.Q, std::max<int64_t>(1, need / 2)) : P;
+            if (g.headroom && !g.opts.record_short)
+                keep = std::min(pl.P[dp], smallest_divisor_geq(pl.Q, need + need / 8 + 8));
+            rec = std::max(rec, g.headroom ? keep : std::min(keep, P));
         }
     }
     const int64_t cp1 = pl.cap[dc] + 1;
@@ -953,6 +957,7 @@ struct ChunkRun {
     int64_t S = 0, G = 0, Ga = 0, Sa = 0, mmax = 1, nmax = 1;
     bool gramian = false, replayed = false, done = false;
     int steps_min = 1, steps_max = 1, it = 0;
+    bool fixed_steps = false;            // prepared batches: no adaptive steps (no host decisions)
     Ctx::Sizes* sizes = nullptr;
     std::vector<SolveDesc> failed;       // descriptors of the groups whose solve failed
 };
@@ -1061,28 +1066,47 @@ static int chunk_step(ChunkRun& r, int it) {
 
 // Uploads the chunk, builds its symbols and right-hand sides and runs the steps every
 // group takes (the solve and `refine` refinement steps).  Device work goes to r.stream.
+// Carves the chunk's buffers from its workspace region and uploads its descriptors.
+static int chunk_upload(ChunkRun& r) {
+    const Plan& pl = r.pl;
+    const int nr = r.nr;
+    r.S = (int64_t)r.sds.size();
+    r.G = r.S / nr;
+    int rc = carve_bufs(pl, r.L, r.G, std::min<int64_t>(r.G, r.mchunk), r.base, &r.b);
+    if (rc) return rc;
+    r.tw = twiddles(pl.Q);
+    if (!r.tw) return TIKH_ENOMEM;
+    const EList el = make_elist(nr);
+    HIPCHK(hipMemcpyAsync(r.b.sd, r.sds.data(), sizeof(SolveDesc) * r.S, hipMemcpyHostToDevice, g.stream));
+    HIPCHK(hipMemcpyAsync(r.b.elist, &el, sizeof(EList), hipMemcpyHostToDevice, g.stream));
+    return TIKH_OK;
+}
+
+static int chunk_setup(ChunkRun& r);
+
 static int chunk_begin(ChunkRun& r) {
+    int rc = chunk_upload(r);
+    if (rc) return rc;
+    if (g.sizes.size() > 4096) g.sizes.clear();   // bound the record over many compositions
+    r.sizes = r.use_sizes ? &g.sizes[sizes_key(r.pl, r.nr, r.sds)] : nullptr;
+    return chunk_setup(r);
+}
+
+// Builds the uploaded chunk's symbols and right-hand sides and runs the steps every
+// group takes; only kernel launches unless transform lengths are read back (a first
+// call of a composition).
+static int chunk_setup(ChunkRun& r) {
     const Plan& pl = r.pl;
     const int nr = r.nr;
     const std::vector<SolveDesc>& sds = r.sds;
-    r.S = (int64_t)sds.size();
-    r.G = r.S / nr;
     const int64_t S = r.S, G = r.G;
-    int rc = carve_bufs(pl, r.L, G, std::min<int64_t>(G, r.mchunk), r.base, &r.b);
-    if (rc) return rc;
+    int rc = TIKH_OK;
     const Layout& L = r.L;
     Bufs& b = r.b;
-    r.tw = twiddles(pl.Q);
-    if (!r.tw) return TIKH_ENOMEM;
     const double2* tw = r.tw;
     const int64_t mmax = r.mmax, nmax = r.nmax;
-    const EList el = make_elist(nr);
-    HIPCHK(hipMemcpyAsync(b.sd, sds.data(), sizeof(SolveDesc) * S, hipMemcpyHostToDevice, g.stream));
-    HIPCHK(hipMemcpyAsync(b.elist, &el, sizeof(EList), hipMemcpyHostToDevice, g.stream));
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, g.stream, b.ovf, (int64_t)1);
     g.launches++;
-    if (g.sizes.size() > 4096) g.sizes.clear();   // bound the record over many compositions
-    r.sizes = r.use_sizes ? &g.sizes[sizes_key(pl, nr, sds)] : nullptr;
     g.cur_sizes = r.sizes;
     g.overflow = b.ovf;
     const int64_t N = pl.N;
@@ -1121,6 +1145,8 @@ static int chunk_begin(ChunkRun& r) {
     // all for the groups whose estimated error is still above refine_tol (chunk_adapt).
     r.steps_min = 1 + std::max(0, std::min(4, (int)g.opts.refine));
     r.steps_max = g.opts.refine > 0 ? std::max(r.steps_min, 1 + std::min(4, (int)g.opts.refine_max)) : r.steps_min;
+    if (r.fixed_steps) r.steps_max = r.steps_min;
+    r.done = false;
     r.Ga = G;
     r.Sa = S;
     for (r.it = 0; r.it < r.steps_min; ++r.it) {
@@ -1452,9 +1478,10 @@ static int run_solves(std::vector<SolveDesc>& sds, int nr, int32_t* info) {
     return rc;
 }
 
-static int run_solves_core(std::vector<SolveDesc>& sds, int nr, int32_t* info,
-                           std::vector<SolveDesc>* failed) {
-    if (sds.empty()) return TIKH_OK;
+// The chunks of a call: solves grouped by plan (extended sizes merged within merge_tol),
+// each plan's groups in equal chunks that fit the budget (and chunk_groups).
+static int make_runs(std::vector<SolveDesc>& sds, int nr, int32_t* info, size_t budget,
+                     std::vector<std::unique_ptr<ChunkRun>>& runs) {
     if (nr != 1 && nr != 2 && nr != 4) return TIKH_EINVAL;
     const int64_t G = (int64_t)sds.size() / nr;
     std::map<int64_t, std::vector<int64_t>> buckets;     // N -> group indices
@@ -1487,15 +1514,6 @@ static int run_solves_core(std::vector<SolveDesc>& sds, int nr, int32_t* info,
         }
         buckets.swap(merged);
     }
-    size_t budget;
-    if (g.ws_ext) {
-        budget = g.ws_size > WS_FIXED ? g.ws_size - WS_FIXED : 0;
-    } else {
-        size_t freeb = 0, totb = 0;
-        (void)hipMemGetInfo(&freeb, &totb);
-        budget = std::max<size_t>((size_t)1 << 30, (size_t)((double)(freeb + g.ws_size) * 0.85)) - WS_FIXED;
-    }
-    std::vector<std::unique_ptr<ChunkRun>> runs;
     for (auto& kv : buckets) {
         Plan pl;
         if (!make_plan(kv.first, shapes[kv.first].first, shapes[kv.first].second, &pl)) return TIKH_EINVAL;
@@ -1533,6 +1551,25 @@ static int run_solves_core(std::vector<SolveDesc>& sds, int nr, int32_t* info,
             g.stats.depth = pl.p;
             g.stats.leaf_nodes = (int32_t)pl.M;
         }
+    }
+    return TIKH_OK;
+}
+
+static int run_solves_core(std::vector<SolveDesc>& sds, int nr, int32_t* info,
+                           std::vector<SolveDesc>* failed) {
+    if (sds.empty()) return TIKH_OK;
+    size_t budget;
+    if (g.ws_ext) {
+        budget = g.ws_size > WS_FIXED ? g.ws_size - WS_FIXED : 0;
+    } else {
+        size_t freeb = 0, totb = 0;
+        (void)hipMemGetInfo(&freeb, &totb);
+        budget = std::max<size_t>((size_t)1 << 30, (size_t)((double)(freeb + g.ws_size) * 0.85)) - WS_FIXED;
+    }
+    std::vector<std::unique_ptr<ChunkRun>> runs;
+    {
+        int rc0 = make_runs(sds, nr, info, budget, runs);
+        if (rc0) return rc0;
     }
     int rc = (runs.size() > 1 && !g.noalloc && g.opts.streams > 1) ? run_concurrent(runs, budget + WS_FIXED)
                                                                     : TIKH_OK;
@@ -1801,6 +1838,7 @@ int tikh_release(void) {
     for (auto& kv : g.tw2) (void)hipFree(kv.second);
     g.tw2.clear();
     g.sizes.clear();
+    g.generation++;
     for (hipStream_t st : g.pool) (void)hipStreamDestroy(st);
     g.pool.clear();
     for (hipEvent_t e : g.events) (void)hipEventDestroy(e);
@@ -1879,6 +1917,7 @@ static int batched_sds(int64_t nprob, const int64_t* m, const int64_t* n, const 
                     d.col = (const char*)col + es * co;
                     d.row = (const char*)row + es * ro;
                     d.m = m[p]; d.n = n[p]; d.lam = lam; d.cplx = complex_data ? 1 : 0; d.mode = 0;
+                    d.lamx = (int32_t)(p * nlam + l);
                     if (r < nrhs) {
                         d.rhs = (const char*)b + es * (bo + r * m[p]);
                         d.x = (char*)x + es * (xo + (l * nrhs + r) * n[p]);
@@ -2079,17 +2118,13 @@ int tikh_toeplitz_solve_backward_z(const tikh_c64* col, const tikh_c64* row, int
     return backward_single(col, row, m, n, b, lambda, x, gx, g_col, g_row, g_b, g_lambda, 1);
 }
 
-int tikh_toeplitz_solve_backward_batched(int64_t nprob, const int64_t* m, const int64_t* n, const void* col,
-                                         const void* row, int64_t nlam, const double* lambdas, int64_t nrhs,
-                                         const void* b, const void* x, const void* gx, void* g_col, void* g_row,
-                                         void* g_b, double* g_lambda, int32_t* info, int complex_data) {
-    ensure_init();
-    if (nprob < 0 || nlam < 1 || nrhs < 1 || !m || !n || !lambdas) return TIKH_EINVAL;
-    if (nprob == 0) return TIKH_OK;
+static int backward_sds(int64_t nprob, const int64_t* m, const int64_t* n, const void* col, const void* row,
+                        int64_t nlam, const double* lambdas, int64_t nrhs, const void* b, const void* x,
+                        const void* gx, void* g_col, void* g_row, void* g_b, double* g_lambda, int complex_data,
+                        std::vector<SolveDesc>& sds) {
     if (!col || !row || !b || !x || !gx || !g_col || !g_row || !g_b || !g_lambda) return TIKH_EINVAL;
     const size_t es = complex_data ? sizeof(double2) : sizeof(double);
     const int nr = group_size(nrhs);
-    std::vector<SolveDesc> sds;
     int64_t co = 0, ro = 0, bo = 0, xo = 0, gco = 0, gro = 0, gbo = 0, si = 0;
     for (int64_t p = 0; p < nprob; ++p) {
         if (m[p] < 1 || n[p] < 1) return TIKH_EINVAL;
@@ -2102,6 +2137,7 @@ int tikh_toeplitz_solve_backward_batched(int64_t nprob, const int64_t* m, const 
                     d.col = (const char*)col + es * co;
                     d.row = (const char*)row + es * ro;
                     d.m = m[p]; d.n = n[p]; d.lam = lam; d.cplx = complex_data ? 1 : 0; d.mode = 1; d.backward = 1;
+                    d.lamx = (int32_t)(p * nlam + l);
                     if (r < nrhs) {
                         const int64_t u = l * nrhs + r;
                         d.bin = (const char*)b + es * (bo + r * m[p]);
@@ -2122,7 +2158,215 @@ int tikh_toeplitz_solve_backward_batched(int64_t nprob, const int64_t* m, const 
         co += m[p]; ro += n[p]; bo += nrhs * m[p]; xo += nlam * nrhs * n[p];
         gco += nlam * nrhs * m[p]; gro += nlam * nrhs * n[p]; gbo += nlam * nrhs * m[p]; si += nlam * nrhs;
     }
-    return run_solves(sds, nr, info);
+    return TIKH_OK;
+}
+
+int tikh_toeplitz_solve_backward_batched(int64_t nprob, const int64_t* m, const int64_t* n, const void* col,
+                                         const void* row, int64_t nlam, const double* lambdas, int64_t nrhs,
+                                         const void* b, const void* x, const void* gx, void* g_col, void* g_row,
+                                         void* g_b, double* g_lambda, int32_t* info, int complex_data) {
+    ensure_init();
+    if (nprob < 0 || nlam < 1 || nrhs < 1 || !m || !n || !lambdas) return TIKH_EINVAL;
+    if (nprob == 0) return TIKH_OK;
+    std::vector<SolveDesc> sds;
+    int rc = backward_sds(nprob, m, n, col, row, nlam, lambdas, nrhs, b, x, gx, g_col, g_row, g_b, g_lambda,
+                          complex_data, sds);
+    if (rc) return rc;
+    return run_solves(sds, group_size(nrhs), info);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- prepared batches
+// A prepared batch fixes a call's composition once: its chunks, their workspace regions
+// and uploaded descriptors, and the product transform lengths recorded (with headroom)
+// by a first run.  Every later run takes the lambdas from the caller's device array and
+// enqueues kernel launches and stream/event ordering only (no host synchronization,
+// allocation or copy from host memory), so that a caller can capture a run into a graph
+// and replay it.
+struct tikh_prepared {
+    std::vector<std::unique_ptr<tikh::ChunkRun>> runs;
+    std::vector<std::unique_ptr<tikh::Ctx::Sizes>> sizes;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    const double* dlam = nullptr;
+    int32_t* info = nullptr;
+    tikh_opts opts{};
+    int64_t generation = 0;
+};
+
+namespace tikh {
+
+// restores the library's options, stream and recording mode however a prepared run ends
+struct PreparedScope {
+    tikh_opts opts;
+    hipStream_t stream;
+    explicit PreparedScope(const tikh_opts& o) : opts(g.opts), stream(g.stream) { g.opts = o; }
+    ~PreparedScope() {
+        g.opts = opts;
+        g.stream = stream;
+        g.cur_sizes = nullptr;
+        g.headroom = false;
+        g.replay = false;
+    }
+};
+
+// Enqueues one run of every chunk, side by side on the stream pool (forked from and joined
+// back into the library stream by events).  The first run records the transform lengths.
+static int prepared_enqueue(tikh_prepared* h, bool first) {
+    PreparedScope scope(h->opts);
+    g.launches = 0;
+    g.syncs = 0;
+    const hipStream_t user = g.stream;
+    const int nuse = (int)std::min<size_t>(h->runs.size(), (size_t)std::max(1, std::min((int)g.opts.streams, 16)));
+    if ((int)g.pool.size() < nuse || g.events.size() < (size_t)nuse + 1) return TIKH_EINVAL;
+    HIPCHK(hipEventRecord(g.events[nuse], user));
+    for (int i = 0; i < nuse; ++i) HIPCHK(hipStreamWaitEvent(g.pool[i], g.events[nuse], 0));
+    g.headroom = first;
+    for (size_t i = 0; i < h->runs.size(); ++i) {
+        ChunkRun& r = *h->runs[i];
+        r.stream = g.pool[i % (size_t)nuse];
+        chunk_enter(r);
+        hipLaunchKernelGGL(k_set_lam, dim3((unsigned)((r.S + 255) / 256)), dim3(256), 0, g.stream, r.b.sd, r.S,
+                           h->dlam);
+        g.launches++;
+        int rc = chunk_setup(r);
+        while (rc == TIKH_OK && !r.done) rc = chunk_adapt(r);
+        if (rc == TIKH_OK) rc = chunk_finish(r);
+        if (rc) return rc;
+        if (h->info) {
+            hipLaunchKernelGGL(k_prepared_info, dim3((unsigned)((r.S + 255) / 256)), dim3(256), 0, g.stream, r.b.sd,
+                               r.S, r.b.ovf, h->dlam, h->info);
+            g.launches++;
+        }
+    }
+    for (int i = 0; i < nuse; ++i) {
+        HIPCHK(hipEventRecord(g.events[i], g.pool[i]));
+        HIPCHK(hipStreamWaitEvent(user, g.events[i], 0));
+    }
+    HIPCHK(hipGetLastError());
+    g.stats.launches = g.launches;
+    g.stats.host_syncs = g.syncs;
+    return TIKH_OK;
+}
+
+static int prepare(std::vector<SolveDesc>& sds, int nr, const double* dlam, int64_t nlamtot, int32_t* info,
+                   tikh_prepared** out) {
+    if (!out || !dlam) return TIKH_EINVAL;
+    *out = nullptr;
+    if (g.opts.defer_tol > 0.0) return TIKH_EINVAL;     // deferral reads its counts back
+    if (sds.empty()) return TIKH_EINVAL;
+    // the lambdas the batch is planned and first run with
+    std::vector<double> hl((size_t)nlamtot);
+    HIPCHK(hipMemcpyAsync(hl.data(), dlam, sizeof(double) * nlamtot, hipMemcpyDeviceToHost, g.stream));
+    HIPCHK(hipStreamSynchronize(g.stream));
+    for (SolveDesc& d : sds) {
+        if (d.lamx < 0 || d.lamx >= nlamtot || bad_lambda(hl[(size_t)d.lamx])) return TIKH_EINVAL;
+        d.lam = hl[(size_t)d.lamx];
+    }
+    std::unique_ptr<tikh_prepared> h(new tikh_prepared());
+    h->opts = g.opts;
+    h->dlam = dlam;
+    h->info = info;
+    h->generation = g.generation;
+    size_t freeb = 0, totb = 0;
+    (void)hipMemGetInfo(&freeb, &totb);
+    const size_t budget = std::max<size_t>((size_t)1 << 30, (size_t)((double)freeb * 0.85)) - WS_FIXED;
+    int rc = make_runs(sds, nr, info, budget, h->runs);
+    if (rc) return rc;
+    size_t total = 0;
+    for (auto& r : h->runs) total += (chunk_run_bytes(*r) + 255) & ~(size_t)255;
+    if (total > budget + WS_FIXED) return TIKH_ENOMEM;   // every chunk keeps its own region
+    if (hipMalloc(&h->ws, total) != hipSuccess) return TIKH_ENOMEM;
+    h->ws_bytes = total;
+    const int nstreams = std::max(1, std::min((int)g.opts.streams, 16));
+    while ((int)g.pool.size() < nstreams) {
+        hipStream_t st;
+        HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        g.pool.push_back(st);
+    }
+    while (g.events.size() < (size_t)nstreams + 1) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        g.events.push_back(e);
+    }
+    size_t off = 0;
+    for (auto& rp : h->runs) {
+        ChunkRun& r = *rp;
+        r.base = h->ws + off;
+        off += (chunk_run_bytes(r) + 255) & ~(size_t)255;
+        r.fixed_steps = true;
+        r.stream = g.stream;
+        h->sizes.emplace_back(new Ctx::Sizes());
+        r.sizes = h->sizes.back().get();
+        rc = chunk_upload(r);
+        if (rc) break;
+    }
+    g.cur_sizes = nullptr;
+    if (rc == TIKH_OK) rc = prepared_enqueue(h.get(), true);
+    if (rc == TIKH_OK) HIPCHK(hipStreamSynchronize(g.stream));
+    if (rc) {
+        (void)hipStreamSynchronize(g.stream);
+        (void)hipFree(h->ws);
+        return rc;
+    }
+    *out = h.release();
+    return TIKH_OK;
+}
+
+}  // namespace tikh
+
+extern "C" {
+
+int tikh_prepare_batched(int64_t nprob, const int64_t* m, const int64_t* n, const void* col, const void* row,
+                         int64_t nlam, const double* lambdas, int64_t nrhs, const void* b, void* x, int32_t* info,
+                         int complex_data, tikh_prepared** handle) {
+    ensure_init();
+    if (!handle) return TIKH_EINVAL;
+    *handle = nullptr;
+    if (nprob < 1 || nlam < 1 || nrhs < 1 || !m || !n || !lambdas) return TIKH_EINVAL;
+    // the descriptors are built with a placeholder lambda; the device array supplies them
+    std::vector<double> one((size_t)(nprob * nlam), 1.0);
+    std::vector<SolveDesc> sds;
+    int rc = batched_sds(nprob, m, n, col, row, nlam, one.data(), nrhs, b, x, complex_data, sds);
+    if (rc) return rc;
+    return prepare(sds, group_size(nrhs), lambdas, nprob * nlam, info, handle);
+}
+
+int tikh_prepare_backward_batched(int64_t nprob, const int64_t* m, const int64_t* n, const void* col,
+                                  const void* row, int64_t nlam, const double* lambdas, int64_t nrhs, const void* b,
+                                  const void* x, const void* gx, void* g_col, void* g_row, void* g_b,
+                                  double* g_lambda, int32_t* info, int complex_data, tikh_prepared** handle) {
+    ensure_init();
+    if (!handle) return TIKH_EINVAL;
+    *handle = nullptr;
+    if (nprob < 1 || nlam < 1 || nrhs < 1 || !m || !n || !lambdas) return TIKH_EINVAL;
+    std::vector<double> one((size_t)(nprob * nlam), 1.0);
+    std::vector<SolveDesc> sds;
+    int rc = backward_sds(nprob, m, n, col, row, nlam, one.data(), nrhs, b, x, gx, g_col, g_row, g_b, g_lambda,
+                          complex_data, sds);
+    if (rc) return rc;
+    return prepare(sds, group_size(nrhs), lambdas, nprob * nlam, info, handle);
+}
+
+int tikh_prepared_run(tikh_prepared* handle) {
+    ensure_init();
+    if (!handle || handle->generation != g.generation) return TIKH_EINVAL;
+    return prepared_enqueue(handle, false);
+}
+
+int tikh_prepared_workspace(const tikh_prepared* handle, size_t* bytes) {
+    if (!handle || !bytes) return TIKH_EINVAL;
+    *bytes = handle->ws_bytes;
+    return TIKH_OK;
+}
+
+int tikh_prepared_free(tikh_prepared* handle) {
+    if (!handle) return TIKH_OK;
+    (void)hipDeviceSynchronize();
+    (void)hipFree(handle->ws);
+    delete handle;
+    return TIKH_OK;
 }
 
 }  // extern "C"

@@ -43,14 +43,15 @@ struct SolveDesc {
     // (p x n), gram the first column of the Hermitian Toeplitz Gramian G (n entries)
     const void* gram;
     int32_t gramian;
-    int32_t pad_;
+    int32_t lamx;      // index of this solve's lambda in the caller's array (problem * nlam + lambda)
 };
 
 // Per-group running state of the recursion.
 struct SolveState {
     int32_t delta[4];  // tau-degrees of basis columns 1..4 (column 5 stays 0)
     int32_t info;      // 0 ok; or of bits 1 breakdown, 2 degree bound, 4 too many deferred conditions, 8 non-finite,
-                       // 16 refinement estimate above its target after the last step
+                       // 16 refinement estimate above its target after the last step, 32 recorded
+                       // transform length too short, 64 invalid lambda (prepared batches)
     int32_t ndef;      // deferred (difficult) conditions of the current solve
     int32_t wide;      // set by the narrow pass of a two-pass kernel: this group is left to the wide pass
     double e0;         // relative size of the first refinement correction (error estimate of the first solve)

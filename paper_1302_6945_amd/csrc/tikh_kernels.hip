@@ -2195,6 +2195,28 @@ __global__ void k_clear_info(const SolveDesc* __restrict__ sd, int64_t S, int32_
     if (s < S && sd[s].rhs) info[sd[s].orig] = 0;
 }
 
+// Prepared batches: every solve takes its lambda from the caller's device array; a value
+// that is not positive and finite is replaced by 1 (finite arithmetic throughout; the
+// solve is flagged by k_prepared_info).
+__global__ void k_set_lam(SolveDesc* __restrict__ sd, int64_t S, const double* __restrict__ lam) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    const double v = lam[sd[s].lamx];
+    sd[s].lam = (v > 0.0 && isfinite(v)) ? v : 1.0;
+}
+
+// Prepared batches, after the results are stored: bit 32 when a recorded transform length
+// was too short for this call's degrees, bit 64 when the solve's lambda was not positive
+// and finite.
+__global__ void k_prepared_info(const SolveDesc* __restrict__ sd, int64_t S, const int* __restrict__ ovf,
+                                const double* __restrict__ lam, int32_t* __restrict__ info) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S || sd[s].orig < 0) return;
+    const double v = lam[sd[s].lamx];
+    const int32_t bits = (*ovf ? 32 : 0) | ((v > 0.0 && isfinite(v)) ? 0 : 64);
+    if (bits) info[sd[s].orig] |= bits;
+}
+
 // Stores x and the solve's info word: the group's bits other than the non-finite
 // bit (the right-hand sides of a group share the pivot sequence), and the
 // non-finite bit (8) from this solve's own entries.
