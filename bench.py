@@ -281,6 +281,81 @@ def config2_leg(P, torch, W, steps, with_oracle):
     return out
 
 
+def config4_leg(P, torch, W, steps, with_oracle):
+    """Bilevel lambda tuning at full size: 256 deblurring problems (Gaussian PSF, sigma in
+    [4, 48], n log-uniform in [2^12, 2^16], one right-hand side), each problem's log lambda by
+    `steps` Adam steps on a validation loss with an independent noise draw; one step (batched
+    forward, upstream gradient, batched backward, Adam update) captured into one graph and
+    replayed.  With the oracle: the first step's dL/dlambda of the three smallest problems
+    against the banded QR oracle (1e-7)."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    # the prepared batches hold workspaces of their own: return the library's shared one
+    P.set_workspace(None)
+    torch.cuda.empty_cache()
+    probs = [W.config4(i) for i in range(256)]
+    t_setup = time.perf_counter()
+    ms = [p.m for p in probs]
+    ns = [p.n for p in probs]
+    col = torch.tensor(np.concatenate([p.col for p in probs]), device=dev)
+    row = torch.tensor(np.concatenate([p.row for p in probs]), device=dev)
+    b = torch.tensor(np.concatenate([p.b[0] for p in probs]), device=dev)
+    bval = torch.tensor(np.concatenate([p.b[1] for p in probs]), device=dev)
+    lam0 = torch.tensor([p.lams[0] for p in probs], dtype=torch.float64, device=dev)
+    tuner = P.BilevelTuner(ms, ns, col, row, b, bval, lam0)
+    try:
+        torch.cuda.synchronize()
+        prepare_s = time.perf_counter() - t_setup
+        s0 = tuner.state()
+        t0 = time.perf_counter()
+        tuner.step()                                   # eager (the same launches, not captured)
+        torch.cuda.synchronize()
+        eager_s = time.perf_counter() - t0
+        tuner.set_state(s0)
+        t0 = time.perf_counter()
+        tuner.capture()
+        capture_s = time.perf_counter() - t0
+        loss0 = tuner.validation_loss()
+        grads0 = None
+        info_max = 0
+        t0 = time.perf_counter()
+        for k in range(steps):
+            tuner.step()
+            if k == 0:
+                grads0 = tuner.grad.clone()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / max(steps, 1)
+        fi, bi = tuner.info()
+        info_max = max(int(fi.max().item()), int(bi.max().item()))
+        tuner.step()                                   # forward solutions at the final lambdas
+        torch.cuda.synchronize()
+        loss1 = tuner.validation_loss()
+        lam = torch.exp(tuner.loglam).cpu().numpy()
+        out = {"workload": "256 deblurring problems, sigma U[4,48], n log-uniform 2^12..2^16, 1 rhs; Adam on "
+                           "log lambda (lr 0.1) on a validation loss; one captured graph per step",
+               "steps": steps, "ms_per_step": round(dt * 1e3, 1), "eager_ms_per_step": round(eager_s * 1e3, 1),
+               "solves_per_s": round(256 / dt, 1), "unit": "fwd+bwd solves/s", "prepare_s": round(prepare_s, 1),
+               "capture_s": round(capture_s, 1), "info_max": info_max,
+               "val_loss_initial": float(loss0.sum().item()), "val_loss_final": float(loss1.sum().item()),
+               "improved_frac": float((loss1 < loss0).double().mean().item()),
+               "lambda_range": [float(lam.min()), float(lam.max())]}
+        if with_oracle and grads0 is not None:
+            import oracle
+            g = grads0.cpu().numpy()
+            worst = 0.0
+            for i in sorted(range(256), key=lambda i: probs[i].n)[:3]:
+                p = probs[i]
+                x = oracle.band_solve(p.col, p.row, [p.b[0]], p.lams[0])[0]
+                gx = oracle.TH_apply(p.col, p.row, oracle.T_apply(p.col, p.row, x) - p.b[1]).real
+                want = p.lams[0] * oracle.band_gradients(p.col, p.row, p.b[0], p.lams[0], x, gx,
+                                                         with_lag_sums=False)["g_lam"]
+                worst = max(worst, float(abs(g[i] - want) / max(abs(want), 1e-300)))
+            out["parity"] = {"grads_checked": 3, "max_rel_err": worst, "tol": 1e-7, "ok": bool(worst <= 1e-7)}
+        return out
+    finally:
+        tuner.free()
+
+
 def measured_traffic(root, kernel, args, nlim):
     """HBM bytes per launch of `kernel` from the committed counter summary, when it was taken on
     the current sources, at this workload and leaf cutoff; None otherwise."""
@@ -332,6 +407,9 @@ def main():
     ap.add_argument("--config2-steps", type=int, default=2,
                     help="timed steps of the 1024-problem ragged batching workload reported beside the headline "
                          "(0 = skip)")
+    ap.add_argument("--config4-steps", type=int, default=20,
+                    help="Adam steps of the 256-problem bilevel lambda tuning workload reported beside the headline "
+                         "(one captured graph per step; 0 = skip)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="after the run, negate a float64 buffer of this many MiB into another three times "
                          "(a plain streaming kernel of known traffic that calibrates the HBM byte counters)")
@@ -503,6 +581,11 @@ def main():
     if args.config2_steps > 0:
         cfg2 = config2_leg(P, torch, W, args.config2_steps, not args.no_oracle)
         P.set_options(n_lim=nlim, refine=1)
+    cfg4 = None
+    if args.config4_steps > 0:
+        P.set_options(n_lim=256, refine=1)
+        cfg4 = config4_leg(P, torch, W, args.config4_steps, not args.no_oracle)
+        P.set_options(n_lim=nlim, refine=1)
 
     if args.copy_calib_mib > 0:
         src = torch.ones(args.copy_calib_mib * 2 ** 20 // 8, dtype=torch.float64, device=dev)
@@ -522,6 +605,9 @@ def main():
     if parity is not None and cfg2 is not None and "parity" in cfg2:
         parity["config2_ok"] = cfg2["parity"]["ok"] and cfg2["other_info"] == 0
         parity["ok"] = parity["ok"] and parity["config2_ok"]
+    if parity is not None and cfg4 is not None and "parity" in cfg4:
+        parity["config4_ok"] = cfg4["parity"]["ok"] and cfg4["info_max"] == 0
+        parity["ok"] = parity["ok"] and parity["config4_ok"]
     ok = parity is None or parity["ok"]
     out = {
         "metric": "batched regularized solves/s (fwd+bwd) at n=2^14 vs plain, rel err <= 1e-9",
@@ -551,6 +637,7 @@ def main():
         "kernel_ms_per_step": kernel_ms,
         "cpu_baseline": cpu,
         "config2": cfg2,
+        "config4": cfg4,
     }
     if not ok:
         out["unmeasured_reason"] = "parity gate failed: no value is reported"

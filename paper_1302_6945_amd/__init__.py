@@ -22,6 +22,7 @@ from ._lib import (TikhError, lib, library_path, set_options, get_options, get_s
                    PreparedBatch, prepare_batched, prepare_backward_batched,
                    tikh_prepare_batched, tikh_prepare_backward_batched, tikh_prepared_run, tikh_prepared_free)
 from .autograd import ToeplitzTikhonov, tikhonov_solve
+from .bilevel import BilevelTuner
 
 __all__ = ["workspace_bytes", "set_workspace", "TikhError", "lib", "library_path", "set_options", "get_options", "get_stats", "plan_info", "fft_batched", "autotune_nlim", "profile_kernel", "profile_read",
            "tikh_toeplitz_solve", "tikh_toeplitz_solve_z", "tikh_toeplitz_solve_normal",
@@ -33,4 +34,4 @@ __all__ = ["workspace_bytes", "set_workspace", "TikhError", "lib", "library_path
            "tikh_toeplitz_solve_backward_batched", "solve", "solve_normal", "solve_batched",
            "backward", "backward_batched", "ToeplitzTikhonov", "tikhonov_solve",
            "PreparedBatch", "prepare_batched", "prepare_backward_batched", "tikh_prepare_batched",
-           "tikh_prepare_backward_batched", "tikh_prepared_run", "tikh_prepared_free"]
+           "tikh_prepare_backward_batched", "tikh_prepared_run", "tikh_prepared_free", "BilevelTuner"]
