@@ -43,6 +43,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 
+_T_START = time.perf_counter()
+
+
+def progress(msg):
+    """A progress line on stderr (the JSON result is the only line on stdout)."""
+    print("bench: %s (%.0f s)" % (msg, time.perf_counter() - _T_START), file=sys.stderr, flush=True)
+
+
 def source_digest(root):
     """Digest of the kernel and driver sources: HBM counters taken on other sources do not apply."""
     import hashlib
@@ -306,6 +314,7 @@ def config4_leg(P, torch, W, steps, with_oracle):
     try:
         torch.cuda.synchronize()
         prepare_s = time.perf_counter() - t_setup
+        progress("bilevel batches prepared")
         s0 = tuner.state()
         t0 = time.perf_counter()
         tuner.step()                                   # eager (the same launches, not captured)
@@ -315,6 +324,7 @@ def config4_leg(P, torch, W, steps, with_oracle):
         t0 = time.perf_counter()
         tuner.capture()
         capture_s = time.perf_counter() - t0
+        progress("bilevel step captured")
         loss0 = tuner.validation_loss()
         grads0 = None
         info_max = 0
@@ -323,6 +333,9 @@ def config4_leg(P, torch, W, steps, with_oracle):
             tuner.step()
             if k == 0:
                 grads0 = tuner.grad.clone()
+            if k % 5 == 4:
+                torch.cuda.synchronize()
+                progress("bilevel step %d" % (k + 1))
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / max(steps, 1)
         fi, bi = tuner.info()
@@ -434,6 +447,7 @@ def main():
         P.set_options(refine=1)
         _, tune_ms = P.autotune_nlim(int(round(float(np.mean(ms)))), args.n, groups=256, nrhs=args.nrhs)
         nlim = pick_nlim(tune_ms)
+        progress("leaf cutoff autotuned: %d" % nlim)
         tune = {str(k): round(v, 1) for k, v in tune_ms.items()}
     else:
         nlim = int(args.nlim)
@@ -465,6 +479,7 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    progress("warmup done")
     stream = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -475,6 +490,7 @@ def main():
     torch.cuda.synchronize()
     ms_total = e0.elapsed_time(e1)
     ms_per_step = ms_total / args.steps
+    progress("timed steps done: %.0f ms per step" % ms_per_step)
     value = nsolve * args.steps / (ms_total / 1e3)
     info_max = int(max(info.max().item(), binfo.max().item()))
     x_timed = x.cpu().numpy()
@@ -495,6 +511,7 @@ def main():
         rl[kern] = (k_ms, k_count, units)
     P.profile_kernel(None)
     kernel_ms = {k: round(v[0], 1) for k, v in rl.items()}
+    progress("kernel timing done")
 
     # the method's algorithmic work per step, from each problem's plan
     alg_flops = alg_bytes = 0.0
@@ -568,6 +585,7 @@ def main():
             return g_col.cpu().numpy(), g_row.cpu().numpy(), g_b.cpu().numpy(), g_lam.cpu().numpy()
 
         cpu, parity = oracle_leg(probs, ip, args.nlam, args.nrhs, x_timed, run_backward, cores)
+        progress("oracle leg done")
         if args.residual_sample > 0:
             cnt, worst = residual_sample(probs, args.nlam, args.nrhs, x_timed, args.residual_sample)
             parity["residual_solves_checked"] = cnt
@@ -580,11 +598,13 @@ def main():
     cfg2 = None
     if args.config2_steps > 0:
         cfg2 = config2_leg(P, torch, W, args.config2_steps, not args.no_oracle)
+        progress("ragged batching workload done")
         P.set_options(n_lim=nlim, refine=1)
     cfg4 = None
     if args.config4_steps > 0:
         P.set_options(n_lim=256, refine=1)
         cfg4 = config4_leg(P, torch, W, args.config4_steps, not args.no_oracle)
+        progress("bilevel workload done")
         P.set_options(n_lim=nlim, refine=1)
 
     if args.copy_calib_mib > 0:

@@ -76,8 +76,13 @@ class BilevelTuner:
         prepared; they apply to every run of them.  By default merge_tol = 4: extended sizes
         within a factor 5 share one plan, so a batch spanning 2^12..2^16 runs as two chunks
         (measured on 256 problems: 4.7 s per step against 9.2 s with the library's default
-        of 0.25, whose dozen chunks of ~20 small groups are bound by launch overhead)."""
+        of 0.25, whose dozen chunks of ~20 small groups are bound by launch overhead), and
+        refine = 2: a prepared batch takes a fixed number of refinement steps (no adaptive
+        ones), and with one step a few solves of the 256-problem workload end above the
+        refinement's failure estimate (info bit 16) once lambda has fallen below 4e-3 (from
+        step 10 of 20); with two none do (7.2 s per step)."""
         options.setdefault("merge_tol", 4.0)
+        options.setdefault("refine", 2)
         dev = col.device
         self.ms, self.ns = list(ms), list(ns)
         self.nprob = len(ms)
