@@ -494,7 +494,7 @@ def main():
     value = nsolve * args.steps / (ms_total / 1e3)
     info_max = int(max(info.max().item(), binfo.max().item()))
     x_timed = x.cpu().numpy()
-    per_call = {k: {f: v[f] for f in ("launches", "host_syncs", "refine_extra", "fallback_groups")}
+    per_call = {k: {f: v[f] for f in ("launches", "host_syncs", "refine_extra", "refine_skipped", "fallback_groups")}
                 for k, v in call_stats.items()}
 
     # dominant kernels: live launch timing over one more step each (HIP events on the library stream)

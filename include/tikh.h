@@ -116,6 +116,16 @@ typedef struct {
     int32_t chunk_groups; /* most groups (recursions run in the same launches) per chunk, 0 = as many as the
                              workspace holds (the default); with streams > 1 the chunks of a call run side by
                              side, so that one chunk's serial leaf steps overlap another's transforms */
+    int32_t refine_skip;  /* 1: before the first refinement step, a group whose first solves are certified
+                             to refine_tol by the a-posteriori bound ||x - x*|| <= ||r|| / lambda^2
+                             (r = y - (T^H T + lambda^2 I) x; T^H T is positive semidefinite), with a margin for
+                             the residual's own rounding, takes no refinement step (one more host
+                             synchronization per call; such solves keep the first solve's residual, about
+                             1e-11 relative at n = 2^14, instead of the refined one); 0 (default): every solve
+                             takes `refine` steps.  Pays off for well-conditioned batches (every solve of the
+                             paper's accuracy workload, lambda^2 = sqrt(2n), is certified); at the headline
+                             lambda path only 5-9% of the solves are, for 0.4% of the time.  Not applied to
+                             the Toeplitz-Gramian problem or to prepared batches */
 } tikh_opts;
 
 /* Per-solve statistics of the last call (host memory, filled by tikh_get_stats). */
@@ -131,6 +141,8 @@ typedef struct {
     int64_t host_syncs;   /* host synchronizations inside the last call (transform sizing read back per
                              merge, refinement decisions, the check of recorded transform lengths) */
     int64_t fallback_groups; /* groups of the last call solved again with the fallback leaf cutoff */
+    int64_t refine_skipped; /* solves of the last call whose refinement steps the a-posteriori bound made
+                               unnecessary (refine_skip) */
 } tikh_stats;
 
 /*

@@ -22,14 +22,15 @@ class _Opts(ctypes.Structure):
     _fields_ = [("n_lim", ctypes.c_int32), ("refine", ctypes.c_int32), ("refine_max", ctypes.c_int32),
                 ("leaf_wave_groups", ctypes.c_int32), ("refine_tol", ctypes.c_double), ("defer_tol", ctypes.c_double),
                 ("record_short", ctypes.c_int32), ("streams", ctypes.c_int32), ("merge_tol", ctypes.c_double),
-                ("fallback_nlim", ctypes.c_int32), ("chunk_groups", ctypes.c_int32)]
+                ("fallback_nlim", ctypes.c_int32), ("chunk_groups", ctypes.c_int32),
+                ("refine_skip", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int64), ("k", ctypes.c_int64), ("depth", ctypes.c_int32),
                 ("leaf_nodes", ctypes.c_int32), ("solves", ctypes.c_int64), ("launches", ctypes.c_int64),
                 ("refine_extra", ctypes.c_int64), ("deferred", ctypes.c_int64), ("host_syncs", ctypes.c_int64),
-                ("fallback_groups", ctypes.c_int64)]
+                ("fallback_groups", ctypes.c_int64), ("refine_skipped", ctypes.c_int64)]
 
 
 def _sig(name, args, res=ctypes.c_int):
@@ -104,7 +105,7 @@ def _stream():
 
 def set_options(n_lim=None, refine=None, refine_max=None, refine_tol=None, defer_tol=None,
                 leaf_wave_groups=None, record_short=None, streams=None, merge_tol=None, fallback_nlim=None,
-                chunk_groups=None):
+                chunk_groups=None, refine_skip=None):
     """Leaf cutoff, refinement steps for every solve, most refinement steps for a solve whose
     estimated error is above the target (see tikh_opts in include/tikh.h)."""
     o = _Opts()
@@ -131,6 +132,8 @@ def set_options(n_lim=None, refine=None, refine_max=None, refine_tol=None, defer
         o.fallback_nlim = int(fallback_nlim)
     if chunk_groups is not None:
         o.chunk_groups = int(chunk_groups)
+    if refine_skip is not None:
+        o.refine_skip = int(refine_skip)
     _check(lib.tikh_set_options(ctypes.byref(o)), "tikh_set_options")
 
 
@@ -140,7 +143,7 @@ def get_options():
     return dict(n_lim=o.n_lim, refine=o.refine, refine_max=o.refine_max, refine_tol=o.refine_tol,
                 defer_tol=o.defer_tol, leaf_wave_groups=o.leaf_wave_groups, record_short=o.record_short,
                 streams=o.streams, merge_tol=o.merge_tol, fallback_nlim=o.fallback_nlim,
-                chunk_groups=o.chunk_groups)
+                chunk_groups=o.chunk_groups, refine_skip=o.refine_skip)
 
 
 def plan_info(m, n, n_lim=256):
@@ -169,7 +172,7 @@ def get_stats():
     _check(lib.tikh_get_stats(ctypes.byref(s)), "tikh_get_stats")
     return dict(N=s.N, k=s.k, depth=s.depth, leaf_nodes=s.leaf_nodes, solves=s.solves, launches=s.launches,
                 refine_extra=s.refine_extra, deferred=s.deferred, host_syncs=s.host_syncs,
-                fallback_groups=s.fallback_groups)
+                fallback_groups=s.fallback_groups, refine_skipped=s.refine_skipped)
 
 
 def _dev(t, dtype):

@@ -154,6 +154,7 @@ static void init_opts() {
     g.opts.streams = 16;
     g.opts.merge_tol = 0.25;
     g.opts.fallback_nlim = 64;
+    g.opts.refine_skip = 0;
     g.opts.refine_tol = 1e-10;
     g.opts.defer_tol = 0.0;
     g.init = true;
@@ -978,6 +979,88 @@ static void chunk_enter(ChunkRun& r) {
     g.overflow = r.b.ovf;
 }
 
+// Residual of the normal equations of the first Sa solves into b.t1: r = y - (T^H T + lam^2) x
+// (Sec. 7.2: iterative refinement); Toeplitz-Gramian problem: r = y - (L^H L + G) x, with G x
+// (bC) from the Gramian's circulant.
+static void chunk_residual(ChunkRun& r) {
+    const Plan& pl = r.pl;
+    const Layout& L = r.L;
+    const Bufs& b = r.b;
+    const double2* tw = r.tw;
+    const int64_t Sa = r.Sa, mmax = r.mmax, nmax = r.nmax, N = pl.N;
+    const double invN = 1.0 / (double)N;
+    const bool gramian = r.gramian;
+    if (gramian) {
+        hipLaunchKernelGGL(k_load_pad, grid1(N, Sa), dim3(256), 0, g.stream, b.sd, 0, b.xacc, L.sn, 1, 0, 1.0,
+                           b.bB, N, L.sN);
+        circ_apply(pl, L, b, Sa, b.bB, 0, tw, b.cg);
+        hipLaunchKernelGGL(k_take_tail, grid1(nmax, Sa), dim3(256), 0, g.stream, b.sd, b.bB, N, L.sN, 1, invN,
+                           b.bC, L.sN);
+        g.launches += 2;
+    }
+    hipLaunchKernelGGL(k_load_pad, grid1(N, Sa), dim3(256), 0, g.stream, b.sd, 0, b.xacc, L.sn, 1, 0, 1.0,
+                       b.bB, N, L.sN);
+    circ_apply(pl, L, b, Sa, b.bB, 0, tw);
+    hipLaunchKernelGGL(k_take_tail, grid1(mmax, Sa), dim3(256), 0, g.stream, b.sd, b.bB, N, L.sN, 0, invN,
+                       b.t1, L.sn);
+    hipLaunchKernelGGL(k_load_pad, grid1(N, Sa), dim3(256), 0, g.stream, b.sd, 0, b.t1, L.sn, 0, 0, 1.0, b.bB,
+                       N, L.sN);
+    circ_apply(pl, L, b, Sa, b.bB, 1, tw);
+    hipLaunchKernelGGL(k_take_tail, grid1(nmax, Sa), dim3(256), 0, g.stream, b.sd, b.bB, N, L.sN, 1, invN,
+                       b.t2, L.sn);
+    hipLaunchKernelGGL(k_normal_residual, grid1(nmax, Sa), dim3(256), 0, g.stream, b.sd, b.yv, b.t2, b.xacc,
+                       b.t1, L.sn, gramian ? (const double2*)b.bC : (const double2*)nullptr, L.sN);
+    g.launches += 5;
+}
+
+// Moves the groups flagged in hflags[0, Ga) to the front of the chunk (exchanging each with an
+// unflagged group of that prefix: descriptors, state, symbols, right-hand side, solution)
+// and makes them the active prefix.
+static int compact_groups(ChunkRun& r, const std::vector<int32_t>& hflags) {
+    Bufs& b = r.b;
+    const Layout& L = r.L;
+    const int64_t Ga = r.Ga;
+    std::vector<int64_t> want, holes;
+    int64_t G2 = 0;
+    for (int64_t gi = 0; gi < Ga; ++gi) G2 += hflags[gi] ? 1 : 0;
+    for (int64_t gi = 0; gi < G2; ++gi) if (!hflags[gi]) holes.push_back(gi);
+    for (int64_t gi = G2; gi < Ga; ++gi) if (hflags[gi]) want.push_back(gi);
+    if (!holes.empty()) {
+        std::vector<int2> hp(holes.size());
+        for (size_t i = 0; i < holes.size(); ++i) hp[i] = make_int2((int)holes[i], (int)want[i]);
+        HIPCHK(hipMemcpyAsync(b.pairs, hp.data(), sizeof(int2) * hp.size(), hipMemcpyHostToDevice, g.stream));
+        HIPCHK(hipStreamSynchronize(g.stream));
+        g.syncs += 1;
+        hipLaunchKernelGGL(k_swap_groups, dim3(64, (unsigned)hp.size()), dim3(256), 0, g.stream, b.sd, b.st, b.chat,
+                           L.sN, b.yv, b.xacc, L.sn, r.nr, b.pairs, r.gramian ? b.cg : nullptr, b.asum);
+        g.launches++;
+    }
+    r.Ga = G2;
+    r.Sa = G2 * r.nr;
+    return TIKH_OK;
+}
+
+// Before the first refinement step: the groups whose first solve the a-posteriori bound
+// already certifies to refine_tol (k_refine_bound) take no refinement step (one host
+// synchronization for the decisions).  Not for the Toeplitz-Gramian problem (A >= lam^2 I
+// does not hold there) nor for prepared batches (no host decisions).
+static bool filter_on(const ChunkRun& r) { return g.opts.refine_skip && !r.gramian && !r.fixed_steps; }
+static int chunk_filter(ChunkRun& r) {
+    if (r.Ga == 0) return TIKH_OK;
+    chunk_residual(r);
+    hipLaunchKernelGGL(k_refine_bound, dim3((unsigned)r.Ga), dim3(256), 0, g.stream, r.b.sd, r.nr, r.b.chat, r.L.sN,
+                       r.pl.N, r.b.t1, r.b.xacc, r.L.sn, g.opts.refine_tol, r.b.flags);
+    g.launches++;
+    std::vector<int32_t> hflags((size_t)r.Ga);
+    HIPCHK(hipMemcpyAsync(hflags.data(), r.b.flags, sizeof(int32_t) * r.Ga, hipMemcpyDeviceToHost, g.stream));
+    HIPCHK(hipStreamSynchronize(g.stream));
+    g.syncs += 1;
+    const int64_t before = r.Sa;
+    int rc = compact_groups(r, hflags);
+    g.stats.refine_skipped += before - r.Sa;
+    return rc;
+}
+
 // One solve of the chunk's current right-hand sides (it = 0: y; it > 0: the
 // refinement residual of the solutions so far) over its first Ga groups.
 static int chunk_step(ChunkRun& r, int it) {
@@ -993,32 +1076,11 @@ static int chunk_step(ChunkRun& r, int it) {
     int rc = TIKH_OK;
     const double2* rhs = b.yv;
     if (it > 0) {
-        // residual of the normal equations, r = y - (T^H T + lam^2) x (Sec. 7.2: iterative refinement);
-        // Toeplitz-Gramian problem: r = y - (L^H L + G) x, with G x (bC) from the Gramian's circulant
-        if (gramian) {
-            hipLaunchKernelGGL(k_load_pad, grid1(N, Sa), dim3(256), 0, g.stream, b.sd, 0, b.xacc, L.sn, 1, 0, 1.0,
-                               b.bB, N, L.sN);
-            circ_apply(pl, L, b, Sa, b.bB, 0, tw, b.cg);
-            hipLaunchKernelGGL(k_take_tail, grid1(nmax, Sa), dim3(256), 0, g.stream, b.sd, b.bB, N, L.sN, 1, invN,
-                               b.bC, L.sN);
-            g.launches += 2;
-        }
-        hipLaunchKernelGGL(k_load_pad, grid1(N, Sa), dim3(256), 0, g.stream, b.sd, 0, b.xacc, L.sn, 1, 0, 1.0,
-                           b.bB, N, L.sN);
-        circ_apply(pl, L, b, Sa, b.bB, 0, tw);
-        hipLaunchKernelGGL(k_take_tail, grid1(mmax, Sa), dim3(256), 0, g.stream, b.sd, b.bB, N, L.sN, 0, invN,
-                           b.t1, L.sn);
-        hipLaunchKernelGGL(k_load_pad, grid1(N, Sa), dim3(256), 0, g.stream, b.sd, 0, b.t1, L.sn, 0, 0, 1.0, b.bB,
-                           N, L.sN);
-        circ_apply(pl, L, b, Sa, b.bB, 1, tw);
-        hipLaunchKernelGGL(k_take_tail, grid1(nmax, Sa), dim3(256), 0, g.stream, b.sd, b.bB, N, L.sN, 1, invN,
-                           b.t2, L.sn);
-        hipLaunchKernelGGL(k_normal_residual, grid1(nmax, Sa), dim3(256), 0, g.stream, b.sd, b.yv, b.t2, b.xacc,
-                           b.t1, L.sn, gramian ? (const double2*)b.bC : (const double2*)nullptr, L.sN);
+        chunk_residual(r);
         hipLaunchKernelGGL(k_init_state, dim3((unsigned)((Ga + 63) / 64)), dim3(64), 0, g.stream, b.sd, nr, b.st,
                            (int)Ga, 1);
         hipLaunchKernelGGL(k_zero_d, grid1(2 * Sa, 1), dim3(256), 0, g.stream, b.nrm, 2 * Sa);
-        g.launches += 7;
+        g.launches += 2;
         rhs = b.t1;
     }
     hipLaunchKernelGGL(k_load_pad, grid1(N, Sa), dim3(256), 0, g.stream, b.sd, 0, rhs, L.sn, 1, 0, 1.0, b.bA, N,
@@ -1149,7 +1211,9 @@ static int chunk_setup(ChunkRun& r) {
     r.done = false;
     r.Ga = G;
     r.Sa = S;
-    for (r.it = 0; r.it < r.steps_min; ++r.it) {
+    // with the a-posteriori filter the refinement steps are taken in chunk_adapt
+    const int upfront = filter_on(r) ? 1 : r.steps_min;
+    for (r.it = 0; r.it < upfront; ++r.it) {
         rc = chunk_step(r, r.it);
         if (rc) return rc;
     }
@@ -1161,6 +1225,17 @@ static int chunk_setup(ChunkRun& r) {
 // synchronization for the decisions).  Sets r.done when no group needs one.
 static int chunk_adapt(ChunkRun& r) {
     if (r.done) return TIKH_OK;
+    if (r.it < r.steps_min) {
+        // a refinement step every group takes, unless the bound certified it before the first
+        if (r.it == 1) {
+            int rc = chunk_filter(r);
+            if (rc) return rc;
+            if (r.Ga == 0) { r.done = true; return TIKH_OK; }
+        }
+        int rc = chunk_step(r, r.it);
+        r.it++;
+        return rc;
+    }
     if (r.it >= r.steps_max) {
         if (r.it > 1) {
             // the groups that took the last step: did their refinement fail (estimate above 1e-4)?
@@ -1173,10 +1248,7 @@ static int chunk_adapt(ChunkRun& r) {
         return TIKH_OK;
     }
     Bufs& b = r.b;
-    const Layout& L = r.L;
-    const int nr = r.nr;
-    const bool gramian = r.gramian;
-    int64_t& Ga = r.Ga;
+    const int64_t Ga = r.Ga;
     std::vector<int32_t> hflags;
     {
         // groups still above the tolerance after the last step
@@ -1184,24 +1256,11 @@ static int chunk_adapt(ChunkRun& r) {
         HIPCHK(hipMemcpyAsync(hflags.data(), b.flags, sizeof(int32_t) * Ga, hipMemcpyDeviceToHost, g.stream));
         HIPCHK(hipStreamSynchronize(g.stream));
         g.syncs += 1;
-        std::vector<int64_t> want, holes;
         int64_t G2 = 0;
         for (int64_t gi = 0; gi < Ga; ++gi) G2 += hflags[gi] ? 1 : 0;
         if (G2 == 0) { r.done = true; return TIKH_OK; }
-        for (int64_t gi = 0; gi < G2; ++gi) if (!hflags[gi]) holes.push_back(gi);
-        for (int64_t gi = G2; gi < Ga; ++gi) if (hflags[gi]) want.push_back(gi);
-        if (!holes.empty()) {
-            std::vector<int2> hp(holes.size());
-            for (size_t i = 0; i < holes.size(); ++i) hp[i] = make_int2((int)holes[i], (int)want[i]);
-            HIPCHK(hipMemcpyAsync(b.pairs, hp.data(), sizeof(int2) * hp.size(), hipMemcpyHostToDevice, g.stream));
-            HIPCHK(hipStreamSynchronize(g.stream));
-            g.syncs += 1;
-            hipLaunchKernelGGL(k_swap_groups, dim3(64, (unsigned)hp.size()), dim3(256), 0, g.stream, b.sd, b.st,
-                               b.chat, L.sN, b.yv, b.xacc, L.sn, nr, b.pairs, gramian ? b.cg : nullptr, b.asum);
-            g.launches++;
-        }
-        Ga = G2;
-        r.Sa = G2 * nr;
+        int rc = compact_groups(r, hflags);
+        if (rc) return rc;
         g.stats.refine_extra += r.Sa;
     }
     int rc = chunk_step(r, r.it);
@@ -1457,6 +1516,7 @@ static int run_solves(std::vector<SolveDesc>& sds, int nr, int32_t* info) {
     g.launches = 0;
     g.syncs = 0;
     g.stats.refine_extra = 0;
+    g.stats.refine_skipped = 0;
     g.stats.deferred = 0;
     g.stats.fallback_groups = 0;
     std::vector<SolveDesc> failed;
@@ -1471,10 +1531,12 @@ static int run_solves(std::vector<SolveDesc>& sds, int nr, int32_t* info) {
     g.opts.n_lim = keep;
     // the statistics describe the main solve (plan, shapes), with the fallback's counts added
     const int64_t launches = g.stats.launches, syncs = g.stats.host_syncs, extra = g.stats.refine_extra;
+    const int64_t skipped = g.stats.refine_skipped;
     g.stats = st;
     g.stats.launches = launches;
     g.stats.host_syncs = syncs;
     g.stats.refine_extra += extra;
+    g.stats.refine_skipped += skipped;
     return rc;
 }
 
@@ -1855,7 +1917,8 @@ int tikh_set_options(const tikh_opts* o) {
         o->refine_max > 4 || !(o->refine_tol > 0.0) || !std::isfinite(o->refine_tol) || !(o->defer_tol >= 0.0) ||
         !(o->defer_tol < 1.0) || o->leaf_wave_groups < 1 || o->streams < 1 || o->streams > 16 ||
         !(o->merge_tol >= 0.0) || !(o->merge_tol <= 4.0) ||
-        (o->fallback_nlim != 0 && (o->fallback_nlim < 64 || o->fallback_nlim > LEAF_MAX)) || o->chunk_groups < 0)
+        (o->fallback_nlim != 0 && (o->fallback_nlim < 64 || o->fallback_nlim > LEAF_MAX)) || o->chunk_groups < 0 ||
+        (o->refine_skip != 0 && o->refine_skip != 1))
         return TIKH_EINVAL;
     g.opts = *o;
     return TIKH_OK;

@@ -2338,6 +2338,54 @@ __global__ void k_refine_decide(const double* __restrict__ nrm, int nr, SolveSta
     else if (above) st[g].info |= 16;
 }
 
+// A-posteriori bound on a solve's error before a refinement step (Sec. 7.2): with
+// A = T^H T + lam^2 I >= lam^2 I the error of x against A^{-1} y is at most ||r|| / lam^2
+// for the exact residual r = y - A x.  The residual computed with transforms of length N
+// differs from it by a small multiple of eps ||C||^2 ||x||, where ||C||_2 = max_nu |c^_nu|
+// bounds ||T||_2 (T is a block of the circulant C); REFINE_BOUND_EPS (1e-13) covers that
+// about 20 times at N = 2^19.  flags[g] = 1 unless every solve of the group is certified:
+// (||r|| + REFINE_BOUND_EPS (||C||^2 + lam^2) ||x||) / (lam^2 ||x||) <= tol.
+#define REFINE_BOUND_EPS 1e-13
+__device__ __forceinline__ double block_sum256(double v, double* red) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return red[0] + red[1] + red[2] + red[3];
+}
+__global__ __launch_bounds__(256) void k_refine_bound(const SolveDesc* __restrict__ sd, int nr,
+                                                      const double2* __restrict__ chat, int64_t sN, int64_t N,
+                                                      const double2* __restrict__ res, const double2* __restrict__ x,
+                                                      int64_t sn, double tol, int32_t* __restrict__ flags) {
+    __shared__ double red[4];
+    const int64_t g = blockIdx.x;
+    double m = 0.0;
+    for (int64_t i = threadIdx.x; i < N; i += 256) m = fmax(m, cabs2(chat[g * sN + i]));
+    m = wave_max_d(m);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    const double c2max = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    int need = 0;
+    for (int q = 0; q < nr; ++q) {
+        const int64_t s = g * nr + q;
+        if (sd[s].orig < 0) continue;                  // padding solve
+        const int64_t n = sd[s].n;
+        const double lam = sd[s].lam;
+        double rr = 0.0, xx = 0.0;
+        for (int64_t i = threadIdx.x; i < n; i += 256) {
+            rr += cabs2(res[s * sn + i]);
+            xx += cabs2(x[s * sn + i]);
+        }
+        rr = block_sum256(rr, red);
+        xx = block_sum256(xx, red);
+        const double lam2 = lam * lam, nx = sqrt(xx);
+        const double bound = (sqrt(rr) + REFINE_BOUND_EPS * (c2max + lam2) * nx) / (lam2 * nx);
+        if (!(bound <= tol)) need = 1;                 // also a zero or non-finite solution
+    }
+    if (threadIdx.x == 0) flags[g] = need;
+}
+
 __global__ void k_zero_d(double* __restrict__ p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = 0.0;

@@ -193,6 +193,41 @@ def test_adaptive_refinement_batched(P):
     assert any(0 < e < 2 * nsolve for e in extras), extras
 
 
+def test_refinement_skipped_when_certified(P):
+    """Before the first refinement step, the groups whose first solves are certified to
+    refine_tol by the a-posteriori bound ||x - x*|| <= ||r|| / lambda^2 (plus the residual's
+    rounding margin) take no refinement step: the large lambdas of a path from kappa ~ 1e6
+    to ~2; the small ones cannot be certified and refine.  Every solve matches the oracle
+    with the filter on and off."""
+    probs = [W.headline(i, n=1024, nrhs=2, nlam=8) for i in range(3)]
+    ms = [p.m for p in probs]
+    ns = [p.n for p in probs]
+    args = (ms, ns, dev(np.concatenate([p.col for p in probs])), dev(np.concatenate([p.row for p in probs])),
+            [l for p in probs for l in p.lams], 2, dev(np.concatenate([np.concatenate(p.b) for p in probs])))
+    nsolve = 3 * 8 * 2
+    ref = [oracle.solve(p.col, p.row, b, lam) for p in probs for lam in p.lams for b in p.b]
+    out = {}
+    for skip in (0, 1):
+        P.set_options(refine=1, refine_max=3, refine_skip=skip)
+        try:
+            x, info = P.solve_batched(*args)
+            torch.cuda.synchronize()
+            out[skip] = (x.cpu().numpy(), info.cpu().numpy(), P.get_stats()["refine_skipped"])
+        finally:
+            P.set_options(refine_skip=0)
+    assert out[0][2] == 0
+    assert 0 < out[1][2] < nsolve and out[1][2] % 2 == 0   # whole groups of 2 right-hand sides
+    for skip in (0, 1):
+        x, info, _ = out[skip]
+        assert (info == 0).all()
+        off = 0
+        for i, xr in enumerate(ref):
+            n = len(xr)
+            assert relerr(x[off:off + n], xr) <= TOL, (skip, i)
+            off += n
+    assert relerr(out[1][0], out[0][0]) <= TOL
+
+
 @pytest.mark.parametrize("defer_tol", [1e-3, 2e-3])
 @pytest.mark.parametrize("nlim", [64, 256])
 def test_difficult_points_deferred(P, defer_tol, nlim):

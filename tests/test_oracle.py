@@ -360,3 +360,16 @@ def test_gramian_mutation_fails():
     x1 = oracle.gramian_solve(gram, lcol, lrow, y)
     x2 = oracle.gramian_solve(np.conj(gram), lcol, lrow, y)
     assert np.linalg.norm(x1 - x2) / np.linalg.norm(x1) > 1e-3
+
+
+def test_replica_workloads_recover_x():
+    """The Table 1 replica workloads (Sec. 7.1-7.2) are consistent: the dense oracle recovers
+    their known x from y (normal form for the l2 problem, (G + L^H L) x = y for the
+    Toeplitz-Gramian one)."""
+    for n in (16, 64):
+        q = W.replica(n, 1)
+        assert np.max(np.abs(oracle.solve_normal(q.col, q.row, q.b[0], q.lams[0]) - q.x_true)) <= 1e-12
+        assert abs(q.lams[0] ** 2 - np.sqrt(2.0 * n)) <= 1e-12
+        p = W.replica_gramian(n, 1)
+        assert abs(p.gram[0] - 10.0 * np.sqrt(2.0 * n)) <= 1e-12
+        assert np.max(np.abs(oracle.gramian_solve(p.gram, p.lcol, p.lrow, p.ys[0]) - p.x_true)) <= 1e-12

@@ -217,6 +217,24 @@ def replica(n, index=0):
     return Problem(col, row, [y], [lam], x, dict(config="replica", normal_form=True))
 
 
+def replica_gramian(n, index=0):
+    """Paper-shaped accuracy workload of the Toeplitz-Gramian problem (Sec. 7.1-7.2): n x n
+    Hermitian Toeplitz G with complex standard normal entries and main diagonal
+    10 sqrt(N), N = 2n; L an n x n Toeplitz matrix with complex standard normal
+    generator; known x; y = (G + L^H L) x."""
+    rng = rng_for(7, index * 100003 + n)
+    cn = lambda k: (rng.standard_normal(k) + 1j * rng.standard_normal(k)) / math.sqrt(2.0)
+    gram = cn(n)
+    gram[0] = 10.0 * math.sqrt(2.0 * n)
+    s = np.arange(-(n - 1), n)
+    lcol, lrow = split_generator(cn(len(s)), n, n)
+    x = cn(n)
+    grow = np.conj(gram)
+    grow[0] = gram[0]
+    y = toeplitz_matvec(gram, grow, x) + toeplitz_rmatvec(lcol, lrow, toeplitz_matvec(lcol, lrow, x))
+    return GramianProblem(gram, lcol, lrow, [y], x, dict(config="replica_gramian"))
+
+
 def random_problem(rng, m, n, cplx=False, L=None):
     """Small random problem for parity sweeps (ragged sizes)."""
     s = np.arange(-(n - 1), m)
