@@ -86,6 +86,11 @@ enum {
  * each step contracts it, so the error left after step k is taken as
  * 1000 * e0 * ||dx_k|| / ||x||).  With refine = 0 no step is taken.
  */
+/* Every option's default can be overridden from the environment when the library first
+ * initializes: TIKH_NLIM, TIKH_REFINE, TIKH_REFINE_MAX, TIKH_REFINE_TOL, TIKH_DEFER_TOL,
+ * TIKH_LEAF_WAVE_GROUPS, TIKH_STREAMS, TIKH_MERGE_TOL, TIKH_FALLBACK_NLIM,
+ * TIKH_CHUNK_GROUPS, TIKH_REFINE_SKIP (a value that does not parse or is out of range is
+ * reported on stderr and ignored); tikh_set_options replaces them all. */
 typedef struct {
     int32_t n_lim;        /* max conditions per leaf (64..256, multiple of 64); default 256 */
     int32_t refine;       /* refinement steps for every solve (0..4); default 1 */

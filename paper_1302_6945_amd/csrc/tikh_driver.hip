@@ -143,6 +143,41 @@ static void prof_print_detail() {
     } while (0)
 #define LAUNCH(kname, kern, grid, block, ...) LAUNCH_SH(kname, kern, grid, block, 0, __VA_ARGS__)
 
+static bool opts_valid(const tikh_opts* o);
+
+// Environment overrides of the defaults, read once: TIKH_<NAME> for every option (for
+// example TIKH_NLIM=128, TIKH_REFINE=2, TIKH_DEFER_TOL=1e-3).  A value that does not parse,
+// or that would make the options invalid, is reported on stderr and ignored.
+static void env_overrides(tikh_opts& o) {
+    struct Ent { const char* name; int32_t* i; double* d; };
+    const Ent ents[] = {{"TIKH_NLIM", &o.n_lim, nullptr}, {"TIKH_REFINE", &o.refine, nullptr},
+                        {"TIKH_REFINE_MAX", &o.refine_max, nullptr}, {"TIKH_REFINE_TOL", nullptr, &o.refine_tol},
+                        {"TIKH_DEFER_TOL", nullptr, &o.defer_tol},
+                        {"TIKH_LEAF_WAVE_GROUPS", &o.leaf_wave_groups, nullptr},
+                        {"TIKH_STREAMS", &o.streams, nullptr}, {"TIKH_MERGE_TOL", nullptr, &o.merge_tol},
+                        {"TIKH_FALLBACK_NLIM", &o.fallback_nlim, nullptr},
+                        {"TIKH_CHUNK_GROUPS", &o.chunk_groups, nullptr},
+                        {"TIKH_REFINE_SKIP", &o.refine_skip, nullptr}};
+    for (const Ent& e : ents) {
+        const char* v = getenv(e.name);
+        if (!v || !*v) continue;
+        char* end = nullptr;
+        tikh_opts t = o;
+        bool ok;
+        if (e.i) {
+            const long x = strtol(v, &end, 10);
+            ok = end && *end == 0 && x >= INT32_MIN && x <= INT32_MAX;
+            if (ok) *(int32_t*)((char*)&t + ((char*)e.i - (char*)&o)) = (int32_t)x;
+        } else {
+            const double x = strtod(v, &end);
+            ok = end && *end == 0;
+            if (ok) *(double*)((char*)&t + ((char*)e.d - (char*)&o)) = x;
+        }
+        if (ok && opts_valid(&t)) o = t;
+        else fprintf(stderr, "tikh: ignoring %s=%s (not a valid value)\n", e.name, v);
+    }
+}
+
 // Options take their defaults once; the degree readback words are (re)allocated
 // until both exist, and a merge that finds either missing reports TIKH_ENOMEM.
 static void init_opts() {
@@ -157,6 +192,7 @@ static void init_opts() {
     g.opts.refine_skip = 0;
     g.opts.refine_tol = 1e-10;
     g.opts.defer_tol = 0.0;
+    env_overrides(g.opts);
     g.init = true;
 }
 static void ensure_init() {
@@ -1912,17 +1948,25 @@ int tikh_set_stream(void* s) { ensure_init(); g.stream = (hipStream_t)s; return 
 
 int tikh_set_options(const tikh_opts* o) {
     ensure_init();
-    if (!o) return TIKH_EINVAL;
+    if (!o || !opts_valid(o)) return TIKH_EINVAL;
+    g.opts = *o;
+    return TIKH_OK;
+}
+
+}  // extern "C"
+
+static bool tikh::opts_valid(const tikh_opts* o) {
     if (o->n_lim < 64 || o->n_lim > LEAF_MAX || o->refine < 0 || o->refine > 4 || o->refine_max < 0 ||
         o->refine_max > 4 || !(o->refine_tol > 0.0) || !std::isfinite(o->refine_tol) || !(o->defer_tol >= 0.0) ||
         !(o->defer_tol < 1.0) || o->leaf_wave_groups < 1 || o->streams < 1 || o->streams > 16 ||
         !(o->merge_tol >= 0.0) || !(o->merge_tol <= 4.0) ||
         (o->fallback_nlim != 0 && (o->fallback_nlim < 64 || o->fallback_nlim > LEAF_MAX)) || o->chunk_groups < 0 ||
         (o->refine_skip != 0 && o->refine_skip != 1))
-        return TIKH_EINVAL;
-    g.opts = *o;
-    return TIKH_OK;
+        return false;
+    return true;
 }
+
+extern "C" {
 
 int tikh_get_options(tikh_opts* o) { ensure_init(); if (!o) return TIKH_EINVAL; *o = g.opts; return TIKH_OK; }
 

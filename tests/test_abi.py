@@ -130,3 +130,22 @@ def test_workspace_query_on_host():
             P.workspace_bytes(*bad)
     # a misaligned caller buffer is rejected before any device work
     assert P.lib.tikh_set_workspace(8, 1024) == -1
+
+
+def test_environment_overrides_options():
+    """TIKH_<NAME> environment variables override the option defaults when the library first
+    initializes; an invalid value is reported and ignored (host-only, fresh processes)."""
+    _ensure_built()
+    import subprocess
+    import sys
+    code = ("import paper_1302_6945_amd as P; o = P.get_options(); "
+            "print(o['n_lim'], o['refine'], o['merge_tol'], o['streams'])")
+    env = dict(os.environ, TIKH_NLIM="128", TIKH_REFINE="2", TIKH_MERGE_TOL="0.5")
+    out = subprocess.run([sys.executable, "-c", code], env=env, cwd=ROOT, capture_output=True, text=True,
+                         check=True)
+    assert out.stdout.split() == ["128", "2", "0.5", "16"]
+    env = dict(os.environ, TIKH_NLIM="7", TIKH_STREAMS="x4")
+    out = subprocess.run([sys.executable, "-c", code], env=env, cwd=ROOT, capture_output=True, text=True,
+                         check=True)
+    assert out.stdout.split() == ["256", "1", "0.25", "16"]
+    assert "TIKH_NLIM" in out.stderr and "TIKH_STREAMS" in out.stderr

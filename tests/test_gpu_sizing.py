@@ -101,3 +101,21 @@ def test_short_recorded_lengths_are_caught(P):
     assert (info1.cpu().numpy() == 0).all() and (info2.cpu().numpy() == 0).all()
     _check_oracle(probs, x1.cpu().numpy())
     _check_oracle(probs, x2.cpu().numpy())
+
+
+def test_repeated_calls_are_bitwise_identical(P):
+    """Determinism: with the transform lengths recorded and a fixed refinement schedule
+    (refine_max = refine: the adaptive decisions compare norms summed by atomics, whose
+    order varies), the same batch solved again gives bitwise-identical solutions and info."""
+    probs, args = _batch(4321)
+    P.set_options(refine=1, refine_max=1)
+    try:
+        P.solve_batched(*args)
+        torch.cuda.synchronize()
+        x2, i2 = P.solve_batched(*args)
+        x3, i3 = P.solve_batched(*args)
+        torch.cuda.synchronize()
+    finally:
+        P.set_options(refine=1, refine_max=3)
+    assert torch.equal(x2, x3) and torch.equal(i2, i3)
+    _check_oracle(probs, x3.cpu().numpy())
