@@ -1511,8 +1511,13 @@ __global__ __launch_bounds__(256) void k_leaf_build(const BuildArgs a) {
 
 // phi <- phi B_L(sigma) for every condition of the right subtree
 // (Alg. 1 step 2, with Thm. 1 giving the data phi_k B_kappa(sigma_k)).
-// The right subtree (depth d, coset offset oR) spans leaves [t0, t0 + 2^{p-d}).
-// V holds each line in four-step order: value j at (j % L1) * (L / L1) + j / L1.
+// The right subtree (depth d, coset offset oR) spans leaves [t0, t0 + 2^{p-d}); each coset
+// holds L = 2^{p-d} M/2 of its nodes, node jn = jlo + 2^{p-d} jhi being node jhi of the
+// leaf whose offset is oR + 2^{d+1} jlo.  V holds each line in four-step order: value jn
+// at position (jn % L1) * L2 + jn / L1 (L2 = L / L1; natural order when L1 = L).
+// Threads run over the positions of V, so that the 4C evaluation lines (four fifths of
+// the data read) are read in order; the residual rows they update are then scattered
+// (two adjacent conditions, F and G, per node).
 template <int NR>
 __global__ __launch_bounds__(256) void k_eval_apply(double2* __restrict__ phi, int64_t phi_stride,
                                                     const double2* __restrict__ V, int64_t v_stride, int64_t L,
@@ -1522,21 +1527,21 @@ __global__ __launch_bounds__(256) void k_eval_apply(double2* __restrict__ phi, i
     const int64_t g = blockIdx.y;
     const int64_t nq = 2 * N;
     // one thread per node: its F and G conditions (adjacent in tree order) share B_L(sigma)
-    const int nodes = (int)(nleaves * K / 2), hk = K / 2, hm = (int)(M / 2);
-    const int L2 = (int)(L / L1), iL1 = (int)L1;
-    const float inv_hk = 1.0f / (float)hk, inv_hm = 1.0f / (float)hm, inv_L1 = 1.0f / (float)L1;
+    const int iL = (int)L, nodes = 2 * iL, hm = (int)(M / 2);
+    const int L2 = (int)(L / L1), iL1 = (int)L1, sh = p - d;
+    const float inv_L2 = 1.0f / (float)L2;
     double2* ph = phi + g * phi_stride;
     const double2* Vs = V + g * v_stride;
     for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < nodes; u += gridDim.x * blockDim.x) {
-        const int tl = fdiv(u, inv_hk, hk), hn = u - tl * hk;          // leaf within the subtree, node within the leaf
-        const int c = fdiv(hn, inv_hm, hm), jhi = hn - c * hm;          // coset, node within the coset
-        const int64_t t = t0 + tl;
+        const int c = u >= iL ? 1 : 0;                                  // coset
+        const int64_t j = u - c * iL;                                   // position in the line
+        const int j1 = fdiv((int)j, inv_L2, L2), j2 = (int)j - j1 * L2;
+        const int jn = j1 + iL1 * j2;                                   // node index within the coset
+        const int jlo = jn & (int)(nleaves - 1), jhi = jn >> sh;
+        const int64_t t = bitrev((int)((oR + ((int64_t)jlo << (d + 1))) >> 1), p);
+        if (t < t0 || t >= t0 + nleaves || jhi >= hm) continue;        // (not reached: jn < L)
+        const int hn = c * hm + jhi;                                    // node within the leaf
         const int64_t q = t * K + 2 * (int64_t)hn;                     // its F condition; q + 1 is G
-        const int ot = 2 * bitrev((int)t, p);
-        const int jlo = (int)((ot - oR) >> (d + 1));
-        const int jn = jlo + (jhi << (p - d));
-        const int a1 = fdiv(jn, inv_L1, iL1);
-        const int64_t j = (int64_t)(jn - a1 * iL1) * L2 + a1;         // four-step position of node jn
         double2 f0[C], f1[C];
 #pragma unroll
         for (int col = 0; col < C; ++col) { f0[col] = ph[col * nq + q]; f1[col] = ph[col * nq + q + 1]; }
