@@ -660,8 +660,9 @@ static int fft_lines(double2* data, int64_t S, int64_t sstride, int64_t nlines, 
     fft_pass(data, S, sstride, nlines * L2, L2, 1, Lf, L2, L1, sign, Lf, tw, Q, 64, fuse, true, false);
     fft_pass(data, S, sstride, nlines * L1, L1, L2, Lf, 1, L2, sign, 0, tw, Q, 64, fuse, false, true);
     if (order == FFT_NATURAL) {
-        hipLaunchKernelGGL(k_fourstep_unscramble, grid1(nlines * Lf, S), dim3(256), 0, g.stream, data, scratch,
-                           sstride, scr_stride, Lf, nlines, L1, L2);
+        const int64_t tiles = ((L1 + 31) / 32) * ((L2 + 31) / 32);
+        hipLaunchKernelGGL(k_fourstep_transpose, dim3((unsigned)(nlines * tiles), (unsigned)S), dim3(256), 0,
+                           g.stream, data, scratch, sstride, scr_stride, Lf, L1, L2);
         hipLaunchKernelGGL(k_copy, grid1(nlines * Lf, S), dim3(256), 0, g.stream, scratch, data, scr_stride, sstride,
                            nlines * Lf);
         g.launches += 2;

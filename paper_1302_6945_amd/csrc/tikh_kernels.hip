@@ -600,19 +600,32 @@ __global__ __launch_bounds__(FFT_THREADS, CAP <= 2048 ? 4 : 1) void k_fft(const 
     }
 }
 
-// Out-of-place transpose per line-block: src holds, for each of `nlines`
-// lines of length L1*L2, the four-step order X[j1 + L1 j2] at j1*L2 + j2;
-// dst receives natural order.
-__global__ void k_fourstep_unscramble(const double2* __restrict__ src, double2* __restrict__ dst,
-                                      int64_t src_solve_stride, int64_t dst_solve_stride, int64_t line_stride,
-                                      int64_t nlines, int64_t L1, int64_t L2) {
-    const int64_t L = L1 * L2;
-    const int64_t tot = nlines * L;
-    const int64_t s = blockIdx.y;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
-        int64_t line = i / L, j = i - line * L;
-        int64_t j1 = j % L1, j2 = j / L1;
-        dst[s * dst_solve_stride + line * line_stride + j] = src[s * src_solve_stride + line * line_stride + j1 * L2 + j2];
+// Four-step order to natural order, out of place: src holds, for each line of length
+// L1*L2, the four-step order X[j1 + L1 j2] at j1*L2 + j2; dst receives natural order.
+// A transpose of each line's L1 x L2 matrix, dst[j2 L1 + j1] = src[j1 L2 + j2], through
+// 32 x 32 LDS tiles so that both sides are read and written in order.  Block x: (line,
+// tile row, tile column); block y: item; 256 threads (32 x 8).
+__global__ __launch_bounds__(256) void k_fourstep_transpose(const double2* __restrict__ src, double2* __restrict__ dst,
+                                                            int64_t src_solve_stride, int64_t dst_solve_stride,
+                                                            int64_t line_stride, int64_t L1, int64_t L2) {
+    __shared__ double2 tile[32][33];
+    const int64_t t1n = (L1 + 31) / 32, t2n = (L2 + 31) / 32;
+    const int64_t b = blockIdx.x;
+    const int64_t line = b / (t1n * t2n), rem = b - line * (t1n * t2n);
+    const int64_t t1 = rem / t2n, t2 = rem - t1 * t2n;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const double2* sl = src + blockIdx.y * src_solve_stride + line * line_stride;
+    double2* dl = dst + blockIdx.y * dst_solve_stride + line * line_stride;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int64_t j1 = t1 * 32 + ty + 8 * r, j2 = t2 * 32 + tx;
+        if (j1 < L1 && j2 < L2) tile[ty + 8 * r][tx] = sl[j1 * L2 + j2];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int64_t j2 = t2 * 32 + ty + 8 * r, j1 = t1 * 32 + tx;
+        if (j1 < L1 && j2 < L2) dl[j2 * L1 + j1] = tile[tx][ty + 8 * r];
     }
 }
 
