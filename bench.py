@@ -429,7 +429,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only; per-GPU batches shard trivially "
+        print("bench.py: runs on one GPU only; batches shard trivially across GPUs "
               "(independent solves), no multi-GPU path is provided", file=sys.stderr)
         sys.exit(2)
 
