@@ -226,3 +226,21 @@ def normal_residual(col, row, b, lam, x):
     r = TH_apply(col, row, _c(b) - T_apply(col, row, x)) - float(lam) ** 2 * _c(x)
     scale = np.linalg.norm(TH_apply(col, row, b)) + float(lam) ** 2 * np.linalg.norm(x)
     return float(np.linalg.norm(r) / scale)
+
+
+def general_solve(col, row, lcol, lrow, b):
+    """The general problem (Sec. 2 eq. (tik) with a Toeplitz Tikhonov matrix L, p x n; Sec. 3.2):
+    x = argmin ||T x - b||^2 + ||L x||^2, i.e. the least-squares solution of the stacked system
+    [T; L] x = [b; 0], written out densely and solved by numpy.linalg.lstsq (small sizes only).
+    (lcol, lrow) follow the Toeplitz convention of T: lcol[i] = l_i (i < p), lrow[j] = l_{-j}."""
+    T, L = dense_T(col, row), dense_T(lcol, lrow)
+    A = np.vstack([T, L])
+    rhs = np.concatenate([_c(b), np.zeros(L.shape[0], np.complex128)])
+    return np.linalg.lstsq(A, rhs, rcond=None)[0]
+
+
+def general_solve_normal(col, row, lcol, lrow, y):
+    """Normal form of the general problem (Sec. 7.1): x = (T^H T + L^H L)^{-1} y, the Gramians
+    formed densely and the system solved by numpy.linalg.solve (small sizes only)."""
+    T, L = dense_T(col, row), dense_T(lcol, lrow)
+    return np.linalg.solve(T.conj().T @ T + L.conj().T @ L, _c(y))

@@ -29,7 +29,7 @@ def _paper():
     with open(GOLDEN) as fh:
         for line in fh:
             if line.strip() and not line.startswith("#"):
-                n, l2, gr = line.split()
+                n, l2, gr = line.split()[:3]        # (the general-problem column is not used here)
                 out[int(n)] = (float(l2), float(gr))
     return out
 

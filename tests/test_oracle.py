@@ -373,3 +373,102 @@ def test_replica_workloads_recover_x():
         p = W.replica_gramian(n, 1)
         assert abs(p.gram[0] - 10.0 * np.sqrt(2.0 * n)) <= 1e-12
         assert np.max(np.abs(oracle.gramian_solve(p.gram, p.lcol, p.lrow, p.ys[0]) - p.x_true)) <= 1e-12
+
+
+# ---------------------------------------------------------------- the general problem (Sec. 3.2)
+def _circ(c):
+    n = len(c)
+    col = np.asarray(c, np.complex128)
+    row = np.concatenate([[col[0]], col[1:][::-1]])
+    return col, row
+
+
+def test_general_reduces_to_l2_with_scaled_identity():
+    """L = lambda I turns the general problem into eq. (tiksol) of the l2 problem: the
+    numpy least-squares oracle must agree with the C Householder QR (O1)."""
+    rng = np.random.default_rng(31)
+    for (m, n, cplx) in ((9, 6, False), (5, 8, True), (20, 20, True)):
+        col, row, b = W.random_problem(rng, m, n, cplx=cplx, L=4.0)
+        lam = 0.37
+        lcol = np.zeros(n, complex); lcol[0] = lam
+        lrow = np.zeros(n, complex); lrow[0] = lam
+        x = oracle.general_solve(col, row, lcol, lrow, b)
+        xr = oracle.solve(col, row, b, lam)
+        assert np.linalg.norm(x - xr) <= 1e-12 * np.linalg.norm(xr)
+
+
+def test_general_exact_rational():
+    """3 x 2 T and 2 x 2 L with integer generators: the normal equations
+    (T^T T + L^T L) x = T^T b solved exactly in rational arithmetic."""
+    a = {-1: 2, 0: 1, 1: -1, 2: 3}            # a_s of T (m = 3, n = 2)
+    l = {-1: 1, 0: 2, 1: -1}                  # l_s of L (p = 2, n = 2)
+    m, n, p = 3, 2, 2
+    T = [[Fraction(a[i - j]) for j in range(n)] for i in range(m)]
+    Lm = [[Fraction(l[i - j]) for j in range(n)] for i in range(p)]
+    b = [Fraction(v) for v in (1, -2, 4)]
+    A = [[sum(T[k][i] * T[k][j] for k in range(m)) + sum(Lm[k][i] * Lm[k][j] for k in range(p))
+          for j in range(n)] for i in range(n)]
+    r = [sum(T[k][i] * b[k] for k in range(m)) for i in range(n)]
+    det = A[0][0] * A[1][1] - A[0][1] * A[1][0]
+    xe = [(r[0] * A[1][1] - A[0][1] * r[1]) / det, (A[0][0] * r[1] - A[1][0] * r[0]) / det]
+    col = np.array([a[0], a[1], a[2]], float); row = np.array([a[0], a[-1]], float)
+    lcol = np.array([l[0], l[1]], float); lrow = np.array([l[0], l[-1]], float)
+    x = oracle.general_solve(col, row, lcol, lrow, np.array([1.0, -2.0, 4.0]))
+    assert np.max(np.abs(x - np.array([float(v) for v in xe]))) <= 1e-13
+
+
+def _circulant_closed_form(t, l, b):
+    th, lh, bh = np.fft.fft(t), np.fft.fft(l), np.fft.fft(b)
+    return np.fft.ifft(np.conj(th) * bh / (np.abs(th) ** 2 + np.abs(lh) ** 2))
+
+
+def test_general_circulant_closed_form():
+    """Circulant T and L (n x n): T^H T + L^H L is diagonal in the Fourier basis, so
+    x = IDFT(conj(t^) b^ / (|t^|^2 + |l^|^2))."""
+    rng = np.random.default_rng(32)
+    for n in (7, 16, 45):
+        t = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+        l = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+        b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+        (tc, tr), (lc, lr) = _circ(t), _circ(l)
+        x = oracle.general_solve(tc, tr, lc, lr, b)
+        xr = _circulant_closed_form(t, l, b)
+        assert np.linalg.norm(x - xr) <= 1e-11 * np.linalg.norm(xr)
+        assert np.linalg.norm(oracle.general_solve_normal(tc, tr, lc, lr,
+                                                          oracle.TH_apply(tc, tr, b)) - xr) <= 1e-11 * np.linalg.norm(xr)
+
+
+def test_general_optimality_with_second_difference():
+    """With L the (n-2) x n second difference (a rectangular Toeplitz L), the solution
+    satisfies the optimality condition T^H (b - T x) = L^H L x."""
+    rng = np.random.default_rng(33)
+    m, n = 40, 30
+    col, row, b = W.random_problem(rng, m, n, cplx=True, L=6.0)
+    lcol = np.zeros(n - 2); lcol[0] = 1.0
+    lrow = np.zeros(n); lrow[0], lrow[1], lrow[2] = 1.0, -2.0, 1.0
+    x = oracle.general_solve(col, row, lcol, lrow, b)
+    T, L = oracle.dense_T(col, row), oracle.dense_T(lcol, lrow)
+    lhs = T.conj().T @ (b - T @ x)
+    rhs = L.conj().T @ (L @ x)
+    assert np.linalg.norm(lhs - rhs) <= 1e-11 * np.linalg.norm(T.conj().T @ b)
+
+
+def test_general_pins_catch_a_transposed_regularizer():
+    """Mutation: the normal equations formed with L^T L instead of L^H L (a dropped
+    conjugate) fail the circulant closed form for complex L."""
+    rng = np.random.default_rng(34)
+    n = 16
+    t = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    l = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    (tc, tr), (lc, lr) = _circ(t), _circ(l)
+    T, L = oracle.dense_T(tc, tr), oracle.dense_T(lc, lr)
+    bad = np.linalg.solve(T.conj().T @ T + L.T @ L, T.conj().T @ b)
+    xr = _circulant_closed_form(t, l, b)
+    assert np.linalg.norm(bad - xr) > 1e-3 * np.linalg.norm(xr)
+
+
+def test_general_replica_workload_recovers_x():
+    for n in (16, 64):
+        col, row, lcol, lrow, y, x = W.replica_general(n, 2)
+        assert np.max(np.abs(oracle.general_solve_normal(col, row, lcol, lrow, y) - x)) <= 1e-12

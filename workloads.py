@@ -235,6 +235,20 @@ def replica_gramian(n, index=0):
     return GramianProblem(gram, lcol, lrow, [y], x, dict(config="replica_gramian"))
 
 
+def replica_general(n, index=0):
+    """Paper-shaped accuracy workload of the general problem (Sec. 7.1-7.2): n x n Toeplitz T
+    and L with complex standard normal generators, known x, y = (T^H T + L^H L) x (normal
+    form).  Returns (col, row, lcol, lrow, y, x)."""
+    rng = rng_for(8, index * 100003 + n)
+    cn = lambda k: (rng.standard_normal(k) + 1j * rng.standard_normal(k)) / math.sqrt(2.0)
+    col, row = split_generator(cn(2 * n - 1), n, n)
+    lcol, lrow = split_generator(cn(2 * n - 1), n, n)
+    x = cn(n)
+    y = toeplitz_rmatvec(col, row, toeplitz_matvec(col, row, x)) + \
+        toeplitz_rmatvec(lcol, lrow, toeplitz_matvec(lcol, lrow, x))
+    return col, row, lcol, lrow, y, x
+
+
 def random_problem(rng, m, n, cplx=False, L=None):
     """Small random problem for parity sweeps (ragged sizes)."""
     s = np.arange(-(n - 1), m)
