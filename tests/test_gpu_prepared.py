@@ -226,3 +226,78 @@ def test_prepared_invalid_arguments(P, batch):
     pb.free()
     with pytest.raises(P.TikhError):
         pb.run()
+
+
+def test_prepared_complex_forward_and_backward(P):
+    """Complex data (complex T, b and x_true): a prepared forward and backward pair, run
+    eagerly at two lambda sets and once from a captured graph, against the oracle's
+    solutions and gradients (every gradient block: generator column and row, b, lambda)."""
+    rng = np.random.default_rng(4471)
+    shapes = [(150, 120), (96, 130)]
+    nlam, nrhs = 2, 2
+    probs = []
+    for (m, n) in shapes:
+        col, row, _ = W.random_problem(rng, m, n, cplx=True, L=10.0)
+        B = [rng.standard_normal(m) + 1j * rng.standard_normal(m) for _ in range(nrhs)]
+        xt = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+        probs.append(dict(col=col, row=row, B=B, xt=xt, m=m, n=n))
+    ms = [p["m"] for p in probs]
+    ns = [p["n"] for p in probs]
+    col = dev(np.concatenate([p["col"] for p in probs]))
+    row = dev(np.concatenate([p["row"] for p in probs]))
+    b = dev(np.concatenate([np.concatenate(p["B"]) for p in probs]))
+    xt = dev(np.concatenate([np.tile(p["xt"], nlam * nrhs) for p in probs]))
+    lam0 = np.array([0.1, 0.6, 0.25, 1.3])
+    lam = dev(lam0)
+    fwd = P.prepare_batched(ms, ns, col, row, lam, nrhs, b, complex_data=True)
+    gx = torch.empty_like(fwd.x)
+    torch.sub(fwd.x, xt, out=gx)
+    bwd = P.prepare_backward_batched(ms, ns, col, row, lam, nrhs, b, fwd.x, gx, complex_data=True)
+
+    def check(lams):
+        assert (fwd.info.cpu().numpy() == 0).all() and (bwd.info.cpu().numpy() == 0).all()
+        x = fwd.x.cpu().numpy()
+        gc, gr, gb, gl = (t.cpu().numpy() for t in (bwd.g_col, bwd.g_row, bwd.g_b, bwd.g_lam))
+        xo = co = k = 0
+        for p, ll in zip(probs, lams.reshape(-1, nlam)):
+            m, n = p["m"], p["n"]
+            for lv in ll:
+                for r in range(nrhs):
+                    xs = x[xo:xo + n]
+                    assert relerr(xs, oracle.solve(p["col"], p["row"], p["B"][r], float(lv))) <= TOL
+                    ref = oracle.gradients(p["col"], p["row"], p["B"][r], float(lv), xs - p["xt"])
+                    ref_row = ref["g_row"].copy(); ref_row[0] = 0
+                    assert relerr(gc[co:co + m], ref["g_col"]) <= TOL, (m, n, lv, r)
+                    assert relerr(gr[xo:xo + n], ref_row) <= TOL, (m, n, lv, r)
+                    assert relerr(gb[co:co + m], ref["g_b"]) <= TOL, (m, n, lv, r)
+                    assert abs(gl[k] - ref["g_lam"]) <= TOL * max(1.0, abs(ref["g_lam"])), (m, n, lv, r)
+                    xo += n; co += m; k += 1
+        assert xo == len(x)
+
+    try:
+        bwd.run()
+        torch.cuda.synchronize()
+        check(lam0)
+        lam.copy_(dev(lam0 * 0.9))
+        fwd.run(); torch.sub(fwd.x, xt, out=gx); bwd.run()
+        torch.cuda.synchronize()
+        check(lam0 * 0.9)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            fwd.run(); torch.sub(fwd.x, xt, out=gx); bwd.run()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            fwd.run()
+            torch.sub(fwd.x, xt, out=gx)
+            bwd.run()
+        torch.cuda.synchronize()
+        lam.copy_(dev(lam0 * 1.2))
+        graph.replay()
+        torch.cuda.synchronize()
+        check(lam0 * 1.2)
+    finally:
+        bwd.free()
+        fwd.free()
