@@ -301,3 +301,51 @@ def test_prepared_complex_forward_and_backward(P):
     finally:
         bwd.free()
         fwd.free()
+
+
+def test_prepared_single_wave_leaves_padded_groups(P, batch):
+    """Options in force at preparation apply to every run: with the one-wavefront-per-group
+    leaf steps forced (leaf_wave_groups = 1) and 3 right-hand sides per (problem, lambda)
+    (groups of 2, the second padded), eager runs at two lambda sets give the oracle's
+    solutions and gradients."""
+    nrhs = 3
+    rng = np.random.default_rng(977)
+    ms = [p["m"] for p in batch]
+    ns = [p["n"] for p in batch]
+    B = [[rng.standard_normal(p["m"]) for _ in range(nrhs)] for p in batch]
+    col = dev(np.concatenate([p["col"] for p in batch]))
+    row = dev(np.concatenate([p["row"] for p in batch]))
+    b = dev(np.concatenate([np.concatenate(bb) for bb in B]))
+    xt = dev(np.concatenate([np.tile(p["xt"], NLAM * nrhs) for p in batch]))
+    lam0 = np.array([l for p in batch for l in p["lams"]])
+    lam = dev(lam0)
+    P.set_options(leaf_wave_groups=1)
+    try:
+        fwd = P.prepare_batched(ms, ns, col, row, lam, nrhs, b)
+        gx = torch.empty_like(fwd.x)
+        torch.sub(fwd.x, xt, out=gx)
+        bwd = P.prepare_backward_batched(ms, ns, col, row, lam, nrhs, b, fwd.x, gx)
+    finally:
+        P.set_options(leaf_wave_groups=1536)
+    try:
+        for scale in (1.0, 1.1):
+            lam.copy_(dev(lam0 * scale))
+            fwd.run(); torch.sub(fwd.x, xt, out=gx); bwd.run()
+            torch.cuda.synchronize()
+            assert (fwd.info.cpu().numpy() == 0).all() and (bwd.info.cpu().numpy() == 0).all()
+            x = fwd.x.cpu().numpy()
+            gb, gl = bwd.g_b.cpu().numpy(), bwd.g_lam.cpu().numpy()
+            xo = bo = k = 0
+            for p, bb, ll in zip(batch, B, (lam0 * scale).reshape(-1, NLAM)):
+                for lv in ll:
+                    for r in range(nrhs):
+                        xs = x[xo:xo + p["n"]]
+                        assert relerr(xs, oracle.solve(p["col"], p["row"], bb[r], float(lv))) <= TOL, (p["n"], lv, r)
+                        ref = oracle.gradients(p["col"], p["row"], bb[r], float(lv), xs - p["xt"])
+                        assert relerr(gb[bo:bo + p["m"]], ref["g_b"].real) <= TOL, (p["n"], lv, r)
+                        assert abs(gl[k] - ref["g_lam"]) <= TOL * max(1.0, abs(ref["g_lam"])), (p["n"], lv, r)
+                        xo += p["n"]; bo += p["m"]; k += 1
+            assert xo == len(x)
+    finally:
+        bwd.free()
+        fwd.free()
