@@ -99,6 +99,28 @@ def test_autograd_function(P):
     assert abs(float(lam.grad) - ref["g_lam"]) <= 1e-9 * max(1, abs(ref["g_lam"]))
 
 
+@pytest.mark.parametrize("cplx", [False, True])
+def test_autograd_function_all_blocks(P, cplx):
+    """torch.autograd through tikhonov_solve, real and complex data: every gradient block
+    (generator column, generator row with its entry 0 folded into the column, b, lambda)
+    against the oracle's adjoint, in torch's complex convention dL/dRe + i dL/dIm."""
+    rng = np.random.default_rng(31 + cplx)
+    m, n = 84, 61
+    col, row, b = W.random_problem(rng, m, n, cplx=cplx, L=10.0)
+    xt_np = rng.standard_normal(n) + (1j * rng.standard_normal(n) if cplx else 0)
+    c, r, bb = dev(col).requires_grad_(), dev(row).requires_grad_(), dev(b).requires_grad_()
+    lam = torch.tensor(0.35, dtype=torch.float64, device="cuda:0", requires_grad=True)
+    x = P.tikhonov_solve(c, r, bb, lam)
+    loss = 0.5 * ((x - dev(xt_np)).abs() ** 2).sum()
+    loss.backward()
+    ref = oracle.gradients(col, row, b, 0.35, x.detach().cpu().numpy() - xt_np)
+    ref_row = ref["g_row"].copy(); ref_row[0] = 0
+    for got, want in ((c.grad, ref["g_col"]), (r.grad, ref_row), (bb.grad, ref["g_b"])):
+        assert got.dtype == (torch.complex128 if cplx else torch.float64)
+        assert rel(got.cpu().numpy(), want if cplx else want.real) <= 1e-9
+    assert abs(float(lam.grad) - ref["g_lam"]) <= 1e-9 * max(1, abs(ref["g_lam"]))
+
+
 def test_backward_batched_matches_single(P):
     rng = np.random.default_rng(123)
     shapes = [(60, 40), (35, 70)]
