@@ -97,6 +97,19 @@ def test_invalid_arguments_rejected_on_host():
     assert P.lib.tikh_set_options(ctypes.byref(o)) == -1
 
 
+
+def test_error_messages():
+    """Every error code the header declares has its own message (TIKH_EHIP, whose text
+    comes from the HIP runtime, aside); unknown codes say so; TikhError carries it."""
+    _ensure_built()
+    import paper_1302_6945_amd as P
+    codes = (0, -1, -2, -4, -5)
+    msgs = [P.lib.tikh_strerror(c).decode() for c in codes]
+    assert all(msgs) and len(set(msgs)) == len(codes)
+    assert P.lib.tikh_strerror(-99).decode() == "unknown error"
+    with pytest.raises(P.TikhError, match="invalid argument"):
+        P.plan_info(0, 5)
+
 def test_workspace_query_on_host():
     """tikh_workspace_bytes is host arithmetic: positive, growing with the batch,
     one bucket per transform size (with several streams the buckets run side by side
