@@ -45,9 +45,10 @@
  * batches only) a recorded product transform length was too short for the
  * call's basis degrees, the results are not valid and the batch must be
  * prepared again, bit 64 = (prepared batches only) the solve's lambda was not
- * positive and finite: it was solved with lambda = 1 (bits may combine).  Right-hand sides of one (problem, lambda) share
- * a pivot sequence, so bits 1, 2 and 4 of a forward solve are those of its
- * (problem, lambda); bit 8 is the solve's own.
+ * positive and finite: it was solved with lambda = 1 (bits may combine).
+ * Right-hand sides of one (problem, lambda) share a pivot sequence, so bits 1,
+ * 2 and 4 of a forward solve are those of its (problem, lambda); bit 8 is the
+ * solve's own.
  * Single-problem calls synchronize the stream and return TIKH_ENUMERIC when
  * info != 0.  Calls are not thread safe (one host thread per library state).
  */
@@ -79,7 +80,8 @@ enum {
  * reads them back once per merge; later recursions and later calls with the
  * same composition (sizes, extension, lambda, element type) reuse the recorded
  * lengths without host synchronization, checked on the device, and a batch
- * whose degrees outgrow a recorded length is run again with read-back sizing.  Every solve takes `refine` refinement steps; a solve whose
+ * whose degrees outgrow a recorded length is run again with read-back sizing.
+ * Every solve takes `refine` refinement steps; a solve whose
  * estimated relative error is still above `refine_tol` takes further steps,
  * up to `refine_max` in all (the estimate: e0 = ||dx_1|| / ||x|| of the
  * first step approximates the first solve's error and the factor by which
