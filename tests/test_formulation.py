@@ -165,3 +165,64 @@ def test_gramian_conditions_hold_at_the_solution(n, p, extra):
     # another x leaves F's tail (G x + L^H L x - y)
     t1, _ = gram_tails(gram, lcol, lrow, x + 1e-3, y, N, fg, fl)
     assert np.max(np.abs(t1)) > 1e-7 * scale
+
+
+def toeplitz_extension(col, row, rows, N):
+    """First column of an N-circulant holding the rows x n Toeplitz block (col, row) in its
+    last `rows` rows and first n columns: c[r] = a_{r-(N-rows)}; the entries below
+    N-(rows+n-1) are the arbitrary ones (left zero here)."""
+    n = len(row)
+    c = np.zeros(N, np.complex128)
+    for r in range(N - (rows + n - 1), N):
+        s = r - (N - rows)
+        c[r] = col[s] if s >= 0 else row[-s]
+    return c
+
+
+def general_tails(col, row, lcol, lrow, x, y, N, conj=True):
+    """The general problem's three condition sets (Sec. 3.2 eqs. (ex2)-(ex3), transformed as
+    eq. (intcond)), unknown [x; s1 = T x; s2 = L x; g1; g2; g3; 1] and one extension size N
+    for both blocks:
+        F = [0, w^{(N-m-n)} conj(t^), w^{(N-p-n)} conj(l^), 1, 0, 0, -w^{(N-n)} y^]
+        G = [-t^, w^{(N-m)}, 0, 0, 1, 0, 0]
+        H = [-l^, 0, w^{(N-p)}, 0, 0, 1, 0]
+    Returns the coefficients of g1, g2, g3 past N-n, N-m and N-p."""
+    m, n, p = len(col), len(row), len(lcol)
+    T, L = oracle.dense_T(col, row), oracle.dense_T(lcol, lrow)
+    th, lh = ev(toeplitz_extension(col, row, m, N), N), ev(toeplitz_extension(lcol, lrow, p, N), N)
+    xh, s1h, s2h, yh = ev(x, N), ev(T @ x, N), ev(L @ x, N), ev(y, N)
+    cj = np.conj if conj else (lambda v: v)
+    g1 = coef(-(wp(N - m - n, N) * cj(th) * s1h + wp(N - p - n, N) * cj(lh) * s2h - wp(N - n, N) * yh))
+    g2 = coef(th * xh - wp(N - m, N) * s1h)
+    g3 = coef(lh * xh - wp(N - p, N) * s2h)
+    return g1[N - n:], g2[N - m:], g3[N - p:]
+
+
+@pytest.mark.parametrize("m,n,p,extra", [(7, 5, 5, 0), (6, 6, 9, 1), (10, 4, 3, 2), (5, 8, 8, 0), (6, 4, 6, 0)])
+def test_general_conditions_hold_at_the_solution(m, n, p, extra):
+    """The general problem's conditions (its GPU path is not built): at the oracle's solution
+    of min ||T x - b||^2 + ||L x||^2 the three gammas have no coefficients past their
+    lengths; with N = max(m, p) + n (one extension entry, as the paper's 1-circulant
+    extensions) the lengths are the paper's degree bounds (eq. (degcon)) when m = p.  A
+    perturbed x, or the adjoint symbols without their conjugates, leave F's tail."""
+    rng = np.random.default_rng(7 * m + 5 * n + p)
+    cn = lambda k: rng.standard_normal(k) + 1j * rng.standard_normal(k)
+    col, row, lcol, lrow, b = cn(m), cn(n), cn(p), cn(n), cn(m)
+    row[0] = col[0]
+    lrow[0] = lcol[0]
+    N = max(m, p) + n + extra
+    x = oracle.general_solve(col, row, lcol, lrow, b)
+    T = oracle.dense_T(col, row)
+    y = T.conj().T @ b
+    scale = np.linalg.norm(x) * (np.sum(np.abs(col)) + np.sum(np.abs(row)) + np.sum(np.abs(lcol))
+                                 + np.sum(np.abs(lrow))) ** 2 + np.linalg.norm(y)
+    tails = general_tails(col, row, lcol, lrow, x, y, N)
+    for t in tails:
+        assert np.max(np.abs(t)) <= 1e-12 * scale
+    if m == p and extra == 0:
+        # gamma lengths N - n, N - m, N - p: the paper's bounds m, n, n (eq. (degcon))
+        assert (N - n, N - m, N - p) == (m, n, n)
+    t1 = general_tails(col, row, lcol, lrow, x + 1e-3, y, N)[0]
+    assert np.max(np.abs(t1)) > 1e-7 * scale
+    t1 = general_tails(col, row, lcol, lrow, x, y, N, conj=False)[0]
+    assert np.max(np.abs(t1)) > 1e-6 * scale
