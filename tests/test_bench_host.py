@@ -1,4 +1,5 @@
-"""Host-side logic of bench.py (no GPU): the leaf-cutoff choice from autotuner timings."""
+"""Host-side logic of bench.py (no GPU): the leaf-cutoff choice from autotuner timings, the
+method's algorithmic work, the oracle leg's parity gate and when committed counter traffic applies."""
 import importlib.util
 import os
 
@@ -85,3 +86,30 @@ def test_oracle_leg_indexing_and_gate():
     bad[off] += 1e-6 * np.abs(x_gpu).max()
     _, parity2 = b.oracle_leg(probs, ip, nlam, nrhs, bad, run_backward, cores=2)
     assert not parity2["ok"]
+
+
+def test_measured_traffic_applies_only_to_its_sources_and_workload(tmp_path):
+    """The bench's `roofline.traffic` comes from a committed counter summary only while the
+    kernel and driver sources digest to the summary's value and the workload (problems, n)
+    and leaf cutoff are the summary's; otherwise it is null."""
+    import json
+    import shutil
+    from types import SimpleNamespace
+    b = _bench()
+    csrc = tmp_path / "paper_1302_6945_amd" / "csrc"
+    csrc.mkdir(parents=True)
+    for f in ("tikh_kernels.hip", "tikh_driver.hip", "tikh_internal.h"):
+        shutil.copy(os.path.join(ROOT, "paper_1302_6945_amd", "csrc", f), csrc / f)
+    (tmp_path / "profiles").mkdir()
+    rec = {"source_digest": b.source_digest(str(tmp_path)), "nprob": 256, "n": 16384, "n_lim": 256,
+           "bytes_per_launch": 123456789}
+    (tmp_path / "profiles" / "k_fft_hbm_traffic_headline_n16384.md").write_text(
+        "# summary\n\ntraffic_json: %s\n" % json.dumps(rec))
+    args = SimpleNamespace(nprob=256, n=16384)
+    assert b.measured_traffic(str(tmp_path), "k_fft", args, 256) == 123456789
+    assert b.measured_traffic(str(tmp_path), "k_fft", args, 192) is None
+    assert b.measured_traffic(str(tmp_path), "k_fft", SimpleNamespace(nprob=64, n=16384), 256) is None
+    assert b.measured_traffic(str(tmp_path), "k_prod_mul", args, 256) is None
+    with open(csrc / "tikh_kernels.hip", "a") as fh:
+        fh.write("\n// changed\n")
+    assert b.measured_traffic(str(tmp_path), "k_fft", args, 256) is None
