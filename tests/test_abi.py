@@ -162,3 +162,30 @@ def test_environment_overrides_options():
                          check=True)
     assert out.stdout.split() == ["256", "1", "0.25", "16"]
     assert "TIKH_NLIM" in out.stderr and "TIKH_STREAMS" in out.stderr
+
+
+def test_package_refuses_to_import_without_the_library(tmp_path):
+    """No CPU fallback: a copy of the package without libtikh.so raises ImportError on import."""
+    import shutil
+    import sys
+    pkg = tmp_path / "paper_1302_6945_amd"
+    shutil.copytree(os.path.join(ROOT, "paper_1302_6945_amd"), pkg,
+                    ignore=shutil.ignore_patterns("*.so", "__pycache__", "csrc"))
+    r = subprocess.run([sys.executable, "-c", "import paper_1302_6945_amd"], cwd=str(tmp_path),
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0
+    assert "ImportError" in r.stderr and "libtikh.so is not built" in r.stderr
+
+
+def test_product_does_not_reference_the_oracle():
+    """The library sources, the header and the binding name nothing under oracle/ (the oracle is
+    test infrastructure; the checked path shares no code with it)."""
+    srcs = [HEADER]
+    for d, _, files in os.walk(os.path.join(ROOT, "paper_1302_6945_amd")):
+        if "__pycache__" in d:
+            continue
+        srcs += [os.path.join(d, f) for f in files if f.endswith((".py", ".hip", ".h", ".cpp"))]
+    assert len(srcs) >= 8
+    for path in srcs:
+        text = open(path).read()
+        assert not re.search(r"\boracle\b|tikh_oracle", text), path
