@@ -189,3 +189,16 @@ def test_product_does_not_reference_the_oracle():
     for path in srcs:
         text = open(path).read()
         assert not re.search(r"\boracle\b|tikh_oracle", text), path
+
+
+def test_oracle_and_inputs_do_not_reference_the_product():
+    """The oracle (and the seeded input generators both sides share) import, link and include
+    nothing of the GPU library."""
+    paths = [os.path.join(ROOT, "workloads.py")]
+    for f in os.listdir(os.path.join(ROOT, "oracle")):
+        if f.endswith((".py", ".c", ".h")):
+            paths.append(os.path.join(ROOT, "oracle", f))
+    assert len(paths) >= 4
+    for path in paths:
+        text = open(path).read()
+        assert not re.search(r"paper_1302_6945_amd|libtikh\.so|tikh\.h|tikh_kernels|tikh_driver", text), path
