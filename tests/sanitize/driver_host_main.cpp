@@ -1,7 +1,8 @@
 // Exercises the library's host-only logic under AddressSanitizer / UndefinedBehaviorSanitizer
 // (no device work): the extension plan of Alg. 2 over many sizes and leaf cutoffs, the
 // workspace query over ragged batches (with plan merging, chunking and several streams),
-// option validation (valid, invalid, boundary values) and the error strings.
+// option validation (valid, invalid, boundary values), the error strings, launch timing with
+// nothing launched and the prepared-batch calls' argument checks.
 #include <cstdio>
 #include <cstdint>
 #include <vector>
@@ -45,6 +46,24 @@ int main() {
     bad |= tikh_set_options(&o) != TIKH_EINVAL;
     bad |= tikh_set_options(&keep) != TIKH_OK;
     for (int code = 0; code >= -6; --code) bad |= tikh_strerror(code) == nullptr;
+    // launch timing with nothing launched, and the prepared-batch calls' argument checks
+    double ms = -1.0, units = -1.0;
+    int64_t count = -1;
+    bad |= tikh_profile_kernel("fft") != TIKH_OK;
+    bad |= tikh_profile_read(&ms, &count) != TIKH_OK || ms != 0.0 || count != 0;
+    bad |= tikh_profile_units(&units) != TIKH_OK || units != 0.0;
+    bad |= tikh_profile_kernel(nullptr) != TIKH_OK;
+    bad |= tikh_profile_read(nullptr, &count) != TIKH_EINVAL;
+    size_t pbytes = 0;
+    bad |= tikh_prepared_run(nullptr) != TIKH_EINVAL;
+    bad |= tikh_prepared_workspace(nullptr, &pbytes) != TIKH_EINVAL;
+    bad |= tikh_prepared_free(nullptr) != TIKH_OK;
+    tikh_prepared* h = reinterpret_cast<tikh_prepared*>(1);
+    int64_t pm = 8, pn = 8;
+    double lam = 1.0;
+    bad |= tikh_prepare_batched(1, &pm, &pn, nullptr, nullptr, 1, &lam, 1, nullptr, nullptr, nullptr, 0, &h) !=
+           TIKH_EINVAL;
+    bad |= h != nullptr;
     std::printf(bad ? "driver host sanitizer run: FAILED\n" : "driver host sanitizer run: clean\n");
     return bad;
 }
