@@ -113,3 +113,15 @@ def test_measured_traffic_applies_only_to_its_sources_and_workload(tmp_path):
     with open(csrc / "tikh_kernels.hip", "a") as fh:
         fh.write("\n// changed\n")
     assert b.measured_traffic(str(tmp_path), "k_fft", args, 256) is None
+
+
+def test_more_than_one_gpu_is_refused():
+    """`bench.py --gpus N` with N > 1 (or under a launcher with WORLD_SIZE > 1) exits with a
+    message before touching any device."""
+    import subprocess
+    import sys
+    for argv, env in ((["--gpus", "2"], {}), ([], {"WORLD_SIZE": "4"})):
+        r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py")] + argv, capture_output=True, text=True,
+                           timeout=120, env=dict(os.environ, **env))
+        assert r.returncode == 2
+        assert "one GPU only" in r.stderr and r.stdout == ""
