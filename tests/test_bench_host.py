@@ -1,5 +1,6 @@
 """Host-side logic of bench.py (no GPU): the leaf-cutoff choice from autotuner timings, the
-method's algorithmic work, the oracle leg's parity gate and when committed counter traffic applies."""
+method's algorithmic work, the oracle leg's parity gate, when committed counter traffic applies and
+the refusal of more than one GPU."""
 import importlib.util
 import os
 
